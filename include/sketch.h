@@ -1,0 +1,136 @@
+/*
+ * sketch.h -- C ABI of the MI355X sketch library (libsketch.so).
+ *
+ * The operation (paper Sec. I-A, eq. (1)): given a tall sparse A (m x n,
+ * m >> n) and a sketch size d (n < d <= 4n typical), sample S (d x m) with
+ * i.i.d. entries from a prescribed distribution and return A_hat = S A.
+ * S is never stored: it is regenerated on the fly from a counter-based
+ * generator (Sec. IV-B-1), Philox4x32-10 keyed by the 64-bit seed with
+ * counter (S-row group, S column), so every entry is a pure function of
+ * (seed, row, column) and the result does not depend on tiling or launch
+ * shape (Sec. IV-C).
+ *
+ * Conventions common to every call:
+ *  - All matrix/vector pointers are DEVICE pointers owned by the caller; the
+ *    library never allocates device memory (the caller passes a workspace),
+ *    so device-memory accounting by the caller is exact.
+ *  - Indices are 0-based (the paper's pseudocode is 1-based).
+ *  - A is CSC: colptr int64[n+1] (colptr[0] = 0, colptr[n] = nnz, non-
+ *    decreasing), rowidx int32[nnz] strictly increasing within a column and
+ *    in [0, m), vals[nnz] of type vtype.  Explicit zeros are structural.
+ *    FP64 values are rounded to FP32 (round to nearest even) on load.
+ *  - Outputs are column-major FP32 with leading dimension ld >= rows, and
+ *    are overwritten (not accumulated into).
+ *  - Calls are asynchronous on the caller's HIP stream (hip_stream may be
+ *    NULL for the default stream).  Argument errors (null pointers, bad
+ *    sizes, too-small workspace) are returned synchronously.  Errors in the
+ *    CSC *contents* are detected on the device; they make the call write
+ *    NaN into the output and record a status in the workspace, which
+ *    sk_sketch_status() returns (it synchronises the stream).
+ *  - HIP launch failures map to SK_EHIP.
+ *  - The library holds no mutable global state; concurrent calls on
+ *    different streams with different workspaces are independent.
+ */
+#ifndef SKETCH_H
+#define SKETCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SK_OK = 0,
+  SK_EINVAL = -1,       /* bad argument (null pointer, size < 1, ld < rows, ...) */
+  SK_EUNSORTED = -2,    /* row indices not strictly increasing within a column   */
+  SK_ERANGE = -3,       /* a row index outside [0, m)                            */
+  SK_EWORKSPACE = -4,   /* workspace pointer null or smaller than required       */
+  SK_EHIP = -5,         /* a HIP runtime call or kernel launch failed            */
+  SK_EUNSUPPORTED = -6, /* valid request this build does not support             */
+  SK_ECOLPTR = -7       /* colptr not non-decreasing from 0 to nnz               */
+} sk_status;
+
+/* Distribution of the i.i.d. entries of S (Sec. I-A): uniform on {+1,-1},
+ * uniform on (-1,1), standard Gaussian. */
+typedef enum { SK_RADEMACHER = 0, SK_UNIFORM = 1, SK_GAUSSIAN = 2 } sk_dist;
+
+/* Element type of the CSC values. */
+typedef enum { SK_F64 = 0, SK_F32 = 1, SK_BF16 = 2 } sk_vtype;
+
+/* Operand precision of row blocks that are dense enough to run as a dense
+ * contraction on the matrix cores.  SK_PREC_F32 keeps FP32 operands; BF16 and
+ * FP8 (E4M3) hold +-1 entries of S exactly and are accepted for the +-1
+ * distribution only.  Accumulation is always FP32. */
+typedef enum { SK_PREC_F32 = 0, SK_PREC_BF16 = 1, SK_PREC_FP8 = 2 } sk_prec;
+
+/* A sparse CSC matrix in device memory (see the conventions above). */
+typedef struct {
+  int64_t m, n, nnz;
+  const int64_t* colptr;
+  const int32_t* rowidx;
+  const void* vals;
+  int32_t vtype; /* sk_vtype */
+} sk_csc;
+
+/* Optional tuning override (NULL = the library's own choice from the shape).
+ * Any valid setting gives the same S and A_hat up to FP32 summation order. */
+typedef struct {
+  int32_t rows_per_block; /* nonempty A rows per S tile (0 = auto)            */
+  int32_t splits;         /* row-range splits combined by a fixed-order sum   */
+  int32_t variant;        /* kernel shape id (0 = auto); see sk_variant_count */
+  int32_t dense_min_pct;  /* densify a row block at >= this % density (0 = auto,
+                             101 = never)                                      */
+  int32_t phases;         /* 0 = all; else a mask of 1 = validate + inspector,
+                             2 = S tiles + accumulation, 4 = split reduction.
+                             Running a subset reuses the workspace contents of
+                             an earlier full call with the same A, d and tuning
+                             (used to time one phase in isolation).           */
+} sk_tuning;
+
+/* Human-readable name of a status code (static storage). */
+const char* sk_status_string(int status);
+
+/* Number of kernel shape variants accepted in sk_tuning.variant (1..count). */
+int sk_variant_count(void);
+
+/* Workspace bytes sk_sketch needs for this A, d and tuning (tune may be
+ * NULL).  Host-only; touches no device memory.  Returns SK_EINVAL on bad
+ * sizes. */
+sk_status sk_sketch_workspace(const sk_csc* A, int64_t d, int32_t dist, int32_t prec,
+                              const sk_tuning* tune, size_t* bytes);
+
+/* A_hat[0:d, 0:n] = S[row0 : row0+d, 0:m] * A   (eq. (1); the row offset is
+ * the paper's r in compute_kernel(A_hat[i:, j:], A[:, j:], i), Algorithm 1).
+ * A_hat: device FP32, column-major, leading dimension ld >= d, written in
+ * full.  ws: device workspace of ws_bytes >= sk_sketch_workspace().  The
+ * call validates A on the device (see sk_sketch_status), builds the blocked
+ * row layout of A (the inspector), regenerates S tile by tile and
+ * accumulates in FP32.  Asynchronous on hip_stream. */
+sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint64_t seed,
+                    int32_t prec, const sk_tuning* tune, float* Ahat, int64_t ld, void* ws,
+                    size_t ws_bytes, void* hip_stream);
+
+/* Status of the last sk_sketch that used this workspace (synchronises
+ * hip_stream).  Also reports the inspector's counts when the pointers are
+ * non-NULL: nonempty rows of A and row blocks.  Returns SK_OK, SK_EUNSORTED,
+ * SK_ERANGE, SK_ECOLPTR or SK_EHIP. */
+sk_status sk_sketch_status(const void* ws, void* hip_stream, int64_t* nonempty_rows,
+                           int64_t* row_blocks);
+
+/* Test hook: S[row0 : row0+d, col0 : col0+ncols] into S (device FP32,
+ * column-major, leading dimension ld >= d), from the same device generator
+ * the sketch uses.  Asynchronous on hip_stream. */
+sk_status sk_materialize_s(int64_t row0, int64_t d, int64_t col0, int64_t ncols, int32_t dist,
+                           uint64_t seed, float* S, int64_t ld, void* hip_stream);
+
+/* Test hook (host only, no device): the FP32 coefficient tables the device
+ * generator uses, for comparison with an independent derivation:
+ * log_c[5], sin_c[7], cos_c[8], misc[3] = {ln2_hi, ln2_lo, sqrt2}. */
+void sk_rng_tables(float* log_c, float* sin_c, float* cos_c, float* misc);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SKETCH_H */

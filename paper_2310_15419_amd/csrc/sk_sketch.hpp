@@ -1,0 +1,274 @@
+// sk_sketch.hpp -- the fused sketch kernel A_hat = S A on the blocked layout.
+//
+// One workgroup owns an output tile A_hat[i0 : i0 + d_b, column range] for a
+// range of row blocks (a "split" of the nonempty rows).  Per row block it
+//   1. regenerates the S tile S[i0 : i0 + d_b, rows of the block] into LDS,
+//      one generator call per (row, 4 S rows) -- every S entry is generated
+//      once per tile and reused by every column that has a nonzero in that
+//      row (the reuse of Algorithm 4, Sec. II-B; generation count of
+//      Sec. III-B),
+//   2. stages the block's entries (ordered by column, then row) into LDS,
+//   3. accumulates: lanes are grouped Q at a time; a group owns CS columns
+//      and, inside the tile, Q*DL consecutive S rows (DL per lane).  For each
+//      of its columns it walks the column's entries in row order (the kji
+//      order of Algorithm 3 restricted to the block) and does
+//      acc[col][r] += a * S_tile[row][r] in FP32 registers.
+// Columns are owned by exactly one group, so there are no atomics; every sum
+// has a fixed order for a fixed tuning, and splits are combined by a
+// fixed-order reduction.  The outer grid is Algorithm 1's blocking over the
+// S rows (tiles) plus a split of the inner dimension.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sk_inspect.hpp"
+#include "sk_rng.hpp"
+
+namespace sk {
+
+struct SketchParams {
+  const int32_t* rowlist;
+  const int32_t* seg;
+  const uint2* ent;
+  const Header* hdr;
+  int64_t n, d, row0;
+  uint64_t seed;
+  int32_t m_b;      // nonempty rows per block
+  int32_t e_max;    // entries staged per pass
+  int32_t d_b;      // S rows per tile = dt * Q * DL (power of two)
+  int32_t log2_cpr; // log2(d_b / rows per generator chunk)
+  int32_t dt;       // S-row subtiles per workgroup
+  int32_t cg;       // column groups per subtile
+  int32_t tiles;    // ceil(d / d_b)
+  int32_t splits;   // row-range splits
+  int32_t col_per_wg; // columns one workgroup covers (cg * CS)
+  float* out;       // A_hat (splits == 1) or the split partials
+  int64_t ld;       // leading dimension of out
+  int64_t split_stride;
+};
+
+// ---------------------------------------------------------------- S tile
+// Fill S_lds[l * d_b + t] = S(grow0 + t, rowlist[b*m_b + l]) for l < rb,
+// t < d_b.
+template <int DIST, int WGS>
+__device__ __forceinline__ void fill_tile(float* __restrict__ S_lds, const SketchParams& P,
+                                          const int32_t* __restrict__ rows, int rb,
+                                          uint64_t grow0) {
+  const int tid = threadIdx.x;
+  const int log2_cpr = P.log2_cpr;
+  const int cmask = (1 << log2_cpr) - 1;
+  const int total = rb << log2_cpr;
+  if (DIST == DIST_RADEMACHER) {
+    const int rpc = P.d_b < 32 ? P.d_b : 32;  // S rows per chunk
+    for (int idx = tid; idx < total; idx += WGS) {
+      const int l = idx >> log2_cpr;
+      const int ch = idx & cmask;
+      const uint64_t j = (uint64_t)(uint32_t)rows[l];
+      const uint32_t bits = sign_bits32(P.seed, grow0 + (uint64_t)ch * 32u, j);
+      float4* dst = reinterpret_cast<float4*>(S_lds + l * P.d_b + ch * 32);
+      for (int t = 0; t < rpc; t += 4) {
+        float4 v;
+        v.x = (bits >> (t + 0)) & 1u ? -1.0f : 1.0f;
+        v.y = (bits >> (t + 1)) & 1u ? -1.0f : 1.0f;
+        v.z = (bits >> (t + 2)) & 1u ? -1.0f : 1.0f;
+        v.w = (bits >> (t + 3)) & 1u ? -1.0f : 1.0f;
+        dst[t >> 2] = v;
+      }
+    }
+  } else if ((grow0 & 3u) == 0) {
+    // aligned: chunk ch of row l is exactly generator group grow0/4 + ch
+    constexpr int U = 4;
+    const uint64_t g0 = grow0 >> 2;
+    for (int base = tid; base < total; base += U * WGS) {
+      int32_t jr[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = base + u * WGS;
+        jr[u] = idx < total ? rows[idx >> log2_cpr] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = base + u * WGS;
+        if (idx < total) {
+          const int l = idx >> log2_cpr;
+          const int ch = idx & cmask;
+          float v[4];
+          quad_values<DIST>(P.seed, g0 + (uint64_t)ch, (uint64_t)(uint32_t)jr[u], v);
+          *reinterpret_cast<float4*>(S_lds + l * P.d_b + ch * 4) =
+              make_float4(v[0], v[1], v[2], v[3]);
+        }
+      }
+    }
+  } else {
+    // misaligned tile start: the tile's rows touch d_b/4 + 1 generator
+    // groups; each group is generated once and its rows inside the tile kept
+    const int ng = (P.d_b >> 2) + 1;
+    const uint64_t g0 = grow0 >> 2;
+    const int shift = (int)(grow0 & 3u);
+    const int tot = rb * ng;
+    for (int idx = tid; idx < tot; idx += WGS) {
+      const int l = idx / ng;
+      const int gi = idx - l * ng;
+      float v[4];
+      quad_values<DIST>(P.seed, g0 + (uint64_t)gi, (uint64_t)(uint32_t)rows[l], v);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int t = gi * 4 + w - shift;  // row inside the tile
+        if (t >= 0 && t < P.d_b) S_lds[l * P.d_b + t] = v[w];
+      }
+    }
+  }
+}
+
+template <int DL>
+__device__ __forceinline__ void load_rows(const float* __restrict__ p, float (&s)[DL]) {
+  static_assert(DL % 4 == 0 || DL == 1 || DL == 2, "DL");
+  if constexpr (DL % 4 == 0) {
+#pragma unroll
+    for (int t = 0; t < DL; t += 4) {
+      const float4 v = *reinterpret_cast<const float4*>(p + t);
+      s[t] = v.x; s[t + 1] = v.y; s[t + 2] = v.z; s[t + 3] = v.w;
+    }
+  } else if constexpr (DL == 2) {
+    const float2 v = *reinterpret_cast<const float2*>(p);
+    s[0] = v.x; s[1] = v.y;
+  } else {
+    s[0] = p[0];
+  }
+}
+
+// ---------------------------------------------------------------- kernel
+template <int DIST, int DL, int Q, int CS, int WGS>
+__global__ __launch_bounds__(WGS) void k_sketch(SketchParams P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* S_lds = reinterpret_cast<float*>(smem);
+  uint2* E_lds = reinterpret_cast<uint2*>(smem + (size_t)P.m_b * P.d_b * sizeof(float));
+
+  const int tid = threadIdx.x;
+  const int bid = blockIdx.x;
+  const int split = bid % P.splits;
+  const int rest = bid / P.splits;
+  const int tile = rest % P.tiles;
+  const int crange = rest / P.tiles;
+  const int64_t i_tile = (int64_t)tile * P.d_b;
+  const uint64_t grow0 = (uint64_t)(P.row0 + i_tile);
+
+  const int grp = tid / Q;
+  const int q = tid - grp * Q;
+  const int dsub = grp / P.cg;
+  const int cgi = grp - dsub * P.cg;
+  const bool active = dsub < P.dt;
+  const int rofs = dsub * (Q * DL) + q * DL;
+  const int64_t kbase = (int64_t)crange * P.col_per_wg + (int64_t)cgi * CS;
+
+  float acc[CS][DL];
+#pragma unroll
+  for (int c = 0; c < CS; ++c)
+#pragma unroll
+    for (int t = 0; t < DL; ++t) acc[c][t] = 0.0f;
+
+  const int status = P.hdr->status;
+  if (status == 0) {
+    const int64_t nb = P.hdr->nblocks;
+    const int64_t R = P.hdr->nonempty;
+    const int64_t b_lo = nb * split / P.splits;
+    const int64_t b_hi = nb * (split + 1) / P.splits;
+    for (int64_t b = b_lo; b < b_hi; ++b) {
+      const int64_t rem = R - b * P.m_b;
+      const int rb = (int)(rem < P.m_b ? rem : P.m_b);
+      const int32_t* segb = P.seg + b * P.n;
+      const int32_t blk_beg = segb[0];
+      const int32_t blk_end = segb[P.n];
+      int32_t pb[CS + 1];
+#pragma unroll
+      for (int c = 0; c <= CS; ++c) {
+        const int64_t k = kbase + c;
+        pb[c] = active ? segb[k < P.n ? k : P.n] : blk_end;
+      }
+      __syncthreads();  // the previous block's tile and entries are consumed
+      fill_tile<DIST, WGS>(S_lds, P, P.rowlist + b * P.m_b, rb, grow0);
+      for (int32_t s0 = blk_beg; s0 < blk_end; s0 += P.e_max) {
+        const int32_t s1 = (blk_end - s0 < P.e_max) ? blk_end : s0 + P.e_max;
+        if (s0 != blk_beg) __syncthreads();
+        for (int32_t p = s0 + tid; p < s1; p += WGS) E_lds[p - s0] = P.ent[p];
+        __syncthreads();
+        if (active) {
+          const float* __restrict__ Sl = S_lds + rofs;
+#pragma unroll
+          for (int c = 0; c < CS; ++c) {
+            const int32_t lo = pb[c] > s0 ? pb[c] : s0;
+            const int32_t hi = pb[c + 1] < s1 ? pb[c + 1] : s1;
+            for (int32_t p = lo; p < hi; ++p) {
+              const uint2 e = E_lds[p - s0];
+              const float a = __uint_as_float(e.y);
+              float s[DL];
+              load_rows<DL>(Sl + (int)e.x * P.d_b, s);
+#pragma unroll
+              for (int t = 0; t < DL; ++t) acc[c][t] = __builtin_fmaf(a, s[t], acc[c][t]);
+            }
+          }
+        }
+      }
+    }
+  }
+  if (active) {
+    float* __restrict__ out = P.out + (int64_t)split * P.split_stride;
+    const float nan = __uint_as_float(0x7FC00000u);
+#pragma unroll
+    for (int c = 0; c < CS; ++c) {
+      const int64_t k = kbase + c;
+      if (k < P.n && k < (int64_t)(crange + 1) * P.col_per_wg) {
+#pragma unroll
+        for (int t = 0; t < DL; ++t) {
+          const int64_t i = i_tile + rofs + t;
+          if (i < P.d) out[i + k * P.ld] = status ? nan : acc[c][t];
+        }
+      }
+    }
+  }
+}
+
+// A_hat = sum over splits of the partials, fixed order.
+__global__ void k_reduce_splits(const float* __restrict__ part, int splits, int64_t d, int64_t n,
+                                float* __restrict__ out, int64_t ld) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= d * n) return;
+  const int64_t k = t / d, i = t - k * d;
+  float s = part[t];
+  for (int q = 1; q < splits; ++q) s += part[(int64_t)q * d * n + t];
+  out[i + k * ld] = s;
+}
+
+// S[r + c*ld] = S(row0 + r, col0 + c): one thread per (generator group,
+// column); rows outside [row0, row0 + d) are skipped.
+template <int DIST>
+__global__ void k_materialize(int64_t row0, int64_t d, int64_t col0, int64_t ncols,
+                              uint64_t seed, float* __restrict__ S, int64_t ld) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int rpg = DIST == DIST_RADEMACHER ? 32 : 4;  // rows per thread
+  const int64_t gfirst = row0 / rpg;
+  const int64_t groups = (row0 + d - 1) / rpg - gfirst + 1;
+  if (t >= groups * ncols) return;
+  const int64_t c = t / groups, gi = t - c * groups;
+  const uint64_t j = (uint64_t)(col0 + c);
+  const int64_t gr = (gfirst + gi) * rpg;  // first global row of the group
+  float* col = S + c * ld;
+  if (DIST == DIST_RADEMACHER) {
+    const uint32_t bits = sign_bits32(seed, (uint64_t)gr, j);
+    for (int u = 0; u < 32; ++u) {
+      const int64_t r = gr + u - row0;
+      if (r >= 0 && r < d) col[r] = (bits >> u) & 1u ? -1.0f : 1.0f;
+    }
+  } else {
+    float v[4];
+    quad_values<DIST>(seed, (uint64_t)(gr >> 2), j, v);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t r = gr + u - row0;
+      if (r >= 0 && r < d) col[r] = v[u];
+    }
+  }
+}
+
+}  // namespace sk

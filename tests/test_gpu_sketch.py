@@ -1,0 +1,199 @@
+"""GPU parity of the HIP sketch against the FP64 oracle (through the C-ABI).
+
+Bar: S bit-exact; A_hat normwise relative error <= 1e-5 (FP32 path) and
+each column within 1e-4; identity blocks bit-exact; results bitwise
+reproducible for a fixed tuning.
+"""
+import numpy as np
+import pytest
+
+from paper_2310_15419_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DISTS = ["rademacher", "uniform", "gaussian"]
+TOL_NORM = 1e-5
+TOL_COL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    from paper_2310_15419_amd import binding
+    binding.lib()
+    return binding
+
+
+def rel_errors(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    diff = got - ref
+    norm = np.linalg.norm(diff) / max(np.linalg.norm(ref), 1e-300)
+    colref = np.linalg.norm(ref, axis=0)
+    col = np.linalg.norm(diff, axis=0) / np.maximum(colref, 1e-300)
+    col = np.where(colref > 0, col, np.linalg.norm(diff, axis=0))
+    return norm, float(col.max()) if col.size else 0.0
+
+
+def run_gpu(B, A, d, dist, seed, row0=0, tune=None, dtype=None):
+    dA = B.DeviceCsc.from_host(A, dtype=dtype)
+    out = B.sketch(dA, d, dist, seed, row0=row0, tune=tune)
+    return out.cpu().numpy().astype(np.float64)
+
+
+def run_oracle(oracle_lib, A, d, dist, seed, row0=0):
+    return oracle_lib.sketch(A.m, A.n, A.colptr, A.rowidx, A.vals.astype(np.float64), d, dist,
+                             seed, row0=row0)
+
+
+# ------------------------------------------------------------------ S
+@pytest.mark.parametrize("dist", DISTS)
+@pytest.mark.parametrize("row0,d,col0,ncols", [(0, 256, 0, 300), (3, 131, 99_990, 17),
+                                               (126, 70, 2**31 - 5, 4), (1, 9, 2**40 + 3, 5)])
+def test_materialize_bit_exact(B, oracle_lib, dist, row0, d, col0, ncols):
+    print(f"materialize {dist} row0={row0} d={d} col0={col0}", flush=True)
+    got = B.materialize_s(row0, d, col0, ncols, dist, 1234).cpu().numpy().astype(np.float64)
+    ref = oracle_lib.materialize_s(dist, 1234, row0, d, col0, ncols)
+    assert np.array_equal(got, ref)
+
+
+# ------------------------------------------------------------- A_hat
+@pytest.mark.parametrize("dist", DISTS)
+@pytest.mark.parametrize("variant", [0, 1, 4, 5, 6])
+def test_sketch_small_all_variants(B, oracle_lib, dist, variant):
+    # several tiles in d, several row blocks, ragged tails everywhere
+    m, n, d = 7001, 77, 203
+    A = inputs.uniform_positions(m, n, 9000, 5, "normal", np.float64)
+    tune = {"variant": variant, "rows_per_block": 97} if variant else None
+    print(f"sketch small {dist} variant={variant}", flush=True)
+    got = run_gpu(B, A, d, dist, 42, tune=tune)
+    ref = run_oracle(oracle_lib, A, d, dist, 42)
+    norm, col = rel_errors(got, ref)
+    assert norm <= TOL_NORM and col <= TOL_COL, (norm, col)
+
+
+@pytest.mark.parametrize("dist", DISTS)
+def test_tiling_independence(B, oracle_lib, dist):
+    m, n, d = 20_000, 150, 300
+    A = inputs.uniform_positions(m, n, 30_000, 8, "uniform", np.float32)
+    ref = run_oracle(oracle_lib, A, d, dist, 3)
+    outs = []
+    for tune in [None, {"rows_per_block": 64, "splits": 3}, {"rows_per_block": 1000, "splits": 1},
+                 {"variant": 6, "splits": 16}, {"variant": 5, "rows_per_block": 31}]:
+        print(f"tiling {dist} {tune}", flush=True)
+        got = run_gpu(B, A, d, dist, 3, tune=tune)
+        norm, col = rel_errors(got, ref)
+        assert norm <= TOL_NORM and col <= TOL_COL, (tune, norm, col)
+        outs.append(got)
+
+
+@pytest.mark.parametrize("dist", DISTS)
+def test_identity_blocks_exact(B, oracle_lib, dist):
+    m, n, d = 50_000, 300, 257
+    rng = np.random.default_rng(2)
+    p = rng.choice(m, size=n, replace=False)
+    e = rng.integers(-3, 4, size=n)
+    A = inputs.from_coo(m, n, p, np.arange(n), (2.0 ** e).astype(np.float32))
+    got = run_gpu(B, A, d, dist, 11)
+    S = np.stack([oracle_lib.materialize_s(dist, 11, 0, d, int(pk), 1)[:, 0] for pk in p], axis=1)
+    assert np.array_equal(got, S * (2.0 ** e)[None, :])
+
+
+def test_row0_stacking_and_determinism(B, oracle_lib):
+    m, n, d = 30_000, 64, 200
+    A = inputs.uniform_positions(m, n, 40_000, 13, "uniform", np.float32)
+    for dist in DISTS:
+        full = run_gpu(B, A, d, dist, 5)
+        again = run_gpu(B, A, d, dist, 5)
+        assert np.array_equal(full, again)  # bitwise reproducible
+        top = run_gpu(B, A, 70, dist, 5)
+        bot = run_gpu(B, A, d - 70, dist, 5, row0=70)
+        ref = run_oracle(oracle_lib, A, d - 70, dist, 5, row0=70)
+        norm, _ = rel_errors(bot, ref)
+        assert norm <= TOL_NORM
+        norm, _ = rel_errors(np.concatenate([top, bot]), full)
+        assert norm <= TOL_NORM
+
+
+def test_value_types(B, oracle_lib):
+    import torch
+    m, n, d = 9000, 40, 96
+    A = inputs.uniform_positions(m, n, 12_000, 21, "uniform", np.float64)
+    ref = run_oracle(oracle_lib, A, d, "uniform", 9)
+    for dt in (np.float64, np.float32):
+        norm, col = rel_errors(run_gpu(B, A, d, "uniform", 9, dtype=dt), ref)
+        assert norm <= TOL_NORM and col <= TOL_COL
+    # bf16 values: compare with the oracle on the bf16-rounded values
+    vb = torch.from_numpy(A.vals).to(torch.bfloat16)
+    Ab = inputs.Csc(A.m, A.n, A.colptr, A.rowidx, vb.to(torch.float64).numpy())
+    dA = B.DeviceCsc(m, n, torch.from_numpy(A.colptr).cuda(), torch.from_numpy(A.rowidx).cuda(),
+                     vb.cuda())
+    got = B.sketch(dA, d, "uniform", 9).cpu().numpy().astype(np.float64)
+    norm, col = rel_errors(got, run_oracle(oracle_lib, Ab, d, "uniform", 9))
+    assert norm <= TOL_NORM and col <= TOL_COL
+
+
+def test_edge_shapes(B, oracle_lib):
+    cases = [(1, 1, 1, 1), (5, 3, 1, 2), (1000, 1, 1, 1000), (64, 64, 4096, 5), (300, 2, 600, 9)]
+    for m, n, nnz, d in cases:
+        nnz = min(nnz, m * n)
+        A = inputs.uniform_positions(m, n, nnz, m + n, "normal", np.float64)
+        for dist in DISTS:
+            print(f"edge {m} {n} {nnz} {d} {dist}", flush=True)
+            got = run_gpu(B, A, d, dist, 1)
+            ref = run_oracle(oracle_lib, A, d, dist, 1)
+            norm, col = rel_errors(got, ref)
+            assert norm <= TOL_NORM and col <= TOL_COL, (m, n, nnz, d, dist)
+
+
+def test_empty_matrix_gives_zeros(B):
+    import torch
+    m, n, d = 1000, 7, 33
+    dA = B.DeviceCsc(m, n, torch.zeros(n + 1, dtype=torch.int64, device="cuda"),
+                     torch.zeros(0, dtype=torch.int32, device="cuda"),
+                     torch.zeros(0, dtype=torch.float32, device="cuda"))
+    out = B.sketch(dA, d, "gaussian", 1)
+    assert torch.count_nonzero(out).item() == 0
+
+
+def test_device_validation_errors(B):
+    import torch
+    m, n = 500, 6
+    A = inputs.uniform_positions(m, n, 400, 3, "normal", np.float32)
+    cases = {}
+    r = A.rowidx.copy()
+    lo = A.colptr[1]
+    r[lo], r[lo + 1] = r[lo + 1], r[lo]
+    cases["unsorted"] = (A.colptr, r, -2)
+    r = A.rowidx.copy()
+    r[7] = m
+    cases["range"] = (A.colptr, r, -3)
+    cp = A.colptr.copy()
+    cp[n] = cp[n] - 1
+    cases["colptr"] = (cp, A.rowidx, -7)
+    for name, (cp, ri, code) in cases.items():
+        print(f"validation {name}", flush=True)
+        dA = B.DeviceCsc(m, n, torch.from_numpy(cp).cuda(), torch.from_numpy(ri).cuda(),
+                         torch.from_numpy(A.vals).cuda())
+        ws = B.alloc_workspace(B.workspace_bytes(dA, 40, "uniform"))
+        out = torch.zeros((n, 40), dtype=torch.float32, device="cuda")
+        B.sketch_into(dA, 40, "uniform", 1, out, ws)
+        st = B.sketch_status(ws)
+        assert st["status"] == code, (name, st)
+        assert torch.isnan(out).all().item()
+        with pytest.raises(B.SketchError):
+            B.sketch(dA, 40, "uniform", 1)
+
+
+def test_nonempty_row_count(B):
+    import torch
+    m, n = 100_000, 200
+    A = inputs.workload_plain_small(seed=0)
+    dA = B.DeviceCsc.from_host(A)
+    ws = B.alloc_workspace(B.workspace_bytes(dA, 8, "rademacher"))
+    out = torch.empty((n, 8), dtype=torch.float32, device="cuda")
+    B.sketch_into(dA, 8, "rademacher", 1, out, ws)
+    st = B.sketch_status(ws)
+    assert st["status"] == 0
+    assert st["nonempty_rows"] == np.unique(A.rowidx).size
+    assert abs(st["nonempty_rows"] - m * (1 - (1 - 0.01) ** n)) < 5 * np.sqrt(m * 0.25)

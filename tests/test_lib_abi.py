@@ -1,0 +1,87 @@
+"""The C-ABI library loads here (no GPU) and exports every declared symbol;
+host-only entry points and synchronous argument checks work without a device."""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2310_15419_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(sk_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    lib = binding.lib()
+    names = declared_symbols()
+    assert len(names) >= 7
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_rng_tables_equal_oracle_tables(oracle_lib):
+    t = binding.rng_tables()
+    o = oracle_lib.tables()
+    for k in ("log", "sin", "cos", "misc"):
+        assert np.array_equal(t[k], o[k]), k
+
+
+def test_status_strings():
+    for code in range(-7, 1):
+        assert binding.status_string(code)
+    assert "unknown" in binding.status_string(-99)
+
+
+def _csc(m=1000, n=20, nnz=5000, vtype=binding.F32):
+    return binding.SkCsc(m, n, nnz, 8, 8, 8, vtype)  # dummy device pointers (never read)
+
+
+def test_workspace_query_and_argument_errors():
+    lib = binding.lib()
+    out = ctypes.c_size_t()
+    c = _csc()
+    assert lib.sk_sketch_workspace(ctypes.byref(c), 64, 1, 0, None, ctypes.byref(out)) == 0
+    assert out.value > 0
+    bad = _csc(m=0)
+    assert lib.sk_sketch_workspace(ctypes.byref(bad), 64, 1, 0, None, ctypes.byref(out)) == -1
+    assert lib.sk_sketch_workspace(ctypes.byref(c), 0, 1, 0, None, ctypes.byref(out)) == -1
+    assert lib.sk_sketch_workspace(ctypes.byref(c), 64, 7, 0, None, ctypes.byref(out)) == -1
+    # null / small workspace is refused before any device work
+    assert lib.sk_sketch(ctypes.byref(c), 0, 64, 1, 1, 0, None, 8, 64, None, 0, None) == -4
+    assert lib.sk_sketch(ctypes.byref(c), 0, 64, 1, 1, 0, None, 8, 64, 8, 16, None) == -4
+    # ld < d, null output, negative row0, bad vtype
+    assert lib.sk_sketch(ctypes.byref(c), 0, 64, 1, 1, 0, None, 8, 63, 8, 1 << 40, None) == -1
+    assert lib.sk_sketch(ctypes.byref(c), 0, 64, 1, 1, 0, None, None, 64, 8, 1 << 40, None) == -1
+    assert lib.sk_sketch(ctypes.byref(c), -1, 64, 1, 1, 0, None, 8, 64, 8, 1 << 40, None) == -1
+    bv = _csc(vtype=9)
+    assert lib.sk_sketch(ctypes.byref(bv), 0, 64, 1, 1, 0, None, 8, 64, 8, 1 << 40, None) == -1
+    # reduced precision is defined for the +-1 distribution only
+    assert lib.sk_sketch(ctypes.byref(c), 0, 64, 1, 1, 1, None, 8, 64, 8, 1 << 40, None) == -6
+    # materialize: bad sizes
+    assert lib.sk_materialize_s(0, 0, 0, 1, 1, 1, 8, 1, None) == -1
+    assert lib.sk_materialize_s(0, 4, 0, 1, 1, 1, 8, 3, None) == -1
+
+
+def test_tuning_variants_all_plan():
+    lib = binding.lib()
+    out = ctypes.c_size_t()
+    for v in range(1, binding.variant_count() + 1):
+        for n in (1, 50, 200, 2000, 5000):
+            c = _csc(m=100000, n=n, nnz=10 * n)
+            t = binding.SkTuning(0, 0, v, 0, 0)
+            assert lib.sk_sketch_workspace(ctypes.byref(c), 3 * n, 1, 0, ctypes.byref(t),
+                                           ctypes.byref(out)) == 0
+    t = binding.SkTuning(0, 0, binding.variant_count() + 1, 0, 0)
+    assert lib.sk_sketch_workspace(ctypes.byref(_csc()), 64, 1, 0, ctypes.byref(t),
+                                   ctypes.byref(out)) == -1
