@@ -19,7 +19,9 @@
 //   seg[b*n + k]       position of block b / column k's segment in `ent`;
 //                      seg[nb_max*n] = nnz.  Block b spans
 //                      [seg[b*n], seg[(b+1)*n]).
-//   ent[p]             {row index inside the block, FP32 bits of the value}
+//   ent[p]             {byte offset of the entry's row in the S tile (row
+//                      inside the block times the tile's row bytes), FP32
+//                      bits of the value}
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -223,11 +225,11 @@ __global__ void k_block_cnt(const int32_t* __restrict__ pos, int64_t n, int64_t 
   seg[t] = hdr->status ? 0 : pos[t + n] - pos[t];
 }
 
-// ent[seg[b n + k] + (p - pos[b n + k])] = {row in block, value}
+// ent[seg[b n + k] + (p - pos[b n + k])] = {row in block * row_bytes, value}
 __global__ void k_scatter(const int64_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
                           const void* __restrict__ vals, int vtype, int64_t n, int64_t nnz,
                           const int32_t* __restrict__ ridx, const int32_t* __restrict__ pos,
-                          const int32_t* __restrict__ seg, int32_t m_b,
+                          const int32_t* __restrict__ seg, int32_t m_b, int32_t row_bytes,
                           const Header* __restrict__ hdr, uint2* __restrict__ ent) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nnz) return;
@@ -239,7 +241,8 @@ __global__ void k_scatter(const int64_t* __restrict__ colptr, const int32_t* __r
   const int64_t k = column_of(colptr, n, p);
   const int64_t bk = (int64_t)b * n + k;
   const int64_t dest = (int64_t)seg[bk] + (p - (int64_t)pos[bk]);
-  ent[dest] = make_uint2((uint32_t)l, __float_as_uint(load_value(vals, vtype, p)));
+  ent[dest] = make_uint2((uint32_t)l * (uint32_t)row_bytes,
+                         __float_as_uint(load_value(vals, vtype, p)));
 }
 
 }  // namespace sk

@@ -19,7 +19,7 @@ using namespace sk;
 namespace {
 
 constexpr int64_t kAlign = 256;
-constexpr int kLdsBudget = 160 * 1024 - 1024;  // bytes of LDS a workgroup may use
+constexpr int kLdsPerCu = 160 * 1024;  // LDS bytes per CU (gfx950)
 
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -52,12 +52,14 @@ const Variant kVariants[] = {
     SK_VARIANT(8, 2, 4, 1024),   // 4: pairs of lanes per column group
     SK_VARIANT(16, 1, 2, 1024),  // 5: one lane per column group
     SK_VARIANT(4, 4, 2, 1024),   // 6: few columns, many S rows per workgroup
+    SK_VARIANT(16, 1, 4, 512),   // 7: two workgroups per CU, one lane per column group
+    SK_VARIANT(8, 2, 8, 512),    // 8: two workgroups per CU, lane pairs
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 struct Plan {
   int variant;  // index into kVariants
-  int32_t m_b, e_max, d_b, dt, cg, tiles, splits, col_per_wg, ncr, log2_cpr;
+  int32_t m_b, e_max, d_b, ldS, dt, cg, tiles, splits, col_per_wg, ncr, log2_cpr;
   int64_t nb_max;
   size_t lds;
 };
@@ -96,21 +98,24 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
     dt *= 2;
   P.dt = dt;
   P.d_b = dt * V.q * V.dl;
+  P.ldS = P.d_b + 4;
   P.tiles = (int32_t)((d + P.d_b - 1) / P.d_b);
   const int rows_per_chunk = dist == DIST_RADEMACHER ? std::min(32, P.d_b) : 4;
   P.log2_cpr = ilog2(P.d_b / rows_per_chunk);
-  // rows per block from the LDS budget: S tile row + the block's entries
+  // rows per block from the LDS budget (1024-thread workgroups: one per CU;
+  // 512-thread workgroups: two per CU): S tile row + the block's entries
+  const int budget = (V.wgs >= 1024 ? kLdsPerCu : kLdsPerCu / 2) - 1024;
   const int64_t rmax = std::max<int64_t>(1, std::min(m, nnz));
   const double per_row = std::max(1.0, (double)nnz / (double)rmax);
   int64_t m_b = tune && tune->rows_per_block > 0
                     ? tune->rows_per_block
-                    : (int64_t)((double)kLdsBudget / (P.d_b * 4.0 + 8.0 * per_row));
+                    : (int64_t)((double)budget / (P.ldS * 4.0 + 8.0 * per_row));
   m_b = std::max<int64_t>(1, std::min<int64_t>(m_b, 8192));
-  while (m_b > 1 && m_b * P.d_b * 4 + 8 * 64 > kLdsBudget) m_b /= 2;
+  while (m_b > 1 && m_b * P.ldS * 4 + 8 * 64 > budget) m_b /= 2;
   P.m_b = (int32_t)m_b;
-  P.e_max = (int32_t)((kLdsBudget - m_b * P.d_b * 4) / 8);
-  if (P.e_max < 1) return false;
-  P.lds = (size_t)m_b * P.d_b * 4 + (size_t)P.e_max * 8;
+  P.e_max = (int32_t)(((budget - m_b * P.ldS * 4) / 8 - 2) & ~int64_t(1));
+  if (P.e_max < 2) return false;
+  P.lds = (size_t)m_b * P.ldS * 4 + (size_t)(P.e_max + 2) * 8;
   P.nb_max = std::max<int64_t>(1, (rmax + m_b - 1) / m_b);
   int64_t splits;
   if (tune && tune->splits > 0) {
@@ -136,7 +141,7 @@ Layout layout_for(int64_t m, int64_t n, int64_t nnz, int64_t d, const Plan& P) {
   L.rowlist = off; off = align_up(off + 4 * (std::min(m, std::max<int64_t>(nnz, 1)) + P.m_b + 1));
   L.pos = off;     off = align_up(off + 4 * (P.nb_max + 1) * n);
   L.seg = off;     off = align_up(off + 4 * (P.nb_max * n + 1));
-  L.ent = off;     off = align_up(off + 8 * std::max<int64_t>(nnz, 1));
+  L.ent = off;     off = align_up(off + 8 * (nnz + 2));  // +2: 16-byte staging tail
   L.part = off;
   if (P.splits > 1) off = align_up(off + 4 * (int64_t)P.splits * d * n);
   L.total = off;
@@ -258,7 +263,8 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
   if ((s = scan_i32(seg, nseg, sums, st)) != SK_OK) return s;
   if (nnz > 0)
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nnz, 256)), dim3(256), 0, st, A->colptr,
-                       A->rowidx, A->vals, A->vtype, n, nnz, ridx, pos, seg, P.m_b, hdr, ent);
+                       A->rowidx, A->vals, A->vtype, n, nnz, ridx, pos, seg, P.m_b, P.ldS * 4,
+                       hdr, ent);
   if ((s = launch_ok()) != SK_OK) return s;
   }
 
@@ -267,7 +273,7 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
   SketchParams K{};
   K.rowlist = rowlist; K.seg = seg; K.ent = ent; K.hdr = hdr;
   K.n = n; K.d = d; K.row0 = row0; K.seed = seed;
-  K.m_b = P.m_b; K.e_max = P.e_max; K.d_b = P.d_b; K.log2_cpr = P.log2_cpr;
+  K.m_b = P.m_b; K.e_max = P.e_max; K.d_b = P.d_b; K.ldS = P.ldS; K.log2_cpr = P.log2_cpr;
   K.dt = P.dt; K.cg = P.cg; K.tiles = P.tiles; K.splits = P.splits;
   K.col_per_wg = P.col_per_wg;
   if (P.splits > 1) { K.out = part; K.ld = d; K.split_stride = d * n; }

@@ -35,8 +35,10 @@ struct SketchParams {
   int64_t n, d, row0;
   uint64_t seed;
   int32_t m_b;      // nonempty rows per block
-  int32_t e_max;    // entries staged per pass
+  int32_t e_max;    // entries staged per pass (even; LDS holds e_max + 2)
   int32_t d_b;      // S rows per tile = dt * Q * DL (power of two)
+  int32_t ldS;      // S tile row stride in floats (d_b + 4: rows start on
+                    // different LDS bank groups)
   int32_t log2_cpr; // log2(d_b / rows per generator chunk)
   int32_t dt;       // S-row subtiles per workgroup
   int32_t cg;       // column groups per subtile
@@ -49,7 +51,7 @@ struct SketchParams {
 };
 
 // ---------------------------------------------------------------- S tile
-// Fill S_lds[l * d_b + t] = S(grow0 + t, rowlist[b*m_b + l]) for l < rb,
+// Fill S_lds[l * ldS + t] = S(grow0 + t, rowlist[b*m_b + l]) for l < rb,
 // t < d_b.
 template <int DIST, int WGS>
 __device__ __forceinline__ void fill_tile(float* __restrict__ S_lds, const SketchParams& P,
@@ -66,7 +68,7 @@ __device__ __forceinline__ void fill_tile(float* __restrict__ S_lds, const Sketc
       const int ch = idx & cmask;
       const uint64_t j = (uint64_t)(uint32_t)rows[l];
       const uint32_t bits = sign_bits32(P.seed, grow0 + (uint64_t)ch * 32u, j);
-      float4* dst = reinterpret_cast<float4*>(S_lds + l * P.d_b + ch * 32);
+      float4* dst = reinterpret_cast<float4*>(S_lds + l * P.ldS + ch * 32);
       for (int t = 0; t < rpc; t += 4) {
         float4 v;
         v.x = (bits >> (t + 0)) & 1u ? -1.0f : 1.0f;
@@ -95,7 +97,7 @@ __device__ __forceinline__ void fill_tile(float* __restrict__ S_lds, const Sketc
           const int ch = idx & cmask;
           float v[4];
           quad_values<DIST>(P.seed, g0 + (uint64_t)ch, (uint64_t)(uint32_t)jr[u], v);
-          *reinterpret_cast<float4*>(S_lds + l * P.d_b + ch * 4) =
+          *reinterpret_cast<float4*>(S_lds + l * P.ldS + ch * 4) =
               make_float4(v[0], v[1], v[2], v[3]);
         }
       }
@@ -115,12 +117,13 @@ __device__ __forceinline__ void fill_tile(float* __restrict__ S_lds, const Sketc
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
         const int t = gi * 4 + w - shift;  // row inside the tile
-        if (t >= 0 && t < P.d_b) S_lds[l * P.d_b + t] = v[w];
+        if (t >= 0 && t < P.d_b) S_lds[l * P.ldS + t] = v[w];
       }
     }
   }
 }
 
+// DL consecutive S values of one tile row (rows start 16-byte aligned).
 template <int DL>
 __device__ __forceinline__ void load_rows(const float* __restrict__ p, float (&s)[DL]) {
   static_assert(DL % 4 == 0 || DL == 1 || DL == 2, "DL");
@@ -138,12 +141,32 @@ __device__ __forceinline__ void load_rows(const float* __restrict__ p, float (&s
   }
 }
 
-// ---------------------------------------------------------------- kernel
+// Stage entries [s0a, s1) (s0a even) of the blocked layout into E_lds with
+// direct global->LDS loads, 16 bytes (two entries) per lane.  Completion is
+// tracked by the vector-memory counter; the caller waits and synchronises.
+template <int WGS>
+__device__ __forceinline__ void stage_entries(uint2* __restrict__ E_lds,
+                                              const uint2* __restrict__ ent, int32_t s0a,
+                                              int32_t s1) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nchunk = (s1 - s0a + 1) >> 1;  // 16-byte chunks
+  for (int c0 = wave * 64; c0 < nchunk; c0 += WGS) {
+    if (c0 + lane < nchunk) {
+      const uint2* src = ent + s0a + 2 * (c0 + lane);
+      __builtin_amdgcn_global_load_lds(
+          (const void __attribute__((address_space(1)))*)src,
+          (void __attribute__((address_space(3)))*)(E_lds + 2 * c0), 16, 0, 0);
+    }
+  }
+}
+
 template <int DIST, int DL, int Q, int CS, int WGS>
-__global__ __launch_bounds__(WGS) void k_sketch(SketchParams P) {
+__global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(4))) void k_sketch(
+    SketchParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
   float* S_lds = reinterpret_cast<float*>(smem);
-  uint2* E_lds = reinterpret_cast<uint2*>(smem + (size_t)P.m_b * P.d_b * sizeof(float));
+  uint2* E_lds = reinterpret_cast<uint2*>(smem + (size_t)P.m_b * P.ldS * sizeof(float));
 
   const int tid = threadIdx.x;
   const int bid = blockIdx.x;
@@ -161,6 +184,8 @@ __global__ __launch_bounds__(WGS) void k_sketch(SketchParams P) {
   const bool active = dsub < P.dt;
   const int rofs = dsub * (Q * DL) + q * DL;
   const int64_t kbase = (int64_t)crange * P.col_per_wg + (int64_t)cgi * CS;
+  // entries hold the byte offset of their row in the S tile
+  const unsigned char* Sl = smem + rofs * (int)sizeof(float);
 
   float acc[CS][DL];
 #pragma unroll
@@ -174,41 +199,79 @@ __global__ __launch_bounds__(WGS) void k_sketch(SketchParams P) {
     const int64_t R = P.hdr->nonempty;
     const int64_t b_lo = nb * split / P.splits;
     const int64_t b_hi = nb * (split + 1) / P.splits;
-    for (int64_t b = b_lo; b < b_hi; ++b) {
-      const int64_t rem = R - b * P.m_b;
-      const int rb = (int)(rem < P.m_b ? rem : P.m_b);
+    // segment bounds of this group's columns in block b: loaded one block
+    // ahead so their latency hides behind the previous block's accumulation
+    int32_t pbn[CS + 1];
+    int32_t beg_n = 0, end_n = 0;
+    auto load_bounds = [&](int64_t b) {
       const int32_t* segb = P.seg + b * P.n;
-      const int32_t blk_beg = segb[0];
-      const int32_t blk_end = segb[P.n];
-      int32_t pb[CS + 1];
+      beg_n = segb[0];
+      end_n = segb[P.n];
 #pragma unroll
       for (int c = 0; c <= CS; ++c) {
         const int64_t k = kbase + c;
-        pb[c] = active ? segb[k < P.n ? k : P.n] : blk_end;
+        pbn[c] = segb[k < P.n ? k : P.n];
       }
+    };
+    if (b_lo < b_hi) load_bounds(b_lo);
+    for (int64_t b = b_lo; b < b_hi; ++b) {
+      const int64_t rem = R - b * P.m_b;
+      const int rb = (int)(rem < P.m_b ? rem : P.m_b);
+      const int32_t blk_beg = beg_n;
+      const int32_t blk_end = end_n;
+      int32_t pb[CS + 1];
+#pragma unroll
+      for (int c = 0; c <= CS; ++c) pb[c] = active ? pbn[c] : blk_end;
       __syncthreads();  // the previous block's tile and entries are consumed
+      // pass: entries [sp, s1) are processed; staging starts at the even s0a
+      int32_t sp = blk_beg;
+      int32_t s0a = sp & ~1;
+      int32_t s1 = (blk_end - s0a < P.e_max) ? blk_end : s0a + P.e_max;
+      stage_entries<WGS>(E_lds, P.ent, s0a, s1);
       fill_tile<DIST, WGS>(S_lds, P, P.rowlist + b * P.m_b, rb, grow0);
-      for (int32_t s0 = blk_beg; s0 < blk_end; s0 += P.e_max) {
-        const int32_t s1 = (blk_end - s0 < P.e_max) ? blk_end : s0 + P.e_max;
-        if (s0 != blk_beg) __syncthreads();
-        for (int32_t p = s0 + tid; p < s1; p += WGS) E_lds[p - s0] = P.ent[p];
+      bool first_pass = true;
+      while (true) {
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
+        if (first_pass && b + 1 < b_hi) load_bounds(b + 1);
+        first_pass = false;
         if (active) {
-          const float* __restrict__ Sl = S_lds + rofs;
 #pragma unroll
           for (int c = 0; c < CS; ++c) {
-            const int32_t lo = pb[c] > s0 ? pb[c] : s0;
+            const int32_t lo = pb[c] > sp ? pb[c] : sp;
             const int32_t hi = pb[c + 1] < s1 ? pb[c + 1] : s1;
-            for (int32_t p = lo; p < hi; ++p) {
-              const uint2 e = E_lds[p - s0];
-              const float a = __uint_as_float(e.y);
-              float s[DL];
-              load_rows<DL>(Sl + (int)e.x * P.d_b, s);
+            int32_t p = lo - s0a;
+            const int32_t pe = hi - s0a;
+            for (; p + 1 < pe; p += 2) {
+              const uint2 e0 = E_lds[p];
+              const uint2 e1 = E_lds[p + 1];
+              float x0[DL], x1[DL];
+              load_rows<DL>(reinterpret_cast<const float*>(Sl + e0.x), x0);
+              load_rows<DL>(reinterpret_cast<const float*>(Sl + e1.x), x1);
+              const float a0 = __uint_as_float(e0.y);
+              const float a1 = __uint_as_float(e1.y);
 #pragma unroll
-              for (int t = 0; t < DL; ++t) acc[c][t] = __builtin_fmaf(a, s[t], acc[c][t]);
+              for (int t = 0; t < DL; ++t) acc[c][t] = __builtin_fmaf(a0, x0[t], acc[c][t]);
+#pragma unroll
+              for (int t = 0; t < DL; ++t) acc[c][t] = __builtin_fmaf(a1, x1[t], acc[c][t]);
+            }
+            if (p < pe) {
+              const uint2 e0 = E_lds[p];
+              float x0[DL];
+              load_rows<DL>(reinterpret_cast<const float*>(Sl + e0.x), x0);
+              const float a0 = __uint_as_float(e0.y);
+#pragma unroll
+              for (int t = 0; t < DL; ++t) acc[c][t] = __builtin_fmaf(a0, x0[t], acc[c][t]);
             }
           }
         }
+        if (s1 >= blk_end) break;
+        // more entries than one pass holds: stage the next pass
+        sp = s1;
+        s0a = sp & ~1;
+        s1 = (blk_end - s0a < P.e_max) ? blk_end : s0a + P.e_max;
+        __syncthreads();
+        stage_entries<WGS>(E_lds, P.ent, s0a, s1);
       }
     }
   }

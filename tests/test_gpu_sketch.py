@@ -197,3 +197,17 @@ def test_nonempty_row_count(B):
     assert st["status"] == 0
     assert st["nonempty_rows"] == np.unique(A.rowidx).size
     assert abs(st["nonempty_rows"] - m * (1 - (1 - 0.01) ** n)) < 5 * np.sqrt(m * 0.25)
+
+
+@pytest.mark.parametrize("dist", DISTS)
+def test_multi_pass_blocks(B, oracle_lib, dist):
+    # dense rows: a block's entries exceed one LDS staging pass
+    m, n, d = 3000, 256, 100
+    A = inputs.uniform_positions(m, n, int(0.3 * m * n), 77, "uniform", np.float32)
+    ref = run_oracle(oracle_lib, A, d, dist, 6)
+    for tune in [{"variant": 5, "rows_per_block": 1500}, {"variant": 1, "rows_per_block": 2000},
+                 None]:
+        print(f"multi-pass {dist} {tune}", flush=True)
+        got = run_gpu(B, A, d, dist, 6, tune=tune)
+        norm, col = rel_errors(got, ref)
+        assert norm <= TOL_NORM and col <= TOL_COL, (tune, norm, col)
