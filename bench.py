@@ -49,6 +49,11 @@ def make_workload(name: str):
         return A, 400, "rademacher", 1, (
             "plain_small: A CSC FP64 m=100000 n=200, 2e5 uniform positions, N(0,1); "
             "S +-1 seed 1; d=400")
+    if name == "skewed":
+        A, r0 = inputs.workload_skewed()
+        return A, 3000, "gaussian", 31, (
+            "skewed: A CSC FP32 m=4000000 n=1000, power-law column nnz (exponent 2, max 5% of "
+            f"m) plus a dense 2000-row block at row {r0}; S Gaussian (Box-Muller) seed 31; d=3000")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -89,6 +94,7 @@ def main():
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--rows-per-block", type=int, default=0)
     ap.add_argument("--splits", type=int, default=0)
+    ap.add_argument("--dense-min-pct", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="launch only a plain 1 GiB device copy (for counter scaling)")
     args = ap.parse_args()
@@ -117,7 +123,7 @@ def main():
           f"(m={A.m}, n={A.n}, nnz={A.nnz}, d={d})", file=sys.stderr, flush=True)
     dA = B.DeviceCsc.from_host(A, dtype=np.float32 if A.vals.dtype != np.float64 else None)
     tune = {"variant": args.variant, "rows_per_block": args.rows_per_block,
-            "splits": args.splits}
+            "splits": args.splits, "dense_min_pct": args.dense_min_pct}
     ws = B.alloc_workspace(B.workspace_bytes(dA, d, dist, tune=tune))
     out = torch.empty((A.n, d), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
@@ -157,7 +163,7 @@ def main():
     rpc = 128 if dist == "rademacher" else 4
     calls = R * -(-d // rpc)
     entries = R * d
-    work = valu_work(calls, entries if dist == "uniform" else 0, nnz * d)
+    work = valu_work(calls, entries if dist != "rademacher" else 0, nnz * d)
     achieved = work / (kms * 1e-3)
     value = nnz * d / (ms * 1e-3)
 

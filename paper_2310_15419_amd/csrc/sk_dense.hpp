@@ -1,0 +1,195 @@
+// sk_dense.hpp -- row blocks of A dense enough to run as a dense contraction
+// on the matrix cores.
+//
+// The sparse kernel spends a few VALU instructions per nonzero on top of the
+// multiply-add; a row block whose density reaches a threshold is cheaper as
+// A_hat_tile += S_tile * A_blk with A_blk densified, on MFMA (the paper's
+// large-density regime of the cost model, Sec. III-A-2, where reuse of the
+// S tile across columns is near its maximum).  Steps:
+//   k_dense_select  picks the dense blocks in increasing block order
+//                   (deterministic list, capped by the workspace capacity)
+//   k_densify       writes each dense block as an rb x n row-major tile
+//   k_dense_mfma    one workgroup per 64 x 64 output tile; per 32-row K chunk
+//                   it regenerates S (64 S rows x 32 A rows) into LDS, loads
+//                   the dense A chunk, and runs v_mfma_f32_32x32x2f32 per wave
+//                   (each wave a 32 x 32 quarter); the tile is summed over all
+//                   dense blocks in block order and written to its own slice
+//                   of the split partials, so the final reduction stays fixed
+//                   order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sk_inspect.hpp"
+#include "sk_rng.hpp"
+
+namespace sk {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+struct DenseHeader {
+  int32_t nd;       // dense blocks selected
+  int32_t pad[15];
+};
+
+// single workgroup: dense blocks in block order; dflag[b] = slot + 1 or 0
+__global__ __launch_bounds__(256) void k_dense_select(const int32_t* __restrict__ seg, int64_t n,
+                                                      int32_t m_b, int32_t min_pct,
+                                                      int32_t nd_max,
+                                                      const Header* __restrict__ hdr,
+                                                      int32_t* __restrict__ dflag,
+                                                      int32_t* __restrict__ dlist,
+                                                      DenseHeader* __restrict__ dh) {
+  __shared__ int32_t sh[256];
+  const int tid = threadIdx.x;
+  const int64_t nb = hdr->status ? 0 : hdr->nblocks;
+  const int64_t R = hdr->nonempty;
+  int32_t base = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+    const int64_t b = b0 + tid;
+    int flag = 0;
+    if (b < nb) {
+      const int64_t rem = R - b * m_b;
+      const int64_t rb = rem < m_b ? rem : m_b;
+      const int64_t cnt = (int64_t)seg[(b + 1) * n] - (int64_t)seg[b * n];
+      // density >= min_pct %  <=>  100 cnt >= min_pct rb n
+      flag = (100 * cnt >= (int64_t)min_pct * rb * n) ? 1 : 0;
+    }
+    sh[tid] = flag;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {  // inclusive scan of the flags
+      const int32_t add = tid >= off ? sh[tid - off] : 0;
+      __syncthreads();
+      sh[tid] += add;
+      __syncthreads();
+    }
+    const int32_t slot = base + sh[tid] - flag;
+    if (b < nb) {
+      const bool take = flag && slot < nd_max;
+      dflag[b] = take ? slot + 1 : 0;
+      if (take) dlist[slot] = (int32_t)b;
+    }
+    base += sh[255];
+    __syncthreads();
+  }
+  if (tid == 0) dh->nd = base < nd_max ? base : nd_max;
+}
+
+// D[slot][l][k] = a for every entry of dense block dlist[slot]; one thread per
+// (slot, column) walks the column's segment.  D must be zeroed before.
+__global__ void k_densify(const int32_t* __restrict__ seg, const uint2* __restrict__ ent, int64_t n,
+                          int32_t m_b, int32_t row_bytes, const int32_t* __restrict__ dlist,
+                          const DenseHeader* __restrict__ dh, float* __restrict__ D) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t slot = t / n, k = t - slot * n;
+  if (slot >= dh->nd) return;
+  const int64_t b = dlist[slot];
+  float* Dt = D + slot * (int64_t)m_b * n;
+  const int32_t p0 = seg[b * n + k], p1 = seg[b * n + k + 1];
+  for (int32_t p = p0; p < p1; ++p) {
+    const uint2 e = ent[p];
+    const int32_t l = (int32_t)(e.x / (uint32_t)row_bytes);
+    Dt[(int64_t)l * n + k] = __uint_as_float(e.y);
+  }
+}
+
+struct DenseParams {
+  const int32_t* rowlist;
+  const int32_t* dlist;
+  const DenseHeader* dh;
+  const Header* hdr;
+  const float* D;
+  int64_t n, d, row0;
+  uint64_t seed;
+  int32_t m_b;
+  float* out;  // the dense slice of the split partials (d x n, ld = d)
+};
+
+constexpr int DT_M = 64, DT_N = 64, DT_K = 32;
+
+// S[grow0 + i][rows[kk]] for i < 64, kk < 32 (kk >= nk: zero) into
+// Ss[i * (DT_K + 1) + kk]
+template <int DIST>
+__device__ __forceinline__ void dense_fill_s(float* __restrict__ Ss, const int32_t* __restrict__ rows,
+                                             int nk, uint64_t grow0, uint64_t seed) {
+  const int tid = threadIdx.x;
+  if (DIST == DIST_RADEMACHER) {
+    // 32 rows x 2 words of 32 sign bits
+    if (tid < 2 * DT_K) {
+      const int kk = tid >> 1, half = tid & 1;
+      uint32_t bits = 0;
+      if (kk < nk) bits = sign_bits32(seed, grow0 + 32u * half, (uint64_t)(uint32_t)rows[kk]);
+      for (int u = 0; u < 32; ++u)
+        Ss[(32 * half + u) * (DT_K + 1) + kk] =
+            kk < nk ? ((bits >> u) & 1u ? -1.0f : 1.0f) : 0.0f;
+    }
+  } else {
+    // 64 S rows span 16 generator groups (17 when grow0 is not 4-aligned)
+    const int shift = (int)(grow0 & 3u);
+    const int ng = shift ? 17 : 16;
+    const uint64_t g0 = grow0 >> 2;
+    for (int idx = tid; idx < ng * DT_K; idx += 256) {
+      const int kk = idx / ng, gi = idx - kk * ng;
+      float v[4] = {0.f, 0.f, 0.f, 0.f};
+      if (kk < nk) quad_values<DIST>(seed, g0 + gi, (uint64_t)(uint32_t)rows[kk], v);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int i = gi * 4 + w - shift;
+        if (i >= 0 && i < DT_M) Ss[i * (DT_K + 1) + kk] = v[w];
+      }
+    }
+  }
+}
+
+template <int DIST>
+__global__ __launch_bounds__(256) void k_dense_mfma(DenseParams P) {
+  __shared__ float Ss[DT_M * (DT_K + 1)];
+  __shared__ float Ds[DT_K * (DT_N + 4)];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t ntiles = (P.n + DT_N - 1) / DT_N;
+  const int64_t tm = blockIdx.x / ntiles, tn = blockIdx.x - tm * ntiles;
+  const int64_t i0 = tm * DT_M, j0 = tn * DT_N;
+  const uint64_t grow0 = (uint64_t)(P.row0 + i0);
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  floatx16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+
+  const int nd = P.hdr->status ? 0 : P.dh->nd;
+  const int64_t R = P.hdr->nonempty;
+  for (int t = 0; t < nd; ++t) {
+    const int64_t b = P.dlist[t];
+    const int64_t rem = R - b * P.m_b;
+    const int rb = (int)(rem < P.m_b ? rem : P.m_b);
+    const float* Dt = P.D + (int64_t)t * P.m_b * P.n;
+    for (int k0 = 0; k0 < rb; k0 += DT_K) {
+      const int nk = rb - k0 < DT_K ? rb - k0 : DT_K;
+      __syncthreads();
+      dense_fill_s<DIST>(Ss, P.rowlist + b * P.m_b + k0, nk, grow0, P.seed);
+      for (int idx = tid; idx < DT_K * DT_N; idx += 256) {
+        const int kk = idx / DT_N, jj = idx - kk * DT_N;
+        const int64_t j = j0 + jj;
+        Ds[kk * (DT_N + 4) + jj] = (kk < nk && j < P.n) ? Dt[(int64_t)(k0 + kk) * P.n + j] : 0.0f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kq = 0; kq < DT_K; kq += 2) {
+        const int kk = kq + (lane >> 5);
+        const float a = Ss[(wm + (lane & 31)) * (DT_K + 1) + kk];
+        const float bv = Ds[kk * (DT_N + 4) + wn + (lane & 31)];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc, 0, 0, 0);
+      }
+    }
+  }
+  // D[i][j]: j = lane % 32, i = 8 (r / 4) + 4 (lane / 32) + r % 4
+  const int64_t j = j0 + wn + (lane & 31);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t i = i0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    if (i < P.d && j < P.n) P.out[i + j * P.d] = acc[r];
+  }
+}
+
+}  // namespace sk

@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstring>
 
+#include "sk_dense.hpp"
 #include "sk_inspect.hpp"
 #include "sk_rng.hpp"
 #include "sk_sketch.hpp"
@@ -62,11 +63,17 @@ struct Plan {
   int32_t m_b, e_max, d_b, ldS, dt, cg, tiles, splits, col_per_wg, ncr, log2_cpr;
   int64_t nb_max;
   size_t lds;
+  int32_t dense_pct;  // densify at >= this % density; 0: no dense path
+  int64_t nd_max;     // capacity in dense blocks
+  int32_t slices;     // partial slices: splits (+1 for the dense path)
 };
 
 struct Layout {
-  int64_t hdr, ridx, sums, rowlist, pos, seg, ent, part, total;
+  int64_t hdr, ridx, sums, rowlist, pos, seg, ent, dflag, dlist, dhdr, dense, part, total;
 };
+
+constexpr int kDenseAutoPct = 40;                 // FP32 operands
+constexpr int64_t kDenseMaxBytes = int64_t(4) << 30;
 
 bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_tuning* tune,
               Plan& P) {
@@ -128,6 +135,20 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
   }
   splits = std::max<int64_t>(1, std::min<int64_t>(splits, P.nb_max));
   P.splits = (int32_t)splits;
+  // dense row blocks: only if at least one block could reach the threshold
+  int pct = tune && tune->dense_min_pct > 0 ? tune->dense_min_pct : kDenseAutoPct;
+  P.dense_pct = 0;
+  P.nd_max = 0;
+  if (pct <= 100 && (double)nnz * 100.0 >= (double)pct * (double)m_b * (double)n) {
+    int64_t ndm = (int64_t)((double)nnz * 100.0 / ((double)pct * (double)m_b * (double)n)) + 1;
+    ndm = std::min<int64_t>(ndm, P.nb_max);
+    ndm = std::min<int64_t>(ndm, kDenseMaxBytes / (4 * (int64_t)m_b * n));
+    if (ndm > 0) {
+      P.dense_pct = pct;
+      P.nd_max = ndm;
+    }
+  }
+  P.slices = P.splits + (P.dense_pct ? 1 : 0);
   return true;
 }
 
@@ -142,8 +163,12 @@ Layout layout_for(int64_t m, int64_t n, int64_t nnz, int64_t d, const Plan& P) {
   L.pos = off;     off = align_up(off + 4 * (P.nb_max + 1) * n);
   L.seg = off;     off = align_up(off + 4 * (P.nb_max * n + 1));
   L.ent = off;     off = align_up(off + 8 * (nnz + 2));  // +2: 16-byte staging tail
+  L.dflag = off;   off = align_up(off + 4 * P.nb_max);
+  L.dlist = off;   off = align_up(off + 4 * std::max<int64_t>(P.nd_max, 1));
+  L.dhdr = off;    off = align_up(off + (int64_t)sizeof(DenseHeader));
+  L.dense = off;   off = align_up(off + 4 * P.nd_max * P.m_b * n);
   L.part = off;
-  if (P.splits > 1) off = align_up(off + 4 * (int64_t)P.splits * d * n);
+  if (P.slices > 1) off = align_up(off + 4 * (int64_t)P.slices * d * n);
   L.total = off;
   return L;
 }
@@ -236,6 +261,10 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
   int32_t* pos = (int32_t*)(w + L.pos);
   int32_t* seg = (int32_t*)(w + L.seg);
   uint2* ent = (uint2*)(w + L.ent);
+  int32_t* dflag = (int32_t*)(w + L.dflag);
+  int32_t* dlist = (int32_t*)(w + L.dlist);
+  DenseHeader* dhdr = (DenseHeader*)(w + L.dhdr);
+  float* dense = (float*)(w + L.dense);
   float* part = (float*)(w + L.part);
 
   if (phases & 1) {
@@ -266,17 +295,28 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
                        A->rowidx, A->vals, A->vtype, n, nnz, ridx, pos, seg, P.m_b, P.ldS * 4,
                        hdr, ent);
   if ((s = launch_ok()) != SK_OK) return s;
+  // a5 (selection): dense row blocks, densified
+  if (P.dense_pct) {
+    hipLaunchKernelGGL(k_dense_select, dim3(1), dim3(256), 0, st, seg, n, P.m_b, P.dense_pct,
+                       (int32_t)P.nd_max, hdr, dflag, dlist, dhdr);
+    hipLaunchKernelGGL(k_fill<float>, dim3(blocks_for(P.nd_max * P.m_b * n, 256 * 16)),
+                       dim3(256), 0, st, dense, P.nd_max * P.m_b * n, 0.0f);
+    hipLaunchKernelGGL(k_densify, dim3(blocks_for(P.nd_max * n, 256)), dim3(256), 0, st, seg,
+                       ent, n, P.m_b, P.ldS * 4, dlist, dhdr, dense);
+    if ((s = launch_ok()) != SK_OK) return s;
+  }
   }
 
   // a3 + a4: S tiles and sparse accumulation
   const Variant& V = kVariants[P.variant];
   SketchParams K{};
   K.rowlist = rowlist; K.seg = seg; K.ent = ent; K.hdr = hdr;
+  K.dflag = P.dense_pct ? dflag : nullptr;
   K.n = n; K.d = d; K.row0 = row0; K.seed = seed;
   K.m_b = P.m_b; K.e_max = P.e_max; K.d_b = P.d_b; K.ldS = P.ldS; K.log2_cpr = P.log2_cpr;
   K.dt = P.dt; K.cg = P.cg; K.tiles = P.tiles; K.splits = P.splits;
   K.col_per_wg = P.col_per_wg;
-  if (P.splits > 1) { K.out = part; K.ld = d; K.split_stride = d * n; }
+  if (P.slices > 1) { K.out = part; K.ld = d; K.split_stride = d * n; }
   else { K.out = Ahat; K.ld = ld; K.split_stride = 0; }
   const int64_t grid = (int64_t)P.tiles * P.ncr * P.splits;
   if (grid >= INT32_MAX) return SK_EUNSUPPORTED;
@@ -288,10 +328,26 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(V.wgs), P.lds, st, K);
     if ((s = launch_ok()) != SK_OK) return s;
   }
-  // a6: fixed-order reduction of the splits
-  if ((phases & 4) && P.splits > 1)
+  // a5: dense row blocks on the matrix cores, into the last partial slice
+  if ((phases & 2) && P.dense_pct) {
+    DenseParams DP{};
+    DP.rowlist = rowlist; DP.dlist = dlist; DP.dh = dhdr; DP.hdr = hdr; DP.D = dense;
+    DP.n = n; DP.d = d; DP.row0 = row0; DP.seed = seed; DP.m_b = P.m_b;
+    DP.out = part + (int64_t)P.splits * d * n;
+    const int64_t dgrid = ((d + DT_M - 1) / DT_M) * ((n + DT_N - 1) / DT_N);
+    if (dgrid >= INT32_MAX) return SK_EUNSUPPORTED;
+    if (dist == SK_RADEMACHER)
+      hipLaunchKernelGGL(k_dense_mfma<DIST_RADEMACHER>, dim3((unsigned)dgrid), dim3(256), 0, st, DP);
+    else if (dist == SK_UNIFORM)
+      hipLaunchKernelGGL(k_dense_mfma<DIST_UNIFORM>, dim3((unsigned)dgrid), dim3(256), 0, st, DP);
+    else
+      hipLaunchKernelGGL(k_dense_mfma<DIST_GAUSSIAN>, dim3((unsigned)dgrid), dim3(256), 0, st, DP);
+    if ((s = launch_ok()) != SK_OK) return s;
+  }
+  // a6: fixed-order reduction of the partial slices
+  if ((phases & 4) && P.slices > 1)
     hipLaunchKernelGGL(k_reduce_splits, dim3(blocks_for(d * n, 256)), dim3(256), 0, st, part,
-                       P.splits, d, n, Ahat, ld);
+                       P.slices, d, n, Ahat, ld);
   return launch_ok();
 }
 

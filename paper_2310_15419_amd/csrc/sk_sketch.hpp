@@ -32,6 +32,7 @@ struct SketchParams {
   const int32_t* seg;
   const uint2* ent;
   const Header* hdr;
+  const int32_t* dflag;  // per block: nonzero when the block runs on the dense path
   int64_t n, d, row0;
   uint64_t seed;
   int32_t m_b;      // nonempty rows per block
@@ -202,11 +203,12 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(4))) void k
     // segment bounds of this group's columns in block b: loaded one block
     // ahead so their latency hides behind the previous block's accumulation
     int32_t pbn[CS + 1];
-    int32_t beg_n = 0, end_n = 0;
+    int32_t beg_n = 0, end_n = 0, dense_n = 0;
     auto load_bounds = [&](int64_t b) {
       const int32_t* segb = P.seg + b * P.n;
       beg_n = segb[0];
       end_n = segb[P.n];
+      dense_n = P.dflag ? P.dflag[b] : 0;
 #pragma unroll
       for (int c = 0; c <= CS; ++c) {
         const int64_t k = kbase + c;
@@ -215,6 +217,10 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(4))) void k
     };
     if (b_lo < b_hi) load_bounds(b_lo);
     for (int64_t b = b_lo; b < b_hi; ++b) {
+      if (dense_n) {  // the block runs on the dense (matrix core) path
+        if (b + 1 < b_hi) load_bounds(b + 1);
+        continue;
+      }
       const int64_t rem = R - b * P.m_b;
       const int rb = (int)(rem < P.m_b ? rem : P.m_b);
       const int32_t blk_beg = beg_n;

@@ -211,3 +211,22 @@ def test_multi_pass_blocks(B, oracle_lib, dist):
         got = run_gpu(B, A, d, dist, 6, tune=tune)
         norm, col = rel_errors(got, ref)
         assert norm <= TOL_NORM and col <= TOL_COL, (tune, norm, col)
+
+
+@pytest.mark.parametrize("dist", DISTS)
+def test_dense_blocks_mfma(B, oracle_lib, dist):
+    # power-law columns plus a dense row block: blocks above the density
+    # threshold run on the matrix cores; every threshold gives the same A_hat
+    A, r0 = inputs.power_law_columns(60_000, 130, 31, 0.05, 700, np.float32)
+    d = 270
+    ref = run_oracle(oracle_lib, A, d, dist, 8)
+    for tune in [None, {"dense_min_pct": 101}, {"dense_min_pct": 5},
+                 {"dense_min_pct": 40, "rows_per_block": 300, "splits": 3}]:
+        print(f"dense {dist} {tune}", flush=True)
+        got = run_gpu(B, A, d, dist, 8, tune=tune)
+        norm, col = rel_errors(got, ref)
+        assert norm <= TOL_NORM and col <= TOL_COL, (tune, norm, col)
+    # misaligned S-row offset on the dense path
+    got = run_gpu(B, A, 130, dist, 8, row0=3, tune={"dense_min_pct": 5})
+    norm, col = rel_errors(got, run_oracle(oracle_lib, A, 130, dist, 8, row0=3))
+    assert norm <= TOL_NORM and col <= TOL_COL, (norm, col)
