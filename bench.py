@@ -26,9 +26,10 @@ sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = full-rate 32-bit VALU lane-ops/s
 VALU_PEAK = 256 * 64 * 2.4e9
-# VALU issue slots (full-rate equivalents) per generator call / per S entry
-# (v_mad_u64_u32 at quarter rate: 2 per round x 4 slots, 4 v_xor_b32 per round)
-PHILOX_SLOTS = 10 * (2 * 4 + 4)
+# VALU issue slots (full-rate equivalents) per generator call / per S entry:
+# Philox4x32-10 is 10 rounds of two 32x32->64 multiplies (v_mad_u64_u32, which
+# issues at full rate on gfx950), four xors and the key bumps: about 60 slots
+PHILOX_SLOTS = 60
 UNIFORM_SLOTS = 4       # shift, shift-add, convert, scale per entry
 FMA_SLOTS = 1           # one v_fma_f32 per multiply-add (packed FP32 disabled)
 
@@ -95,6 +96,7 @@ def main():
     ap.add_argument("--rows-per-block", type=int, default=0)
     ap.add_argument("--splits", type=int, default=0)
     ap.add_argument("--dense-min-pct", type=int, default=0)
+    ap.add_argument("--col-split", type=int, default=0, help="0 auto, 1 off, 2 on")
     ap.add_argument("--copy-probe", action="store_true",
                     help="launch only a plain 1 GiB device copy (for counter scaling)")
     args = ap.parse_args()
@@ -123,7 +125,8 @@ def main():
           f"(m={A.m}, n={A.n}, nnz={A.nnz}, d={d})", file=sys.stderr, flush=True)
     dA = B.DeviceCsc.from_host(A, dtype=np.float32 if A.vals.dtype != np.float64 else None)
     tune = {"variant": args.variant, "rows_per_block": args.rows_per_block,
-            "splits": args.splits, "dense_min_pct": args.dense_min_pct}
+            "splits": args.splits, "dense_min_pct": args.dense_min_pct,
+            "col_split": args.col_split}
     ws = B.alloc_workspace(B.workspace_bytes(dA, d, dist, tune=tune))
     out = torch.empty((A.n, d), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()

@@ -87,6 +87,11 @@ typedef struct {
                              Running a subset reuses the workspace contents of
                              an earlier full call with the same A, d and tuning
                              (used to time one phase in isolation).           */
+  int32_t tile_rows;      /* S rows per workgroup tile (0 = autotuner's choice;
+                             else a power-of-two multiple of the kernel shape's
+                             rows per column group)                           */
+  int32_t col_split;      /* heavy-column splitting: 0 = auto (on for n >= 512),
+                             1 = off, 2 = on                                  */
 } sk_tuning;
 
 /* Human-readable name of a status code (static storage). */
@@ -118,6 +123,43 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
  * SK_ERANGE, SK_ECOLPTR or SK_EHIP. */
 sk_status sk_sketch_status(const void* ws, void* hip_stream, int64_t* nonempty_rows,
                            int64_t* row_blocks);
+
+/* Autotuner: the tuning sk_sketch would choose for this shape (a cost model
+ * over S-row tile height, rows per block and splits; the kernel shape follows
+ * the column count).  Host-only. */
+sk_status sk_autotune(const sk_csc* A, int64_t d, int32_t dist, sk_tuning* out);
+
+/* Many independent sketches in one pass (the batched form of sk_sketch):
+ * item i computes Ahat[i] = S_i[0:d[i], :] A[i] with S_i from seed[i] and
+ * dist[i].  A, d, dist, seed, Ahat and ld are HOST arrays of `count`
+ * entries; the matrices and outputs they describe are device memory.  tune
+ * is NULL or a host array of per-item overrides (kernel shape must agree
+ * across the batch).  One batched inspector pass covers all items, then one
+ * persistent launch per distribution runs every item's work units from a
+ * longest-first list (the only shared state is one atomic work counter);
+ * each item's result is bitwise the one sk_sketch gives with the tuning
+ * sk_sketch_batched_plan reports for it.  prec must be SK_PREC_F32.
+ * Asynchronous on hip_stream; per-item device validation status via
+ * sk_sketch_batched_status. */
+sk_status sk_sketch_batched_workspace(int32_t count, const sk_csc* A, const int64_t* d,
+                                      const int32_t* dist, int32_t prec, const sk_tuning* tune,
+                                      size_t* bytes);
+sk_status sk_sketch_batched(int32_t count, const sk_csc* A, const int64_t* d, const int32_t* dist,
+                            const uint64_t* seed, int32_t prec, const sk_tuning* tune,
+                            float* const* Ahat, const int64_t* ld, void* ws, size_t ws_bytes,
+                            void* hip_stream);
+
+/* The per-item tunings the batched call uses (host only; chosen has `count`
+ * entries). */
+sk_status sk_sketch_batched_plan(int32_t count, const sk_csc* A, const int64_t* d,
+                                 const int32_t* dist, int32_t prec, const sk_tuning* tune,
+                                 sk_tuning* chosen);
+
+/* Per-item device validation status of the last batched call on this
+ * workspace (synchronises hip_stream); returns the last failing status or
+ * SK_OK. */
+sk_status sk_sketch_batched_status(const void* ws, int32_t count, void* hip_stream,
+                                   int32_t* statuses);
 
 /* Test hook: S[row0 : row0+d, col0 : col0+ncols] into S (device FP32,
  * column-major, leading dimension ld >= d), from the same device generator

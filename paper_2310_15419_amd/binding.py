@@ -30,7 +30,8 @@ class SkCsc(ctypes.Structure):
 class SkTuning(ctypes.Structure):
     _fields_ = [("rows_per_block", ctypes.c_int32), ("splits", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("dense_min_pct", ctypes.c_int32),
-                ("phases", ctypes.c_int32)]
+                ("phases", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("col_split", ctypes.c_int32)]
 
 
 class SketchError(RuntimeError):
@@ -59,9 +60,19 @@ def lib():
                                 ctypes.c_size_t, vp]
         L.sk_sketch_status.argtypes = [vp, vp, P(i64), P(i64)]
         L.sk_materialize_s.argtypes = [i64, i64, i64, i64, i32, u64, vp, i64, vp]
+        L.sk_autotune.argtypes = [P(SkCsc), i64, i32, P(SkTuning)]
+        L.sk_sketch_batched_workspace.argtypes = [i32, P(SkCsc), P(i64), P(i32), i32, P(SkTuning),
+                                                  P(ctypes.c_size_t)]
+        L.sk_sketch_batched.argtypes = [i32, P(SkCsc), P(i64), P(i32), P(u64), i32, P(SkTuning),
+                                        P(vp), P(i64), vp, ctypes.c_size_t, vp]
+        L.sk_sketch_batched_plan.argtypes = [i32, P(SkCsc), P(i64), P(i32), i32, P(SkTuning),
+                                             P(SkTuning)]
+        L.sk_sketch_batched_status.argtypes = [vp, i32, vp, P(i32)]
         L.sk_rng_tables.argtypes = [vp, vp, vp, vp]
         L.sk_rng_tables.restype = None
-        for name in ("sk_sketch_workspace", "sk_sketch", "sk_sketch_status", "sk_materialize_s"):
+        for name in ("sk_sketch_workspace", "sk_sketch", "sk_sketch_status", "sk_materialize_s",
+                     "sk_autotune", "sk_sketch_batched_workspace", "sk_sketch_batched",
+                     "sk_sketch_batched_plan", "sk_sketch_batched_status"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -93,7 +104,8 @@ def _tuning(tune):
         return ctypes.byref(tune)
     t = SkTuning(int(tune.get("rows_per_block", 0)), int(tune.get("splits", 0)),
                  int(tune.get("variant", 0)), int(tune.get("dense_min_pct", 0)),
-                 int(tune.get("phases", 0)))
+                 int(tune.get("phases", 0)), int(tune.get("tile_rows", 0)),
+                 int(tune.get("col_split", 0)))
     return ctypes.byref(t)
 
 
@@ -199,5 +211,65 @@ def variant_count() -> int:
     return int(lib().sk_variant_count())
 
 
+def autotune(A: DeviceCsc, d: int, dist) -> dict:
+    """The tuning the library picks for this shape."""
+    t = SkTuning()
+    c = A.c_struct()
+    _check(lib().sk_autotune(ctypes.byref(c), d, _dist(dist), ctypes.byref(t)), "sk_autotune")
+    return tuning_dict(t)
+
+
+def tuning_dict(t: SkTuning) -> dict:
+    return {f[0]: int(getattr(t, f[0])) for f in SkTuning._fields_}
+
+
+class Batch:
+    """Marshalled arguments of one batched call (host arrays of the C ABI)."""
+
+    def __init__(self, mats, ds, dists, seeds, tunes=None, prec: int = PREC_F32):
+        n = len(mats)
+        self.count = n
+        self.mats = mats
+        self.c_mats = (SkCsc * n)(*[A.c_struct() for A in mats])
+        self.c_d = (ctypes.c_int64 * n)(*[int(x) for x in ds])
+        self.c_dist = (ctypes.c_int32 * n)(*[_dist(x) for x in dists])
+        self.c_seed = (ctypes.c_uint64 * n)(*[int(x) for x in seeds])
+        self.c_tune = None
+        if tunes is not None:
+            self.c_tune = (SkTuning * n)(*[SkTuning(*[int(t.get(f[0], 0)) for f in SkTuning._fields_])
+                                          for t in tunes])
+        self.prec = prec
+        self.ds = [int(x) for x in ds]
+
+    def workspace_bytes(self) -> int:
+        out = ctypes.c_size_t()
+        _check(lib().sk_sketch_batched_workspace(self.count, self.c_mats, self.c_d, self.c_dist,
+                                                 self.prec, self.c_tune, ctypes.byref(out)),
+               "sk_sketch_batched_workspace")
+        return int(out.value)
+
+    def plan(self) -> list:
+        out = (SkTuning * self.count)()
+        _check(lib().sk_sketch_batched_plan(self.count, self.c_mats, self.c_d, self.c_dist,
+                                            self.prec, self.c_tune, out), "sk_sketch_batched_plan")
+        return [tuning_dict(t) for t in out]
+
+    def run(self, outs, ws, stream=None) -> None:
+        """outs[i]: FP32 tensor of shape (n_i, d_i) (column-major d_i x n_i)."""
+        ptrs = (ctypes.c_void_p * self.count)(*[o.data_ptr() for o in outs])
+        lds = (ctypes.c_int64 * self.count)(*self.ds)
+        _check(lib().sk_sketch_batched(self.count, self.c_mats, self.c_d, self.c_dist, self.c_seed,
+                                       self.prec, self.c_tune, ptrs, lds, ws.data_ptr(), ws.numel(),
+                                       _stream(stream)), "sk_sketch_batched")
+
+    def status(self, ws, stream=None) -> list:
+        st = (ctypes.c_int32 * self.count)()
+        lib().sk_sketch_batched_status(ctypes.c_void_p(ws.data_ptr()), self.count, _stream(stream),
+                                       st)
+        return list(st)
+
+
 EXPORTED = ["sk_status_string", "sk_variant_count", "sk_sketch_workspace", "sk_sketch",
-            "sk_sketch_status", "sk_materialize_s", "sk_rng_tables"]
+            "sk_sketch_status", "sk_materialize_s", "sk_rng_tables", "sk_autotune",
+            "sk_sketch_batched_workspace", "sk_sketch_batched", "sk_sketch_batched_plan",
+            "sk_sketch_batched_status"]

@@ -34,8 +34,8 @@ struct DenseHeader {
 };
 
 // single workgroup: dense blocks in block order; dflag[b] = slot + 1 or 0
-__global__ __launch_bounds__(256) void k_dense_select(const int32_t* __restrict__ seg, int64_t n,
-                                                      int32_t m_b, int32_t min_pct,
+__global__ __launch_bounds__(256) void k_dense_select(const int32_t* __restrict__ seg, int64_t nv,
+                                                      int64_t n, int32_t m_b, int32_t min_pct,
                                                       int32_t nd_max,
                                                       const Header* __restrict__ hdr,
                                                       int32_t* __restrict__ dflag,
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_dense_select(const int32_t* __restrict_
     if (b < nb) {
       const int64_t rem = R - b * m_b;
       const int64_t rb = rem < m_b ? rem : m_b;
-      const int64_t cnt = (int64_t)seg[(b + 1) * n] - (int64_t)seg[b * n];
+      const int64_t cnt = (int64_t)seg[(b + 1) * nv] - (int64_t)seg[b * nv];
       // density >= min_pct %  <=>  100 cnt >= min_pct rb n
       flag = (100 * cnt >= (int64_t)min_pct * rb * n) ? 1 : 0;
     }
@@ -77,16 +77,20 @@ __global__ __launch_bounds__(256) void k_dense_select(const int32_t* __restrict_
 }
 
 // D[slot][l][k] = a for every entry of dense block dlist[slot]; one thread per
-// (slot, column) walks the column's segment.  D must be zeroed before.
-__global__ void k_densify(const int32_t* __restrict__ seg, const uint2* __restrict__ ent, int64_t n,
-                          int32_t m_b, int32_t row_bytes, const int32_t* __restrict__ dlist,
+// (slot, virtual column) walks the column's segment and writes real column k
+// (vbase == nullptr: virtual == real).  D must be zeroed before.
+__global__ void k_densify(const int32_t* __restrict__ seg, const uint2* __restrict__ ent, int64_t nv,
+                          int64_t n, const int32_t* __restrict__ vbase, int32_t m_b,
+                          int32_t row_bytes, const int32_t* __restrict__ dlist,
                           const DenseHeader* __restrict__ dh, float* __restrict__ D) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t slot = t / n, k = t - slot * n;
+  const int64_t slot = t / nv, v = t - slot * nv;
   if (slot >= dh->nd) return;
+  if (vbase && v >= vbase[n]) return;
+  const int64_t k = vbase ? real_column(vbase, n, v) : v;
   const int64_t b = dlist[slot];
   float* Dt = D + slot * (int64_t)m_b * n;
-  const int32_t p0 = seg[b * n + k], p1 = seg[b * n + k + 1];
+  const int32_t p0 = seg[b * nv + v], p1 = seg[b * nv + v + 1];
   for (int32_t p = p0; p < p1; ++p) {
     const uint2 e = ent[p];
     const int32_t l = (int32_t)(e.x / (uint32_t)row_bytes);

@@ -245,4 +245,96 @@ __global__ void k_scatter(const int64_t* __restrict__ colptr, const int32_t* __r
                          __float_as_uint(load_value(vals, vtype, p)));
 }
 
+
+// ---------------------------------------------------- heavy-column splitting
+// A column with many more entries than average would make its owning lane
+// the straggler of every block.  Column k is split into s_k interleaved
+// virtual columns (entry t of the column goes to virtual column
+// vbase[k] + t mod s_k, position t / s_k), s_k = ceil(cnt_k / L) with
+// L = ceil(nnz / spare): the virtual column count stays within the planned
+// capacity n_v.  The sketch runs on virtual columns; the final reduction adds
+// them back up.
+
+// vbase[k] = s_k (scanned afterwards); one thread per column
+__global__ void k_colsplit_count(const int64_t* __restrict__ colptr, int64_t n, int64_t nnz,
+                                 int64_t spare, const Header* __restrict__ hdr,
+                                 int32_t* __restrict__ vbase) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int64_t s = 1;
+  if (!hdr->status && spare > 0 && nnz > 0) {
+    const int64_t L = (nnz + spare - 1) / spare;
+    const int64_t c = colptr[k + 1] - colptr[k];
+    s = c > L ? (c + L - 1) / L : 1;
+  }
+  vbase[k] = (int32_t)s;
+}
+
+// real column of virtual column v (v < vbase[n])
+__device__ __forceinline__ int64_t real_column(const int32_t* __restrict__ vbase, int64_t n,
+                                               int64_t v) {
+  int64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (vbase[mid] <= v) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// pos[b*nv + v] (in units of the virtual column's own positions), b = 0..nb_max
+__global__ void k_block_pos_v(const int64_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
+                              int64_t n, int64_t nv, const int32_t* __restrict__ vbase,
+                              const int32_t* __restrict__ rowlist, int32_t m_b, int64_t nb_max,
+                              const Header* __restrict__ hdr, int32_t* __restrict__ pos) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (nb_max + 1) * nv) return;
+  if (hdr->status) return;
+  const int64_t b = t / nv, v = t - b * nv;
+  const int64_t vtot = vbase[n];
+  if (v >= vtot) {
+    pos[t] = 0;
+    return;
+  }
+  const int64_t k = real_column(vbase, n, v);
+  const int64_t s = vbase[k + 1] - vbase[k], r = v - vbase[k];
+  const int64_t c0 = colptr[k], cnt = colptr[k + 1] - c0;
+  const int64_t T = cnt > r ? (cnt - r + s - 1) / s : 0;  // entries of this virtual column
+  int64_t lo = 0, hi = T;
+  if (b < hdr->nblocks) {
+    const int32_t fr = rowlist[b * m_b];
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (rowidx[c0 + r + mid * s] < fr) lo = mid + 1;
+      else hi = mid;
+    }
+  } else {
+    lo = hi;
+  }
+  pos[t] = (int32_t)lo;
+}
+
+__global__ void k_scatter_v(const int64_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
+                            const void* __restrict__ vals, int vtype, int64_t n, int64_t nv,
+                            int64_t nnz, const int32_t* __restrict__ vbase,
+                            const int32_t* __restrict__ ridx, const int32_t* __restrict__ pos,
+                            const int32_t* __restrict__ seg, int32_t m_b, int32_t row_bytes,
+                            const Header* __restrict__ hdr, uint2* __restrict__ ent) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  if (hdr->status) return;
+  const int32_t r = rowidx[p];
+  const int32_t c = ridx[r];
+  const int32_t b = c / m_b;
+  const int32_t l = c - b * m_b;
+  const int64_t k = column_of(colptr, n, p);
+  const int64_t s = vbase[k + 1] - vbase[k];
+  const int64_t tall = p - colptr[k];
+  const int64_t v = vbase[k] + tall % s;
+  const int64_t bv = (int64_t)b * nv + v;
+  const int64_t dest = (int64_t)seg[bv] + (tall / s - (int64_t)pos[bv]);
+  ent[dest] = make_uint2((uint32_t)l * (uint32_t)row_bytes,
+                         __float_as_uint(load_value(vals, vtype, p)));
+}
+
 }  // namespace sk

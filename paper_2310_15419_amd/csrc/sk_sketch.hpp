@@ -162,19 +162,16 @@ __device__ __forceinline__ void stage_entries(uint2* __restrict__ E_lds,
   }
 }
 
+// One work unit: S-row tile `tile`, column range `crange`, row-block split
+// `split` of one sketch.  Used by the plain grid and by the persistent batched
+// kernel.
 template <int DIST, int DL, int Q, int CS, int WGS>
-__global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(4))) void k_sketch(
-    SketchParams P) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, int tile, int crange,
+                                            unsigned char* __restrict__ smem) {
   float* S_lds = reinterpret_cast<float*>(smem);
   uint2* E_lds = reinterpret_cast<uint2*>(smem + (size_t)P.m_b * P.ldS * sizeof(float));
 
   const int tid = threadIdx.x;
-  const int bid = blockIdx.x;
-  const int split = bid % P.splits;
-  const int rest = bid / P.splits;
-  const int tile = rest % P.tiles;
-  const int crange = rest / P.tiles;
   const int64_t i_tile = (int64_t)tile * P.d_b;
   const uint64_t grow0 = (uint64_t)(P.row0 + i_tile);
 
@@ -298,16 +295,40 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
 }
 
-// A_hat = sum over splits of the partials, fixed order.
-__global__ void k_reduce_splits(const float* __restrict__ part, int splits, int64_t d, int64_t n,
-                                float* __restrict__ out, int64_t ld) {
+template <int DIST, int DL, int Q, int CS, int WGS>
+__global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(4))) void k_sketch(
+    SketchParams P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int bid = blockIdx.x;
+  const int split = bid % P.splits;
+  const int rest = bid / P.splits;
+  sketch_unit<DIST, DL, Q, CS, WGS>(P, split, rest % P.tiles, rest / P.tiles, smem);
+}
+
+// A_hat[i, k] = sum over sparse slices of the virtual columns of k, then the
+// dense slice (if any); fixed order.  vbase == nullptr: virtual == real.
+__global__ void k_reduce_virtual(const float* __restrict__ part, int splits, int64_t d, int64_t n,
+                                 int64_t nv, const int32_t* __restrict__ vbase,
+                                 const float* __restrict__ dense_slice, float* __restrict__ out,
+                                 int64_t ld) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= d * n) return;
   const int64_t k = t / d, i = t - k * d;
-  float s = part[t];
-  for (int q = 1; q < splits; ++q) s += part[(int64_t)q * d * n + t];
+  const int64_t v0 = vbase ? vbase[k] : k, v1 = vbase ? vbase[k + 1] : k + 1;
+  float s = 0.0f;
+  bool first = true;
+  for (int q = 0; q < splits; ++q) {
+    const float* sl = part + (int64_t)q * d * nv;
+    for (int64_t v = v0; v < v1; ++v) {
+      const float x = sl[i + v * d];
+      s = first ? x : s + x;
+      first = false;
+    }
+  }
+  if (dense_slice) s += dense_slice[i + k * d];
   out[i + k * ld] = s;
 }
+
 
 // S[r + c*ld] = S(row0 + r, col0 + c): one thread per (generator group,
 // column); rows outside [row0, row0 + d) are skipped.

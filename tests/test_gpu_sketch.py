@@ -230,3 +230,41 @@ def test_dense_blocks_mfma(B, oracle_lib, dist):
     got = run_gpu(B, A, 130, dist, 8, row0=3, tune={"dense_min_pct": 5})
     norm, col = rel_errors(got, run_oracle(oracle_lib, A, 130, dist, 8, row0=3))
     assert norm <= TOL_NORM and col <= TOL_COL, (norm, col)
+
+
+@pytest.mark.parametrize("dist", DISTS)
+def test_heavy_column_split(B, oracle_lib, dist):
+    # power-law columns: the heaviest columns are split into interleaved
+    # virtual columns and summed back in fixed order; forced on, forced off
+    # and with the other tiling knobs, the result matches the oracle
+    A, _ = inputs.power_law_columns(60_000, 130, 41, 0.2, 0, np.float32)
+    d = 190
+    ref = run_oracle(oracle_lib, A, d, dist, 4)
+    outs = {}
+    for tune in [{"col_split": 1}, {"col_split": 2}, {"col_split": 2, "dense_min_pct": 101},
+                 {"col_split": 2, "variant": 1, "rows_per_block": 300, "splits": 3},
+                 {"col_split": 2, "variant": 6, "dense_min_pct": 5}]:
+        print(f"col split {dist} {tune}", flush=True)
+        got = run_gpu(B, A, d, dist, 4, tune=tune)
+        norm, col = rel_errors(got, ref)
+        assert norm <= TOL_NORM and col <= TOL_COL, (tune, norm, col)
+        outs[str(tune)] = got
+    again = run_gpu(B, A, d, dist, 4, tune={"col_split": 2})
+    assert np.array_equal(again, outs[str({"col_split": 2})])
+
+
+def test_heavy_column_split_auto_and_single_column(B, oracle_lib):
+    # n >= 512 turns splitting on by itself; one column holding every row
+    m, n, d = 40_000, 600, 140
+    rng = np.random.default_rng(9)
+    er, ec = rng.integers(0, m, 5000), rng.integers(0, n, 5000)
+    key = np.unique(ec[ec != 17] * m + er[ec != 17])
+    rows = np.concatenate([np.arange(m), key % m])
+    cols = np.concatenate([np.full(m, 17), key // m])
+    A = inputs.from_coo(m, n, rows, cols, rng.standard_normal(rows.size).astype(np.float32))
+    for dist in DISTS:
+        print(f"single heavy column {dist}", flush=True)
+        ref = run_oracle(oracle_lib, A, d, dist, 2)
+        for tune in [None, {"col_split": 1}]:
+            norm, col = rel_errors(run_gpu(B, A, d, dist, 2, tune=tune), ref)
+            assert norm <= TOL_NORM and col <= TOL_COL, (dist, tune, norm, col)

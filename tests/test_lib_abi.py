@@ -79,9 +79,39 @@ def test_tuning_variants_all_plan():
     for v in range(1, binding.variant_count() + 1):
         for n in (1, 50, 200, 2000, 5000):
             c = _csc(m=100000, n=n, nnz=10 * n)
-            t = binding.SkTuning(0, 0, v, 0, 0)
+            t = binding.SkTuning(0, 0, v, 0, 0, 0, 0)
             assert lib.sk_sketch_workspace(ctypes.byref(c), 3 * n, 1, 0, ctypes.byref(t),
                                            ctypes.byref(out)) == 0
-    t = binding.SkTuning(0, 0, binding.variant_count() + 1, 0, 0)
+    t = binding.SkTuning(0, 0, binding.variant_count() + 1, 0, 0, 0, 0)
     assert lib.sk_sketch_workspace(ctypes.byref(_csc()), 64, 1, 0, ctypes.byref(t),
                                    ctypes.byref(out)) == -1
+
+
+def test_batched_plan_host_only():
+    lib = binding.lib()
+    n = 5
+    mats = (binding.SkCsc * n)(*[binding.SkCsc(1000 * (i + 1), 50 + 40 * i, 3000 * (i + 1), 8, 8, 8,
+                                               binding.F32) for i in range(n)])
+    ds = (ctypes.c_int64 * n)(*[120 + 80 * i for i in range(n)])
+    dist = (ctypes.c_int32 * n)(*[i % 3 for i in range(n)])
+    out = ctypes.c_size_t()
+    assert lib.sk_sketch_batched_workspace(n, mats, ds, dist, 0, None, ctypes.byref(out)) == 0
+    assert out.value > 0
+    chosen = (binding.SkTuning * n)()
+    assert lib.sk_sketch_batched_plan(n, mats, ds, dist, 0, None, chosen) == 0
+    assert len({c.variant for c in chosen}) == 1
+    for c in chosen:
+        assert c.rows_per_block >= 1 and c.splits >= 1 and c.tile_rows >= 1
+    # precision path is single-sketch only; bad count; bad d
+    assert lib.sk_sketch_batched_workspace(n, mats, ds, dist, 1, None, ctypes.byref(out)) == -6
+    assert lib.sk_sketch_batched_workspace(0, mats, ds, dist, 0, None, ctypes.byref(out)) == -1
+    ds[2] = 0
+    assert lib.sk_sketch_batched_workspace(n, mats, ds, dist, 0, None, ctypes.byref(out)) == -1
+
+
+def test_autotune_host_only():
+    lib = binding.lib()
+    t = binding.SkTuning()
+    c = _csc(m=2_000_000, n=2000, nnz=20_000_000)
+    assert lib.sk_autotune(ctypes.byref(c), 4000, 1, ctypes.byref(t)) == 0
+    assert t.tile_rows >= 16 and t.rows_per_block > 100 and t.splits >= 1
