@@ -97,6 +97,7 @@ def main():
     ap.add_argument("--splits", type=int, default=0)
     ap.add_argument("--dense-min-pct", type=int, default=0)
     ap.add_argument("--col-split", type=int, default=0, help="0 auto, 1 off, 2 on")
+    ap.add_argument("--row-pad", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="launch only a plain 1 GiB device copy (for counter scaling)")
     args = ap.parse_args()
@@ -126,7 +127,7 @@ def main():
     dA = B.DeviceCsc.from_host(A, dtype=np.float32 if A.vals.dtype != np.float64 else None)
     tune = {"variant": args.variant, "rows_per_block": args.rows_per_block,
             "splits": args.splits, "dense_min_pct": args.dense_min_pct,
-            "col_split": args.col_split}
+            "col_split": args.col_split, "row_pad": args.row_pad}
     ws = B.alloc_workspace(B.workspace_bytes(dA, d, dist, tune=tune))
     out = torch.empty((A.n, d), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()

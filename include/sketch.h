@@ -92,6 +92,9 @@ typedef struct {
                              rows per column group)                           */
   int32_t col_split;      /* heavy-column splitting: 0 = auto (on for n >= 512),
                              1 = off, 2 = on                                  */
+  int32_t row_pad;        /* S-tile row padding in floats: 0 = none (rows of
+                             d_b floats), else this many extra floats per row
+                             (a multiple of 4)                                */
 } sk_tuning;
 
 /* Human-readable name of a status code (static storage). */

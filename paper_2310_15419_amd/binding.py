@@ -31,7 +31,7 @@ class SkTuning(ctypes.Structure):
     _fields_ = [("rows_per_block", ctypes.c_int32), ("splits", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("dense_min_pct", ctypes.c_int32),
                 ("phases", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-                ("col_split", ctypes.c_int32)]
+                ("col_split", ctypes.c_int32), ("row_pad", ctypes.c_int32)]
 
 
 class SketchError(RuntimeError):
@@ -105,7 +105,7 @@ def _tuning(tune):
     t = SkTuning(int(tune.get("rows_per_block", 0)), int(tune.get("splits", 0)),
                  int(tune.get("variant", 0)), int(tune.get("dense_min_pct", 0)),
                  int(tune.get("phases", 0)), int(tune.get("tile_rows", 0)),
-                 int(tune.get("col_split", 0)))
+                 int(tune.get("col_split", 0)), int(tune.get("row_pad", 0)))
     return ctypes.byref(t)
 
 

@@ -7,15 +7,15 @@
 // large-density regime of the cost model, Sec. III-A-2, where reuse of the
 // S tile across columns is near its maximum).  Steps:
 //   k_dense_select  picks the dense blocks in increasing block order
-//                   (deterministic list, capped by the workspace capacity)
-//   k_densify       writes each dense block as an rb x n row-major tile
+//                   (deterministic list, capped by the workspace capacity);
+//                   their rows are concatenated in that order
+//   k_densify       writes the dense rows as a row-major (rows x n) matrix
 //   k_dense_mfma    one workgroup per 64 x 64 output tile; per 32-row K chunk
-//                   it regenerates S (64 S rows x 32 A rows) into LDS, loads
-//                   the dense A chunk, and runs v_mfma_f32_32x32x2f32 per wave
-//                   (each wave a 32 x 32 quarter); the tile is summed over all
-//                   dense blocks in block order and written to its own slice
-//                   of the split partials, so the final reduction stays fixed
-//                   order.
+//                   of the dense rows it regenerates S (64 S rows x 32 A
+//                   rows) into LDS, loads the dense A chunk, and runs
+//                   v_mfma_f32_32x32x2f32 per wave (each wave a 32 x 32
+//                   quarter); the tile is written to its own slice of the
+//                   split partials, so the final reduction stays fixed order.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,58 +30,105 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 struct DenseHeader {
   int32_t nd;       // dense blocks selected
-  int32_t pad[15];
+  int32_t rows;     // their rows, concatenated in block order
+  int32_t pad[14];
 };
 
-// single workgroup: dense blocks in block order; dflag[b] = slot + 1 or 0
+// single workgroup: dense blocks in block order, taken while the dense-row
+// capacity lasts; dflag[b] = slot + 1 or 0, doff[slot] = first dense row
 __global__ __launch_bounds__(256) void k_dense_select(const int32_t* __restrict__ seg, int64_t nv,
-                                                      int64_t n, int32_t m_b, int32_t min_pct,
-                                                      int32_t nd_max,
+                                                      int64_t n, const int32_t* __restrict__ bstart,
+                                                      int32_t min_pct, int64_t kd_max,
                                                       const Header* __restrict__ hdr,
                                                       int32_t* __restrict__ dflag,
                                                       int32_t* __restrict__ dlist,
+                                                      int32_t* __restrict__ doff,
                                                       DenseHeader* __restrict__ dh) {
-  __shared__ int32_t sh[256];
+  __shared__ int32_t sh_f[256];
+  __shared__ int32_t sh_r[256];
   const int tid = threadIdx.x;
   const int64_t nb = hdr->status ? 0 : hdr->nblocks;
-  const int64_t R = hdr->nonempty;
-  int32_t base = 0;
+  int32_t base_f = 0, base_r = 0;
+  bool full = false;
   for (int64_t b0 = 0; b0 < nb; b0 += 256) {
     const int64_t b = b0 + tid;
-    int flag = 0;
+    int flag = 0, rb = 0;
     if (b < nb) {
-      const int64_t rem = R - b * m_b;
-      const int64_t rb = rem < m_b ? rem : m_b;
+      rb = bstart[b + 1] - bstart[b];
       const int64_t cnt = (int64_t)seg[(b + 1) * nv] - (int64_t)seg[b * nv];
       // density >= min_pct %  <=>  100 cnt >= min_pct rb n
-      flag = (100 * cnt >= (int64_t)min_pct * rb * n) ? 1 : 0;
+      flag = (!full && 100 * cnt >= (int64_t)min_pct * rb * n) ? 1 : 0;
     }
-    sh[tid] = flag;
+    sh_f[tid] = flag;
+    sh_r[tid] = flag ? rb : 0;
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {  // inclusive scan of the flags
-      const int32_t add = tid >= off ? sh[tid - off] : 0;
+    for (int off = 1; off < 256; off <<= 1) {  // inclusive scans
+      const int32_t af = tid >= off ? sh_f[tid - off] : 0;
+      const int32_t ar = tid >= off ? sh_r[tid - off] : 0;
       __syncthreads();
-      sh[tid] += add;
+      sh_f[tid] += af;
+      sh_r[tid] += ar;
       __syncthreads();
     }
-    const int32_t slot = base + sh[tid] - flag;
+    const int32_t slot = base_f + sh_f[tid] - flag;
+    const int64_t row_end = (int64_t)base_r + sh_r[tid];  // inclusive of this block
+    const bool take = flag && row_end <= kd_max;
     if (b < nb) {
-      const bool take = flag && slot < nd_max;
       dflag[b] = take ? slot + 1 : 0;
-      if (take) dlist[slot] = (int32_t)b;
+      if (take) {
+        dlist[slot] = (int32_t)b;
+        doff[slot] = (int32_t)(row_end - rb);
+      }
     }
-    base += sh[255];
+    // the taken blocks are a prefix of the flagged ones: count them
+    const int taken = __syncthreads_count(take ? 1 : 0);
+    const bool overflow = __syncthreads_or(flag && !take);
+    int32_t rows_taken = 0;
+    if (tid == 0) sh_f[0] = 0;
     __syncthreads();
+    if (take) atomicAdd(&sh_f[0], rb);
+    __syncthreads();
+    rows_taken = sh_f[0];
+    __syncthreads();
+    base_f += taken;
+    base_r += rows_taken;
+    if (overflow) full = true;
   }
-  if (tid == 0) dh->nd = base < nd_max ? base : nd_max;
+  if (tid == 0) {
+    dh->nd = base_f;
+    dh->rows = base_r;
+  }
 }
 
-// D[slot][l][k] = a for every entry of dense block dlist[slot]; one thread per
-// (slot, virtual column) walks the column's segment and writes real column k
-// (vbase == nullptr: virtual == real).  D must be zeroed before.
+// zero the dense rows in use (grid-stride)
+__global__ void k_dense_zero(float* __restrict__ D, int64_t n, const DenseHeader* __restrict__ dh) {
+  const int64_t total = (int64_t)dh->rows * n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x)
+    D[i] = 0.0f;
+}
+
+// drows[t] = the A row of dense row t (t < rows); one thread per dense row
+__global__ void k_dense_rows(const int32_t* __restrict__ rowlist, const int32_t* __restrict__ bstart,
+                             const int32_t* __restrict__ dlist, const int32_t* __restrict__ doff,
+                             const DenseHeader* __restrict__ dh, int32_t* __restrict__ drows) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= dh->rows) return;
+  int lo = 0, hi = dh->nd - 1;  // last slot with doff <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (doff[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  drows[t] = rowlist[bstart[dlist[lo]] + (t - doff[lo])];
+}
+
+// D[doff[slot] + l][k] = a for every entry of dense block dlist[slot]; one
+// thread per (slot, virtual column) walks the column's segment and writes
+// real column k (vbase == nullptr: virtual == real).
 __global__ void k_densify(const int32_t* __restrict__ seg, const uint2* __restrict__ ent, int64_t nv,
-                          int64_t n, const int32_t* __restrict__ vbase, int32_t m_b,
-                          int32_t row_bytes, const int32_t* __restrict__ dlist,
+                          int64_t n, const int32_t* __restrict__ vbase, int32_t row_bytes,
+                          const int32_t* __restrict__ dlist, const int32_t* __restrict__ doff,
                           const DenseHeader* __restrict__ dh, float* __restrict__ D) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t slot = t / nv, v = t - slot * nv;
@@ -89,7 +136,7 @@ __global__ void k_densify(const int32_t* __restrict__ seg, const uint2* __restri
   if (vbase && v >= vbase[n]) return;
   const int64_t k = vbase ? real_column(vbase, n, v) : v;
   const int64_t b = dlist[slot];
-  float* Dt = D + slot * (int64_t)m_b * n;
+  float* Dt = D + (int64_t)doff[slot] * n;
   const int32_t p0 = seg[b * nv + v], p1 = seg[b * nv + v + 1];
   for (int32_t p = p0; p < p1; ++p) {
     const uint2 e = ent[p];
@@ -99,14 +146,12 @@ __global__ void k_densify(const int32_t* __restrict__ seg, const uint2* __restri
 }
 
 struct DenseParams {
-  const int32_t* rowlist;
-  const int32_t* dlist;
+  const int32_t* drows;  // A row of each dense row
   const DenseHeader* dh;
   const Header* hdr;
-  const float* D;
+  const float* D;        // dense rows x n, row-major
   int64_t n, d, row0;
   uint64_t seed;
-  int32_t m_b;
   float* out;  // the dense slice of the split partials (d x n, ld = d)
 };
 
@@ -161,30 +206,24 @@ __global__ __launch_bounds__(256) void k_dense_mfma(DenseParams P) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 
-  const int nd = P.hdr->status ? 0 : P.dh->nd;
-  const int64_t R = P.hdr->nonempty;
-  for (int t = 0; t < nd; ++t) {
-    const int64_t b = P.dlist[t];
-    const int64_t rem = R - b * P.m_b;
-    const int rb = (int)(rem < P.m_b ? rem : P.m_b);
-    const float* Dt = P.D + (int64_t)t * P.m_b * P.n;
-    for (int k0 = 0; k0 < rb; k0 += DT_K) {
-      const int nk = rb - k0 < DT_K ? rb - k0 : DT_K;
-      __syncthreads();
-      dense_fill_s<DIST>(Ss, P.rowlist + b * P.m_b + k0, nk, grow0, P.seed);
-      for (int idx = tid; idx < DT_K * DT_N; idx += 256) {
-        const int kk = idx / DT_N, jj = idx - kk * DT_N;
-        const int64_t j = j0 + jj;
-        Ds[kk * (DT_N + 4) + jj] = (kk < nk && j < P.n) ? Dt[(int64_t)(k0 + kk) * P.n + j] : 0.0f;
-      }
-      __syncthreads();
+  const int64_t K = P.hdr->status ? 0 : P.dh->rows;
+  for (int64_t k0 = 0; k0 < K; k0 += DT_K) {
+    const int nk = (int)(K - k0 < DT_K ? K - k0 : DT_K);
+    __syncthreads();
+    dense_fill_s<DIST>(Ss, P.drows + k0, nk, grow0, P.seed);
+    const float* Dt = P.D + k0 * P.n;
+    for (int idx = tid; idx < DT_K * DT_N; idx += 256) {
+      const int kk = idx / DT_N, jj = idx - kk * DT_N;
+      const int64_t j = j0 + jj;
+      Ds[kk * (DT_N + 4) + jj] = (kk < nk && j < P.n) ? Dt[(int64_t)kk * P.n + j] : 0.0f;
+    }
+    __syncthreads();
 #pragma unroll
-      for (int kq = 0; kq < DT_K; kq += 2) {
-        const int kk = kq + (lane >> 5);
-        const float a = Ss[(wm + (lane & 31)) * (DT_K + 1) + kk];
-        const float bv = Ds[kk * (DT_N + 4) + wn + (lane & 31)];
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc, 0, 0, 0);
-      }
+    for (int kq = 0; kq < DT_K; kq += 2) {
+      const int kk = kq + (lane >> 5);
+      const float a = Ss[(wm + (lane & 31)) * (DT_K + 1) + kk];
+      const float bv = Ds[kk * (DT_N + 4) + wn + (lane & 31)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc, 0, 0, 0);
     }
   }
   // D[i][j]: j = lane % 32, i = 8 (r / 4) + 4 (lane / 32) + r % 4

@@ -5,20 +5,36 @@
 // The paper's Algorithm 4 needs a blocked representation built from the CSC
 // input (Sec. III-B: the conversion costs O(ceil(n/b_n) m + nnz) and is cheap
 // next to the multiplication, Table IV).  Here the blocks run the other way:
-// a row block is a run of m_b consecutive *nonempty* rows of A (empty rows
-// need no S column at all, Sec. III-B), and inside a block the entries are
-// ordered by column, then row, so one S tile of the block's rows is reused by
-// every column that has nonzeros there.
+// a row block is a run of consecutive *nonempty* rows of A (empty rows need
+// no S column at all, Sec. III-B), and inside a block the entries are ordered
+// by column, then row, so one S tile of the block's rows is reused by every
+// column that has nonzeros there.
 //
-// Layout produced (all int32; nnz, m and the block grid must fit in int32):
-//   ridx[r]            position of row r among the nonempty rows (exclusive
-//                      scan of the occupancy flags); ridx[m] = R
-//   rowlist[c]         the c-th nonempty row
-//   pos[b*n + k]       first CSC position of column k with row >= first row
-//                      of block b (b = 0..nb_max, the last one = colptr[k+1])
-//   seg[b*n + k]       position of block b / column k's segment in `ent`;
-//                      seg[nb_max*n] = nnz.  Block b spans
-//                      [seg[b*n], seg[(b+1)*n]).
+// Blocks are balanced by entries: the nonempty rows are cut into groups of
+// m_b (the S-tile capacity), and each group is cut further, greedily in row
+// order, so that no block holds more than e_cap entries (the LDS staging
+// capacity) unless one row alone does.  Rows of very different weight (a few
+// dense rows among many light ones) then never make a block that needs many
+// staging passes.
+//
+// Every kernel here runs over a flattened index space that concatenates the
+// items of a batch (a single sketch is a batch of one): a thread finds its
+// item by binary search over the items' prefix offsets.  Per-item exclusive
+// scans are one scan over the concatenated regions, followed by subtraction
+// of each item's value at its region start.
+//
+// Layout produced per item (all int32; nnz, m and the block grid fit int32):
+//   ridx[r]            position of row r among the nonempty rows; ridx[m] = R
+//   rowlist[c], rowcnt[c]  the c-th nonempty row and its entry count
+//   bfl[c]             number of block starts among rows < c (so row c is in
+//                      block bfl[c + 1] - 1); bfl[R] = number of blocks
+//   bstart[b]          first nonempty row of block b; bstart[nblocks] = R
+//   vbase[k]           first virtual column of column k (heavy-column
+//                      splitting; absent when off)
+//   pos[b*nv + v]      first position of (virtual) column v whose row is >=
+//                      the first row of block b (b = 0..nb_max)
+//   seg[b*nv + v]      start of block b / column v's segment in `ent`;
+//                      block b spans [seg[b*nv], seg[(b+1)*nv])
 //   ent[p]             {byte offset of the entry's row in the S tile (row
 //                      inside the block times the tile's row bytes), FP32
 //                      bits of the value}
@@ -30,14 +46,63 @@
 namespace sk {
 
 // status bits written by the validation kernel
-enum : int { ST_RANGE = 1, ST_UNSORTED = 2, ST_COLPTR = 4 };
+enum : int { ST_RANGE = 1, ST_UNSORTED = 2, ST_COLPTR = 4, ST_CAPACITY = 8 };
 
-struct Header {       // first bytes of the workspace
+struct Header {       // one per item, in the workspace
   int32_t status;     // OR of ST_* bits
   int32_t pad;
   int64_t nonempty;   // R
-  int64_t nblocks;    // ceil(R / m_b)
+  int64_t nblocks;
   int64_t reserved[5];
+};
+
+struct Item {
+  // input (device memory)
+  int64_t m, n, nnz;
+  const int64_t* colptr;
+  const int32_t* rowidx;
+  const void* vals;
+  int32_t vtype;
+  // plan
+  int32_t m_b;        // rows per row group (S-tile capacity)
+  int32_t e_cap;      // entries per block (staging capacity)
+  int32_t row_bytes;  // S-tile row stride in bytes
+  int64_t nv;         // (virtual) columns of the layout
+  int64_t nb_max;     // block capacity
+  int64_t r_max;      // nonempty-row capacity, min(m, max(nnz, 1))
+  // workspace (device memory)
+  Header* hdr;
+  int32_t* ridx;      // m + 1, region of a concatenated array
+  int32_t* rcnt;      // m
+  int32_t* rowlist;   // r_max + m_b + 1 (padded for whole-group reads)
+  int32_t* rowcnt;    // r_max
+  int32_t* bfl;       // r_max + 1, region of a concatenated array
+  int32_t* bstart;    // nb_max + 1
+  int32_t* vbase;     // n + 1, region of a concatenated array; nullptr: no splitting
+  int32_t* pos;       // (nb_max + 1) * nv
+  int32_t* seg;       // nb_max * nv + 1, region of a concatenated array
+  uint2* ent;         // nnz + 2
+  int32_t* bcost;     // nb_max + 1, region of a concatenated array: block costs,
+                      // then their exclusive prefix (splits cut it evenly)
+  const int32_t* dflag;  // per block: nonzero on the dense path (may be null)
+  // block cost model: (rows w_row + entries w_ent + w_blk) >> cost_shift
+  int32_t w_row, w_ent, w_blk, cost_shift;
+  // value of each concatenated scan at this item's region start
+  int32_t base_ridx, base_bfl, base_vbase, base_seg, base_cost;
+  // exclusive prefix offsets of this item in each flattened index space
+  int64_t o_valid;    // max(nnz, n + 1)
+  int64_t o_ridx;     // m + 1
+  int64_t o_m;        // m
+  int64_t o_grp;      // row groups, ceil(r_max / m_b)
+  int64_t o_bfl;      // r_max + 1
+  int64_t o_rmax;     // r_max
+  int64_t o_col;      // n
+  int64_t o_vb;       // n + 1
+  int64_t o_pos;      // (nb_max + 1) * nv
+  int64_t o_cnt;      // nb_max * nv
+  int64_t o_seg;      // nb_max * nv + 1
+  int64_t o_nnz;      // nnz
+  int64_t o_blk;      // nb_max + 1
 };
 
 template <typename T>
@@ -65,36 +130,6 @@ __device__ __forceinline__ float load_value(const void* vals, int vtype, int64_t
   if (vtype == 1) return ((const float*)vals)[p];
   const uint16_t h = ((const uint16_t*)vals)[p];          // bf16 -> fp32 exact
   return __uint_as_float((uint32_t)h << 16);
-}
-
-// Validate and mark occupied rows.  One thread per nonzero (and per colptr
-// entry).
-__global__ void k_validate_mark(const int64_t* __restrict__ colptr,
-                                const int32_t* __restrict__ rowidx, int64_t m, int64_t n,
-                                int64_t nnz, int32_t* __restrict__ flags,
-                                Header* __restrict__ hdr) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int bad = 0;
-  if (t <= n) {
-    const int64_t c = colptr[t];
-    if (t == 0 && c != 0) bad |= ST_COLPTR;
-    if (t == n && c != nnz) bad |= ST_COLPTR;
-    if (t < n && colptr[t + 1] < c) bad |= ST_COLPTR;
-    if (c < 0 || c > nnz) bad |= ST_COLPTR;
-  }
-  if (t < nnz) {
-    const int32_t r = rowidx[t];
-    if (r < 0 || r >= m) {
-      bad |= ST_RANGE;
-    } else {
-      flags[r] = 1;
-    }
-    if (t > 0) {
-      const int64_t k = column_of(colptr, n, t);
-      if (colptr[k] < t && rowidx[t - 1] >= r) bad |= ST_UNSORTED;
-    }
-  }
-  if (bad) atomicOr(&hdr->status, bad);
 }
 
 // ------------------------------------------------------------- scan (int32)
@@ -179,96 +214,192 @@ __global__ void k_scan_add(int32_t* __restrict__ a, int64_t count,
   if (i < count) a[i] += sums[i / SCAN_CHUNK];
 }
 
-// nonempty-row list and block count.  ridx = scanned flags, ridx[m] = R.
-__global__ void k_rowlist(const int32_t* __restrict__ ridx, int64_t m,
-                          int32_t* __restrict__ rowlist, int32_t m_b, int64_t nb_max,
-                          Header* __restrict__ hdr) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < m && ridx[r + 1] > ridx[r]) rowlist[ridx[r]] = (int32_t)r;
-  if (r == 0) {
-    const int64_t R = ridx[m];
-    hdr->nonempty = R;
-    int64_t nb = (R + m_b - 1) / m_b;
-    hdr->nblocks = nb < nb_max ? nb : nb_max;
+
+// item owning flattened index t of the space whose offsets are field F
+template <int64_t Item::*F>
+__device__ __forceinline__ int find_item(const Item* __restrict__ it, int count, int64_t t) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (it[mid].*F <= t) lo = mid;
+    else hi = mid - 1;
   }
+  return lo;
 }
 
-// pos[b*n + k], b = 0..nb_max: first position of column k whose row is >= the
-// first row of block b (b >= nblocks: the end of the column).
-__global__ void k_block_pos(const int64_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
-                            int64_t m, int64_t n, const int32_t* __restrict__ rowlist,
-                            int32_t m_b, int64_t nb_max, const Header* __restrict__ hdr,
-                            int32_t* __restrict__ pos) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (nb_max + 1) * n) return;
-  if (hdr->status) return;
-  const int64_t b = t / n, k = t - b * n;
-  int64_t lo = colptr[k], hi = colptr[k + 1];
-  if (b < hdr->nblocks) {
-    const int32_t fr = rowlist[b * m_b];
-    while (lo < hi) {  // lower bound of fr in rowidx[lo, hi)
-      const int64_t mid = (lo + hi) >> 1;
-      if (rowidx[mid] < fr) lo = mid + 1;
-      else hi = mid;
+// One thread per flattened index: Op::run(item, index inside the item).
+template <int64_t Item::*F, class Op>
+__global__ void k_items(const Item* __restrict__ it, int count, int64_t total) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int i = count == 1 ? 0 : find_item<F>(it, count, g);
+  Op::run(it[i], g - it[i].*F);
+}
+
+// Validate, mark occupied rows and count entries per row.  One thread per
+// nonzero (and per colptr entry).
+struct OpValidate {
+  static __device__ void run(const Item& I, int64_t t) {
+    int bad = 0;
+    if (t <= I.n) {
+      const int64_t c = I.colptr[t];
+      if (t == 0 && c != 0) bad |= ST_COLPTR;
+      if (t == I.n && c != I.nnz) bad |= ST_COLPTR;
+      if (t < I.n && I.colptr[t + 1] < c) bad |= ST_COLPTR;
+      if (c < 0 || c > I.nnz) bad |= ST_COLPTR;
     }
-  } else {
-    lo = hi;
+    if (t < I.nnz) {
+      const int32_t r = I.rowidx[t];
+      if (r < 0 || r >= I.m) {
+        bad |= ST_RANGE;
+      } else {
+        I.ridx[r] = 1;
+        atomicAdd(&I.rcnt[r], 1);
+      }
+      if (t > 0) {
+        const int64_t k = column_of(I.colptr, I.n, t);
+        if (I.colptr[k] < t && I.rowidx[t - 1] >= r) bad |= ST_UNSORTED;
+      }
+    }
+    if (bad) atomicOr(&I.hdr->status, bad);
   }
-  pos[t] = (int32_t)lo;
+};
+
+// region bases after a concatenated scan
+enum : int { SCAN_RIDX = 0, SCAN_BFL = 1, SCAN_VBASE = 2, SCAN_SEG = 3, SCAN_COST = 4 };
+
+__global__ void k_item_bases(Item* __restrict__ it, int count, int which) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  Item& I = it[i];
+  if (which == SCAN_RIDX) I.base_ridx = I.ridx[0];
+  else if (which == SCAN_BFL) I.base_bfl = I.bfl[0];
+  else if (which == SCAN_VBASE) I.base_vbase = I.vbase ? I.vbase[0] : 0;
+  else if (which == SCAN_SEG) I.base_seg = I.seg[0];
+  else I.base_cost = I.bcost[0];
 }
 
-// seg[b*n + k] = count of (b, k), b < nb_max (scanned afterwards)
-__global__ void k_block_cnt(const int32_t* __restrict__ pos, int64_t n, int64_t nb_max,
-                            const Header* __restrict__ hdr, int32_t* __restrict__ seg) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nb_max * n) return;
-  seg[t] = hdr->status ? 0 : pos[t + n] - pos[t];
+template <int WHICH>
+struct OpRebase {
+  static __device__ void run(const Item& I, int64_t t) {
+    if (WHICH == SCAN_RIDX) I.ridx[t] -= I.base_ridx;
+    else if (WHICH == SCAN_BFL) I.bfl[t] -= I.base_bfl;
+    else if (WHICH == SCAN_VBASE) { if (I.vbase) I.vbase[t] -= I.base_vbase; }
+    else if (WHICH == SCAN_SEG) I.seg[t] -= I.base_seg;
+    else I.bcost[t] -= I.base_cost;
+  }
+};
+
+// nonempty-row list with entry counts; R to the header
+struct OpRowlist {
+  static __device__ void run(const Item& I, int64_t r) {
+    const int32_t c = I.ridx[r];
+    if (I.ridx[r + 1] > c) {
+      I.rowlist[c] = (int32_t)r;
+      I.rowcnt[c] = I.rcnt[r];
+    }
+    if (r == 0) I.hdr->nonempty = I.ridx[I.m];
+  }
+};
+
+// Block starts inside row group g (rows [g m_b, min(R, (g+1) m_b))): greedy
+// in row order, a new block starts at the first row that would take the open
+// block past e_cap entries; a row that alone exceeds e_cap is a block of its
+// own.  One wave per group, 64 rows per step: a wave-wide prefix sum of the
+// row counts, then one ballot per block start found in the step.
+__global__ __launch_bounds__(256) void k_partition(const Item* __restrict__ it, int count,
+                                                   int64_t total_groups) {
+  const int64_t g_all = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (g_all >= total_groups) return;  // wave-uniform
+  const int i = count == 1 ? 0 : find_item<&Item::o_grp>(it, count, g_all);
+  const Item& I = it[i];
+  if (I.hdr->status) return;
+  const int64_t R = I.hdr->nonempty;
+  const int64_t c0 = (g_all - I.o_grp) * I.m_b;
+  if (c0 >= R) return;
+  const int64_t c1 = c0 + I.m_b < R ? c0 + I.m_b : R;
+  const int32_t E = I.e_cap;
+  if (lane == 0) I.bfl[c0] = 1;
+  int32_t cur = 0;  // entries of the open block
+  for (int64_t cb = c0; cb < c1; cb += 64) {
+    const int nvalid = (int)(c1 - cb < 64 ? c1 - cb : 64);
+    const int32_t x = lane < nvalid ? I.rowcnt[cb + lane] : 0;
+    int32_t pre = x;  // inclusive prefix over the lanes
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t y = __shfl_up(pre, off, 64);
+      if (lane >= off) pre += y;
+    }
+    int base = 0;       // first lane not yet placed in a closed block
+    int32_t pbase = 0;  // prefix before lane `base`
+    while (true) {
+      const bool over = lane >= base && lane < nvalid && cur + (pre - pbase) > E;
+      const uint64_t mask = __ballot(over);
+      if (mask == 0) {
+        cur += __shfl(pre, nvalid - 1, 64) - pbase;
+        break;
+      }
+      const int f = __ffsll((unsigned long long)mask) - 1;
+      const int32_t pre_f = __shfl(pre, f, 64);
+      const int32_t x_f = __shfl(x, f, 64);
+      if (f == base && cur == 0) {
+        // row f alone exceeds the cap: it closes its own block
+        if (lane == 0 && cb + f + 1 < c1) I.bfl[cb + f + 1] = 1;
+        base = f + 1;
+        pbase = pre_f;
+      } else {
+        if (lane == 0) I.bfl[cb + f] = 1;
+        base = f;
+        pbase = pre_f - x_f;
+      }
+      cur = 0;
+    }
+  }
 }
 
-// ent[seg[b n + k] + (p - pos[b n + k])] = {row in block * row_bytes, value}
-__global__ void k_scatter(const int64_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
-                          const void* __restrict__ vals, int vtype, int64_t n, int64_t nnz,
-                          const int32_t* __restrict__ ridx, const int32_t* __restrict__ pos,
-                          const int32_t* __restrict__ seg, int32_t m_b, int32_t row_bytes,
-                          const Header* __restrict__ hdr, uint2* __restrict__ ent) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nnz) return;
-  if (hdr->status) return;
-  const int32_t r = rowidx[p];
-  const int32_t c = ridx[r];
-  const int32_t b = c / m_b;
-  const int32_t l = c - b * m_b;
-  const int64_t k = column_of(colptr, n, p);
-  const int64_t bk = (int64_t)b * n + k;
-  const int64_t dest = (int64_t)seg[bk] + (p - (int64_t)pos[bk]);
-  ent[dest] = make_uint2((uint32_t)l * (uint32_t)row_bytes,
-                         __float_as_uint(load_value(vals, vtype, p)));
-}
-
+// block start rows from the scanned flags; block count to the header
+struct OpBstart {
+  static __device__ void run(const Item& I, int64_t c) {
+    if (I.hdr->status) return;
+    const int64_t R = I.hdr->nonempty;
+    if (c < R) {
+      const int32_t b = I.bfl[c];
+      if (I.bfl[c + 1] != b && b < I.nb_max) I.bstart[b] = (int32_t)c;
+    }
+    if (c == 0) {
+      const int64_t nb = I.bfl[R];
+      if (nb > I.nb_max) atomicOr(&I.hdr->status, ST_CAPACITY);
+      const int64_t nbc = nb < I.nb_max ? nb : I.nb_max;
+      I.hdr->nblocks = nbc;
+      I.bstart[nbc] = (int32_t)R;
+    }
+  }
+};
 
 // ---------------------------------------------------- heavy-column splitting
 // A column with many more entries than average would make its owning lane
 // the straggler of every block.  Column k is split into s_k interleaved
 // virtual columns (entry t of the column goes to virtual column
 // vbase[k] + t mod s_k, position t / s_k), s_k = ceil(cnt_k / L) with
-// L = ceil(nnz / spare): the virtual column count stays within the planned
-// capacity n_v.  The sketch runs on virtual columns; the final reduction adds
-// them back up.
+// L = ceil(nnz / (nv - n)): the virtual column count stays within the
+// planned capacity nv.  The sketch runs on virtual columns; the final
+// reduction adds them back up.
 
-// vbase[k] = s_k (scanned afterwards); one thread per column
-__global__ void k_colsplit_count(const int64_t* __restrict__ colptr, int64_t n, int64_t nnz,
-                                 int64_t spare, const Header* __restrict__ hdr,
-                                 int32_t* __restrict__ vbase) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  int64_t s = 1;
-  if (!hdr->status && spare > 0 && nnz > 0) {
-    const int64_t L = (nnz + spare - 1) / spare;
-    const int64_t c = colptr[k + 1] - colptr[k];
-    s = c > L ? (c + L - 1) / L : 1;
+// vbase[k] = s_k (scanned afterwards)
+struct OpColsplit {
+  static __device__ void run(const Item& I, int64_t k) {
+    if (!I.vbase) return;
+    int64_t s = 1;
+    const int64_t spare = I.nv - I.n;
+    if (!I.hdr->status && spare > 0 && I.nnz > 0) {
+      const int64_t L = (I.nnz + spare - 1) / spare;
+      const int64_t c = I.colptr[k + 1] - I.colptr[k];
+      s = c > L ? (c + L - 1) / L : 1;
+    }
+    I.vbase[k] = (int32_t)s;
   }
-  vbase[k] = (int32_t)s;
-}
+};
 
 // real column of virtual column v (v < vbase[n])
 __device__ __forceinline__ int64_t real_column(const int32_t* __restrict__ vbase, int64_t n,
@@ -282,59 +413,89 @@ __device__ __forceinline__ int64_t real_column(const int32_t* __restrict__ vbase
   return lo;
 }
 
-// pos[b*nv + v] (in units of the virtual column's own positions), b = 0..nb_max
-__global__ void k_block_pos_v(const int64_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
-                              int64_t n, int64_t nv, const int32_t* __restrict__ vbase,
-                              const int32_t* __restrict__ rowlist, int32_t m_b, int64_t nb_max,
-                              const Header* __restrict__ hdr, int32_t* __restrict__ pos) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (nb_max + 1) * nv) return;
-  if (hdr->status) return;
-  const int64_t b = t / nv, v = t - b * nv;
-  const int64_t vtot = vbase[n];
-  if (v >= vtot) {
-    pos[t] = 0;
-    return;
-  }
-  const int64_t k = real_column(vbase, n, v);
-  const int64_t s = vbase[k + 1] - vbase[k], r = v - vbase[k];
-  const int64_t c0 = colptr[k], cnt = colptr[k + 1] - c0;
-  const int64_t T = cnt > r ? (cnt - r + s - 1) / s : 0;  // entries of this virtual column
-  int64_t lo = 0, hi = T;
-  if (b < hdr->nblocks) {
-    const int32_t fr = rowlist[b * m_b];
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (rowidx[c0 + r + mid * s] < fr) lo = mid + 1;
-      else hi = mid;
+// pos[b*nv + v], b = 0..nb_max, in units of the (virtual) column's own
+// positions: how many of its entries lie above block b (all of them for
+// b >= nblocks)
+struct OpBlockPos {
+  static __device__ void run(const Item& I, int64_t t) {
+    if (I.hdr->status) return;
+    const int64_t b = t / I.nv, v = t - b * I.nv;
+    int64_t k = v, s = 1, r = 0;
+    if (I.vbase) {
+      if (v >= I.vbase[I.n]) {
+        I.pos[t] = 0;
+        return;
+      }
+      k = real_column(I.vbase, I.n, v);
+      s = I.vbase[k + 1] - I.vbase[k];
+      r = v - I.vbase[k];
     }
-  } else {
-    lo = hi;
+    const int64_t c0 = I.colptr[k], cnt = I.colptr[k + 1] - c0;
+    const int64_t T = cnt > r ? (cnt - r + s - 1) / s : 0;
+    int64_t lo = 0, hi = T;
+    if (b < I.hdr->nblocks) {
+      const int32_t fr = I.rowlist[I.bstart[b]];
+      while (lo < hi) {  // lower bound of fr among rows c0 + r + t s
+        const int64_t mid = (lo + hi) >> 1;
+        if (I.rowidx[c0 + r + mid * s] < fr) lo = mid + 1;
+        else hi = mid;
+      }
+    } else {
+      lo = hi;
+    }
+    I.pos[t] = (int32_t)lo;
   }
-  pos[t] = (int32_t)lo;
-}
+};
 
-__global__ void k_scatter_v(const int64_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
-                            const void* __restrict__ vals, int vtype, int64_t n, int64_t nv,
-                            int64_t nnz, const int32_t* __restrict__ vbase,
-                            const int32_t* __restrict__ ridx, const int32_t* __restrict__ pos,
-                            const int32_t* __restrict__ seg, int32_t m_b, int32_t row_bytes,
-                            const Header* __restrict__ hdr, uint2* __restrict__ ent) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nnz) return;
-  if (hdr->status) return;
-  const int32_t r = rowidx[p];
-  const int32_t c = ridx[r];
-  const int32_t b = c / m_b;
-  const int32_t l = c - b * m_b;
-  const int64_t k = column_of(colptr, n, p);
-  const int64_t s = vbase[k + 1] - vbase[k];
-  const int64_t tall = p - colptr[k];
-  const int64_t v = vbase[k] + tall % s;
-  const int64_t bv = (int64_t)b * nv + v;
-  const int64_t dest = (int64_t)seg[bv] + (tall / s - (int64_t)pos[bv]);
-  ent[dest] = make_uint2((uint32_t)l * (uint32_t)row_bytes,
-                         __float_as_uint(load_value(vals, vtype, p)));
-}
+// seg[b*nv + v] = entries of (b, v), b < nb_max (scanned afterwards)
+struct OpBlockCnt {
+  static __device__ void run(const Item& I, int64_t t) {
+    I.seg[t] = I.hdr->status ? 0 : I.pos[t + I.nv] - I.pos[t];
+  }
+};
+
+// ent[seg[b nv + v] + (position in v - pos[b nv + v])] = {row in block *
+// row_bytes, value}
+struct OpScatter {
+  static __device__ void run(const Item& I, int64_t p) {
+    if (I.hdr->status) return;
+    const int32_t r = I.rowidx[p];
+    const int32_t c = I.ridx[r];
+    const int32_t b = I.bfl[c + 1] - 1;
+    const int32_t l = c - I.bstart[b];
+    const int64_t k = column_of(I.colptr, I.n, p);
+    int64_t v = k, q = p - I.colptr[k];
+    if (I.vbase) {
+      const int64_t s = I.vbase[k + 1] - I.vbase[k];
+      v = I.vbase[k] + q % s;
+      q = q / s;
+    }
+    const int64_t bv = (int64_t)b * I.nv + v;
+    const int64_t dest = (int64_t)I.seg[bv] + (q - (int64_t)I.pos[bv]);
+    I.ent[dest] = make_uint2((uint32_t)l * (uint32_t)I.row_bytes,
+                             __float_as_uint(load_value(I.vals, I.vtype, p)));
+  }
+};
+
+// Estimated cost of block b for one tile (b < nblocks; 0 past the end, so
+// the scanned prefix ends at the total).  The sketch kernel gives each split
+// a contiguous run of blocks holding an equal share of the total, so cheap
+// blocks (dense ones, which the matrix cores take) do not leave splits idle.
+struct OpBlockCost {
+  static __device__ void run(const Item& I, int64_t b) {
+    int32_t c = 0;
+    if (!I.hdr->status && b < I.hdr->nblocks) {
+      int64_t w = I.w_blk;
+      if (!(I.dflag && I.dflag[b])) {
+        const int64_t rb = I.bstart[b + 1] - I.bstart[b];
+        const int64_t e = (int64_t)I.seg[(b + 1) * I.nv] - I.seg[b * I.nv];
+        w += rb * I.w_row + e * I.w_ent;
+      }
+      w >>= I.cost_shift;
+      c = (int32_t)(w < 1 ? 1 : (w > 0x3FFFFFFF ? 0x3FFFFFFF : w));
+    }
+    I.bcost[b] = c;
+  }
+};
 
 }  // namespace sk

@@ -36,7 +36,7 @@ int ilog2(int64_t v) {
 // ------------------------------------------------------------ kernel table
 using SketchKernel = void (*)(SketchParams);
 
-using PersistentKernel = void (*)(const BatchItem*, const int2*, int, int32_t*);
+using PersistentKernel = void (*)(const BatchOut*, const int2*, int, int32_t*);
 
 struct Variant {
   int dl, q, cs, wgs;
@@ -69,17 +69,15 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 struct Plan {
   int variant;  // index into kVariants
   int32_t m_b, e_max, d_b, ldS, dt, cg, tiles, splits, col_per_wg, ncr, log2_cpr;
-  int64_t nb_max;
+  int64_t r_max;      // nonempty-row capacity
+  int64_t ngroups;    // row groups of m_b rows
+  int64_t nb_max;     // block capacity
+  int64_t nv;         // virtual columns (== n without heavy-column splitting)
   size_t lds;
   int32_t dense_pct;  // densify at >= this % density; 0: no dense path
-  int64_t nd_max;     // capacity in dense blocks
+  int64_t kd_max;     // dense-row capacity
   int32_t slices;     // partial slices: splits (+1 for the dense path)
   double cost;        // autotuner's cost estimate (CU-cycles)
-  int64_t nv;         // virtual columns (== n without heavy-column splitting)
-};
-
-struct Layout {
-  int64_t hdr, ridx, sums, rowlist, vbase, pos, seg, ent, dflag, dlist, dhdr, dense, part, total;
 };
 
 constexpr int kDenseAutoPct = 40;                 // FP32 operands
@@ -120,6 +118,7 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
               Plan& P, int forced_variant = -1, double unit_cycles = 0.0) {
   int v = forced_variant >= 0 ? forced_variant : (tune && tune->variant > 0 ? tune->variant - 1 : -1);
   if (v >= kNumVariants) return false;
+  if (tune && (tune->row_pad < 0 || tune->row_pad % 4)) return false;
   if (forced_variant >= 0 && tune && tune->variant > 0 && tune->variant - 1 != forced_variant)
     return false;
   if (v < 0) {
@@ -149,7 +148,10 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
   P.col_per_wg = (int32_t)(cg * V.cs);
   const int budget = (V.wgs >= 1024 ? kLdsPerCu : kLdsPerCu / 2) - 1024;
   const int64_t rmax = std::max<int64_t>(1, std::min(m, nnz));
-  const double per_row = std::max(1.0, (double)nnz / (double)rmax);
+  // entries per nonempty row if the positions were uniform (the expected
+  // number of nonempty rows is m (1 - exp(-nnz / m)))
+  const double r_est = std::max(1.0, (double)m * -std::expm1(-(double)nnz / (double)m));
+  const double per_row = std::max(1.0, (double)nnz / r_est);
 
   // candidate S-row subtile counts: powers of two that the column groups
   // allow, d_b <= 128, not far beyond d
@@ -171,7 +173,7 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
     Plan Q = P;
     Q.dt = dt;
     Q.d_b = dt * V.q * V.dl;
-    Q.ldS = Q.d_b + 4;
+    Q.ldS = Q.d_b + (tune && tune->row_pad > 0 ? std::min(tune->row_pad, 64) : 0);
     Q.tiles = (int32_t)((d + Q.d_b - 1) / Q.d_b);
     const int rows_per_chunk = dist == DIST_RADEMACHER ? std::min(32, Q.d_b) : 4;
     Q.log2_cpr = ilog2(Q.d_b / rows_per_chunk);
@@ -182,11 +184,22 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
                       : (int64_t)((double)budget / (Q.ldS * 4.0 + 8.0 * per_row));
     m_b = std::max<int64_t>(1, std::min<int64_t>(m_b, 8192));
     while (m_b > 1 && m_b * Q.ldS * 4 + 8 * 64 > budget) m_b /= 2;
+    auto e_of = [&](int64_t mb) {
+      return (int64_t)(((budget - mb * Q.ldS * 4) / 8 - 2) & ~int64_t(1));
+    };
+    // leave room for the spread of a group's entry count around its mean, so
+    // a typical group stays one block
+    if (!(tune && tune->rows_per_block > 0))
+      while (m_b > 64 && (double)e_of(m_b) < m_b * per_row + 3.0 * std::sqrt(m_b * per_row) + 2.0)
+        m_b -= std::max<int64_t>(1, m_b / 64);
     Q.m_b = (int32_t)m_b;
-    Q.e_max = (int32_t)(((budget - m_b * Q.ldS * 4) / 8 - 2) & ~int64_t(1));
+    Q.e_max = (int32_t)e_of(m_b);
     if (Q.e_max < 2) continue;
     Q.lds = (size_t)m_b * Q.ldS * 4 + (size_t)(Q.e_max + 2) * 8;
-    Q.nb_max = std::max<int64_t>(1, (rmax + m_b - 1) / m_b);
+    Q.r_max = rmax;
+    Q.ngroups = (rmax + m_b - 1) / m_b;
+    // groups, plus at most two blocks per e_max entries from the entry cuts
+    Q.nb_max = Q.ngroups + (2 * std::max<int64_t>(nnz, 1) + Q.e_max - 1) / Q.e_max + 1;
     const double c = plan_cost(Q, V, m, P.nv, nnz, d, dist);
     if (best < 0 || c < best) {
       best = c;
@@ -208,19 +221,18 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
   }
   splits = std::max<int64_t>(1, std::min<int64_t>(splits, P.nb_max));
   P.splits = (int32_t)splits;
-  // dense row blocks: only if at least one block could reach the threshold
+  // dense row blocks: only if some row could reach the threshold; capacity
+  // in dense rows (a dense block of rb rows holds >= pct % of rb * n entries)
   int pct = tune && tune->dense_min_pct > 0 ? tune->dense_min_pct : kDenseAutoPct;
   P.dense_pct = 0;
-  P.nd_max = 0;
-  const int64_t m_b = P.m_b;
-  if (unit_cycles <= 0 && pct <= 100 &&
-      (double)nnz * 100.0 >= (double)pct * (double)m_b * (double)n) {
-    int64_t ndm = (int64_t)((double)nnz * 100.0 / ((double)pct * (double)m_b * (double)n)) + 1;
-    ndm = std::min<int64_t>(ndm, P.nb_max);
-    ndm = std::min<int64_t>(ndm, kDenseMaxBytes / (4 * (int64_t)m_b * n));
-    if (ndm > 0) {
+  P.kd_max = 0;
+  if (unit_cycles <= 0 && pct <= 100 && (double)nnz * 100.0 >= (double)pct * (double)n) {
+    int64_t kd = (int64_t)((double)nnz * 100.0 / ((double)pct * (double)n));
+    kd = std::min<int64_t>(kd, rmax);
+    kd = std::min<int64_t>(kd, kDenseMaxBytes / (4 * n));
+    if (kd > 0) {
       P.dense_pct = pct;
-      P.nd_max = ndm;
+      P.kd_max = kd;
     }
   }
   P.slices = P.splits + (P.dense_pct ? 1 : 0);
@@ -228,22 +240,41 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
   return true;
 }
 
+// Workspace of one sketch.  The header sits at offset 0 (the status call
+// reads it there).
+struct Layout {
+  int64_t hdr, item, ridx, rcnt, rowlist, rowcnt, bfl, bstart, vbase, pos, seg, ent, bcost, sums;
+  int64_t dflag, dlist, doff, dhdr, drows, dense, part, total;
+};
+
+int64_t scan_sums_len(int64_t longest) { return longest / SCAN_CHUNK + 2; }
+
 Layout layout_for(int64_t m, int64_t n, int64_t nnz, int64_t d, const Plan& P) {
   Layout L{};
   int64_t off = 0;
+  const int64_t nd_cap = std::max<int64_t>(1, std::min(P.nb_max, P.kd_max));
   L.hdr = off;     off = align_up(off + (int64_t)sizeof(Header));
-  L.ridx = off;    off = align_up(off + 4 * (m + 1));
-  const int64_t big = std::max<int64_t>({m, (P.nb_max + 1) * P.nv, nnz, 1});
-  L.sums = off;    off = align_up(off + 4 * (big / SCAN_CHUNK + 2));
-  L.rowlist = off; off = align_up(off + 4 * (std::min(m, std::max<int64_t>(nnz, 1)) + P.m_b + 1));
-  L.vbase = off;   off = align_up(off + 4 * (n + 1));
+  L.item = off;    off = align_up(off + (int64_t)sizeof(Item));
+  // scanned arrays hold one more element: the scan's grand total
+  L.ridx = off;    off = align_up(off + 4 * (m + 2));
+  L.rcnt = off;    off = align_up(off + 4 * m);
+  L.rowlist = off; off = align_up(off + 4 * (P.r_max + P.m_b + 1));
+  L.rowcnt = off;  off = align_up(off + 4 * P.r_max);
+  L.bfl = off;     off = align_up(off + 4 * (P.r_max + 2));
+  L.bstart = off;  off = align_up(off + 4 * (P.nb_max + 1));
+  L.vbase = off;   if (P.nv != n) off = align_up(off + 4 * (n + 2));
   L.pos = off;     off = align_up(off + 4 * (P.nb_max + 1) * P.nv);
-  L.seg = off;     off = align_up(off + 4 * (P.nb_max * P.nv + 1));
+  L.seg = off;     off = align_up(off + 4 * (P.nb_max * P.nv + 2));
   L.ent = off;     off = align_up(off + 8 * (nnz + 2));  // +2: 16-byte staging tail
+  L.bcost = off;   off = align_up(off + 4 * (P.nb_max + 2));
+  const int64_t longest = std::max<int64_t>({m + 1, P.r_max + 1, n + 1, P.nb_max * P.nv + 1});
+  L.sums = off;    off = align_up(off + 4 * scan_sums_len(longest));
   L.dflag = off;   off = align_up(off + 4 * P.nb_max);
-  L.dlist = off;   off = align_up(off + 4 * std::max<int64_t>(P.nd_max, 1));
+  L.dlist = off;   off = align_up(off + 4 * nd_cap);
+  L.doff = off;    off = align_up(off + 4 * nd_cap);
   L.dhdr = off;    off = align_up(off + (int64_t)sizeof(DenseHeader));
-  L.dense = off;   off = align_up(off + 4 * P.nd_max * P.m_b * n);
+  L.drows = off;   off = align_up(off + 4 * std::max<int64_t>(P.kd_max, 1));
+  L.dense = off;   off = align_up(off + 4 * P.kd_max * n);
   L.part = off;
   if (P.slices > 1 || P.nv != n)
     off = align_up(off + 4 * ((int64_t)P.splits * d * P.nv + (P.dense_pct ? d * n : 0)));
@@ -284,14 +315,152 @@ sk_status scan_i32(int32_t* a, int64_t count, int32_t* sums, hipStream_t st) {
 }
 
 
+// ------------------------------------------------------------- inspector
+// Flattened index-space sizes of a batch of items (a single sketch is a
+// batch of one), and the concatenated arrays the per-item scans run over.
+struct InspectSizes {
+  int64_t valid = 0, ridx = 0, m = 0, grp = 0, bfl = 0, rmax = 0, col = 0, vb = 0, pos = 0,
+          cnt = 0, seg = 0, nnz = 0, blk = 0;
+};
+
+// offsets of item I in each index space; sizes accumulate into Z
+void item_offsets(Item& I, InspectSizes& Z) {
+  I.o_valid = Z.valid; Z.valid += std::max<int64_t>(I.nnz, I.n + 1);
+  I.o_ridx = Z.ridx;   Z.ridx += I.m + 1;
+  I.o_m = Z.m;         Z.m += I.m;
+  I.o_grp = Z.grp;     Z.grp += (I.r_max + I.m_b - 1) / I.m_b;
+  I.o_bfl = Z.bfl;     Z.bfl += I.r_max + 1;
+  I.o_rmax = Z.rmax;   Z.rmax += I.r_max;
+  I.o_col = Z.col;     Z.col += I.n;
+  I.o_vb = Z.vb;       if (I.vbase) Z.vb += I.n + 1;
+  I.o_pos = Z.pos;     Z.pos += (I.nb_max + 1) * I.nv;
+  I.o_cnt = Z.cnt;     Z.cnt += I.nb_max * I.nv;
+  I.o_seg = Z.seg;     Z.seg += I.nb_max * I.nv + 1;
+  I.o_nnz = Z.nnz;     Z.nnz += I.nnz;
+  I.o_blk = Z.blk;     Z.blk += I.nb_max + 1;
+}
+
+struct InspectArrays {
+  int32_t* ridx;   // Z.ridx (+1 for the scan total)
+  int32_t* rcnt;   // Z.m
+  int32_t* bfl;    // Z.bfl (+1)
+  int32_t* vbase;  // Z.vb (+1), may be null when no item splits
+  int32_t* seg;    // Z.seg (+1)
+  int32_t* bcost;  // Z.blk (+1)
+  int32_t* sums;   // scan_sums_len(longest)
+};
+
+template <int64_t Item::*F, class Op>
+void launch_items(Item* it, int count, int64_t total, hipStream_t st) {
+  if (total > 0)
+    hipLaunchKernelGGL((k_items<F, Op>), dim3(blocks_for(total, 256)), dim3(256), 0, st, it, count,
+                       total);
+}
+
+// exclusive scan of a concatenated array, then per-region rebasing
+template <int WHICH, int64_t Item::*F>
+sk_status scan_regions(int32_t* all, int64_t total, Item* it, int count, int32_t* sums,
+                       hipStream_t st) {
+  sk_status s = scan_i32(all, total, sums, st);
+  if (s != SK_OK || count == 1) return s;
+  hipLaunchKernelGGL(k_item_bases, dim3(blocks_for(count, 256)), dim3(256), 0, st, it, count, WHICH);
+  launch_items<F, OpRebase<WHICH>>(it, count, total, st);
+  return launch_ok();
+}
+
+// a1 + a2 for every item: validation, nonempty rows, entry-balanced row
+// blocks, heavy-column splitting, segments and the entry scatter.  The
+// items' headers must be zero.
+sk_status run_inspector(Item* it, int count, const InspectSizes& Z, const InspectArrays& W,
+                        hipStream_t st) {
+  sk_status s;
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(Z.ridx + 1, 256 * 8)), dim3(256), 0, st,
+                     W.ridx, Z.ridx + 1, 0);
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(Z.m, 256 * 8)), dim3(256), 0, st, W.rcnt,
+                     Z.m, 0);
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(Z.bfl + 1, 256 * 8)), dim3(256), 0, st,
+                     W.bfl, Z.bfl + 1, 0);
+  launch_items<&Item::o_valid, OpValidate>(it, count, Z.valid, st);
+  if ((s = scan_regions<SCAN_RIDX, &Item::o_ridx>(W.ridx, Z.ridx, it, count, W.sums, st)) != SK_OK)
+    return s;
+  launch_items<&Item::o_m, OpRowlist>(it, count, Z.m, st);
+  hipLaunchKernelGGL(k_partition, dim3(blocks_for(Z.grp * 64, 256)), dim3(256), 0, st, it, count,
+                     Z.grp);
+  if ((s = scan_regions<SCAN_BFL, &Item::o_bfl>(W.bfl, Z.bfl, it, count, W.sums, st)) != SK_OK)
+    return s;
+  launch_items<&Item::o_rmax, OpBstart>(it, count, Z.rmax, st);
+  if (Z.vb > 0) {
+    launch_items<&Item::o_col, OpColsplit>(it, count, Z.col, st);
+    if ((s = scan_regions<SCAN_VBASE, &Item::o_vb>(W.vbase, Z.vb, it, count, W.sums, st)) !=
+        SK_OK)
+      return s;
+  }
+  launch_items<&Item::o_pos, OpBlockPos>(it, count, Z.pos, st);
+  launch_items<&Item::o_cnt, OpBlockCnt>(it, count, Z.cnt, st);
+  if ((s = scan_regions<SCAN_SEG, &Item::o_seg>(W.seg, Z.seg, it, count, W.sums, st)) != SK_OK)
+    return s;
+  launch_items<&Item::o_nnz, OpScatter>(it, count, Z.nnz, st);
+  return launch_ok();
+}
+
+// block costs and their prefix (after the dense selection, if any)
+sk_status run_block_costs(Item* it, int count, const InspectSizes& Z, const InspectArrays& W,
+                          hipStream_t st) {
+  launch_items<&Item::o_blk, OpBlockCost>(it, count, Z.blk, st);
+  return scan_regions<SCAN_COST, &Item::o_blk>(W.bcost, Z.blk, it, count, W.sums, st);
+}
+
+// the device copy of a single item, written from a kernel argument (no host
+// staging of the descriptor)
+__global__ void k_put_item(Item I, Item* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = I;
+}
+
+Item make_item(const sk_csc* A, const Plan& P, int dist) {
+  Item I;
+  std::memset(&I, 0, sizeof I);
+  I.m = A->m; I.n = A->n; I.nnz = A->nnz;
+  I.colptr = A->colptr; I.rowidx = A->rowidx; I.vals = A->vals; I.vtype = A->vtype;
+  I.m_b = P.m_b; I.e_cap = P.e_max; I.row_bytes = P.ldS * 4;
+  I.nv = P.nv; I.nb_max = P.nb_max; I.r_max = P.r_max;
+  // block cost weights in 1/16 wave instructions per tile: S generation per
+  // row, multiply-adds (with the lockstep padding) and staging per entry, a
+  // fixed cost per block
+  const Variant& V = kVariants[P.variant];
+  const int rpc = dist == DIST_RADEMACHER ? std::min(32, P.d_b) : 4;
+  const double call_ops = dist == DIST_GAUSSIAN ? 200.0 : (dist == DIST_UNIFORM ? 75.0 : 70.0);
+  I.w_row = (int32_t)std::max(1.0, std::round(16.0 * (P.d_b / rpc) * call_ops / 64.0));
+  I.w_ent = (int32_t)std::max(
+      1.0, std::round(16.0 * (P.d_b * (V.dl + 3.0) / V.dl * 2.0 / 64.0 + 0.25)));
+  I.w_blk = 16 * 400;
+  const double bound = (double)P.r_max * I.w_row + (double)A->nnz * I.w_ent +
+                       (double)(P.nb_max + 1) * I.w_blk;
+  I.cost_shift = 0;
+  while (bound / (double)(int64_t(1) << I.cost_shift) > (double)(1 << 29)) ++I.cost_shift;
+  return I;
+}
+
+SketchParams make_params(const Plan& P, const Item& I, int64_t d, int64_t row0, uint64_t seed) {
+  SketchParams K{};
+  K.rowlist = I.rowlist; K.bstart = I.bstart; K.seg = I.seg; K.ent = I.ent; K.hdr = I.hdr;
+  K.bcost = I.bcost;
+  K.dflag = nullptr;
+  K.n = P.nv; K.d = d; K.row0 = row0; K.seed = seed;
+  K.m_b = P.m_b; K.e_max = P.e_max; K.d_b = P.d_b; K.ldS = P.ldS; K.log2_cpr = P.log2_cpr;
+  K.dt = P.dt; K.cg = P.cg; K.tiles = P.tiles; K.splits = P.splits;
+  K.col_per_wg = P.col_per_wg;
+  return K;
+}
+
 // ------------------------------------------------------------------ batch
 struct BatchPlan {
   int variant = 0;
   std::vector<Plan> plans;
-  std::vector<int64_t> rowlist, pos, ent, part;
-  int64_t hdrs = 0, items = 0, work = 0, counters = 0, ridx_all = 0, seg_all = 0, sums = 0;
-  int64_t total = 0;
-  int64_t t_valid = 0, t_ridx = 0, t_m = 0, t_pos = 0, t_cnt = 0, t_seg = 0, t_nnz = 0, t_out = 0;
+  std::vector<int64_t> rowlist, rowcnt, bstart, pos, ent, part;
+  InspectSizes Z;
+  int64_t hdrs = 0, items = 0, outs = 0, work = 0, counters = 0;
+  int64_t ridx_all = 0, rcnt_all = 0, bfl_all = 0, seg_all = 0, bcost_all = 0, sums = 0;
+  int64_t total = 0, t_out = 0;
   int64_t units[3] = {0, 0, 0};
   size_t lds[3] = {0, 0, 0};
 };
@@ -319,46 +488,52 @@ sk_status batch_plan(int32_t count, const sk_csc* A, const int64_t* d, const int
     total_cost += B.plans[i].cost;
   }
   int cus = 256;
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess) cus = 256;
   const double unit = std::max(1.0, total_cost / ((double)cus * kBatchUnitsPerSlot));
   for (int i = 0; i < count; ++i) {
     const sk_tuning* t = tune ? &tune[i] : nullptr;
     if (!plan_for(A[i].m, A[i].n, A[i].nnz, d[i], dist[i], t, B.plans[i], B.variant, unit))
       return SK_EINVAL;
     const Plan& P = B.plans[i];
-    if ((int64_t)(P.nb_max + 1) * A[i].n >= INT32_MAX) return SK_EUNSUPPORTED;
+    if ((int64_t)(P.nb_max + 1) * P.nv >= INT32_MAX) return SK_EUNSUPPORTED;
   }
-  // layout: shared arrays first, then per-item regions
+  // layout: headers first (the status call reads them there), shared arrays,
+  // then per-item regions
   int64_t off = 0;
   B.hdrs = off;     off = align_up(off + (int64_t)sizeof(Header) * count);
-  B.items = off;    off = align_up(off + (int64_t)sizeof(BatchItem) * count);
+  B.items = off;    off = align_up(off + (int64_t)sizeof(Item) * count);
+  B.outs = off;     off = align_up(off + (int64_t)sizeof(BatchOut) * count);
+  B.Z = InspectSizes{};
+  B.t_out = 0;
   for (int i = 0; i < count; ++i) {
     const Plan& P = B.plans[i];
-    const int64_t u = (int64_t)P.tiles * P.ncr * P.splits;
-    B.units[dist[i]] += u;
+    Item I = make_item(&A[i], P, dist[i]);
+    item_offsets(I, B.Z);
+    B.units[dist[i]] += (int64_t)P.tiles * P.ncr * P.splits;
     B.lds[dist[i]] = std::max(B.lds[dist[i]], P.lds);
-    const int64_t m = A[i].m, n = A[i].n, nnz = A[i].nnz;
-    B.t_valid += std::max<int64_t>(nnz, n + 1);
-    B.t_ridx += m + 1;
-    B.t_m += m;
-    B.t_pos += (P.nb_max + 1) * n;
-    B.t_cnt += P.nb_max * n;
-    B.t_seg += P.nb_max * n + 1;
-    B.t_nnz += nnz;
-    if (P.slices > 1) B.t_out += d[i] * n;
+    if (P.slices > 1) B.t_out += d[i] * A[i].n;
   }
+  const InspectSizes& Z = B.Z;
   const int64_t nunits = B.units[0] + B.units[1] + B.units[2];
-  if (nunits >= INT32_MAX || B.t_ridx >= INT32_MAX || B.t_seg >= INT32_MAX) return SK_EUNSUPPORTED;
+  if (nunits >= INT32_MAX || Z.ridx >= INT32_MAX || Z.seg >= INT32_MAX || Z.bfl >= INT32_MAX)
+    return SK_EUNSUPPORTED;
   B.work = off;     off = align_up(off + 8 * std::max<int64_t>(nunits, 1));
   B.counters = off; off = align_up(off + 4 * 4);
-  B.ridx_all = off; off = align_up(off + 4 * (B.t_ridx + 1));
-  B.seg_all = off;  off = align_up(off + 4 * (B.t_seg + 1));
-  B.sums = off;     off = align_up(off + 4 * (std::max(B.t_ridx, B.t_seg) / SCAN_CHUNK + 2));
-  B.rowlist.resize(count); B.pos.resize(count); B.ent.resize(count); B.part.resize(count);
+  B.ridx_all = off; off = align_up(off + 4 * (Z.ridx + 1));
+  B.rcnt_all = off; off = align_up(off + 4 * std::max<int64_t>(Z.m, 1));
+  B.bfl_all = off;  off = align_up(off + 4 * (Z.bfl + 1));
+  B.seg_all = off;  off = align_up(off + 4 * (Z.seg + 1));
+  B.bcost_all = off; off = align_up(off + 4 * (Z.blk + 1));
+  B.sums = off;
+  off = align_up(off + 4 * scan_sums_len(std::max({Z.ridx, Z.bfl, Z.seg, Z.blk})));
+  B.rowlist.resize(count); B.rowcnt.resize(count); B.bstart.resize(count);
+  B.pos.resize(count); B.ent.resize(count); B.part.resize(count);
   for (int i = 0; i < count; ++i) {
     const Plan& P = B.plans[i];
-    const int64_t m = A[i].m, n = A[i].n, nnz = A[i].nnz;
-    B.rowlist[i] = off; off = align_up(off + 4 * (std::min(m, std::max<int64_t>(nnz, 1)) + P.m_b + 1));
+    const int64_t n = A[i].n, nnz = A[i].nnz;
+    B.rowlist[i] = off; off = align_up(off + 4 * (P.r_max + P.m_b + 1));
+    B.rowcnt[i] = off;  off = align_up(off + 4 * P.r_max);
+    B.bstart[i] = off;  off = align_up(off + 4 * (P.nb_max + 1));
     B.pos[i] = off;     off = align_up(off + 4 * (P.nb_max + 1) * n);
     B.ent[i] = off;     off = align_up(off + 8 * (nnz + 2));
     B.part[i] = off;
@@ -413,90 +588,67 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
   const Layout L = layout_for(A->m, A->n, A->nnz, d, P);
   if (!ws || ws_bytes < (size_t)L.total) return SK_EWORKSPACE;
   hipStream_t st = (hipStream_t)hip_stream;
-  const int64_t m = A->m, n = A->n, nnz = A->nnz;
+  const int64_t n = A->n;
   const int phases = tune && tune->phases ? tune->phases : 7;
   char* w = (char*)ws;
-  Header* hdr = (Header*)(w + L.hdr);
-  int32_t* ridx = (int32_t*)(w + L.ridx);
-  int32_t* sums = (int32_t*)(w + L.sums);
-  int32_t* rowlist = (int32_t*)(w + L.rowlist);
-  int32_t* vbase = (int32_t*)(w + L.vbase);
-  int32_t* pos = (int32_t*)(w + L.pos);
-  int32_t* seg = (int32_t*)(w + L.seg);
-  uint2* ent = (uint2*)(w + L.ent);
+  Item I = make_item(A, P, dist);
+  I.hdr = (Header*)(w + L.hdr);
+  I.ridx = (int32_t*)(w + L.ridx);
+  I.rcnt = (int32_t*)(w + L.rcnt);
+  I.rowlist = (int32_t*)(w + L.rowlist);
+  I.rowcnt = (int32_t*)(w + L.rowcnt);
+  I.bfl = (int32_t*)(w + L.bfl);
+  I.bstart = (int32_t*)(w + L.bstart);
+  I.vbase = P.nv != n ? (int32_t*)(w + L.vbase) : nullptr;
+  I.pos = (int32_t*)(w + L.pos);
+  I.seg = (int32_t*)(w + L.seg);
+  I.ent = (uint2*)(w + L.ent);
+  I.bcost = (int32_t*)(w + L.bcost);
+  I.dflag = P.dense_pct ? (int32_t*)(w + L.dflag) : nullptr;
+  InspectSizes Z;
+  item_offsets(I, Z);
+  Item* d_item = (Item*)(w + L.item);
   int32_t* dflag = (int32_t*)(w + L.dflag);
   int32_t* dlist = (int32_t*)(w + L.dlist);
+  int32_t* doff = (int32_t*)(w + L.doff);
   DenseHeader* dhdr = (DenseHeader*)(w + L.dhdr);
+  int32_t* drows = (int32_t*)(w + L.drows);
   float* dense = (float*)(w + L.dense);
   float* part = (float*)(w + L.part);
+  const int64_t nv = P.nv;
 
   if (phases & 1) {
-  // a1: validate + mark nonempty rows
-  hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, (int32_t*)hdr,
-                     (int64_t)(sizeof(Header) / 4), 0);
-  hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st, ridx, m + 1,
-                     0);
-  const int64_t vthreads = std::max<int64_t>(nnz, n + 1);
-  hipLaunchKernelGGL(k_validate_mark, dim3(blocks_for(vthreads, 256)), dim3(256), 0, st,
-                     A->colptr, A->rowidx, m, n, nnz, ridx, hdr);
-  // a2: inspector -- compaction of nonempty rows, blocked layout
-  if ((s = scan_i32(ridx, m, sums, st)) != SK_OK) return s;
-  hipLaunchKernelGGL(k_rowlist, dim3(blocks_for(m, 256)), dim3(256), 0, st, ridx, m, rowlist,
-                     P.m_b, P.nb_max, hdr);
-  // pad the row list so every block reads a full m_b rows
-  hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(256), 0, st,
-                     rowlist + std::min(m, std::max<int64_t>(nnz, 1)), (int64_t)P.m_b + 1, 0);
-  const int64_t nv = P.nv;
-  const int64_t npos = (P.nb_max + 1) * nv;
-  const int64_t nseg = P.nb_max * nv;
-  if (nv != n) {
-    // heavy columns become s_k interleaved virtual columns (entry t of
-    // column k goes to virtual column vbase[k] + t mod s_k)
-    hipLaunchKernelGGL(k_colsplit_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, A->colptr,
-                       n, nnz, nv - n, hdr, vbase);
-    if ((s = scan_i32(vbase, n, sums, st)) != SK_OK) return s;
-    hipLaunchKernelGGL(k_block_pos_v, dim3(blocks_for(npos, 256)), dim3(256), 0, st, A->colptr,
-                       A->rowidx, n, nv, vbase, rowlist, P.m_b, P.nb_max, hdr, pos);
-  } else {
-    hipLaunchKernelGGL(k_block_pos, dim3(blocks_for(npos, 256)), dim3(256), 0, st, A->colptr,
-                       A->rowidx, m, n, rowlist, P.m_b, P.nb_max, hdr, pos);
-  }
-  hipLaunchKernelGGL(k_block_cnt, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, pos, nv,
-                     P.nb_max, hdr, seg);
-  if ((s = scan_i32(seg, nseg, sums, st)) != SK_OK) return s;
-  if (nnz > 0 && nv != n)
-    hipLaunchKernelGGL(k_scatter_v, dim3(blocks_for(nnz, 256)), dim3(256), 0, st, A->colptr,
-                       A->rowidx, A->vals, A->vtype, n, nv, nnz, vbase, ridx, pos, seg, P.m_b,
-                       P.ldS * 4, hdr, ent);
-  else if (nnz > 0)
-    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nnz, 256)), dim3(256), 0, st, A->colptr,
-                       A->rowidx, A->vals, A->vtype, n, nnz, ridx, pos, seg, P.m_b, P.ldS * 4,
-                       hdr, ent);
-  if ((s = launch_ok()) != SK_OK) return s;
-  // a5 (selection): dense row blocks, densified
-  if (P.dense_pct) {
-    hipLaunchKernelGGL(k_dense_select, dim3(1), dim3(256), 0, st, seg, nv, n, P.m_b,
-                       P.dense_pct, (int32_t)P.nd_max, hdr, dflag, dlist, dhdr);
-    hipLaunchKernelGGL(k_fill<float>, dim3(blocks_for(P.nd_max * P.m_b * n, 256 * 16)),
-                       dim3(256), 0, st, dense, P.nd_max * P.m_b * n, 0.0f);
-    hipLaunchKernelGGL(k_densify, dim3(blocks_for(P.nd_max * nv, 256)), dim3(256), 0, st, seg,
-                       ent, nv, n, nv != n ? vbase : nullptr, P.m_b, P.ldS * 4, dlist, dhdr,
-                       dense);
-    if ((s = launch_ok()) != SK_OK) return s;
-  }
+    // a1 + a2: validation and the blocked layout
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, (int32_t*)I.hdr,
+                       (int64_t)(sizeof(Header) / 4), 0);
+    hipLaunchKernelGGL(k_put_item, dim3(1), dim3(64), 0, st, I, d_item);
+    // pad the row list so a block can read past its last row
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(256), 0, st, I.rowlist + P.r_max,
+                       (int64_t)P.m_b + 1, 0);
+    const InspectArrays W{I.ridx, I.rcnt, I.bfl, I.vbase, I.seg, I.bcost, (int32_t*)(w + L.sums)};
+    if ((s = run_inspector(d_item, 1, Z, W, st)) != SK_OK) return s;
+    // a5 (selection): dense row blocks, their rows concatenated and densified
+    if (P.dense_pct) {
+      hipLaunchKernelGGL(k_dense_select, dim3(1), dim3(256), 0, st, I.seg, nv, n, I.bstart,
+                         P.dense_pct, P.kd_max, I.hdr, dflag, dlist, doff, dhdr);
+      hipLaunchKernelGGL(k_dense_zero, dim3(blocks_for(P.kd_max * n, 256 * 16)), dim3(256), 0, st,
+                         dense, n, dhdr);
+      hipLaunchKernelGGL(k_dense_rows, dim3(blocks_for(P.kd_max, 256)), dim3(256), 0, st,
+                         I.rowlist, I.bstart, dlist, doff, dhdr, drows);
+      const int64_t nd_cap = std::max<int64_t>(1, std::min(P.nb_max, P.kd_max));
+      hipLaunchKernelGGL(k_densify, dim3(blocks_for(nd_cap * nv, 256)), dim3(256), 0, st, I.seg,
+                         I.ent, nv, n, I.vbase, P.ldS * 4, dlist, doff, dhdr, dense);
+      if ((s = launch_ok()) != SK_OK) return s;
+    }
+    if ((s = run_block_costs(d_item, 1, Z, W, st)) != SK_OK) return s;
   }
 
   // a3 + a4: S tiles and sparse accumulation
   const Variant& V = kVariants[P.variant];
-  SketchParams K{};
-  K.rowlist = rowlist; K.seg = seg; K.ent = ent; K.hdr = hdr;
+  SketchParams K = make_params(P, I, d, row0, seed);
   K.dflag = P.dense_pct ? dflag : nullptr;
-  K.n = P.nv; K.d = d; K.row0 = row0; K.seed = seed;
-  K.m_b = P.m_b; K.e_max = P.e_max; K.d_b = P.d_b; K.ldS = P.ldS; K.log2_cpr = P.log2_cpr;
-  K.dt = P.dt; K.cg = P.cg; K.tiles = P.tiles; K.splits = P.splits;
-  K.col_per_wg = P.col_per_wg;
-  const bool staged = P.slices > 1 || P.nv != n;  // partials, then the reduction
-  if (staged) { K.out = part; K.ld = d; K.split_stride = d * P.nv; }
+  const bool staged = P.slices > 1 || nv != n;  // partials, then the reduction
+  if (staged) { K.out = part; K.ld = d; K.split_stride = d * nv; }
   else { K.out = Ahat; K.ld = ld; K.split_stride = 0; }
   const int64_t grid = (int64_t)P.tiles * P.ncr * P.splits;
   if (grid >= INT32_MAX) return SK_EUNSUPPORTED;
@@ -511,9 +663,9 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
   // a5: dense row blocks on the matrix cores, into the last partial slice
   if ((phases & 2) && P.dense_pct) {
     DenseParams DP{};
-    DP.rowlist = rowlist; DP.dlist = dlist; DP.dh = dhdr; DP.hdr = hdr; DP.D = dense;
-    DP.n = n; DP.d = d; DP.row0 = row0; DP.seed = seed; DP.m_b = P.m_b;
-    DP.out = part + (int64_t)P.splits * d * P.nv;
+    DP.drows = drows; DP.dh = dhdr; DP.hdr = I.hdr; DP.D = dense;
+    DP.n = n; DP.d = d; DP.row0 = row0; DP.seed = seed;
+    DP.out = part + (int64_t)P.splits * d * nv;
     const int64_t dgrid = ((d + DT_M - 1) / DT_M) * ((n + DT_N - 1) / DT_N);
     if (dgrid >= INT32_MAX) return SK_EUNSUPPORTED;
     if (dist == SK_RADEMACHER)
@@ -524,11 +676,11 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
       hipLaunchKernelGGL(k_dense_mfma<DIST_GAUSSIAN>, dim3((unsigned)dgrid), dim3(256), 0, st, DP);
     if ((s = launch_ok()) != SK_OK) return s;
   }
-  // a6: fixed-order reduction of the partial slices
+  // a6: fixed-order reduction of the partial slices (and virtual columns)
   if ((phases & 4) && staged)
     hipLaunchKernelGGL(k_reduce_virtual, dim3(blocks_for(d * n, 256)), dim3(256), 0, st, part,
-                       P.splits, d, n, P.nv, P.nv != n ? vbase : nullptr,
-                       P.dense_pct ? part + (int64_t)P.splits * d * P.nv : nullptr, Ahat, ld);
+                       P.splits, d, n, nv, I.vbase,
+                       P.dense_pct ? part + (int64_t)P.splits * d * nv : nullptr, Ahat, ld);
   return launch_ok();
 }
 
@@ -544,6 +696,7 @@ sk_status sk_sketch_status(const void* ws, void* hip_stream, int64_t* nonempty_r
   if (h.status & ST_COLPTR) return SK_ECOLPTR;
   if (h.status & ST_RANGE) return SK_ERANGE;
   if (h.status & ST_UNSORTED) return SK_EUNSORTED;
+  if (h.status & ST_CAPACITY) return SK_EUNSUPPORTED;  // block capacity (a planning bound) exceeded
   return SK_OK;
 }
 
@@ -592,47 +745,47 @@ sk_status sk_sketch_batched(int32_t count, const sk_csc* A, const int64_t* d, co
   hipStream_t st = (hipStream_t)hip_stream;
   char* w = (char*)ws;
   Header* hdrs = (Header*)(w + B.hdrs);
-  BatchItem* d_items = (BatchItem*)(w + B.items);
+  Item* d_items = (Item*)(w + B.items);
+  BatchOut* d_outs = (BatchOut*)(w + B.outs);
   int2* d_work = (int2*)(w + B.work);
   int32_t* counters = (int32_t*)(w + B.counters);
-  int32_t* ridx_all = (int32_t*)(w + B.ridx_all);
-  int32_t* seg_all = (int32_t*)(w + B.seg_all);
-  int32_t* sums = (int32_t*)(w + B.sums);
+  const InspectArrays W{(int32_t*)(w + B.ridx_all), (int32_t*)(w + B.rcnt_all),
+                        (int32_t*)(w + B.bfl_all), nullptr, (int32_t*)(w + B.seg_all),
+                        (int32_t*)(w + B.bcost_all), (int32_t*)(w + B.sums)};
   const Variant& V = kVariants[B.variant];
 
   // item descriptors (host), copied to the workspace
-  std::vector<BatchItem> items(count);
-  int64_t o_valid = 0, o_ridx = 0, o_m = 0, o_pos = 0, o_cnt = 0, o_seg = 0, o_nnz = 0, o_out = 0;
+  std::vector<Item> items(count);
+  std::vector<BatchOut> outs(count);
+  InspectSizes Z;
+  int64_t o_ridx = 0, o_m = 0, o_bfl = 0, o_seg = 0, o_blk = 0, o_out = 0;
   for (int i = 0; i < count; ++i) {
     const Plan& P = B.plans[i];
-    BatchItem& I = items[i];
-    std::memset(&I, 0, sizeof I);
-    const int64_t m = A[i].m, n = A[i].n, nnz = A[i].nnz;
-    I.m = m; I.n = n; I.nnz = nnz;
-    I.colptr = A[i].colptr; I.rowidx = A[i].rowidx; I.vals = A[i].vals; I.vtype = A[i].vtype;
-    I.slices = P.slices; I.Ahat = Ahat[i]; I.ld = ld[i]; I.nb_max = P.nb_max;
-    I.ridx = ridx_all + o_ridx;
+    Item& I = items[i];
+    I = make_item(&A[i], P, dist[i]);
+    I.hdr = hdrs + i;
+    I.ridx = W.ridx + o_ridx;  o_ridx += I.m + 1;
+    I.rcnt = W.rcnt + o_m;     o_m += I.m;
+    I.bfl = W.bfl + o_bfl;     o_bfl += I.r_max + 1;
+    I.seg = W.seg + o_seg;     o_seg += I.nb_max * I.nv + 1;
+    I.bcost = W.bcost + o_blk; o_blk += I.nb_max + 1;
+    I.dflag = nullptr;
+    I.rowlist = (int32_t*)(w + B.rowlist[i]);
+    I.rowcnt = (int32_t*)(w + B.rowcnt[i]);
+    I.bstart = (int32_t*)(w + B.bstart[i]);
+    I.vbase = nullptr;
     I.pos = (int32_t*)(w + B.pos[i]);
-    I.seg_region = seg_all + o_seg;
-    I.part = (float*)(w + B.part[i]);
-    I.o_valid = o_valid; o_valid += std::max<int64_t>(nnz, n + 1);
-    I.o_ridx = o_ridx;   o_ridx += m + 1;
-    I.o_m = o_m;         o_m += m;
-    I.o_pos = o_pos;     o_pos += (P.nb_max + 1) * n;
-    I.o_cnt = o_cnt;     o_cnt += P.nb_max * n;
-    I.o_seg = o_seg;     o_seg += P.nb_max * n + 1;
-    I.o_nnz = o_nnz;     o_nnz += nnz;
-    I.o_out = o_out;     if (P.slices > 1) o_out += d[i] * n;
-    SketchParams& K = I.P;
-    K.rowlist = (int32_t*)(w + B.rowlist[i]);
-    K.seg = I.seg_region;
-    K.ent = (uint2*)(w + B.ent[i]);
-    K.hdr = hdrs + i;
-    K.dflag = nullptr;
-    K.n = n; K.d = d[i]; K.row0 = 0; K.seed = seed[i];
-    K.m_b = P.m_b; K.e_max = P.e_max; K.d_b = P.d_b; K.ldS = P.ldS; K.log2_cpr = P.log2_cpr;
-    K.dt = P.dt; K.cg = P.cg; K.tiles = P.tiles; K.splits = P.splits; K.col_per_wg = P.col_per_wg;
-    if (P.slices > 1) { K.out = I.part; K.ld = d[i]; K.split_stride = d[i] * n; }
+    I.ent = (uint2*)(w + B.ent[i]);
+    item_offsets(I, Z);
+    BatchOut& O = outs[i];
+    std::memset(&O, 0, sizeof O);
+    O.slices = P.slices; O.Ahat = Ahat[i]; O.ld = ld[i];
+    O.part = (float*)(w + B.part[i]);
+    O.d = d[i]; O.n = I.n;
+    O.o_out = o_out;  if (P.slices > 1) o_out += d[i] * I.n;
+    SketchParams& K = O.P;
+    K = make_params(P, I, d[i], 0, seed[i]);
+    if (P.slices > 1) { K.out = (float*)O.part; K.ld = d[i]; K.split_stride = d[i] * I.n; }
     else { K.out = Ahat[i]; K.ld = ld[i]; K.split_stride = 0; }
   }
   // work list: grouped by distribution, longest units first (LPT)
@@ -650,7 +803,10 @@ sk_status sk_sketch_batched(int32_t count, const sk_csc* A, const int64_t* d, co
   std::vector<int2> work(std::max<size_t>(units.size(), 1));
   for (size_t k = 0; k < units.size(); ++k) work[k] = make_int2(units[k].item, units[k].unit);
   // host vectors are staged by the runtime before these calls return
-  if (hipMemcpyAsync(d_items, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, st) !=
+  if (hipMemcpyAsync(d_items, items.data(), sizeof(Item) * count, hipMemcpyHostToDevice, st) !=
+      hipSuccess)
+    return SK_EHIP;
+  if (hipMemcpyAsync(d_outs, outs.data(), sizeof(BatchOut) * count, hipMemcpyHostToDevice, st) !=
       hipSuccess)
     return SK_EHIP;
   if (hipMemcpyAsync(d_work, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, st) !=
@@ -660,36 +816,12 @@ sk_status sk_sketch_batched(int32_t count, const sk_csc* A, const int64_t* d, co
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(count * (int64_t)sizeof(Header) / 4, 256)),
                      dim3(256), 0, st, (int32_t*)hdrs, count * (int64_t)sizeof(Header) / 4, 0);
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, counters, int64_t(4), 0);
-  hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(B.t_ridx + 1, 256 * 8)), dim3(256), 0, st,
-                     ridx_all, B.t_ridx + 1, 0);
-  hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(B.t_seg + 1, 256 * 8)), dim3(256), 0, st,
-                     seg_all, B.t_seg + 1, 0);
   // a1 + a2 for every item at once
-  hipLaunchKernelGGL(k_batch_validate_mark, dim3(blocks_for(B.t_valid, 256)), dim3(256), 0, st,
-                     d_items, count, B.t_valid);
-  if ((s = scan_i32(ridx_all, B.t_ridx, sums, st)) != SK_OK) return s;
-  hipLaunchKernelGGL(k_batch_bases, dim3(blocks_for(count, 256)), dim3(256), 0, st, d_items, count,
-                     0);
-  hipLaunchKernelGGL(k_batch_rebase, dim3(blocks_for(B.t_ridx, 256)), dim3(256), 0, st, d_items,
-                     count, B.t_ridx, 0);
-  hipLaunchKernelGGL(k_batch_rowlist, dim3(blocks_for(B.t_m, 256)), dim3(256), 0, st, d_items,
-                     count, B.t_m);
-  hipLaunchKernelGGL(k_batch_block_pos, dim3(blocks_for(B.t_pos, 256)), dim3(256), 0, st, d_items,
-                     count, B.t_pos);
-  hipLaunchKernelGGL(k_batch_block_cnt, dim3(blocks_for(B.t_cnt, 256)), dim3(256), 0, st, d_items,
-                     count, B.t_cnt);
-  if ((s = scan_i32(seg_all, B.t_seg, sums, st)) != SK_OK) return s;
-  hipLaunchKernelGGL(k_batch_bases, dim3(blocks_for(count, 256)), dim3(256), 0, st, d_items, count,
-                     1);
-  hipLaunchKernelGGL(k_batch_rebase, dim3(blocks_for(B.t_seg, 256)), dim3(256), 0, st, d_items,
-                     count, B.t_seg, 1);
-  if (B.t_nnz > 0)
-    hipLaunchKernelGGL(k_batch_scatter, dim3(blocks_for(B.t_nnz, 256)), dim3(256), 0, st, d_items,
-                       count, B.t_nnz);
-  if ((s = launch_ok()) != SK_OK) return s;
+  if ((s = run_inspector(d_items, count, Z, W, st)) != SK_OK) return s;
+  if ((s = run_block_costs(d_items, count, Z, W, st)) != SK_OK) return s;
   // a7: one persistent launch per distribution present
   int cus = 256;
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess) cus = 256;
   int64_t first = 0;
   for (int dd = 0; dd < 3; ++dd) {
     if (B.units[dd] == 0) continue;
@@ -699,14 +831,14 @@ sk_status sk_sketch_batched(int32_t count, const sk_csc* A, const int64_t* d, co
       return SK_EHIP;
     const int per_cu = V.wgs >= 1024 ? 1 : 2;
     const int64_t grid = std::min<int64_t>(B.units[dd], (int64_t)cus * per_cu);
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(V.wgs), B.lds[dd], st, d_items,
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(V.wgs), B.lds[dd], st, d_outs,
                        d_work + first, (int)B.units[dd], counters + dd);
     if ((s = launch_ok()) != SK_OK) return s;
     first += B.units[dd];
   }
   // a6 for every item with split partials
   if (B.t_out > 0)
-    hipLaunchKernelGGL(k_batch_reduce, dim3(blocks_for(B.t_out, 256)), dim3(256), 0, st, d_items,
+    hipLaunchKernelGGL(k_batch_reduce, dim3(blocks_for(B.t_out, 256)), dim3(256), 0, st, d_outs,
                        count, B.t_out);
   return launch_ok();
 }
@@ -745,6 +877,7 @@ sk_status sk_sketch_batched_status(const void* ws, int32_t count, void* hip_stre
     if (h[i].status & ST_COLPTR) si = SK_ECOLPTR;
     else if (h[i].status & ST_RANGE) si = SK_ERANGE;
     else if (h[i].status & ST_UNSORTED) si = SK_EUNSORTED;
+    else if (h[i].status & ST_CAPACITY) si = SK_EUNSUPPORTED;
     statuses[i] = si;
     if (si != SK_OK) worst = si;
   }

@@ -29,17 +29,19 @@ namespace sk {
 
 struct SketchParams {
   const int32_t* rowlist;
+  const int32_t* bstart;  // first nonempty row of each block (nblocks + 1)
   const int32_t* seg;
   const uint2* ent;
   const Header* hdr;
   const int32_t* dflag;  // per block: nonzero when the block runs on the dense path
+  const int32_t* bcost;  // exclusive prefix of the block costs (nblocks + 1)
   int64_t n, d, row0;
   uint64_t seed;
-  int32_t m_b;      // nonempty rows per block
+  int32_t m_b;      // rows per block at most (S-tile capacity)
   int32_t e_max;    // entries staged per pass (even; LDS holds e_max + 2)
   int32_t d_b;      // S rows per tile = dt * Q * DL (power of two)
-  int32_t ldS;      // S tile row stride in floats (d_b + 4: rows start on
-                    // different LDS bank groups)
+  int32_t ldS;      // S tile row stride in floats (d_b plus optional padding,
+                    // a multiple of 4 so rows stay 16-byte aligned)
   int32_t log2_cpr; // log2(d_b / rows per generator chunk)
   int32_t dt;       // S-row subtiles per workgroup
   int32_t cg;       // column groups per subtile
@@ -52,8 +54,7 @@ struct SketchParams {
 };
 
 // ---------------------------------------------------------------- S tile
-// Fill S_lds[l * ldS + t] = S(grow0 + t, rowlist[b*m_b + l]) for l < rb,
-// t < d_b.
+// Fill S_lds[l * ldS + t] = S(grow0 + t, rows[l]) for l < rb, t < d_b.
 template <int DIST, int WGS>
 __device__ __forceinline__ void fill_tile(float* __restrict__ S_lds, const SketchParams& P,
                                           const int32_t* __restrict__ rows, int rb,
@@ -194,17 +195,30 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
   const int status = P.hdr->status;
   if (status == 0) {
     const int64_t nb = P.hdr->nblocks;
-    const int64_t R = P.hdr->nonempty;
-    const int64_t b_lo = nb * split / P.splits;
-    const int64_t b_hi = nb * (split + 1) / P.splits;
+    // this split's blocks: an equal share of the total estimated cost
+    const int64_t T = P.bcost[nb];
+    auto first_at = [&](int64_t x) {  // first b in [0, nb] with bcost[b] >= x
+      int64_t lo = 0, hi = nb;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (P.bcost[mid] < x) lo = mid + 1;
+        else hi = mid;
+      }
+      return lo;
+    };
+    const int64_t b_lo = first_at((split * T + P.splits - 1) / P.splits);
+    const int64_t b_hi =
+        split + 1 == P.splits ? nb : first_at(((split + 1) * T + P.splits - 1) / P.splits);
     // segment bounds of this group's columns in block b: loaded one block
     // ahead so their latency hides behind the previous block's accumulation
     int32_t pbn[CS + 1];
-    int32_t beg_n = 0, end_n = 0, dense_n = 0;
+    int32_t beg_n = 0, end_n = 0, dense_n = 0, r0_n = 0, r1_n = 0;
     auto load_bounds = [&](int64_t b) {
       const int32_t* segb = P.seg + b * P.n;
       beg_n = segb[0];
       end_n = segb[P.n];
+      r0_n = P.bstart[b];
+      r1_n = P.bstart[b + 1];
       dense_n = P.dflag ? P.dflag[b] : 0;
 #pragma unroll
       for (int c = 0; c <= CS; ++c) {
@@ -218,8 +232,8 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
         if (b + 1 < b_hi) load_bounds(b + 1);
         continue;
       }
-      const int64_t rem = R - b * P.m_b;
-      const int rb = (int)(rem < P.m_b ? rem : P.m_b);
+      const int32_t row_beg = r0_n;
+      const int rb = r1_n - r0_n;
       const int32_t blk_beg = beg_n;
       const int32_t blk_end = end_n;
       int32_t pb[CS + 1];
@@ -231,7 +245,7 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
       int32_t s0a = sp & ~1;
       int32_t s1 = (blk_end - s0a < P.e_max) ? blk_end : s0a + P.e_max;
       stage_entries<WGS>(E_lds, P.ent, s0a, s1);
-      fill_tile<DIST, WGS>(S_lds, P, P.rowlist + b * P.m_b, rb, grow0);
+      fill_tile<DIST, WGS>(S_lds, P, P.rowlist + row_beg, rb, grow0);
       bool first_pass = true;
       while (true) {
         __builtin_amdgcn_s_waitcnt(0);

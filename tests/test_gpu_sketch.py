@@ -59,7 +59,7 @@ def test_materialize_bit_exact(B, oracle_lib, dist, row0, d, col0, ncols):
 
 # ------------------------------------------------------------- A_hat
 @pytest.mark.parametrize("dist", DISTS)
-@pytest.mark.parametrize("variant", [0, 1, 4, 5, 6])
+@pytest.mark.parametrize("variant", [0, 1, 4, 5, 6, 8])
 def test_sketch_small_all_variants(B, oracle_lib, dist, variant):
     # several tiles in d, several row blocks, ragged tails everywhere
     m, n, d = 7001, 77, 203
@@ -79,7 +79,8 @@ def test_tiling_independence(B, oracle_lib, dist):
     ref = run_oracle(oracle_lib, A, d, dist, 3)
     outs = []
     for tune in [None, {"rows_per_block": 64, "splits": 3}, {"rows_per_block": 1000, "splits": 1},
-                 {"variant": 6, "splits": 16}, {"variant": 5, "rows_per_block": 31}]:
+                 {"variant": 6, "splits": 16}, {"variant": 5, "rows_per_block": 31},
+                 {"variant": 1, "row_pad": 4}, {"variant": 3, "row_pad": 8, "tile_rows": 64}]:
         print(f"tiling {dist} {tune}", flush=True)
         got = run_gpu(B, A, d, dist, 3, tune=tune)
         norm, col = rel_errors(got, ref)
@@ -268,3 +269,27 @@ def test_heavy_column_split_auto_and_single_column(B, oracle_lib):
         for tune in [None, {"col_split": 1}]:
             norm, col = rel_errors(run_gpu(B, A, d, dist, 2, tune=tune), ref)
             assert norm <= TOL_NORM and col <= TOL_COL, (dist, tune, norm, col)
+
+
+@pytest.mark.parametrize("dist", DISTS)
+def test_row_weight_mix(B, oracle_lib, dist):
+    # a few full rows among light ones: blocks are cut by entry count, a row
+    # heavier than the staging capacity forms a block of its own (several
+    # staging passes), and the dense path takes the full rows
+    m, n, d = 20_000, 1500, 96
+    rng = np.random.default_rng(12)
+    heavy = rng.choice(m, size=30, replace=False)
+    light = np.setdiff1d(np.arange(m), heavy)
+    lr = np.repeat(light, 2)
+    lc = rng.integers(0, n, lr.size)
+    key = np.unique(lc * m + lr)
+    rows = np.concatenate([key % m, np.repeat(heavy, n)])
+    cols = np.concatenate([key // m, np.tile(np.arange(n), heavy.size)])
+    A = inputs.from_coo(m, n, rows, cols, rng.uniform(-1, 1, rows.size).astype(np.float32))
+    ref = run_oracle(oracle_lib, A, d, dist, 17)
+    for tune in [None, {"dense_min_pct": 101}, {"rows_per_block": 1900, "dense_min_pct": 101},
+                 {"rows_per_block": 1900, "dense_min_pct": 30}, {"col_split": 1, "splits": 5}]:
+        print(f"row mix {dist} {tune}", flush=True)
+        got = run_gpu(B, A, d, dist, 17, tune=tune)
+        norm, col = rel_errors(got, ref)
+        assert norm <= TOL_NORM and col <= TOL_COL, (tune, norm, col)

@@ -79,10 +79,10 @@ def test_tuning_variants_all_plan():
     for v in range(1, binding.variant_count() + 1):
         for n in (1, 50, 200, 2000, 5000):
             c = _csc(m=100000, n=n, nnz=10 * n)
-            t = binding.SkTuning(0, 0, v, 0, 0, 0, 0)
+            t = binding.SkTuning(0, 0, v, 0, 0, 0, 0, 0)
             assert lib.sk_sketch_workspace(ctypes.byref(c), 3 * n, 1, 0, ctypes.byref(t),
                                            ctypes.byref(out)) == 0
-    t = binding.SkTuning(0, 0, binding.variant_count() + 1, 0, 0, 0, 0)
+    t = binding.SkTuning(0, 0, binding.variant_count() + 1, 0, 0, 0, 0, 0)
     assert lib.sk_sketch_workspace(ctypes.byref(_csc()), 64, 1, 0, ctypes.byref(t),
                                    ctypes.byref(out)) == -1
 
