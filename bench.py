@@ -30,12 +30,47 @@ VALU_PEAK = 256 * 64 * 2.4e9
 # Philox4x32-10 is 10 rounds of two 32x32->64 multiplies (v_mad_u64_u32, which
 # issues at full rate on gfx950), four xors and the key bumps: about 60 slots
 PHILOX_SLOTS = 60
-UNIFORM_SLOTS = 4       # shift, shift-add, convert, scale per entry
+# transform slots per S entry: uniform = shift, convert, multiply-add; Gaussian
+# = half a Box-Muller pair (logarithm, square root, sine/cosine polynomials)
+TRANSFORM_SLOTS = {"rademacher": 0.0, "uniform": 4.0, "gaussian": 30.0}
 FMA_SLOTS = 1           # one v_fma_f32 per multiply-add (packed FP32 disabled)
+# HBM traffic of the sketch kernel on the default workload, from hardware
+# counters, valid while the kernel sources are the ones it was measured on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sketch_plain_scale_traffic.txt")
+KERNEL_SOURCES = ["paper_2310_15419_amd/csrc/sk_sketch.hpp",
+                  "paper_2310_15419_amd/csrc/sk_rng.hpp"]
 
 
-def valu_work(calls: float, entries: float, fmas: float) -> float:
-    return calls * PHILOX_SLOTS + entries * UNIFORM_SLOTS + fmas * FMA_SLOTS
+def valu_work(dist: str, calls: float, entries: float, fmas: float) -> float:
+    return calls * PHILOX_SLOTS + entries * TRANSFORM_SLOTS[dist] + fmas * FMA_SLOTS
+
+
+def kernel_sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(workload: str):
+    """HBM bytes per launch of the sketch kernel from the committed counter
+    summary, or None when it does not apply (other workload, changed kernel)."""
+    if workload != "plain_scale" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_sources_sha256") != kernel_sources_sha():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def make_workload(name: str):
@@ -151,7 +186,8 @@ def main():
     wall = time.perf_counter() - wall0
     ms = e0.elapsed_time(e1) / args.steps
 
-    # the dominant kernel alone (S tiles + accumulation), same stream, same workspace
+    # the dominant kernel alone (S tiles + sparse accumulation), same stream,
+    # same workspace
     ktune = dict(tune, phases=2)
     k0 = torch.cuda.Event(enable_timing=True)
     k1 = torch.cuda.Event(enable_timing=True)
@@ -167,7 +203,7 @@ def main():
     rpc = 128 if dist == "rademacher" else 4
     calls = R * -(-d // rpc)
     entries = R * d
-    work = valu_work(calls, entries if dist != "rademacher" else 0, nnz * d)
+    work = valu_work(dist, calls, entries, nnz * d)
     achieved = work / (kms * 1e-3)
     value = nnz * d / (ms * 1e-3)
 
@@ -188,7 +224,8 @@ def main():
         "config": {"workload": desc, "nnz": nnz, "d": d, "nonempty_rows": R, "row_blocks": nb},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "TOP/s (full-rate VALU lane-ops)", "frac": achieved / VALU_PEAK,
-                     "traffic": None, "kernel": "k_sketch", "kernel_ms": kms},
+                     "traffic": counter_traffic(args.workload), "kernel": "k_sketch",
+                     "kernel_ms": kms},
         "wall_s_timed": wall,
     }
     if not args.no_cpu_baseline:

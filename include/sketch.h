@@ -83,7 +83,8 @@ typedef struct {
   int32_t dense_min_pct;  /* densify a row block at >= this % density (0 = auto,
                              101 = never)                                      */
   int32_t phases;         /* 0 = all; else a mask of 1 = validate + inspector,
-                             2 = S tiles + accumulation, 4 = split reduction.
+                             2 = S tiles + sparse accumulation, 4 = split
+                             reduction, 8 = dense blocks on the matrix cores.
                              Running a subset reuses the workspace contents of
                              an earlier full call with the same A, d and tuning
                              (used to time one phase in isolation).           */

@@ -589,7 +589,7 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
   if (!ws || ws_bytes < (size_t)L.total) return SK_EWORKSPACE;
   hipStream_t st = (hipStream_t)hip_stream;
   const int64_t n = A->n;
-  const int phases = tune && tune->phases ? tune->phases : 7;
+  const int phases = tune && tune->phases ? tune->phases : 15;
   char* w = (char*)ws;
   Item I = make_item(A, P, dist);
   I.hdr = (Header*)(w + L.hdr);
@@ -661,7 +661,7 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
     if ((s = launch_ok()) != SK_OK) return s;
   }
   // a5: dense row blocks on the matrix cores, into the last partial slice
-  if ((phases & 2) && P.dense_pct) {
+  if ((phases & 8) && P.dense_pct) {
     DenseParams DP{};
     DP.drows = drows; DP.dh = dhdr; DP.hdr = I.hdr; DP.D = dense;
     DP.n = n; DP.d = d; DP.row0 = row0; DP.seed = seed;
