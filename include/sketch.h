@@ -176,6 +176,78 @@ sk_status sk_materialize_s(int64_t row0, int64_t d, int64_t col0, int64_t ncols,
  * log_c[5], sin_c[7], cos_c[8], misc[3] = {ln2_hi, ln2_lo, sqrt2}. */
 void sk_rng_tables(float* log_c, float* sin_c, float* cos_c, float* misc);
 
+/* ------------------------------------------------------------------------
+ * Sketch-and-precondition least squares (paper Sec. V-E): x = argmin ||Ax - b||
+ * for tall A.  The sketch A_hat = S A (d >= n rows, FP32) is widened to FP64
+ * and factored by Householder QR, A_hat = Q R; LSQR then solves
+ * min ||(A R^{-1}) y - b|| and x = R^{-1} y.  The QR, R^{-1} and every LSQR
+ * recurrence run in FP64 on the device.
+ * ------------------------------------------------------------------------ */
+
+/* Householder QR of a d x n FP64 matrix (d >= n >= 1, column-major, lda >= d),
+ * in place: on return the upper triangle of A holds R and the reflectors sit
+ * below the diagonal; R (n x n, upper, zeros below, ldr >= n) is also copied
+ * out.  Blocked (compact WY) right-looking factorisation.  ws: device
+ * workspace of sk_qr_f64_workspace bytes.  Asynchronous on hip_stream. */
+sk_status sk_qr_f64_workspace(int64_t d, int64_t n, size_t* bytes);
+sk_status sk_qr_f64(int64_t d, int64_t n, double* A, int64_t lda, double* R, int64_t ldr,
+                    void* ws, size_t ws_bytes, void* hip_stream);
+
+/* Rinv = R^{-1} for an n x n upper triangular FP64 R with nonzero diagonal
+ * (1 <= n <= 8192; ldr, ldi >= n; device memory).  Asynchronous. */
+sk_status sk_trinv_f64(int64_t n, const double* R, int64_t ldr, double* Rinv, int64_t ldi,
+                       void* hip_stream);
+
+typedef struct {
+  int64_t d;        /* sketch rows, n <= d (the paper uses d = 2n)            */
+  int32_t dist;     /* sk_dist of S                                           */
+  int32_t prec;     /* sk_prec of the sketch                                  */
+  uint64_t seed;
+  double atol;      /* LSQR stopping tolerances (Paige-Saunders' atol, btol,  */
+  double btol;      /* conlim); conlim <= 0 disables the condition test       */
+  double conlim;
+  int32_t iter_lim; /* LSQR iteration limit                                   */
+  int32_t pad;
+} sk_sap_params;
+
+/* Solver info; the first sizeof(sk_sap_info) bytes of an SAP workspace hold it
+ * (device memory) from sk_sap_begin on.  istop follows LSQR's codes: 0 running,
+ * 1 residual small, 2 normal-equation residual small, 3 condition limit,
+ * 4-6 the same at machine precision, 7 iteration limit. */
+typedef struct {
+  int32_t iterations, istop, done, iter_lim;
+  double rnorm;   /* ||b - A x|| estimate               */
+  double arnorm;  /* ||(A R^{-1})^T r|| estimate        */
+  double anorm;   /* ||A R^{-1}||_F estimate            */
+  double acond;   /* cond(A R^{-1}) estimate            */
+  double xnorm;   /* ||y|| estimate                     */
+  double bnorm;
+  double test1, test2, test3;
+} sk_sap_info;
+
+/* Workspace for one solve (device bytes; includes the sketch's workspace, the
+ * FP64 QR, R^{-1}, a row-major copy of A and the LSQR vectors). */
+sk_status sk_sap_workspace(const sk_csc* A, const sk_sap_params* p, size_t* bytes);
+
+/* Enqueue on hip_stream: sketch, widen, QR, R^{-1}, the row-major copy of A,
+ * and LSQR's start from b (device FP64, m entries). */
+sk_status sk_sap_begin(const sk_csc* A, const double* b, const sk_sap_params* p, void* ws,
+                       size_t ws_bytes, void* hip_stream);
+
+/* Enqueue `iters` LSQR iterations (each returns at once after the solve has
+ * stopped, so extra iterations cost only their launches). */
+sk_status sk_sap_iterate(const sk_csc* A, const sk_sap_params* p, int32_t iters, void* ws,
+                         size_t ws_bytes, void* hip_stream);
+
+/* Enqueue x = R^{-1} y (x: device FP64, n entries). */
+sk_status sk_sap_finish(const sk_csc* A, const sk_sap_params* p, double* x, void* ws,
+                        size_t ws_bytes, void* hip_stream);
+
+/* Copy the solver info to the host (synchronises hip_stream); also returns the
+ * sketch's validation status (SK_OK or the input error). */
+sk_status sk_sap_read_info(const sk_csc* A, const sk_sap_params* p, const void* ws,
+                           size_t ws_bytes, void* hip_stream, sk_sap_info* info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,6 +34,23 @@ class SkTuning(ctypes.Structure):
                 ("col_split", ctypes.c_int32), ("row_pad", ctypes.c_int32)]
 
 
+class SapParams(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int64), ("dist", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("atol", ctypes.c_double), ("btol", ctypes.c_double),
+                ("conlim", ctypes.c_double), ("iter_lim", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+class SapInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("istop", ctypes.c_int32),
+                ("done", ctypes.c_int32), ("iter_lim", ctypes.c_int32),
+                ("rnorm", ctypes.c_double), ("arnorm", ctypes.c_double),
+                ("anorm", ctypes.c_double), ("acond", ctypes.c_double),
+                ("xnorm", ctypes.c_double), ("bnorm", ctypes.c_double),
+                ("test1", ctypes.c_double), ("test2", ctypes.c_double),
+                ("test3", ctypes.c_double)]
+
+
 class SketchError(RuntimeError):
     def __init__(self, code: int, what: str):
         super().__init__(f"{what}: {status_string(code)} ({code})")
@@ -70,9 +87,20 @@ def lib():
         L.sk_sketch_batched_status.argtypes = [vp, i32, vp, P(i32)]
         L.sk_rng_tables.argtypes = [vp, vp, vp, vp]
         L.sk_rng_tables.restype = None
+        L.sk_qr_f64_workspace.argtypes = [i64, i64, P(ctypes.c_size_t)]
+        L.sk_qr_f64.argtypes = [i64, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
+        L.sk_trinv_f64.argtypes = [i64, vp, i64, vp, i64, vp]
+        L.sk_sap_workspace.argtypes = [P(SkCsc), P(SapParams), P(ctypes.c_size_t)]
+        L.sk_sap_begin.argtypes = [P(SkCsc), vp, P(SapParams), vp, ctypes.c_size_t, vp]
+        L.sk_sap_iterate.argtypes = [P(SkCsc), P(SapParams), i32, vp, ctypes.c_size_t, vp]
+        L.sk_sap_finish.argtypes = [P(SkCsc), P(SapParams), vp, vp, ctypes.c_size_t, vp]
+        L.sk_sap_read_info.argtypes = [P(SkCsc), P(SapParams), vp, ctypes.c_size_t, vp,
+                                       P(SapInfo)]
         for name in ("sk_sketch_workspace", "sk_sketch", "sk_sketch_status", "sk_materialize_s",
                      "sk_autotune", "sk_sketch_batched_workspace", "sk_sketch_batched",
-                     "sk_sketch_batched_plan", "sk_sketch_batched_status"):
+                     "sk_sketch_batched_plan", "sk_sketch_batched_status", "sk_qr_f64_workspace",
+                     "sk_qr_f64", "sk_trinv_f64", "sk_sap_workspace", "sk_sap_begin",
+                     "sk_sap_iterate", "sk_sap_finish", "sk_sap_read_info"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -269,7 +297,116 @@ class Batch:
         return list(st)
 
 
+def qr_f64(A, stream=None):
+    """Householder QR of a device FP64 tensor holding a d x n column-major matrix
+    (torch shape (n, d)), in place; returns R as a torch (n, n) row-major view of
+    the column-major R (i.e. R = returned.t())."""
+    import torch
+    n, d = A.shape
+    need = ctypes.c_size_t()
+    _check(lib().sk_qr_f64_workspace(d, n, ctypes.byref(need)), "sk_qr_f64_workspace")
+    ws = alloc_workspace(need.value, A.device)
+    R = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    _check(lib().sk_qr_f64(d, n, A.data_ptr(), d, R.data_ptr(), n, ws.data_ptr(), ws.numel(),
+                           _stream(stream)), "sk_qr_f64")
+    return R.t()
+
+
+def trinv_f64(R, stream=None):
+    """Inverse of an upper triangular FP64 matrix given as a torch (n, n) tensor
+    (row-major); returns the inverse in the same convention."""
+    import torch
+    n = R.shape[0]
+    Rc = R.t().contiguous()  # column-major storage
+    out = torch.empty((n, n), dtype=torch.float64, device=R.device)
+    _check(lib().sk_trinv_f64(n, Rc.data_ptr(), n, out.data_ptr(), n, _stream(stream)),
+           "sk_trinv_f64")
+    return out.t()
+
+
+def sap_params(d: int, dist, seed: int, atol: float = 1e-10, btol: float = 1e-10,
+               conlim: float = 1e8, iter_lim: int = 1000, prec: int = PREC_F32) -> SapParams:
+    return SapParams(int(d), _dist(dist), int(prec), int(seed), float(atol), float(btol),
+                     float(conlim), int(iter_lim), 0)
+
+
+class SapSolve:
+    """One sketch-and-precondition least-squares solve on a device workspace.
+
+    begin() enqueues sketch + QR + R^{-1} + LSQR start, iterate(k) enqueues k
+    LSQR iterations, finish() enqueues x = R^{-1} y; all asynchronous on the
+    given stream.  The solver info lives in the first bytes of the workspace."""
+
+    INFO_BYTES = ctypes.sizeof(SapInfo)
+
+    def __init__(self, A: DeviceCsc, b, params: SapParams, ws=None):
+        import torch
+        self.A = A
+        self.c = A.c_struct()
+        self.p = params
+        self.b = b
+        need = ctypes.c_size_t()
+        _check(lib().sk_sap_workspace(ctypes.byref(self.c), ctypes.byref(self.p),
+                                      ctypes.byref(need)), "sk_sap_workspace")
+        self.ws_bytes = int(need.value)
+        self.ws = ws if ws is not None else alloc_workspace(self.ws_bytes, A.colptr.device)
+        self.x = torch.empty(A.n, dtype=torch.float64, device=A.colptr.device)
+
+    @staticmethod
+    def workspace_bytes(A: DeviceCsc, params: SapParams) -> int:
+        need = ctypes.c_size_t()
+        c = A.c_struct()
+        _check(lib().sk_sap_workspace(ctypes.byref(c), ctypes.byref(params), ctypes.byref(need)),
+               "sk_sap_workspace")
+        return int(need.value)
+
+    def begin(self, stream=None):
+        _check(lib().sk_sap_begin(ctypes.byref(self.c), self.b.data_ptr(), ctypes.byref(self.p),
+                                  self.ws.data_ptr(), self.ws_bytes, _stream(stream)),
+               "sk_sap_begin")
+
+    def iterate(self, iters: int, stream=None):
+        _check(lib().sk_sap_iterate(ctypes.byref(self.c), ctypes.byref(self.p), int(iters),
+                                    self.ws.data_ptr(), self.ws_bytes, _stream(stream)),
+               "sk_sap_iterate")
+
+    def finish(self, stream=None):
+        _check(lib().sk_sap_finish(ctypes.byref(self.c), ctypes.byref(self.p), self.x.data_ptr(),
+                                   self.ws.data_ptr(), self.ws_bytes, _stream(stream)),
+               "sk_sap_finish")
+        return self.x
+
+    def info(self, stream=None) -> dict:
+        """Synchronous read of the solver info (and the sketch's input status)."""
+        inf = SapInfo()
+        code = lib().sk_sap_read_info(ctypes.byref(self.c), ctypes.byref(self.p),
+                                      self.ws.data_ptr(), self.ws_bytes, _stream(stream),
+                                      ctypes.byref(inf))
+        out = {f[0]: getattr(inf, f[0]) for f in SapInfo._fields_}
+        out["status"] = int(code)
+        return out
+
+    @staticmethod
+    def parse_info(raw: bytes) -> dict:
+        inf = SapInfo.from_buffer_copy(raw[:ctypes.sizeof(SapInfo)])
+        return {f[0]: getattr(inf, f[0]) for f in SapInfo._fields_}
+
+    def solve(self, chunk: int = 16, stream=None) -> tuple:
+        """Run to completion on one stream (polling between chunks)."""
+        self.begin(stream)
+        while True:
+            self.iterate(chunk, stream)
+            inf = self.info(stream)
+            if inf["status"] != 0:
+                raise SketchError(inf["status"], "sk_sap (sketch input)")
+            if inf["done"]:
+                break
+        return self.finish(stream), inf
+
+
 EXPORTED = ["sk_status_string", "sk_variant_count", "sk_sketch_workspace", "sk_sketch",
             "sk_sketch_status", "sk_materialize_s", "sk_rng_tables", "sk_autotune",
             "sk_sketch_batched_workspace", "sk_sketch_batched", "sk_sketch_batched_plan",
-            "sk_sketch_batched_status"]
+            "sk_sketch_batched_status", "sk_qr_f64_workspace", "sk_qr_f64", "sk_trinv_f64",
+            "sk_sap_workspace", "sk_sap_begin", "sk_sap_iterate", "sk_sap_finish",
+            "sk_sap_read_info"]

@@ -9,12 +9,14 @@
 #include <cmath>
 #include <vector>
 #include <cstdint>
+#include <cstddef>
 #include <cstring>
 
 #include "sk_batch.hpp"
 #include "sk_dense.hpp"
 #include "sk_inspect.hpp"
 #include "sk_rng.hpp"
+#include "sk_sap.hpp"
 #include "sk_sketch.hpp"
 #include "sketch.h"
 
@@ -542,6 +544,112 @@ sk_status batch_plan(int32_t count, const sk_csc* A, const int64_t* d, const int
   B.total = off;
   return SK_OK;
 }
+
+// ------------------------------------------------------------------ SAP
+static_assert(offsetof(LsqrState, rnorm) == offsetof(sk_sap_info, rnorm) &&
+                  offsetof(LsqrState, test3) == offsetof(sk_sap_info, test3) &&
+                  offsetof(LsqrState, itn) == offsetof(sk_sap_info, iterations) &&
+                  offsetof(LsqrState, done) == offsetof(sk_sap_info, done),
+              "solver info prefix");
+
+struct SapLayout {
+  int64_t state, sk_ws, sk_bytes, ahat, q, tau, tq, r, rinv, v64, rcnt, rowptr, cursor, ccol,
+      cval, sums, cbase, cpart, u, partial, v, w, y, tn, sn, t2, total;
+  int64_t nchunk_max, nblk_m;
+};
+
+sk_status sap_layout(const sk_csc* A, const sk_sap_params* p, SapLayout& L) {
+  sk_status s = check_csc(A);
+  if (s != SK_OK) return s;
+  if (!p) return SK_EINVAL;
+  const int64_t m = A->m, n = A->n, nnz = A->nnz, d = p->d;
+  if (n > m || d < n || n > SAP_MAX_N || p->dist < 0 || p->dist > 2 || p->iter_lim < 1)
+    return SK_EINVAL;
+  Plan P;
+  if (!plan_for(m, n, nnz, d, p->dist, nullptr, P)) return SK_EINVAL;
+  const Layout SL = layout_for(m, n, nnz, d, P);
+  int64_t off = 0;
+  L.state = off;   off = align_up(off + (int64_t)sizeof(LsqrState));
+  L.sk_ws = off;   L.sk_bytes = SL.total; off = align_up(off + SL.total);
+  L.ahat = off;    off = align_up(off + 4 * d * n);
+  L.q = off;       off = align_up(off + 8 * d * n);
+  L.tau = off;     off = align_up(off + 8 * n);
+  L.tq = off;      off = align_up(off + 8 * QR_NB * QR_NB);
+  L.r = off;       off = align_up(off + 8 * n * n);
+  L.rinv = off;    off = align_up(off + 8 * n * n);
+  L.v64 = off;     off = align_up(off + 8 * std::max<int64_t>(nnz, 1));
+  L.rcnt = off;    off = align_up(off + 4 * m);
+  L.rowptr = off;  off = align_up(off + 4 * (m + 2));
+  L.cursor = off;  off = align_up(off + 4 * m);
+  L.ccol = off;    off = align_up(off + 4 * std::max<int64_t>(nnz, 1));
+  L.cval = off;    off = align_up(off + 8 * std::max<int64_t>(nnz, 1));
+  L.sums = off;    off = align_up(off + 4 * scan_sums_len(std::max<int64_t>(m + 1, n + 1)));
+  L.nchunk_max = n + nnz / SAP_CHUNK + 1;
+  L.cbase = off;   off = align_up(off + 4 * (n + 2));
+  L.cpart = off;   off = align_up(off + 8 * L.nchunk_max);
+  L.nblk_m = (m + SAP_THREADS - 1) / SAP_THREADS;
+  L.u = off;       off = align_up(off + 8 * m);
+  L.partial = off; off = align_up(off + 8 * L.nblk_m);
+  L.v = off;       off = align_up(off + 8 * n);
+  L.w = off;       off = align_up(off + 8 * n);
+  L.y = off;       off = align_up(off + 8 * n);
+  L.tn = off;      off = align_up(off + 8 * n);
+  L.sn = off;      off = align_up(off + 8 * n);
+  L.t2 = off;      off = align_up(off + 8 * n);
+  L.total = off;
+  return SK_OK;
+}
+
+sk_status qr_launch(int64_t d, int64_t n, double* A, int64_t lda, double* R, int64_t ldr,
+                    double* tau, double* T, hipStream_t st) {
+  for (int64_t j0 = 0; j0 < n; j0 += QR_NB) {
+    const int nb = (int)std::min<int64_t>(QR_NB, n - j0);
+    hipLaunchKernelGGL(k_qr_panel, dim3(1), dim3(SAP_THREADS), 0, st, A, lda, d, j0, nb, tau, T);
+    const int64_t trail = n - j0 - nb;
+    if (trail > 0)
+      hipLaunchKernelGGL(k_qr_update, dim3((unsigned)trail), dim3(SAP_THREADS), 0, st, A, lda, d,
+                         n, j0, nb, T);
+  }
+  hipLaunchKernelGGL(k_qr_extract_r, dim3(blocks_for(n * n, 256)), dim3(256), 0, st, A, lda, n, R,
+                     ldr);
+  return launch_ok();
+}
+
+sk_status trinv_launch(int64_t n, const double* R, int64_t ldr, double* Ri, int64_t ldi,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_trinv_upper, dim3((unsigned)n), dim3(SAP_THREADS), (size_t)(8 * n), st, R,
+                     ldr, n, Ri, ldi);
+  return launch_ok();
+}
+
+// one LSQR iteration's launches (every kernel returns at once after the stop)
+void lsqr_iteration(const sk_csc* A, const SapLayout& L, char* w, hipStream_t st) {
+  const int64_t m = A->m, n = A->n;
+  LsqrState* state = (LsqrState*)(w + L.state);
+  const double* Ri = (const double*)(w + L.rinv);
+  double* v = (double*)(w + L.v);
+  double* tn = (double*)(w + L.tn);
+  double* u = (double*)(w + L.u);
+  double* partial = (double*)(w + L.partial);
+  hipLaunchKernelGGL(k_gemv_upper, dim3(blocks_for(n, 256)), dim3(256), 0, st, Ri, n, n, v, tn,
+                     state);
+  hipLaunchKernelGGL(k_lsqr_av<false>, dim3((unsigned)L.nblk_m), dim3(SAP_THREADS), 0, st,
+                     (const int32_t*)(w + L.rowptr), (const int32_t*)(w + L.ccol),
+                     (const double*)(w + L.cval), m, tn, (const double*)nullptr, u, partial,
+                     state);
+  hipLaunchKernelGGL(k_lsqr_beta<false>, dim3(1), dim3(1024), 0, st, partial, L.nblk_m, state);
+  hipLaunchKernelGGL(k_lsqr_atu, dim3(blocks_for(L.nchunk_max * 64, 256)), dim3(256), 0, st,
+                     A->colptr, A->rowidx, (const double*)(w + L.v64), n,
+                     (const int32_t*)(w + L.cbase), u, (double*)(w + L.cpart), state,
+                     (const Header*)(w + L.sk_ws));
+  hipLaunchKernelGGL(k_lsqr_colsum, dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                     (const int32_t*)(w + L.cbase), n, (const double*)(w + L.cpart),
+                     (double*)(w + L.sn), state);
+  hipLaunchKernelGGL(k_gemv_upper_t, dim3(blocks_for(n * 64, 256)), dim3(256), 0, st, Ri, n, n,
+                     (const double*)(w + L.sn), (double*)(w + L.t2), state);
+  hipLaunchKernelGGL(k_lsqr_update<false>, dim3(1), dim3(1024), 0, st, n,
+                     (const double*)(w + L.t2), v, (double*)(w + L.w), (double*)(w + L.y), state);
+}
 }  // namespace
 
 extern "C" {
@@ -899,6 +1007,153 @@ sk_status sk_autotune(const sk_csc* A, int64_t d, int32_t dist, sk_tuning* out) 
   out->tile_rows = P.d_b;
   out->col_split = P.nv != A->n ? 2 : 1;
   return SK_OK;
+}
+
+// ------------------------------------------------------------------ SAP
+sk_status sk_qr_f64_workspace(int64_t d, int64_t n, size_t* bytes) {
+  if (!bytes || n < 1 || d < n) return SK_EINVAL;
+  *bytes = (size_t)(align_up(8 * n) + 8 * QR_NB * QR_NB);
+  return SK_OK;
+}
+
+sk_status sk_qr_f64(int64_t d, int64_t n, double* A, int64_t lda, double* R, int64_t ldr,
+                    void* ws, size_t ws_bytes, void* hip_stream) {
+  if (n < 1 || d < n || !A || lda < d || !R || ldr < n) return SK_EINVAL;
+  size_t need = 0;
+  sk_qr_f64_workspace(d, n, &need);
+  if (!ws || ws_bytes < need) return SK_EWORKSPACE;
+  double* tau = (double*)ws;
+  double* T = (double*)((char*)ws + align_up(8 * n));
+  return qr_launch(d, n, A, lda, R, ldr, tau, T, (hipStream_t)hip_stream);
+}
+
+sk_status sk_trinv_f64(int64_t n, const double* R, int64_t ldr, double* Rinv, int64_t ldi,
+                       void* hip_stream) {
+  if (n < 1 || n > SAP_MAX_N || !R || !Rinv || ldr < n || ldi < n) return SK_EINVAL;
+  return trinv_launch(n, R, ldr, Rinv, ldi, (hipStream_t)hip_stream);
+}
+
+sk_status sk_sap_workspace(const sk_csc* A, const sk_sap_params* p, size_t* bytes) {
+  if (!bytes) return SK_EINVAL;
+  SapLayout L;
+  sk_status s = sap_layout(A, p, L);
+  if (s != SK_OK) return s;
+  *bytes = (size_t)L.total;
+  return SK_OK;
+}
+
+sk_status sk_sap_begin(const sk_csc* A, const double* b, const sk_sap_params* p, void* ws,
+                       size_t ws_bytes, void* hip_stream) {
+  SapLayout L;
+  sk_status s = sap_layout(A, p, L);
+  if (s != SK_OK) return s;
+  if (!b) return SK_EINVAL;
+  if (!ws || ws_bytes < (size_t)L.total) return SK_EWORKSPACE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  char* w = (char*)ws;
+  const int64_t m = A->m, n = A->n, nnz = A->nnz, d = p->d;
+  LsqrState* state = (LsqrState*)(w + L.state);
+  const double ctol = p->conlim > 0.0 ? 1.0 / p->conlim : 0.0;
+  hipLaunchKernelGGL(k_lsqr_set, dim3(1), dim3(64), 0, st, state, p->atol, p->btol, ctol,
+                     p->iter_lim);
+  // the sketch (FP32), widened to FP64
+  float* ahat = (float*)(w + L.ahat);
+  if ((s = sk_sketch(A, 0, d, p->dist, p->seed, p->prec, nullptr, ahat, d, w + L.sk_ws,
+                     (size_t)L.sk_bytes, hip_stream)) != SK_OK)
+    return s;
+  double* q = (double*)(w + L.q);
+  hipLaunchKernelGGL(k_widen, dim3(blocks_for(d * n, 256)), dim3(256), 0, st, ahat, d, d, n, q, d);
+  // R and R^{-1}
+  double* R = (double*)(w + L.r);
+  double* Ri = (double*)(w + L.rinv);
+  if ((s = qr_launch(d, n, q, d, R, n, (double*)(w + L.tau), (double*)(w + L.tq), st)) != SK_OK)
+    return s;
+  if ((s = trinv_launch(n, R, n, Ri, n, st)) != SK_OK) return s;
+  // FP64 values, row counts, row-major copy (only of input the sketch's
+  // validation passed: its header sits at the start of its workspace)
+  const Header* skh = (const Header*)(w + L.sk_ws);
+  int32_t* rcnt = (int32_t*)(w + L.rcnt);
+  int32_t* rowptr = (int32_t*)(w + L.rowptr);
+  int32_t* cursor = (int32_t*)(w + L.cursor);
+  double* v64 = (double*)(w + L.v64);
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(m, 256 * 8)), dim3(256), 0, st, rcnt, m, 0);
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_csc_f64_count, dim3(blocks_for(nnz, 256)), dim3(256), 0, st, A->rowidx,
+                       A->vals, A->vtype, nnz, v64, rcnt, skh);
+  hipLaunchKernelGGL(k_copy_i32, dim3(blocks_for(m, 256)), dim3(256), 0, st, rcnt, m, rowptr);
+  if ((s = scan_i32(rowptr, m, (int32_t*)(w + L.sums), st)) != SK_OK) return s;
+  hipLaunchKernelGGL(k_copy_i32, dim3(blocks_for(m, 256)), dim3(256), 0, st, rowptr, m, cursor);
+  if (nnz > 0) {
+    hipLaunchKernelGGL(k_csr_scatter, dim3(blocks_for(nnz, 256)), dim3(256), 0, st, A->colptr,
+                       A->rowidx, v64, n, nnz, cursor, (int32_t*)(w + L.ccol),
+                       (double*)(w + L.cval), skh);
+    hipLaunchKernelGGL(k_csr_sort_rows, dim3(blocks_for(m, 256)), dim3(256), 0, st, rowptr, m,
+                       (int32_t*)(w + L.ccol), (double*)(w + L.cval));
+  }
+  int32_t* cbase = (int32_t*)(w + L.cbase);
+  hipLaunchKernelGGL(k_col_chunks, dim3(blocks_for(n, 256)), dim3(256), 0, st, A->colptr, n, cbase,
+                     skh);
+  if ((s = scan_i32(cbase, n, (int32_t*)(w + L.sums), st)) != SK_OK) return s;
+  // LSQR start: beta u = b, alpha v = (A R^{-1})^T u, w = v, y = 0
+  double* u = (double*)(w + L.u);
+  double* partial = (double*)(w + L.partial);
+  hipLaunchKernelGGL(k_lsqr_av<true>, dim3((unsigned)L.nblk_m), dim3(SAP_THREADS), 0, st,
+                     (const int32_t*)nullptr, (const int32_t*)nullptr, (const double*)nullptr, m,
+                     (const double*)nullptr, b, u, partial, state);
+  hipLaunchKernelGGL(k_lsqr_beta<true>, dim3(1), dim3(1024), 0, st, partial, L.nblk_m, state);
+  hipLaunchKernelGGL(k_lsqr_atu, dim3(blocks_for(L.nchunk_max * 64, 256)), dim3(256), 0, st,
+                     A->colptr, A->rowidx, (const double*)v64, n, (const int32_t*)cbase, u,
+                     (double*)(w + L.cpart), state, skh);
+  hipLaunchKernelGGL(k_lsqr_colsum, dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                     (const int32_t*)cbase, n, (const double*)(w + L.cpart), (double*)(w + L.sn),
+                     state);
+  hipLaunchKernelGGL(k_gemv_upper_t, dim3(blocks_for(n * 64, 256)), dim3(256), 0, st,
+                     (const double*)Ri, n, n, (const double*)(w + L.sn), (double*)(w + L.t2),
+                     state);
+  hipLaunchKernelGGL(k_lsqr_update<true>, dim3(1), dim3(1024), 0, st, n,
+                     (const double*)(w + L.t2), (double*)(w + L.v), (double*)(w + L.w),
+                     (double*)(w + L.y), state);
+  return launch_ok();
+}
+
+sk_status sk_sap_iterate(const sk_csc* A, const sk_sap_params* p, int32_t iters, void* ws,
+                         size_t ws_bytes, void* hip_stream) {
+  SapLayout L;
+  sk_status s = sap_layout(A, p, L);
+  if (s != SK_OK) return s;
+  if (iters < 0) return SK_EINVAL;
+  if (!ws || ws_bytes < (size_t)L.total) return SK_EWORKSPACE;
+  for (int32_t k = 0; k < iters; ++k) lsqr_iteration(A, L, (char*)ws, (hipStream_t)hip_stream);
+  return launch_ok();
+}
+
+sk_status sk_sap_finish(const sk_csc* A, const sk_sap_params* p, double* x, void* ws,
+                        size_t ws_bytes, void* hip_stream) {
+  SapLayout L;
+  sk_status s = sap_layout(A, p, L);
+  if (s != SK_OK) return s;
+  if (!x) return SK_EINVAL;
+  if (!ws || ws_bytes < (size_t)L.total) return SK_EWORKSPACE;
+  char* w = (char*)ws;
+  const int64_t n = A->n;
+  hipLaunchKernelGGL(k_gemv_upper_final, dim3(blocks_for(n, 256)), dim3(256), 0,
+                     (hipStream_t)hip_stream, (const double*)(w + L.rinv), n, n,
+                     (const double*)(w + L.y), x);
+  return launch_ok();
+}
+
+sk_status sk_sap_read_info(const sk_csc* A, const sk_sap_params* p, const void* ws,
+                           size_t ws_bytes, void* hip_stream, sk_sap_info* info) {
+  SapLayout L;
+  sk_status s = sap_layout(A, p, L);
+  if (s != SK_OK) return s;
+  if (!info) return SK_EINVAL;
+  if (!ws || ws_bytes < (size_t)L.total) return SK_EWORKSPACE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (hipMemcpyAsync(info, (const char*)ws + L.state, sizeof *info, hipMemcpyDeviceToHost, st) !=
+      hipSuccess)
+    return SK_EHIP;
+  return sk_sketch_status((const char*)ws + L.sk_ws, hip_stream, nullptr, nullptr);
 }
 
 void sk_rng_tables(float* log_c, float* sin_c, float* cos_c, float* misc) {

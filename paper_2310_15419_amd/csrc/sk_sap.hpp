@@ -1,0 +1,565 @@
+// sk_sap.hpp -- device kernels of the sketch-and-precondition least-squares
+// solve (paper Sec. V-E): QR of the sketch A_hat = S A gives R, and LSQR runs
+// on the preconditioned operator A R^{-1}; x = R^{-1} y.  Everything is FP64
+// (the sketch itself is accumulated in FP32 and widened), since the
+// orthogonalisation and the Krylov recurrences need the precision.
+//
+//   QR      blocked Householder, panels of QR_NB columns: one workgroup
+//           factors a panel (reflectors stored below the diagonal as in
+//           LAPACK, plus the triangular factor T of the compact WY form
+//           I - V T V^T), then every trailing column gets
+//           C <- C - V T^T (V^T C) from its own workgroup.
+//   R^{-1}  upper triangular inverse, one workgroup per column (column-
+//           oriented back substitution); LSQR then applies R^{-1} and R^{-T}
+//           as plain matrix-vector products.
+//   CSR     a row-major copy of A for A z (deterministic: counts, scan,
+//           scatter, then each row sorted by column), and FP64 values of the
+//           CSC for A^T u, whose heavy columns are cut into chunks summed in
+//           a fixed order.
+//   LSQR    the recurrences of Paige and Saunders' LSQR (the same quantities
+//           and stopping tests as their published algorithm) with all
+//           scalars on the device; every kernel returns at once after the
+//           solve has stopped, so the host can enqueue iterations in chunks
+//           and poll.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sk_inspect.hpp"
+
+namespace sk {
+
+constexpr int QR_NB = 16;          // panel width
+constexpr int SAP_THREADS = 256;
+constexpr int SAP_CHUNK = 2048;    // entries per A^T u chunk
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;  // lane 0 holds the sum
+}
+
+// sum over the workgroup (blockDim.x a multiple of 64, <= 1024); every
+// thread gets the result.  sh: 16 doubles.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += sh[w];  // fixed order
+  return s;
+}
+
+__global__ void k_copy_i32(const int32_t* __restrict__ src, int64_t count, int32_t* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = src[i];
+}
+
+// FP32 sketch (d x n, ld) -> FP64 (d x n, ldq)
+__global__ void k_widen(const float* __restrict__ src, int64_t ld, int64_t d, int64_t n,
+                        double* __restrict__ dst, int64_t ldq) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= d * n) return;
+  const int64_t j = t / d, i = t - j * d;
+  dst[i + j * ldq] = (double)src[i + j * ld];
+}
+
+// ------------------------------------------------------------------- QR
+// Factor columns [j0, j0 + nb) of A (d x n, column-major, lda), rows >= j0.
+// Reflector k (global column c = j0 + k): H = I - tau v v^T with v[c] = 1 and
+// v[r] (r > c) stored in A[r, c]; A[c, c] becomes beta.  T (ldt = QR_NB) is
+// the upper triangular factor with H_0 ... H_{nb-1} = I - V T V^T.
+// One workgroup; partial dot products of the panel columns in registers.
+__global__ __launch_bounds__(SAP_THREADS) void k_qr_panel(double* __restrict__ A, int64_t lda,
+                                                           int64_t d, int64_t j0, int nb,
+                                                           double* __restrict__ tau,
+                                                           double* __restrict__ T) {
+  __shared__ double sh[16];
+  __shared__ double s_dot[QR_NB][SAP_THREADS / 64];
+  __shared__ double s_w[QR_NB];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int k = 0; k < nb; ++k) {
+    const int64_t c = j0 + k;
+    double* col = A + c * lda;
+    // ||A[c+1:, c]||^2
+    double ss = 0.0;
+    for (int64_t r = c + 1 + tid; r < d; r += SAP_THREADS) ss += col[r] * col[r];
+    const double sigma = block_sum(ss, sh);
+    const double alpha = col[c];
+    double t_k, beta, scale;
+    if (sigma == 0.0) {
+      t_k = 0.0;
+      beta = alpha;
+      scale = 0.0;
+    } else {
+      const double nrm = sqrt(alpha * alpha + sigma);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      t_k = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    // v below the diagonal
+    for (int64_t r = c + 1 + tid; r < d; r += SAP_THREADS) col[r] *= scale;
+    __syncthreads();
+    if (tid == 0) {
+      col[c] = beta;
+      tau[c] = t_k;
+    }
+    // dots of v with every other panel column: j < k gives V_j^T v (for T),
+    // j > k gives v^T A[:, j] (for the update)
+    double part[QR_NB];
+#pragma unroll
+    for (int j = 0; j < QR_NB; ++j) part[j] = 0.0;
+    for (int64_t r = c + 1 + tid; r < d; r += SAP_THREADS) {
+      const double vr = col[r];
+#pragma unroll
+      for (int j = 0; j < QR_NB; ++j)
+        if (j < nb && j != k) part[j] += A[r + (j0 + j) * lda] * vr;
+    }
+#pragma unroll
+    for (int j = 0; j < QR_NB; ++j) {
+      const double s = wave_sum(part[j]);
+      if (lane == 0) s_dot[j][wave] = s;
+    }
+    __syncthreads();
+    if (tid < nb && tid != k) {
+      double s = 0.0;
+      for (int w = 0; w < SAP_THREADS / 64; ++w) s += s_dot[tid][w];
+      // the row-c term: v[c] = 1
+      s_w[tid] = s + A[c + (j0 + tid) * lda];
+    }
+    __syncthreads();
+    // apply H to the panel columns right of c
+    for (int j = k + 1; j < nb; ++j) {
+      const double wj = t_k * s_w[j];
+      double* cj = A + (j0 + j) * lda;
+      for (int64_t r = c + 1 + tid; r < d; r += SAP_THREADS) cj[r] -= wj * col[r];
+      if (tid == 0) cj[c] -= wj;
+    }
+    // T[0:k, k] = -tau_k T[0:k, 0:k] z, z_j = V_j^T v (j < k); T[k, k] = tau_k
+    if (tid == 0) {
+      for (int i = 0; i < k; ++i) {
+        double s = 0.0;
+        for (int j = i; j < k; ++j) s += T[i + j * QR_NB] * s_w[j];
+        T[i + k * QR_NB] = -t_k * s;
+      }
+      T[k + k * QR_NB] = t_k;
+      for (int i = k + 1; i < QR_NB; ++i) T[i + k * QR_NB] = 0.0;
+    }
+    __syncthreads();
+  }
+}
+
+// C <- C - V T^T (V^T C) for the trailing columns j >= j0 + nb, rows >= j0;
+// one workgroup per trailing column.
+__global__ __launch_bounds__(SAP_THREADS) void k_qr_update(double* __restrict__ A, int64_t lda,
+                                                            int64_t d, int64_t n, int64_t j0,
+                                                            int nb, const double* __restrict__ T) {
+  __shared__ double s_dot[QR_NB][SAP_THREADS / 64];
+  __shared__ double s_w[QR_NB];
+  __shared__ double s_w2[QR_NB];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t j = j0 + nb + blockIdx.x;
+  if (j >= n) return;
+  double* cj = A + j * lda;
+  // W = V^T C[:, j]; V_i has 1 at row j0 + i, zeros above, A[r, j0 + i] below
+  double part[QR_NB];
+#pragma unroll
+  for (int i = 0; i < QR_NB; ++i) part[i] = 0.0;
+  for (int64_t r = j0 + tid; r < d; r += SAP_THREADS) {
+    const double cr = cj[r];
+#pragma unroll
+    for (int i = 0; i < QR_NB; ++i) {
+      if (i < nb) {
+        const int64_t ri = j0 + i;
+        const double vi = r > ri ? A[r + ri * lda] : (r == ri ? 1.0 : 0.0);
+        part[i] += vi * cr;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < QR_NB; ++i) {
+    const double s = wave_sum(part[i]);
+    if (lane == 0) s_dot[i][wave] = s;
+  }
+  __syncthreads();
+  if (tid < nb) {
+    double s = 0.0;
+    for (int w = 0; w < SAP_THREADS / 64; ++w) s += s_dot[tid][w];
+    s_w[tid] = s;
+  }
+  __syncthreads();
+  // W2 = T^T W
+  if (tid < nb) {
+    double s = 0.0;
+    for (int i = 0; i <= tid; ++i) s += T[i + tid * QR_NB] * s_w[i];
+    s_w2[tid] = s;
+  }
+  __syncthreads();
+  // C -= V W2
+  for (int64_t r = j0 + tid; r < d; r += SAP_THREADS) {
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) {
+      const int64_t ri = j0 + i;
+      if (r < ri) break;
+      const double vi = r > ri ? A[r + ri * lda] : 1.0;
+      s += vi * s_w2[i];
+    }
+    cj[r] -= s;
+  }
+}
+
+// R (n x n, ldr) = upper triangle of the factored A
+__global__ void k_qr_extract_r(const double* __restrict__ A, int64_t lda, int64_t n,
+                               double* __restrict__ R, int64_t ldr) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n) return;
+  const int64_t j = t / n, i = t - j * n;
+  R[i + j * ldr] = i <= j ? A[i + j * lda] : 0.0;
+}
+
+// Rinv = R^{-1} (upper triangular); one workgroup per column j: solve
+// R x = e_j by column-oriented back substitution with the right-hand side
+// in LDS (n <= SAP_MAX_N).
+constexpr int SAP_MAX_N = 8192;
+__global__ __launch_bounds__(SAP_THREADS) void k_trinv_upper(const double* __restrict__ R,
+                                                              int64_t ldr, int64_t n,
+                                                              double* __restrict__ Ri,
+                                                              int64_t ldi) {
+  extern __shared__ double rhs[];  // n doubles
+  const int tid = threadIdx.x;
+  const int64_t j = blockIdx.x;
+  if (j >= n) return;
+  for (int64_t i = tid; i < n; i += SAP_THREADS) rhs[i] = i == j ? 1.0 : 0.0;
+  __syncthreads();
+  for (int64_t i = j; i >= 0; --i) {
+    const double xi = rhs[i] / R[i + i * ldr];
+    __syncthreads();  // every thread has read rhs[i]
+    if (tid == 0) rhs[i] = xi;
+    const double* ci = R + i * ldr;
+    for (int64_t r = tid; r < i; r += SAP_THREADS) rhs[r] -= xi * ci[r];
+    __syncthreads();
+  }
+  double* out = Ri + j * ldi;
+  for (int64_t i = tid; i < n; i += SAP_THREADS) out[i] = i <= j ? rhs[i] : 0.0;
+}
+
+// ------------------------------------------------------------- A copies
+// The kernels that index by A's structure run only on input the sketch's
+// validation passed (hdr: the sketch's header, final by then on the stream).
+
+// FP64 values of the CSC, and per-row entry counts (rcnt zeroed before)
+__global__ void k_csc_f64_count(const int32_t* __restrict__ rowidx, const void* __restrict__ vals,
+                                int vtype, int64_t nnz, double* __restrict__ v64,
+                                int32_t* __restrict__ rcnt, const Header* __restrict__ hdr) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz || hdr->status) return;
+  double a;
+  if (vtype == 0) a = ((const double*)vals)[p];
+  else if (vtype == 1) a = (double)((const float*)vals)[p];
+  else a = (double)__uint_as_float((uint32_t)((const uint16_t*)vals)[p] << 16);
+  v64[p] = a;
+  atomicAdd(&rcnt[rowidx[p]], 1);
+}
+
+// scatter into CSR rows (cursor = copy of rowptr); order inside a row is
+// fixed afterwards by k_csr_sort_rows
+__global__ void k_csr_scatter(const int64_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
+                              const double* __restrict__ v64, int64_t n, int64_t nnz,
+                              int32_t* __restrict__ cursor, int32_t* __restrict__ ccol,
+                              double* __restrict__ cval, const Header* __restrict__ hdr) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz || hdr->status) return;
+  int64_t lo = 0, hi = n - 1;  // column of p
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (colptr[mid] <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  const int32_t q = atomicAdd(&cursor[rowidx[p]], 1);
+  ccol[q] = (int32_t)lo;
+  cval[q] = v64[p];
+}
+
+// sort each CSR row by column (insertion sort; rows are short, columns unique)
+__global__ void k_csr_sort_rows(const int32_t* __restrict__ rowptr, int64_t m,
+                                int32_t* __restrict__ ccol, double* __restrict__ cval) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= m) return;
+  const int32_t a = rowptr[r], b = rowptr[r + 1];
+  for (int32_t i = a + 1; i < b; ++i) {
+    const int32_t c = ccol[i];
+    const double v = cval[i];
+    int32_t k = i - 1;
+    while (k >= a && ccol[k] > c) {
+      ccol[k + 1] = ccol[k];
+      cval[k + 1] = cval[k];
+      --k;
+    }
+    ccol[k + 1] = c;
+    cval[k + 1] = v;
+  }
+}
+
+// chunks of at most SAP_CHUNK entries per column: cbase[k] = chunks of k
+// (scanned afterwards)
+__global__ void k_col_chunks(const int64_t* __restrict__ colptr, int64_t n,
+                             int32_t* __restrict__ cbase, const Header* __restrict__ hdr) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t c = hdr->status ? 0 : colptr[k + 1] - colptr[k];
+  cbase[k] = (int32_t)(c > 0 ? (c + SAP_CHUNK - 1) / SAP_CHUNK : 1);
+}
+
+// ------------------------------------------------------------------ LSQR
+// The first fields are the public solver info (sk_sap_info in the C header,
+// same layout); the rest is private.
+struct LsqrState {
+  int32_t itn, istop, done, iter_lim;
+  double rnorm, arnorm, anorm, acond, xnorm, bnorm, test1, test2, test3;
+  // private
+  double alpha, beta, rhobar, phibar;
+  double ddnorm, res2, xxnorm, z, cs2, sn2;
+  double atol, btol, ctol;
+  double pad[3];
+};
+
+// t = Rinv v (upper triangular, column-major): one thread per row
+__global__ void k_gemv_upper(const double* __restrict__ Ri, int64_t ldi, int64_t n,
+                             const double* __restrict__ v, double* __restrict__ t,
+                             const LsqrState* __restrict__ st) {
+  if (st->done) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int64_t j = i; j < n; ++j) s += Ri[i + j * ldi] * v[j];
+  t[i] = s;
+}
+
+// t = Rinv^T s: one wave per column j (t[j] = sum_{i <= j} Ri[i, j] s[i])
+__global__ void k_gemv_upper_t(const double* __restrict__ Ri, int64_t ldi, int64_t n,
+                               const double* __restrict__ s, double* __restrict__ t,
+                               const LsqrState* __restrict__ st) {
+  if (st->done) return;
+  const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (j >= n) return;
+  double acc = 0.0;
+  for (int64_t i = lane; i <= j; i += 64) acc += Ri[i + j * ldi] * s[i];
+  acc = wave_sum(acc);
+  if (lane == 0) t[j] = acc;
+}
+
+// u is kept unnormalised (the normalised vector is u / beta):
+// u <- A z - alpha (u / beta), or u <- b at the start; partial sums of u^2
+// per workgroup
+template <bool INIT>
+__global__ __launch_bounds__(SAP_THREADS) void k_lsqr_av(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ ccol,
+    const double* __restrict__ cval, int64_t m, const double* __restrict__ z,
+    const double* __restrict__ b, double* __restrict__ u, double* __restrict__ partial,
+    const LsqrState* __restrict__ st) {
+  __shared__ double sh[16];
+  if (st->done) return;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double val = 0.0;
+  if (r < m) {
+    if (INIT) {
+      val = b[r];
+    } else {
+      double s = 0.0;
+      for (int32_t p = rowptr[r]; p < rowptr[r + 1]; ++p) s += cval[p] * z[ccol[p]];
+      const double beta = st->beta;
+      val = s - st->alpha * (beta > 0.0 ? u[r] / beta : 0.0);
+    }
+    u[r] = val;
+  }
+  const double tot = block_sum(val * val, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// beta = sqrt(sum of partials) (fixed order), one workgroup
+template <bool INIT>
+__global__ __launch_bounds__(1024) void k_lsqr_beta(const double* __restrict__ partial,
+                                                     int64_t np, LsqrState* __restrict__ st) {
+  __shared__ double sh[16];
+  if (st->done) return;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < np; i += blockDim.x) s += partial[i];
+  const double tot = block_sum(s, sh);
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(tot);
+    st->beta = beta;
+    if (INIT) st->bnorm = beta;
+  }
+}
+
+// chunk sums of A^T (u / beta): chunk q of column k covers entries
+// [colptr[k] + q SAP_CHUNK, ...); one wave per chunk
+__global__ void k_lsqr_atu(const int64_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
+                           const double* __restrict__ v64, int64_t n,
+                           const int32_t* __restrict__ cbase, const double* __restrict__ u,
+                           double* __restrict__ cpart, const LsqrState* __restrict__ st,
+                           const Header* __restrict__ hdr) {
+  if (st->done) return;
+  const bool valid = hdr->status == 0;
+  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (g >= cbase[n]) return;
+  int64_t lo = 0, hi = n - 1;  // column of chunk g
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (cbase[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t k = lo;
+  const int64_t p0 = colptr[k] + (g - cbase[k]) * SAP_CHUNK;
+  const int64_t p1 = p0 + SAP_CHUNK < colptr[k + 1] ? p0 + SAP_CHUNK : colptr[k + 1];
+  double acc = 0.0;
+  if (valid)
+    for (int64_t p = p0 + lane; p < p1; p += 64) acc += v64[p] * u[rowidx[p]];
+  acc = wave_sum(acc);
+  if (lane == 0) cpart[g] = acc / (st->beta > 0.0 ? st->beta : 1.0);
+}
+
+// s[k] = sum of k's chunk sums (in order)
+__global__ void k_lsqr_colsum(const int32_t* __restrict__ cbase, int64_t n,
+                              const double* __restrict__ cpart, double* __restrict__ s,
+                              const LsqrState* __restrict__ st) {
+  if (st->done) return;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double acc = 0.0;
+  for (int32_t g = cbase[k]; g < cbase[k + 1]; ++g) acc += cpart[g];
+  s[k] = acc;
+}
+
+// One workgroup: v' = t - beta v (t = R^{-T} A^T u), alpha = ||v'||, v = v'/alpha,
+// then the LSQR scalar recurrences and the updates of x and w.  INIT: the
+// start of the iteration (v' = t, w = v, x = 0).
+template <bool INIT>
+__global__ __launch_bounds__(1024) void k_lsqr_update(int64_t n, const double* __restrict__ t,
+                                                       double* __restrict__ v,
+                                                       double* __restrict__ w,
+                                                       double* __restrict__ x,
+                                                       LsqrState* __restrict__ st) {
+  __shared__ double sh[16];
+  if (st->done) return;
+  const double beta = st->beta;
+  double ss = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double vi = INIT ? t[i] : t[i] - beta * v[i];
+    v[i] = vi;
+    ss += vi * vi;
+  }
+  const double alpha = sqrt(block_sum(ss, sh));
+  const double inv_a = alpha > 0.0 ? 1.0 / alpha : 0.0;
+  if (INIT) {
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const double vi = v[i] * inv_a;
+      v[i] = vi;
+      w[i] = vi;
+      x[i] = 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      st->alpha = alpha;
+      st->rhobar = alpha;
+      st->phibar = st->beta;
+      st->rnorm = st->beta;
+      st->arnorm = alpha * st->beta;
+      st->anorm = 0.0; st->acond = 0.0; st->ddnorm = 0.0; st->res2 = 0.0;
+      st->xnorm = 0.0; st->xxnorm = 0.0; st->z = 0.0; st->cs2 = -1.0; st->sn2 = 0.0;
+      st->itn = 0;
+      st->istop = 0;
+      if (st->arnorm == 0.0) st->done = 1;
+    }
+    return;
+  }
+  // scalar recurrences (every thread computes them; thread 0 stores)
+  const double anorm = sqrt(st->anorm * st->anorm + st->alpha * st->alpha + beta * beta);
+  const double rhobar1 = st->rhobar;
+  const double phibar0 = st->phibar;
+  const double rho = sqrt(rhobar1 * rhobar1 + beta * beta);
+  const double cs = rhobar1 / rho, sn = beta / rho;
+  const double theta = sn * alpha;
+  const double rhobar = -cs * alpha;
+  const double phi = cs * phibar0;
+  const double phibar = sn * phibar0;
+  const double tau = sn * phi;
+  const double t1 = phi / rho, t2 = -theta / rho;
+  double dd = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double vi = v[i] * inv_a;
+    const double wi = w[i];
+    const double dk = wi / rho;
+    dd += dk * dk;
+    x[i] += t1 * wi;
+    w[i] = vi + t2 * wi;
+    v[i] = vi;
+  }
+  const double ddnorm = st->ddnorm + block_sum(dd, sh);
+  if (threadIdx.x == 0) {
+    const double delta = st->sn2 * rho;
+    const double gambar = -st->cs2 * rho;
+    const double rhs = phi - delta * st->z;
+    const double zbar = rhs / gambar;
+    const double xnorm = sqrt(st->xxnorm + zbar * zbar);
+    const double gamma = sqrt(gambar * gambar + theta * theta);
+    const double cs2 = gambar / gamma, sn2 = theta / gamma;
+    const double z = rhs / gamma;
+    const double xxnorm = st->xxnorm + z * z;
+    const double acond = anorm * sqrt(ddnorm);
+    const double rnorm = sqrt(phibar * phibar + st->res2);
+    const double arnorm = alpha * fabs(tau);
+    const double bnorm = st->bnorm;
+    const double test1 = rnorm / bnorm;
+    const double test2 = arnorm / (anorm * rnorm);
+    const double test3 = 1.0 / acond;
+    const double tt1 = test1 / (1.0 + anorm * xnorm / bnorm);
+    const double rtol = st->btol + st->atol * anorm * xnorm / bnorm;
+    const int itn = st->itn + 1;
+    int istop = 0;
+    if (itn >= st->iter_lim) istop = 7;
+    if (1.0 + test3 <= 1.0) istop = 6;
+    if (1.0 + test2 <= 1.0) istop = 5;
+    if (1.0 + tt1 <= 1.0) istop = 4;
+    if (test3 <= st->ctol) istop = 3;
+    if (test2 <= st->atol) istop = 2;
+    if (test1 <= rtol) istop = 1;
+    st->alpha = alpha; st->rhobar = rhobar; st->phibar = phibar; st->anorm = anorm;
+    st->acond = acond; st->ddnorm = ddnorm; st->xnorm = xnorm; st->xxnorm = xxnorm;
+    st->z = z; st->cs2 = cs2; st->sn2 = sn2; st->rnorm = rnorm; st->arnorm = arnorm;
+    st->test1 = test1; st->test2 = test2; st->test3 = test3;
+    st->itn = itn;
+    st->istop = istop;
+    if (istop) st->done = 1;
+  }
+}
+
+// x = Rinv y (after the solve); not gated by the stop flag
+__global__ void k_gemv_upper_final(const double* __restrict__ Ri, int64_t ldi, int64_t n,
+                                   const double* __restrict__ y, double* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int64_t j = i; j < n; ++j) s += Ri[i + j * ldi] * y[j];
+  x[i] = s;
+}
+
+__global__ void k_lsqr_set(LsqrState* __restrict__ st, double atol, double btol, double ctol,
+                           int32_t iter_lim) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    LsqrState s{};
+    s.atol = atol; s.btol = btol; s.ctol = ctol; s.iter_lim = iter_lim;
+    *st = s;
+  }
+}
+
+}  // namespace sk

@@ -1,0 +1,82 @@
+"""GPU parity of the sketch-and-precondition least-squares pipeline (paper
+Sec. V-E): FP64 Householder QR and triangular inverse against numpy, and the
+full solve against a dense least-squares solution and the oracle's own SAP."""
+import numpy as np
+import pytest
+
+from paper_2310_15419_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    from paper_2310_15419_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.mark.parametrize("d,n", [(300, 77), (64, 64), (40, 1), (1000, 513), (33, 17), (257, 32)])
+def test_qr_against_numpy(B, d, n):
+    import torch
+    rng = np.random.default_rng(d * 1000 + n)
+    M = rng.standard_normal((d, n))
+    print(f"qr d={d} n={n}", flush=True)
+    A = torch.from_numpy(M.T.copy()).cuda()  # column-major d x n
+    R = B.qr_f64(A).cpu().numpy()
+    assert np.allclose(np.tril(R, -1), 0.0)
+    # R^T R = M^T M, and R equals numpy's R up to the signs of its rows
+    G = M.T @ M
+    assert np.linalg.norm(R.T @ R - G) <= 1e-13 * n * np.linalg.norm(G)
+    Rn = np.linalg.qr(M, mode="r")
+    sgn = np.sign(np.diag(R)) * np.sign(np.diag(Rn))
+    assert np.linalg.norm(R - sgn[:, None] * Rn) <= 1e-12 * n * np.linalg.norm(Rn)
+
+
+@pytest.mark.parametrize("n", [1, 5, 64, 300, 1001])
+def test_trinv_against_numpy(B, n):
+    import torch
+    rng = np.random.default_rng(n)
+    R = np.linalg.qr(rng.standard_normal((2 * n, n)), mode="r")
+    print(f"trinv n={n}", flush=True)
+    Ri = B.trinv_f64(torch.from_numpy(R).cuda()).cpu().numpy()
+    assert np.allclose(np.tril(Ri, -1), 0.0)
+    cond = np.linalg.cond(R)
+    assert np.linalg.norm(Ri @ R - np.eye(n)) <= 1e-14 * cond * n
+    assert np.linalg.norm(Ri - np.linalg.inv(R)) <= 1e-13 * cond * np.linalg.norm(Ri)
+
+
+def device_request(B, A, b):
+    import torch
+    dA = B.DeviceCsc.from_host(A)
+    return dA, torch.from_numpy(b).cuda()
+
+
+@pytest.mark.parametrize("dist", ["rademacher", "uniform", "gaussian"])
+@pytest.mark.parametrize("m,n,dense_rows", [(20_000, 60, 200), (60_000, 150, 400)])
+def test_sap_solve_matches_lstsq(B, oracle_lib, dist, m, n, dense_rows):
+    A, b, _ = inputs.ls_request(11 + n, m, n, dense_rows=dense_rows)
+    dA, db = device_request(B, A, b)
+    p = B.sap_params(2 * n, dist, 99, atol=1e-10, btol=1e-10)
+    print(f"sap m={m} n={n} {dist}", flush=True)
+    x, info = B.SapSolve(dA, db, p).solve(chunk=8)
+    x = x.cpu().numpy()
+    assert info["status"] == 0 and info["done"] == 1 and info["istop"] in (1, 2), info
+    xs = np.linalg.lstsq(A.to_dense(), b, rcond=None)[0]
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs), np.linalg.norm(x - xs)
+    assert oracle_lib.ls_error(A.to_scipy(), x, b) <= 1e-9
+    # the oracle's SAP with its own FP64 sketch of the same S takes about as
+    # many iterations (both preconditioners are subspace embeddings, d = 2n)
+    Ahat = oracle_lib.sketch(A.m, A.n, A.colptr, A.rowidx, A.vals, 2 * n, dist, 99)
+    _, itn, _ = oracle_lib.sap_solve_reference(A.to_scipy(), b, Ahat, tol=1e-10)
+    assert abs(info["iterations"] - itn) <= max(3, itn // 10), (info["iterations"], itn)
+
+
+def test_sap_rejects_bad_shapes(B):
+    import torch
+    A, b, _ = inputs.ls_request(1, 5000, 40, dense_rows=100)
+    dA, db = device_request(B, A, b)
+    with pytest.raises(B.SketchError):
+        B.SapSolve(dA, db, B.sap_params(30, "rademacher", 1))  # d < n
