@@ -553,9 +553,10 @@ static_assert(offsetof(LsqrState, rnorm) == offsetof(sk_sap_info, rnorm) &&
               "solver info prefix");
 
 struct SapLayout {
-  int64_t state, sk_ws, sk_bytes, ahat, q, tau, tq, r, rinv, v64, rcnt, rowptr, cursor, ccol,
-      cval, sums, cbase, cpart, u, partial, v, w, y, tn, sn, t2, total;
-  int64_t nchunk_max, nblk_m;
+  int64_t state, sk_ws, sk_bytes, ahat, q, tau, tq, r, rinv, rinvt, v64, rcnt, rowptr, cursor,
+      ccol, cval, lidx, lrows, sums, cbase, cpart, u, partial, partial2, v, w, y, tn, sn, t2,
+      total;
+  int64_t nchunk_max, nblk_m, nlong_max, nblk_long;
 };
 
 sk_status sap_layout(const sk_csc* A, const sk_sap_params* p, SapLayout& L) {
@@ -577,12 +578,17 @@ sk_status sap_layout(const sk_csc* A, const sk_sap_params* p, SapLayout& L) {
   L.tq = off;      off = align_up(off + 8 * QR_NB * QR_NB);
   L.r = off;       off = align_up(off + 8 * n * n);
   L.rinv = off;    off = align_up(off + 8 * n * n);
+  L.rinvt = off;   off = align_up(off + 8 * n * n);
   L.v64 = off;     off = align_up(off + 8 * std::max<int64_t>(nnz, 1));
   L.rcnt = off;    off = align_up(off + 4 * m);
   L.rowptr = off;  off = align_up(off + 4 * (m + 2));
   L.cursor = off;  off = align_up(off + 4 * m);
   L.ccol = off;    off = align_up(off + 4 * std::max<int64_t>(nnz, 1));
   L.cval = off;    off = align_up(off + 8 * std::max<int64_t>(nnz, 1));
+  L.nlong_max = nnz / (SAP_LONG + 1) + 1;  // rows with more than SAP_LONG entries
+  L.nblk_long = (L.nlong_max + 3) / 4;     // four waves per workgroup
+  L.lidx = off;    off = align_up(off + 4 * (m + 2));
+  L.lrows = off;   off = align_up(off + 4 * L.nlong_max);
   L.sums = off;    off = align_up(off + 4 * scan_sums_len(std::max<int64_t>(m + 1, n + 1)));
   L.nchunk_max = n + nnz / SAP_CHUNK + 1;
   L.cbase = off;   off = align_up(off + 4 * (n + 2));
@@ -590,6 +596,7 @@ sk_status sap_layout(const sk_csc* A, const sk_sap_params* p, SapLayout& L) {
   L.nblk_m = (m + SAP_THREADS - 1) / SAP_THREADS;
   L.u = off;       off = align_up(off + 8 * m);
   L.partial = off; off = align_up(off + 8 * L.nblk_m);
+  L.partial2 = off; off = align_up(off + 8 * L.nblk_long);
   L.v = off;       off = align_up(off + 8 * n);
   L.w = off;       off = align_up(off + 8 * n);
   L.y = off;       off = align_up(off + 8 * n);
@@ -602,13 +609,24 @@ sk_status sap_layout(const sk_csc* A, const sk_sap_params* p, SapLayout& L) {
 
 sk_status qr_launch(int64_t d, int64_t n, double* A, int64_t lda, double* R, int64_t ldr,
                     double* tau, double* T, hipStream_t st) {
-  for (int64_t j0 = 0; j0 < n; j0 += QR_NB) {
-    const int nb = (int)std::min<int64_t>(QR_NB, n - j0);
-    hipLaunchKernelGGL(k_qr_panel, dim3(1), dim3(SAP_THREADS), 0, st, A, lda, d, j0, nb, tau, T);
+  if (hipFuncSetAttribute((const void*)k_qr_panel_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          8 * QR_NB_LDS * QR_LDS_ROWS) != hipSuccess)
+    return SK_EHIP;
+  for (int64_t j0 = 0; j0 < n;) {
+    // panels whose rows fit in LDS are factored there, eight columns at a time
+    const bool in_lds = d - j0 <= QR_LDS_ROWS;
+    const int nb = (int)std::min<int64_t>(in_lds ? QR_NB_LDS : QR_NB, n - j0);
+    if (in_lds)
+      hipLaunchKernelGGL(k_qr_panel_lds, dim3(1), dim3(1024), (size_t)(8 * nb * (d - j0)), st, A,
+                         lda, d, j0, nb, tau, T);
+    else
+      hipLaunchKernelGGL(k_qr_panel, dim3(1), dim3(SAP_THREADS), 0, st, A, lda, d, j0, nb, tau,
+                         T);
     const int64_t trail = n - j0 - nb;
     if (trail > 0)
       hipLaunchKernelGGL(k_qr_update, dim3((unsigned)trail), dim3(SAP_THREADS), 0, st, A, lda, d,
                          n, j0, nb, T);
+    j0 += nb;
   }
   hipLaunchKernelGGL(k_qr_extract_r, dim3(blocks_for(n * n, 256)), dim3(256), 0, st, A, lda, n, R,
                      ldr);
@@ -631,13 +649,19 @@ void lsqr_iteration(const sk_csc* A, const SapLayout& L, char* w, hipStream_t st
   double* tn = (double*)(w + L.tn);
   double* u = (double*)(w + L.u);
   double* partial = (double*)(w + L.partial);
-  hipLaunchKernelGGL(k_gemv_upper, dim3(blocks_for(n, 256)), dim3(256), 0, st, Ri, n, n, v, tn,
-                     state);
+  double* partial2 = (double*)(w + L.partial2);
+  hipLaunchKernelGGL(k_gemv_upper, dim3(blocks_for(n * 64, 256)), dim3(256), 0, st,
+                     (const double*)(w + L.rinvt), n, v, tn, state);
   hipLaunchKernelGGL(k_lsqr_av<false>, dim3((unsigned)L.nblk_m), dim3(SAP_THREADS), 0, st,
                      (const int32_t*)(w + L.rowptr), (const int32_t*)(w + L.ccol),
                      (const double*)(w + L.cval), m, tn, (const double*)nullptr, u, partial,
                      state);
-  hipLaunchKernelGGL(k_lsqr_beta<false>, dim3(1), dim3(1024), 0, st, partial, L.nblk_m, state);
+  hipLaunchKernelGGL(k_lsqr_av_long, dim3((unsigned)L.nblk_long), dim3(SAP_THREADS), 0, st,
+                     (const int32_t*)(w + L.rowptr), (const int32_t*)(w + L.ccol),
+                     (const double*)(w + L.cval), (const int32_t*)(w + L.lidx), m,
+                     (const int32_t*)(w + L.lrows), tn, u, partial2, state);
+  hipLaunchKernelGGL(k_lsqr_beta<false>, dim3(1), dim3(1024), 0, st, partial, L.nblk_m,
+                     (const double*)partial2, L.nblk_long, state);
   hipLaunchKernelGGL(k_lsqr_atu, dim3(blocks_for(L.nchunk_max * 64, 256)), dim3(256), 0, st,
                      A->colptr, A->rowidx, (const double*)(w + L.v64), n,
                      (const int32_t*)(w + L.cbase), u, (double*)(w + L.cpart), state,
@@ -1069,6 +1093,8 @@ sk_status sk_sap_begin(const sk_csc* A, const double* b, const sk_sap_params* p,
   if ((s = qr_launch(d, n, q, d, R, n, (double*)(w + L.tau), (double*)(w + L.tq), st)) != SK_OK)
     return s;
   if ((s = trinv_launch(n, R, n, Ri, n, st)) != SK_OK) return s;
+  hipLaunchKernelGGL(k_transpose, dim3(blocks_for(n * n, 256)), dim3(256), 0, st, (const double*)Ri,
+                     n, (double*)(w + L.rinvt));
   // FP64 values, row counts, row-major copy (only of input the sketch's
   // validation passed: its header sits at the start of its workspace)
   const Header* skh = (const Header*)(w + L.sk_ws);
@@ -1087,8 +1113,19 @@ sk_status sk_sap_begin(const sk_csc* A, const double* b, const sk_sap_params* p,
     hipLaunchKernelGGL(k_csr_scatter, dim3(blocks_for(nnz, 256)), dim3(256), 0, st, A->colptr,
                        A->rowidx, v64, n, nnz, cursor, (int32_t*)(w + L.ccol),
                        (double*)(w + L.cval), skh);
+  }
+  // long rows: listed, sorted by a workgroup each; short rows by a thread
+  int32_t* lidx = (int32_t*)(w + L.lidx);
+  hipLaunchKernelGGL(k_long_flags, dim3(blocks_for(m, 256)), dim3(256), 0, st, rowptr, m, lidx);
+  if ((s = scan_i32(lidx, m, (int32_t*)(w + L.sums), st)) != SK_OK) return s;
+  hipLaunchKernelGGL(k_long_list, dim3(blocks_for(m, 256)), dim3(256), 0, st, lidx, m,
+                     (int32_t*)(w + L.lrows));
+  if (nnz > 0) {
     hipLaunchKernelGGL(k_csr_sort_rows, dim3(blocks_for(m, 256)), dim3(256), 0, st, rowptr, m,
                        (int32_t*)(w + L.ccol), (double*)(w + L.cval));
+    hipLaunchKernelGGL(k_csr_sort_long, dim3((unsigned)L.nlong_max), dim3(SAP_THREADS), 0, st,
+                       rowptr, lidx, m, (const int32_t*)(w + L.lrows), (int32_t*)(w + L.ccol),
+                       (double*)(w + L.cval));
   }
   int32_t* cbase = (int32_t*)(w + L.cbase);
   hipLaunchKernelGGL(k_col_chunks, dim3(blocks_for(n, 256)), dim3(256), 0, st, A->colptr, n, cbase,
@@ -1100,7 +1137,8 @@ sk_status sk_sap_begin(const sk_csc* A, const double* b, const sk_sap_params* p,
   hipLaunchKernelGGL(k_lsqr_av<true>, dim3((unsigned)L.nblk_m), dim3(SAP_THREADS), 0, st,
                      (const int32_t*)nullptr, (const int32_t*)nullptr, (const double*)nullptr, m,
                      (const double*)nullptr, b, u, partial, state);
-  hipLaunchKernelGGL(k_lsqr_beta<true>, dim3(1), dim3(1024), 0, st, partial, L.nblk_m, state);
+  hipLaunchKernelGGL(k_lsqr_beta<true>, dim3(1), dim3(1024), 0, st, partial, L.nblk_m,
+                     (const double*)nullptr, int64_t(0), state);
   hipLaunchKernelGGL(k_lsqr_atu, dim3(blocks_for(L.nchunk_max * 64, 256)), dim3(256), 0, st,
                      A->colptr, A->rowidx, (const double*)v64, n, (const int32_t*)cbase, u,
                      (double*)(w + L.cpart), state, skh);

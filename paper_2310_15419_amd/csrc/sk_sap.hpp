@@ -155,6 +155,88 @@ __global__ __launch_bounds__(SAP_THREADS) void k_qr_panel(double* __restrict__ A
   }
 }
 
+// The same factorisation with the panel (rows j0..d-1, nb <= QR_NB_LDS
+// columns) held in LDS: one workgroup of 1024 threads, every step's
+// reductions and updates on LDS data.
+constexpr int QR_NB_LDS = 8;
+constexpr int QR_LDS_ROWS = 2304;  // panel rows that fit: 2304 * 8 * 8 B = 144 KiB
+__global__ __launch_bounds__(1024) void k_qr_panel_lds(double* __restrict__ A, int64_t lda,
+                                                        int64_t d, int64_t j0, int nb,
+                                                        double* __restrict__ tau,
+                                                        double* __restrict__ T) {
+  extern __shared__ double P[];  // (d - j0) x nb, column-major, ld = rows
+  __shared__ double sh[16];
+  __shared__ double s_dot[QR_NB_LDS][16];
+  __shared__ double s_w[QR_NB_LDS];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int rows = (int)(d - j0);
+  for (int j = 0; j < nb; ++j)
+    for (int r = tid; r < rows; r += 1024) P[r + j * rows] = A[j0 + r + (j0 + j) * lda];
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    double* col = P + k * rows;  // row c = j0 + k is local row k
+    double ss = 0.0;
+    for (int r = k + 1 + tid; r < rows; r += 1024) ss += col[r] * col[r];
+    const double sigma = block_sum(ss, sh);
+    const double alpha = col[k];
+    double t_k, beta, scale;
+    if (sigma == 0.0) {
+      t_k = 0.0;
+      beta = alpha;
+      scale = 0.0;
+    } else {
+      const double nrm = sqrt(alpha * alpha + sigma);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      t_k = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    for (int r = k + 1 + tid; r < rows; r += 1024) col[r] *= scale;
+    __syncthreads();
+    double part[QR_NB_LDS];
+#pragma unroll
+    for (int j = 0; j < QR_NB_LDS; ++j) part[j] = 0.0;
+    for (int r = k + 1 + tid; r < rows; r += 1024) {
+      const double vr = col[r];
+#pragma unroll
+      for (int j = 0; j < QR_NB_LDS; ++j)
+        if (j < nb && j != k) part[j] += P[r + j * rows] * vr;
+    }
+#pragma unroll
+    for (int j = 0; j < QR_NB_LDS; ++j) {
+      const double sj = wave_sum(part[j]);
+      if (lane == 0) s_dot[j][wave] = sj;
+    }
+    __syncthreads();
+    if (tid < nb && tid != k) {
+      double sj = 0.0;
+      for (int w = 0; w < 16; ++w) sj += s_dot[tid][w];
+      s_w[tid] = sj + P[k + tid * rows];  // row c: v[c] = 1
+    }
+    __syncthreads();
+    for (int j = k + 1; j < nb; ++j) {
+      const double wj = t_k * s_w[j];
+      double* cj = P + j * rows;
+      for (int r = k + 1 + tid; r < rows; r += 1024) cj[r] -= wj * col[r];
+      if (tid == 0) cj[k] -= wj;
+    }
+    if (tid == 0) {
+      col[k] = beta;
+      tau[j0 + k] = t_k;
+      for (int i = 0; i < k; ++i) {
+        double si = 0.0;
+        for (int j = i; j < k; ++j) si += T[i + j * QR_NB] * s_w[j];
+        T[i + k * QR_NB] = -t_k * si;
+      }
+      T[k + k * QR_NB] = t_k;
+      for (int i = k + 1; i < QR_NB; ++i) T[i + k * QR_NB] = 0.0;
+    }
+    __syncthreads();
+  }
+  for (int j = 0; j < nb; ++j)
+    for (int r = tid; r < rows; r += 1024) A[j0 + r + (j0 + j) * lda] = P[r + j * rows];
+}
+
 // C <- C - V T^T (V^T C) for the trailing columns j >= j0 + nb, rows >= j0;
 // one workgroup per trailing column.
 __global__ __launch_bounds__(SAP_THREADS) void k_qr_update(double* __restrict__ A, int64_t lda,
@@ -287,12 +369,30 @@ __global__ void k_csr_scatter(const int64_t* __restrict__ colptr, const int32_t*
   cval[q] = v64[p];
 }
 
-// sort each CSR row by column (insertion sort; rows are short, columns unique)
+// Rows with more than SAP_LONG entries are "long": their products run on a
+// whole wave and they are sorted by a workgroup; the rest by one thread.
+constexpr int SAP_LONG = 32;
+constexpr int SAP_SORT_MAX = 8192;  // entries of a long row sorted in LDS (n <= SAP_MAX_N)
+
+// lflag[r] = row r is long (scanned afterwards into its index in lrows)
+__global__ void k_long_flags(const int32_t* __restrict__ rowptr, int64_t m,
+                             int32_t* __restrict__ lflag) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < m) lflag[r] = rowptr[r + 1] - rowptr[r] > SAP_LONG ? 1 : 0;
+}
+
+__global__ void k_long_list(const int32_t* __restrict__ lidx, int64_t m, int32_t* __restrict__ lrows) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < m && lidx[r + 1] > lidx[r]) lrows[lidx[r]] = (int32_t)r;
+}
+
+// sort each short CSR row by column (insertion sort; columns are unique)
 __global__ void k_csr_sort_rows(const int32_t* __restrict__ rowptr, int64_t m,
                                 int32_t* __restrict__ ccol, double* __restrict__ cval) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= m) return;
   const int32_t a = rowptr[r], b = rowptr[r + 1];
+  if (b - a > SAP_LONG) return;
   for (int32_t i = a + 1; i < b; ++i) {
     const int32_t c = ccol[i];
     const double v = cval[i];
@@ -304,6 +404,51 @@ __global__ void k_csr_sort_rows(const int32_t* __restrict__ rowptr, int64_t m,
     }
     ccol[k + 1] = c;
     cval[k + 1] = v;
+  }
+}
+
+// one workgroup per long row: bitonic sort of (column, value) in LDS
+__global__ __launch_bounds__(SAP_THREADS) void k_csr_sort_long(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ lidx, int64_t m,
+    const int32_t* __restrict__ lrows, int32_t* __restrict__ ccol, double* __restrict__ cval) {
+  __shared__ int32_t kc[SAP_SORT_MAX];
+  __shared__ int32_t kp[SAP_SORT_MAX];  // position in the row (to move the values)
+  const int64_t li = blockIdx.x;
+  if (li >= lidx[m]) return;
+  const int32_t r = lrows[li];
+  const int32_t a = rowptr[r], len = rowptr[r + 1] - a;
+  int np2 = 1;
+  while (np2 < len) np2 <<= 1;
+  for (int i = threadIdx.x; i < np2; i += SAP_THREADS) {
+    kc[i] = i < len ? ccol[a + i] : 0x7FFFFFFF;
+    kp[i] = i;
+  }
+  __syncthreads();
+  for (int size = 2; size <= np2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < np2; i += SAP_THREADS) {
+        const int jx = i ^ stride;
+        if (jx > i) {
+          const bool up = (i & size) == 0;
+          const int32_t ci = kc[i], cj = kc[jx];
+          if ((ci > cj) == up) {
+            kc[i] = cj; kc[jx] = ci;
+            const int32_t t = kp[i]; kp[i] = kp[jx]; kp[jx] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // gather the values in the new order, then write both back
+  double v[SAP_SORT_MAX / SAP_THREADS];
+  int cnt = 0;
+  for (int i = threadIdx.x; i < len; i += SAP_THREADS) v[cnt++] = cval[a + kp[i]];
+  __syncthreads();
+  cnt = 0;
+  for (int i = threadIdx.x; i < len; i += SAP_THREADS) {
+    cval[a + i] = v[cnt++];
+    ccol[a + i] = kc[i];
   }
 }
 
@@ -330,16 +475,28 @@ struct LsqrState {
   double pad[3];
 };
 
-// t = Rinv v (upper triangular, column-major): one thread per row
-__global__ void k_gemv_upper(const double* __restrict__ Ri, int64_t ldi, int64_t n,
+// Rt = R^T (n x n, column-major both)
+__global__ void k_transpose(const double* __restrict__ R, int64_t n, double* __restrict__ Rt) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n) return;
+  const int64_t j = t / n, i = t - j * n;
+  Rt[j + i * n] = R[i + j * n];
+}
+
+// t = Rinv v from the transposed copy Rit = Rinv^T (row i of Rinv is column i
+// of Rit, contiguous): one wave per row
+__global__ void k_gemv_upper(const double* __restrict__ Rit, int64_t n,
                              const double* __restrict__ v, double* __restrict__ t,
                              const LsqrState* __restrict__ st) {
   if (st->done) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
   if (i >= n) return;
-  double s = 0.0;
-  for (int64_t j = i; j < n; ++j) s += Ri[i + j * ldi] * v[j];
-  t[i] = s;
+  const double* row = Rit + i * n;
+  double acc = 0.0;
+  for (int64_t j = i + lane; j < n; j += 64) acc += row[j] * v[j];
+  acc = wave_sum(acc);
+  if (lane == 0) t[i] = acc;
 }
 
 // t = Rinv^T s: one wave per column j (t[j] = sum_{i <= j} Ri[i, j] s[i])
@@ -372,26 +529,57 @@ __global__ __launch_bounds__(SAP_THREADS) void k_lsqr_av(
   if (r < m) {
     if (INIT) {
       val = b[r];
-    } else {
+      u[r] = val;
+    } else if (rowptr[r + 1] - rowptr[r] <= SAP_LONG) {  // long rows: k_lsqr_av_long
       double s = 0.0;
       for (int32_t p = rowptr[r]; p < rowptr[r + 1]; ++p) s += cval[p] * z[ccol[p]];
       const double beta = st->beta;
       val = s - st->alpha * (beta > 0.0 ? u[r] / beta : 0.0);
+      u[r] = val;
     }
-    u[r] = val;
   }
   const double tot = block_sum(val * val, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// beta = sqrt(sum of partials) (fixed order), one workgroup
+// the long rows of u <- A z - alpha (u / beta): one wave per long row;
+// partial sums of their u^2 per workgroup (4 waves)
+__global__ __launch_bounds__(SAP_THREADS) void k_lsqr_av_long(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ ccol,
+    const double* __restrict__ cval, const int32_t* __restrict__ lidx, int64_t m,
+    const int32_t* __restrict__ lrows, const double* __restrict__ z, double* __restrict__ u,
+    double* __restrict__ partial, const LsqrState* __restrict__ st) {
+  __shared__ double sh[16];
+  if (st->done) return;
+  const int64_t li = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  double val = 0.0;
+  if (li < lidx[m]) {
+    const int32_t r = lrows[li];
+    double s = 0.0;
+    for (int32_t p = rowptr[r] + lane; p < rowptr[r + 1]; p += 64) s += cval[p] * z[ccol[p]];
+    s = wave_sum(s);
+    if (lane == 0) {
+      const double beta = st->beta;
+      val = s - st->alpha * (beta > 0.0 ? u[r] / beta : 0.0);
+      u[r] = val;
+    }
+  }
+  const double tot = block_sum(val * val, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// beta = sqrt(sum of both partial arrays) (fixed order), one workgroup
 template <bool INIT>
 __global__ __launch_bounds__(1024) void k_lsqr_beta(const double* __restrict__ partial,
-                                                     int64_t np, LsqrState* __restrict__ st) {
+                                                     int64_t np, const double* __restrict__ partial2,
+                                                     int64_t np2, LsqrState* __restrict__ st) {
   __shared__ double sh[16];
   if (st->done) return;
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < np; i += blockDim.x) s += partial[i];
+  if (!INIT)
+    for (int64_t i = threadIdx.x; i < np2; i += blockDim.x) s += partial2[i];
   const double tot = block_sum(s, sh);
   if (threadIdx.x == 0) {
     const double beta = sqrt(tot);
