@@ -119,6 +119,170 @@ def cpu_baseline(A, d, dist, seed, target_s: float):
             "sample": f"first {rows} rows of A (nnz={S.nnz}), full d={d}, {dt:.1f} s"}
 
 
+def bench_serving(args):
+    """Config 5: a Poisson stream of sketch-and-precondition least-squares
+    requests; p50/p99 latency and solves/s of continuous batching (several
+    slots) against the plain per-request path (one slot), at arrival rates
+    that are fractions of the measured single-request capacity."""
+    import torch
+    from paper_2310_15419_amd import binding as B, inputs, serving as S
+    rng = np.random.default_rng(50)
+    pool = []
+    t_gen = time.perf_counter()
+    for i in range(args.serve_pool):
+        m = int(np.exp(rng.uniform(np.log(1e5), np.log(args.serve_m_hi))))
+        n = int(rng.integers(100, args.serve_n_hi + 1))
+        A, b, _ = inputs.ls_request(500 + i, m, n, dense_rows=2000)
+        pool.append((B.DeviceCsc.from_host(A), torch.from_numpy(b).cuda(), m, n, A.nnz))
+    print(f"[bench] {len(pool)} request matrices in {time.perf_counter() - t_gen:.1f} s",
+          file=sys.stderr, flush=True)
+
+    def requests(count, arrivals, seed):
+        r = np.random.default_rng(seed)
+        out = []
+        for k in range(count):
+            dA, db, m, n, _ = pool[int(r.integers(0, len(pool)))]
+            p = B.sap_params(2 * n, "rademacher", 60000 + k, atol=1e-10, btol=1e-10)
+            out.append(S.Request(k, dA, db, p, arrival=float(arrivals[k])))
+        return out
+
+    budget = int(args.serve_budget_gb * (1 << 30))
+    # warm-up, then the single-request service time (one slot, all queued)
+    S.Server(budget, 1).run(requests(2, np.zeros(2), 1))
+    probe = requests(len(pool), np.zeros(len(pool)), 2)
+    t0 = time.perf_counter()
+    S.Server(budget, 1).run(probe)
+    service = (time.perf_counter() - t0) / len(probe)
+    capacity = 1.0 / service
+    print(f"[bench] single-request service {service * 1e3:.2f} ms -> capacity {capacity:.1f}/s",
+          file=sys.stderr, flush=True)
+    points = []
+    for frac in args.serve_rates:
+        rate = frac * capacity
+        arr = S.poisson_arrivals(args.serve_requests, rate, seed=int(frac * 1000))
+        row = {"rate_frac": frac, "rate_per_s": rate}
+        for name, slots in (("plain", 1), ("batched", args.serve_slots)):
+            srv = S.Server(budget, slots, chunk=16)
+            reqs = srv.run(requests(args.serve_requests, arr, 7))
+            st = S.latency_stats(reqs)
+            st["peak_inflight"] = srv.peak_inflight
+            st["converged"] = sum(r.info["istop"] in (1, 2) for r in reqs)
+            row[name] = st
+            print(f"[bench] rate {frac:.2f}x {name}: p50 {st['p50_ms']:.1f} ms, p99 "
+                  f"{st['p99_ms']:.1f} ms, {st['solves_per_s']:.1f} solves/s",
+                  file=sys.stderr, flush=True)
+        points.append(row)
+    head = next((p for p in points if abs(p["rate_frac"] - 0.9) < 1e-9), points[-1])
+    res = {
+        "metric": "p99 latency of served sketch-and-precondition least-squares solves",
+        "value": head["batched"]["p99_ms"], "unit": "ms", "n_gpus": 1,
+        "steps": args.serve_requests, "warmup": 2,
+        "ms_per_step": head["batched"]["mean_ms"], "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (sketch f32)",
+        "data": "synthetic",
+        "config": {"workload": "serving: Poisson stream of min ||Ax-b||, A from the power-law "
+                               f"generator with a dense 2000-row block, m log-uniform in [1e5, "
+                               f"{args.serve_m_hi:.0e}], n in [100, {args.serve_n_hi}], d = 2n, "
+                               "S +-1, LSQR to 1e-10, "
+                               f"{len(pool)} distinct matrices, HBM budget "
+                               f"{args.serve_budget_gb} GiB, {args.serve_slots} slots",
+                   "single_request_ms": service * 1e3, "capacity_per_s": capacity,
+                   "points": points},
+    }
+    print(json.dumps(res), flush=True)
+
+
+def bench_batched(args):
+    """Config 4: 512 uneven +-1 sketches, A values BF16; plain launches (one
+    sk_sketch per item) against one batched launch, with S in FP32 on the
+    sparse kernel and in BF16 / FP8 on the matrix cores, each checked against
+    the FP64 oracle on a sample of items."""
+    import torch
+    from paper_2310_15419_amd import binding as B, inputs
+    t_gen = time.perf_counter()
+    workers = min(16, len(os.sched_getaffinity(0)))
+    items = inputs.workload_batched(args.batch_count, workers=workers)
+    print(f"[bench] {len(items)} items in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr,
+          flush=True)
+    mats, host = [], []
+    for it in items:
+        vb = torch.from_numpy(it.A.vals).to(torch.bfloat16)
+        host.append(inputs.Csc(it.A.m, it.A.n, it.A.colptr, it.A.rowidx,
+                               vb.to(torch.float64).numpy()))
+        mats.append(B.DeviceCsc(it.A.m, it.A.n, torch.from_numpy(it.A.colptr).cuda(),
+                                torch.from_numpy(it.A.rowidx).cuda(), vb.cuda()))
+    ds = [it.d for it in items]
+    seeds = [it.seed for it in items]
+    work = float(sum(h.nnz * d for h, d in zip(host, ds)))
+    outs = [torch.empty((A.n, d), dtype=torch.float32, device="cuda") for A, d in zip(mats, ds)]
+    # oracle sample: the cheapest items and a few mid-size ones
+    order = sorted(range(len(items)), key=lambda i: host[i].nnz * ds[i])
+    sample = order[:6] + order[len(order) // 2: len(order) // 2 + 2]
+    import oracle
+    oracle.build()
+    refs = {i: oracle.sketch(host[i].m, host[i].n, host[i].colptr, host[i].rowidx, host[i].vals,
+                             ds[i], "rademacher", seeds[i]) for i in sample}
+
+    def err():
+        e = 0.0
+        for i in sample:
+            got = outs[i].t().cpu().numpy().astype(np.float64)
+            e = max(e, float(np.linalg.norm(got - refs[i]) / np.linalg.norm(refs[i])))
+        return e
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        best = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best.append(e0.elapsed_time(e1))
+        return float(np.median(best))
+
+    modes = {}
+    for prec, pname in ((0, "f32"), (1, "bf16"), (2, "fp8")):
+        wss = [B.alloc_workspace(B.workspace_bytes(A, d, "rademacher", prec))
+               for A, d in zip(mats, ds)]
+
+        def plain():
+            for A, d, sd, o, w in zip(mats, ds, seeds, outs, wss):
+                B.sketch_into(A, d, "rademacher", sd, o, w, prec=prec)
+        ms = timed(plain, args.steps)
+        modes[f"plain_{pname}"] = {"ms": ms, "nnz_d_per_s": work / (ms * 1e-3), "error": err()}
+        del wss
+        batch = B.Batch(mats, ds, ["rademacher"] * len(mats), seeds, prec=prec)
+        ws = B.alloc_workspace(batch.workspace_bytes())
+        ms = timed(lambda: batch.run(outs, ws), args.steps)
+        st = batch.status(ws)
+        assert all(c == 0 for c in st), st
+        modes[f"batched_{pname}"] = {"ms": ms, "nnz_d_per_s": work / (ms * 1e-3), "error": err(),
+                                     "matrix_core_items": sum(p["variant"] == 0
+                                                              for p in batch.plan())}
+        del ws
+        for k in (f"plain_{pname}", f"batched_{pname}"):
+            print(f"[bench] {k}: {modes[k]['ms']:.2f} ms, {modes[k]['nnz_d_per_s']:.3e} nnz*d/s, "
+                  f"max rel error {modes[k]['error']:.2e}", file=sys.stderr, flush=True)
+    best = max((v["nnz_d_per_s"], k) for k, v in modes.items() if v["error"] <= 1e-2)
+    res = {
+        "metric": "batched vs plain at fixed error (512 sketches)",
+        "value": modes["batched_bf16"]["nnz_d_per_s"], "unit": "nnz*d/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": modes["batched_bf16"]["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 operands, f32 accumulate", "data": "synthetic",
+        "config": {"workload": f"batched: {len(items)} sketches, m log-uniform [1e4, 5e5], n in "
+                               "[50, 500], d in [2n, 4n], density U(0.5%, 5%), A values BF16, "
+                               "S +-1 (seeds 40000+b)",
+                   "sum_nnz_d": work, "modes": modes, "best_within_1e-2": best[1],
+                   "oracle_sample_items": len(sample)},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +297,14 @@ def main():
     ap.add_argument("--dense-min-pct", type=int, default=0)
     ap.add_argument("--col-split", type=int, default=0, help="0 auto, 1 off, 2 on")
     ap.add_argument("--row-pad", type=int, default=0)
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--serve-pool", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=150)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-m-hi", type=float, default=4e6)
+    ap.add_argument("--serve-n-hi", type=int, default=1000)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[0.5, 0.9, 1.2])
     ap.add_argument("--copy-probe", action="store_true",
                     help="launch only a plain 1 GiB device copy (for counter scaling)")
     args = ap.parse_args()
@@ -153,6 +325,13 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": x.numel() * 4, "copies": 3}))
+        return
+
+    if args.workload == "serving":
+        bench_serving(args)
+        return
+    if args.workload == "batched":
+        bench_batched(args)
         return
 
     t_gen = time.perf_counter()

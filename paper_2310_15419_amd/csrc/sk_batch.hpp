@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sk_mfma.hpp"
 #include "sk_sketch.hpp"
 
 namespace sk {
@@ -57,6 +58,28 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int rest = w.y / P.splits;
     sketch_unit<DIST, DL, Q, CS, WGS>(P, split, rest % P.tiles, rest / P.tiles, smem);
     __syncthreads();  // LDS of this unit is consumed before the next one starts
+  }
+}
+
+// persistent form of the matrix-core kernel (+-1 S in BF16 / FP8)
+template <int FMT>
+__global__ __launch_bounds__(MF_THREADS) void k_sketch_mfma_persistent(
+    const BatchOut* __restrict__ it, const int2* __restrict__ work, int total,
+    int32_t* __restrict__ counter) {
+  __shared__ __align__(16) unsigned char smem[sizeof(MfmaLds<FMT>)];
+  __shared__ int s_unit;
+  while (true) {
+    if (threadIdx.x == 0) s_unit = atomicAdd(counter, 1);
+    __syncthreads();
+    const int u = s_unit;
+    __syncthreads();
+    if (u >= total) break;
+    const int2 w = work[u];
+    const SketchParams P = it[w.x].P;
+    const int split = w.y % P.splits;
+    const int rest = w.y / P.splits;
+    mfma_unit<FMT>(P, split, rest % P.tiles, rest / P.tiles, smem);
+    __syncthreads();
   }
 }
 

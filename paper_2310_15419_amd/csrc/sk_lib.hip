@@ -15,6 +15,7 @@
 #include "sk_batch.hpp"
 #include "sk_dense.hpp"
 #include "sk_inspect.hpp"
+#include "sk_mfma.hpp"
 #include "sk_rng.hpp"
 #include "sk_sap.hpp"
 #include "sk_sketch.hpp"
@@ -80,6 +81,8 @@ struct Plan {
   int64_t kd_max;     // dense-row capacity
   int32_t slices;     // partial slices: splits (+1 for the dense path)
   double cost;        // autotuner's cost estimate (CU-cycles)
+  int32_t row_bytes;  // row offset unit of the entries (S-tile row bytes; 1 on MFMA)
+  int32_t mfma;       // 0: sparse FP32 kernel; MF_BF16 / MF_FP8: matrix-core kernel
 };
 
 constexpr int kDenseAutoPct = 40;                 // FP32 operands
@@ -239,7 +242,81 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
   }
   P.slices = P.splits + (P.dense_pct ? 1 : 0);
   P.cost = best;
+  P.row_bytes = P.ldS * 4;
+  P.mfma = 0;
   return true;
+}
+
+// --------------------------------------------------------- precision path
+// +-1 S on the matrix cores in BF16 or FP8 when the matrix is dense enough
+// for the dense contraction (d m n MACs at MFMA rate) to beat the sparse
+// kernel (nnz d FMAs at the VALU rate, with its gather and padding costs).
+// The threshold is a density in percent (the measured crossover of the two
+// kernels on MI355X); dense_min_pct overrides it.
+constexpr double kMfmaAutoPct[3] = {0.0, 3.5, 4.0};  // unused, BF16, FP8
+
+int mfma_format(int64_t m, int64_t n, int64_t nnz, int dist, int prec, const sk_tuning* tune) {
+  if (prec == SK_PREC_F32 || dist != SK_RADEMACHER) return 0;
+  const double pct = tune && tune->dense_min_pct > 0 ? (double)tune->dense_min_pct
+                                                     : kMfmaAutoPct[prec];
+  if (pct > 100.0) return 0;
+  const double density = 100.0 * (double)nnz / ((double)m * (double)n);
+  if (density < pct) return 0;
+  return prec == SK_PREC_BF16 ? MF_BF16 : MF_FP8;
+}
+
+bool plan_mfma(int64_t m, int64_t n, int64_t nnz, int64_t d, int fmt, const sk_tuning* tune,
+               Plan& P, double unit_cycles = 0.0) {
+  P = Plan{};
+  P.variant = 0;
+  P.mfma = fmt;
+  P.m_b = MF_MB;
+  P.e_max = 1 << 30;  // blocks are cut by rows only
+  P.row_bytes = 1;
+  P.d_b = MF_TM;
+  P.ldS = 0;
+  P.dt = 1;
+  P.cg = 0;
+  P.log2_cpr = 0;
+  P.tiles = (int32_t)((d + MF_TM - 1) / MF_TM);
+  P.ncr = (int32_t)((n + MF_TN - 1) / MF_TN);
+  P.col_per_wg = MF_TN;
+  P.nv = n;
+  P.r_max = std::max<int64_t>(1, std::min(m, nnz));
+  P.ngroups = (P.r_max + P.m_b - 1) / P.m_b;
+  P.nb_max = P.ngroups + 1;
+  P.lds = fmt == MF_BF16 ? sizeof(MfmaLds<MF_BF16>) : sizeof(MfmaLds<MF_FP8>);
+  P.dense_pct = 0;
+  P.kd_max = 0;
+  // cost per unit and block: MFMA issue (two accumulators per wave, 16
+  // rows per instruction, twice for FP8's hi + lo), the S tile and the
+  // scatter, a fixed overhead
+  const double R = (double)m * -std::expm1(-(double)nnz / (double)m);
+  const double blocks = std::ceil(R / P.m_b);
+  const double mf = (double)P.m_b / 16.0 * 2.0 * (fmt == MF_FP8 ? 2.0 : 1.0) * 16.0;
+  const double per_unit_block = mf + 300.0 + (double)nnz / std::max(1.0, blocks) / P.ncr / 4.0;
+  P.cost = blocks * per_unit_block * (double)P.tiles * P.ncr;
+  int64_t splits;
+  if (tune && tune->splits > 0) {
+    splits = tune->splits;
+  } else if (unit_cycles > 0) {
+    splits = (int64_t)std::ceil(P.cost / ((double)P.tiles * P.ncr * unit_cycles));
+  } else {
+    const int64_t units = (int64_t)P.tiles * P.ncr;
+    splits = (3 * 256 * 2 + units - 1) / units;  // about two rounds of three units per CU
+    splits = std::min<int64_t>(splits, 64);
+  }
+  P.splits = (int32_t)std::max<int64_t>(1, std::min<int64_t>(splits, P.nb_max));
+  P.slices = P.splits;
+  return true;
+}
+
+// the plan a request runs with: the matrix-core path or the sparse kernel
+bool plan_any(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, int prec,
+              const sk_tuning* tune, Plan& P, int forced_variant = -1, double unit_cycles = 0.0) {
+  const int fmt = mfma_format(m, n, nnz, dist, prec, tune);
+  if (fmt) return plan_mfma(m, n, nnz, d, fmt, tune, P, unit_cycles);
+  return plan_for(m, n, nnz, d, dist, tune, P, forced_variant, unit_cycles);
 }
 
 // Workspace of one sketch.  The header sits at offset 0 (the status call
@@ -423,8 +500,18 @@ Item make_item(const sk_csc* A, const Plan& P, int dist) {
   std::memset(&I, 0, sizeof I);
   I.m = A->m; I.n = A->n; I.nnz = A->nnz;
   I.colptr = A->colptr; I.rowidx = A->rowidx; I.vals = A->vals; I.vtype = A->vtype;
-  I.m_b = P.m_b; I.e_cap = P.e_max; I.row_bytes = P.ldS * 4;
+  I.m_b = P.m_b; I.e_cap = P.e_max; I.row_bytes = P.row_bytes;
   I.nv = P.nv; I.nb_max = P.nb_max; I.r_max = P.r_max;
+  if (P.mfma) {  // blocks of equal height; the cost follows the rows
+    I.w_row = 16;
+    I.w_ent = 1;
+    I.w_blk = 16 * 300;
+    I.cost_shift = 0;
+    const double bound = (double)P.r_max * I.w_row + (double)A->nnz * I.w_ent +
+                         (double)(P.nb_max + 1) * I.w_blk;
+    while (bound / (double)(int64_t(1) << I.cost_shift) > (double)(1 << 29)) ++I.cost_shift;
+    return I;
+  }
   // block cost weights in 1/16 wave instructions per tile: S generation per
   // row, multiply-adds (with the lockstep padding) and staging per entry, a
   // fixed cost per block
@@ -463,21 +550,26 @@ struct BatchPlan {
   int64_t hdrs = 0, items = 0, outs = 0, work = 0, counters = 0;
   int64_t ridx_all = 0, rcnt_all = 0, bfl_all = 0, seg_all = 0, bcost_all = 0, sums = 0;
   int64_t total = 0, t_out = 0;
-  int64_t units[3] = {0, 0, 0};
-  size_t lds[3] = {0, 0, 0};
+  // work-unit kinds: 0..2 the sparse kernel per distribution, 3 / 4 the
+  // matrix-core kernel in BF16 / FP8
+  int64_t units[5] = {0, 0, 0, 0, 0};
+  size_t lds[5] = {0, 0, 0, 0, 0};
 };
+
+int unit_kind(const Plan& P, int dist) { return P.mfma ? 2 + P.mfma : dist; }
 
 constexpr int kBatchUnitsPerSlot = 8;  // work units per persistent workgroup, for balance
 
 sk_status batch_plan(int32_t count, const sk_csc* A, const int64_t* d, const int32_t* dist,
                      int32_t prec, const sk_tuning* tune, BatchPlan& B) {
   if (count < 1 || !A || !d || !dist) return SK_EINVAL;
-  if (prec != SK_PREC_F32) return SK_EUNSUPPORTED;
+  if (prec < 0 || prec > 2) return SK_EINVAL;
   int64_t nmax = 0;
   for (int i = 0; i < count; ++i) {
     sk_status s = check_csc(&A[i]);
     if (s != SK_OK) return s;
     if (d[i] < 1 || dist[i] < 0 || dist[i] > 2) return SK_EINVAL;
+    if (prec != SK_PREC_F32 && dist[i] != SK_RADEMACHER) return SK_EUNSUPPORTED;
     nmax = std::max(nmax, A[i].n);
   }
   B.variant = nmax <= 512 ? 5 : (nmax <= 2048 ? 0 : 1);
@@ -485,7 +577,7 @@ sk_status batch_plan(int32_t count, const sk_csc* A, const int64_t* d, const int
   double total_cost = 0.0;
   for (int i = 0; i < count; ++i) {
     const sk_tuning* t = tune ? &tune[i] : nullptr;
-    if (!plan_for(A[i].m, A[i].n, A[i].nnz, d[i], dist[i], t, B.plans[i], B.variant, 0.0))
+    if (!plan_any(A[i].m, A[i].n, A[i].nnz, d[i], dist[i], prec, t, B.plans[i], B.variant, 0.0))
       return SK_EINVAL;
     total_cost += B.plans[i].cost;
   }
@@ -494,7 +586,7 @@ sk_status batch_plan(int32_t count, const sk_csc* A, const int64_t* d, const int
   const double unit = std::max(1.0, total_cost / ((double)cus * kBatchUnitsPerSlot));
   for (int i = 0; i < count; ++i) {
     const sk_tuning* t = tune ? &tune[i] : nullptr;
-    if (!plan_for(A[i].m, A[i].n, A[i].nnz, d[i], dist[i], t, B.plans[i], B.variant, unit))
+    if (!plan_any(A[i].m, A[i].n, A[i].nnz, d[i], dist[i], prec, t, B.plans[i], B.variant, unit))
       return SK_EINVAL;
     const Plan& P = B.plans[i];
     if ((int64_t)(P.nb_max + 1) * P.nv >= INT32_MAX) return SK_EUNSUPPORTED;
@@ -511,16 +603,17 @@ sk_status batch_plan(int32_t count, const sk_csc* A, const int64_t* d, const int
     const Plan& P = B.plans[i];
     Item I = make_item(&A[i], P, dist[i]);
     item_offsets(I, B.Z);
-    B.units[dist[i]] += (int64_t)P.tiles * P.ncr * P.splits;
-    B.lds[dist[i]] = std::max(B.lds[dist[i]], P.lds);
+    const int kind = unit_kind(P, dist[i]);
+    B.units[kind] += (int64_t)P.tiles * P.ncr * P.splits;
+    B.lds[kind] = std::max(B.lds[kind], P.lds);
     if (P.slices > 1) B.t_out += d[i] * A[i].n;
   }
   const InspectSizes& Z = B.Z;
-  const int64_t nunits = B.units[0] + B.units[1] + B.units[2];
+  const int64_t nunits = B.units[0] + B.units[1] + B.units[2] + B.units[3] + B.units[4];
   if (nunits >= INT32_MAX || Z.ridx >= INT32_MAX || Z.seg >= INT32_MAX || Z.bfl >= INT32_MAX)
     return SK_EUNSUPPORTED;
   B.work = off;     off = align_up(off + 8 * std::max<int64_t>(nunits, 1));
-  B.counters = off; off = align_up(off + 4 * 4);
+  B.counters = off; off = align_up(off + 4 * 8);
   B.ridx_all = off; off = align_up(off + 4 * (Z.ridx + 1));
   B.rcnt_all = off; off = align_up(off + 4 * std::max<int64_t>(Z.m, 1));
   B.bfl_all = off;  off = align_up(off + 4 * (Z.bfl + 1));
@@ -700,8 +793,9 @@ sk_status sk_sketch_workspace(const sk_csc* A, int64_t d, int32_t dist, int32_t 
   sk_status s = check_csc(A);
   if (s != SK_OK) return s;
   if (d < 1 || dist < 0 || dist > 2 || prec < 0 || prec > 2) return SK_EINVAL;
+  if (prec != SK_PREC_F32 && dist != SK_RADEMACHER) return SK_EUNSUPPORTED;
   Plan P;
-  if (!plan_for(A->m, A->n, A->nnz, d, dist, tune, P)) return SK_EINVAL;
+  if (!plan_any(A->m, A->n, A->nnz, d, dist, prec, tune, P)) return SK_EINVAL;
   *bytes = (size_t)layout_for(A->m, A->n, A->nnz, d, P).total;
   return SK_OK;
 }
@@ -715,7 +809,7 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
   if (prec < 0 || prec > 2) return SK_EINVAL;
   if (prec != SK_PREC_F32 && dist != SK_RADEMACHER) return SK_EUNSUPPORTED;
   Plan P;
-  if (!plan_for(A->m, A->n, A->nnz, d, dist, tune, P)) return SK_EINVAL;
+  if (!plan_any(A->m, A->n, A->nnz, d, dist, prec, tune, P)) return SK_EINVAL;
   if ((int64_t)(P.nb_max + 1) * P.nv >= INT32_MAX) return SK_EUNSUPPORTED;
   const Layout L = layout_for(A->m, A->n, A->nnz, d, P);
   if (!ws || ws_bytes < (size_t)L.total) return SK_EWORKSPACE;
@@ -769,14 +863,14 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
                          I.rowlist, I.bstart, dlist, doff, dhdr, drows);
       const int64_t nd_cap = std::max<int64_t>(1, std::min(P.nb_max, P.kd_max));
       hipLaunchKernelGGL(k_densify, dim3(blocks_for(nd_cap * nv, 256)), dim3(256), 0, st, I.seg,
-                         I.ent, nv, n, I.vbase, P.ldS * 4, dlist, doff, dhdr, dense);
+                         I.ent, nv, n, I.vbase, P.row_bytes, dlist, doff, dhdr, dense);
       if ((s = launch_ok()) != SK_OK) return s;
     }
     if ((s = run_block_costs(d_item, 1, Z, W, st)) != SK_OK) return s;
   }
 
-  // a3 + a4: S tiles and sparse accumulation
-  const Variant& V = kVariants[P.variant];
+  // a3 + a4: S tiles and sparse accumulation (or the whole contraction on
+  // the matrix cores for +-1 S in BF16/FP8)
   SketchParams K = make_params(P, I, d, row0, seed);
   K.dflag = P.dense_pct ? dflag : nullptr;
   const bool staged = P.slices > 1 || nv != n;  // partials, then the reduction
@@ -784,13 +878,24 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
   else { K.out = Ahat; K.ld = ld; K.split_stride = 0; }
   const int64_t grid = (int64_t)P.tiles * P.ncr * P.splits;
   if (grid >= INT32_MAX) return SK_EUNSUPPORTED;
-  SketchKernel kern = V.k[dist];
-  if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)P.lds) != hipSuccess)
-    return SK_EHIP;
-  if (phases & 2) {
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(V.wgs), P.lds, st, K);
-    if ((s = launch_ok()) != SK_OK) return s;
+  if (P.mfma) {
+    if (phases & 2) {
+      if (P.mfma == MF_BF16)
+        hipLaunchKernelGGL(k_sketch_mfma<MF_BF16>, dim3((unsigned)grid), dim3(MF_THREADS), 0, st, K);
+      else
+        hipLaunchKernelGGL(k_sketch_mfma<MF_FP8>, dim3((unsigned)grid), dim3(MF_THREADS), 0, st, K);
+      if ((s = launch_ok()) != SK_OK) return s;
+    }
+  } else {
+    const Variant& V = kVariants[P.variant];
+    SketchKernel kern = V.k[dist];
+    if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)P.lds) != hipSuccess)
+      return SK_EHIP;
+    if (phases & 2) {
+      hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(V.wgs), P.lds, st, K);
+      if ((s = launch_ok()) != SK_OK) return s;
+    }
   }
   // a5: dense row blocks on the matrix cores, into the last partial slice
   if ((phases & 8) && P.dense_pct) {
@@ -926,7 +1031,7 @@ sk_status sk_sketch_batched(int32_t count, const sk_csc* A, const int64_t* d, co
   for (int i = 0; i < count; ++i) {
     const Plan& P = B.plans[i];
     const int32_t nu = P.tiles * P.ncr * P.splits;
-    for (int32_t u = 0; u < nu; ++u) units.push_back({P.cost / nu, i, u, dist[i]});
+    for (int32_t u = 0; u < nu; ++u) units.push_back({P.cost / nu, i, u, unit_kind(P, dist[i])});
   }
   std::stable_sort(units.begin(), units.end(), [](const U& a, const U& b) {
     if (a.dist != b.dist) return a.dist < b.dist;
@@ -947,26 +1052,38 @@ sk_status sk_sketch_batched(int32_t count, const sk_csc* A, const int64_t* d, co
 
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(count * (int64_t)sizeof(Header) / 4, 256)),
                      dim3(256), 0, st, (int32_t*)hdrs, count * (int64_t)sizeof(Header) / 4, 0);
-  hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, counters, int64_t(4), 0);
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, counters, int64_t(8), 0);
   // a1 + a2 for every item at once
   if ((s = run_inspector(d_items, count, Z, W, st)) != SK_OK) return s;
   if ((s = run_block_costs(d_items, count, Z, W, st)) != SK_OK) return s;
-  // a7: one persistent launch per distribution present
+  // a7: one persistent launch per kind of work unit present
   int cus = 256;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess) cus = 256;
   int64_t first = 0;
-  for (int dd = 0; dd < 3; ++dd) {
-    if (B.units[dd] == 0) continue;
-    PersistentKernel kern = V.p[dd];
-    if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)B.lds[dd]) != hipSuccess)
-      return SK_EHIP;
-    const int per_cu = V.wgs >= 1024 ? 1 : 2;
-    const int64_t grid = std::min<int64_t>(B.units[dd], (int64_t)cus * per_cu);
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(V.wgs), B.lds[dd], st, d_outs,
-                       d_work + first, (int)B.units[dd], counters + dd);
+  for (int kind = 0; kind < 5; ++kind) {
+    if (B.units[kind] == 0) continue;
+    if (kind < 3) {
+      PersistentKernel kern = V.p[kind];
+      if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)B.lds[kind]) != hipSuccess)
+        return SK_EHIP;
+      const int per_cu = V.wgs >= 1024 ? 1 : 2;
+      const int64_t grid = std::min<int64_t>(B.units[kind], (int64_t)cus * per_cu);
+      hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(V.wgs), B.lds[kind], st, d_outs,
+                         d_work + first, (int)B.units[kind], counters + kind);
+    } else {
+      const int64_t grid = std::min<int64_t>(B.units[kind], (int64_t)cus * 3);
+      if (kind == 2 + MF_BF16)
+        hipLaunchKernelGGL(k_sketch_mfma_persistent<MF_BF16>, dim3((unsigned)grid),
+                           dim3(MF_THREADS), 0, st, d_outs, d_work + first, (int)B.units[kind],
+                           counters + kind);
+      else
+        hipLaunchKernelGGL(k_sketch_mfma_persistent<MF_FP8>, dim3((unsigned)grid),
+                           dim3(MF_THREADS), 0, st, d_outs, d_work + first, (int)B.units[kind],
+                           counters + kind);
+    }
     if ((s = launch_ok()) != SK_OK) return s;
-    first += B.units[dd];
+    first += B.units[kind];
   }
   // a6 for every item with split partials
   if (B.t_out > 0)
@@ -987,9 +1104,11 @@ sk_status sk_sketch_batched_plan(int32_t count, const sk_csc* A, const int64_t* 
     std::memset(&chosen[i], 0, sizeof chosen[i]);
     chosen[i].rows_per_block = P.m_b;
     chosen[i].splits = P.splits;
-    chosen[i].variant = P.variant + 1;
-    chosen[i].dense_min_pct = 101;
-    chosen[i].tile_rows = P.d_b;
+    chosen[i].variant = P.mfma ? 0 : P.variant + 1;
+    // sparse items: no dense blocks (and no matrix-core path); matrix-core
+    // items: the caller's threshold (0 = the automatic one) picks it again
+    chosen[i].dense_min_pct = P.mfma ? (tune ? tune[i].dense_min_pct : 0) : 101;
+    chosen[i].tile_rows = P.mfma ? 0 : P.d_b;
     chosen[i].col_split = 1;
   }
   return SK_OK;

@@ -181,22 +181,38 @@ class BatchItem:
     density: float
 
 
-def workload_batched(count: int = 512, seed: int = 40, m_lo: int = 10_000, m_hi: int = 500_000,
-                     n_lo: int = 50, n_hi: int = 500, rho_lo: float = 0.005,
-                     rho_hi: float = 0.05) -> list[BatchItem]:
-    """``count`` independent sketches: m log-uniform, n uniform, d uniform in [2n, 4n],
-    density uniform, exact round(rho m n) positions, values U(-1,1) FP32; S seed 40000+b."""
+def workload_batched_specs(count: int = 512, seed: int = 40, m_lo: int = 10_000,
+                           m_hi: int = 500_000, n_lo: int = 50, n_hi: int = 500,
+                           rho_lo: float = 0.005, rho_hi: float = 0.05) -> list[tuple]:
+    """The items' shapes: (m, n, d, nnz, matrix seed, S seed, rho) per item, drawn in
+    order from one seeded stream (m log-uniform, n and d uniform, d in [2n, 4n])."""
     rng = np.random.default_rng(seed)
-    items = []
+    specs = []
     for b in range(count):
         m = int(np.floor(np.exp(rng.uniform(np.log(m_lo), np.log(m_hi)))))
         n = int(rng.integers(n_lo, n_hi + 1))
         d = int(rng.integers(2 * n, 4 * n + 1))
         rho = float(rng.uniform(rho_lo, rho_hi))
         nnz = int(round(rho * m * n))
-        A = uniform_positions(m, n, nnz, int(rng.integers(0, 2**31)), "uniform", np.float32)
-        items.append(BatchItem(A, d, 40000 + b, rho))
-    return items
+        specs.append((m, n, d, nnz, int(rng.integers(0, 2**31)), 40000 + b, rho))
+    return specs
+
+
+def _batched_item(spec) -> BatchItem:
+    m, n, d, nnz, mseed, sseed, rho = spec
+    return BatchItem(uniform_positions(m, n, nnz, mseed, "uniform", np.float32), d, sseed, rho)
+
+
+def workload_batched(count: int = 512, seed: int = 40, workers: int = 1, **kw) -> list[BatchItem]:
+    """``count`` independent sketches: m log-uniform, n uniform, d uniform in [2n, 4n],
+    density uniform, exact round(rho m n) positions, values U(-1,1) FP32; S seed 40000+b.
+    ``workers`` > 1 generates the items in a process pool (same items)."""
+    specs = workload_batched_specs(count, seed, **kw)
+    if workers <= 1:
+        return [_batched_item(s) for s in specs]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_batched_item, specs, chunksize=1)
 
 
 def ls_request(seed: int, m: int, n: int, dense_rows: int = 2000, noise: float = 1e-6,

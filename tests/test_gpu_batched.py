@@ -41,11 +41,11 @@ def _rel(got, ref):
     return norm, (col.max() if col.size else 0.0)
 
 
-def _run_batch(B, items):
+def _run_batch(B, items, prec=0):
     import torch
     mats = [B.DeviceCsc.from_host(A) for A, _, _, _ in items]
     batch = B.Batch(mats, [d for _, d, _, _ in items], [s for _, _, s, _ in items],
-                    [sd for _, _, _, sd in items])
+                    [sd for _, _, _, sd in items], prec=prec)
     ws = B.alloc_workspace(batch.workspace_bytes())
     outs = [torch.full((A.n, d), float("nan"), dtype=torch.float32, device="cuda")
             for A, d, _, _ in items]
@@ -93,3 +93,34 @@ def test_batched_edge_items_and_validation(B, oracle_lib):
                                 sd) if A.nnz else np.zeros((d, A.n))
         norm, col = _rel(got, ref)
         assert norm <= TOL_NORM and col <= TOL_COL
+
+
+@pytest.mark.parametrize("prec", [1, 2])  # BF16, FP8
+def test_batched_precision_path(B, oracle_lib, prec):
+    # +-1 items: the dense-enough ones on the matrix cores (within 1e-2 of
+    # the FP64 oracle), the sparsest on the FP32 kernel (within 1e-5); each
+    # bitwise equal to its single call with the reported tuning
+    rng = np.random.default_rng(40 + prec)
+    items = []
+    for b in range(14):
+        m = int(np.exp(rng.uniform(np.log(2_000), np.log(60_000))))
+        n = int(rng.integers(20, 300))
+        d = int(rng.integers(2 * n, 4 * n + 1))
+        rho = 0.001 if b % 5 == 0 else float(rng.uniform(0.005, 0.08))
+        A = inputs.uniform_positions(m, n, int(round(rho * m * n)), int(rng.integers(1 << 30)),
+                                     "uniform", np.float32)
+        items.append((A, d, "rademacher", 7000 + b))
+    batch, mats, outs, ws = _run_batch(B, items, prec)
+    assert batch.status(ws) == [0] * len(items)
+    plans = batch.plan()
+    for i, ((A, d, dist, sd), dA, out, plan) in enumerate(zip(items, mats, outs, plans)):
+        mf = plan["variant"] == 0
+        print(f"item {i}: m={A.m} n={A.n} nnz={A.nnz} d={d} mfma={mf}", flush=True)
+        got = out.t().cpu().numpy().astype(np.float64)
+        ref = oracle_lib.sketch(A.m, A.n, A.colptr, A.rowidx, A.vals.astype(np.float64), d, dist,
+                                sd)
+        norm, col = _rel(got, ref)
+        assert norm <= (1e-2 if mf else TOL_NORM), (i, norm)
+        assert mf == (A.nnz / (A.m * A.n) >= 0.035 * (prec == 1) + 0.04 * (prec == 2)), i
+        single = B.sketch(dA, d, dist, sd, prec=prec, tune=plan).cpu().numpy().astype(np.float64)
+        assert np.array_equal(single, got), i

@@ -293,3 +293,39 @@ def test_row_weight_mix(B, oracle_lib, dist):
         got = run_gpu(B, A, d, dist, 17, tune=tune)
         norm, col = rel_errors(got, ref)
         assert norm <= TOL_NORM and col <= TOL_COL, (tune, norm, col)
+
+
+# --------------------------------------------------------- precision path
+@pytest.mark.parametrize("prec", [1, 2])  # BF16, FP8
+@pytest.mark.parametrize("m,n,d,row0", [(20_000, 300, 700, 0), (9_001, 77, 203, 45),
+                                        (4_000, 129, 64, 128)])
+def test_precision_path_against_oracle(B, oracle_lib, prec, m, n, d, row0):
+    # +-1 S is exact in BF16 and FP8: on the matrix cores only A's values round;
+    # within 1e-2 of the FP64 oracle on U(-1,1) values
+    A = inputs.uniform_positions(m, n, int(0.03 * m * n), m + n + prec, "uniform", np.float32)
+    ref = run_oracle(oracle_lib, A, d, "rademacher", 31, row0=row0)
+    print(f"precision {prec} m={m} n={n} d={d} row0={row0}", flush=True)
+    dA = B.DeviceCsc.from_host(A)
+    got = B.sketch(dA, d, "rademacher", 31, row0=row0, prec=prec,
+                   tune={"dense_min_pct": 1}).cpu().numpy().astype(np.float64)
+    norm, _ = rel_errors(got, ref)
+    assert norm <= 1e-2, norm
+    # values exact in the operand format: the error is that of FP32 sums
+    vals = np.where(A.vals >= 0, 1.0, -1.0) * np.where(np.abs(A.vals) > 0.5, 0.5, 0.25)
+    Ae = inputs.Csc(A.m, A.n, A.colptr, A.rowidx, vals.astype(np.float32))
+    got = B.sketch(B.DeviceCsc.from_host(Ae), d, "rademacher", 31, row0=row0, prec=prec,
+                   tune={"dense_min_pct": 1}).cpu().numpy().astype(np.float64)
+    norm, col = rel_errors(got, run_oracle(oracle_lib, Ae, d, "rademacher", 31, row0=row0))
+    assert norm <= TOL_NORM and col <= TOL_COL, (norm, col)
+
+
+def test_precision_path_rules(B):
+    m, n = 5000, 40
+    A = inputs.uniform_positions(m, n, 2000, 4, "uniform", np.float32)
+    dA = B.DeviceCsc.from_host(A)
+    with pytest.raises(B.SketchError):  # only +-1 S is exact in the narrow formats
+        B.sketch(dA, 80, "uniform", 1, prec=1)
+    # below the density threshold the FP32 sparse kernel runs (same result as prec 0)
+    a = B.sketch(dA, 80, "rademacher", 1, prec=1, tune={"dense_min_pct": 50}).cpu().numpy()
+    b = B.sketch(dA, 80, "rademacher", 1, prec=0).cpu().numpy()
+    assert np.array_equal(a, b)
