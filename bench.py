@@ -245,17 +245,21 @@ def bench_batched(args):
         return float(np.median(best))
 
     modes = {}
+    # --dense-min-pct: the density (percent) from which items run on the
+    # matrix cores in the BF16/FP8 modes (0: the library's measured threshold)
     for prec, pname in ((0, "f32"), (1, "bf16"), (2, "fp8")):
-        wss = [B.alloc_workspace(B.workspace_bytes(A, d, "rademacher", prec))
+        tune = {"dense_min_pct": args.dense_min_pct} if args.dense_min_pct and prec else None
+        wss = [B.alloc_workspace(B.workspace_bytes(A, d, "rademacher", prec, tune))
                for A, d in zip(mats, ds)]
 
         def plain():
             for A, d, sd, o, w in zip(mats, ds, seeds, outs, wss):
-                B.sketch_into(A, d, "rademacher", sd, o, w, prec=prec)
+                B.sketch_into(A, d, "rademacher", sd, o, w, prec=prec, tune=tune)
         ms = timed(plain, args.steps)
         modes[f"plain_{pname}"] = {"ms": ms, "nnz_d_per_s": work / (ms * 1e-3), "error": err()}
         del wss
-        batch = B.Batch(mats, ds, ["rademacher"] * len(mats), seeds, prec=prec)
+        batch = B.Batch(mats, ds, ["rademacher"] * len(mats), seeds,
+                        tunes=[tune] * len(mats) if tune else None, prec=prec)
         ws = B.alloc_workspace(batch.workspace_bytes())
         ms = timed(lambda: batch.run(outs, ws), args.steps)
         st = batch.status(ws)
@@ -297,6 +301,7 @@ def main():
     ap.add_argument("--dense-min-pct", type=int, default=0)
     ap.add_argument("--col-split", type=int, default=0, help="0 auto, 1 off, 2 on")
     ap.add_argument("--row-pad", type=int, default=0)
+    ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-pool", type=int, default=24)
     ap.add_argument("--serve-requests", type=int, default=150)
@@ -341,7 +346,7 @@ def main():
     dA = B.DeviceCsc.from_host(A, dtype=np.float32 if A.vals.dtype != np.float64 else None)
     tune = {"variant": args.variant, "rows_per_block": args.rows_per_block,
             "splits": args.splits, "dense_min_pct": args.dense_min_pct,
-            "col_split": args.col_split, "row_pad": args.row_pad}
+            "col_split": args.col_split, "row_pad": args.row_pad, "tile_rows": args.tile_rows}
     ws = B.alloc_workspace(B.workspace_bytes(dA, d, dist, tune=tune))
     out = torch.empty((A.n, d), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()

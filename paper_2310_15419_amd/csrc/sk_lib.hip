@@ -129,7 +129,7 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
   if (v < 0) {
     // auto: enough columns per workgroup, then the most S rows per lane
     if (n <= 512) v = 5;
-    else if (n <= 2048) v = 0;
+    else if (n <= 2048) v = 2;  // eight S rows per lane: measured fastest at n ~ 1e3
     else v = 1;
   }
   const Variant& V = kVariants[v];
@@ -151,7 +151,9 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
   P.cg = (int32_t)cg;
   P.ncr = ncr;
   P.col_per_wg = (int32_t)(cg * V.cs);
-  const int budget = (V.wgs >= 1024 ? kLdsPerCu : kLdsPerCu / 2) - 1024;
+  // LDS per workgroup minus the static part and the staged segment bounds
+  const int seg_bytes = (P.col_per_wg + 1) * 4;
+  const int budget = (V.wgs >= 1024 ? kLdsPerCu : kLdsPerCu / 2) - 1024 - seg_bytes;
   const int64_t rmax = std::max<int64_t>(1, std::min(m, nnz));
   // entries per nonempty row if the positions were uniform (the expected
   // number of nonempty rows is m (1 - exp(-nnz / m)))
@@ -200,7 +202,7 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
     Q.m_b = (int32_t)m_b;
     Q.e_max = (int32_t)e_of(m_b);
     if (Q.e_max < 2) continue;
-    Q.lds = (size_t)m_b * Q.ldS * 4 + (size_t)(Q.e_max + 2) * 8;
+    Q.lds = (size_t)m_b * Q.ldS * 4 + (size_t)(Q.e_max + 2) * 8 + (size_t)seg_bytes;
     Q.r_max = rmax;
     Q.ngroups = (rmax + m_b - 1) / m_b;
     // groups, plus at most two blocks per e_max entries from the entry cuts
@@ -288,13 +290,13 @@ bool plan_mfma(int64_t m, int64_t n, int64_t nnz, int64_t d, int fmt, const sk_t
   P.lds = fmt == MF_BF16 ? sizeof(MfmaLds<MF_BF16>) : sizeof(MfmaLds<MF_FP8>);
   P.dense_pct = 0;
   P.kd_max = 0;
-  // cost per unit and block: MFMA issue (two accumulators per wave, 16
-  // rows per instruction, twice for FP8's hi + lo), the S tile and the
-  // scatter, a fixed overhead
+  // cost per unit and block in CU-cycles: MFMA issue (four accumulators per
+  // wave, 16 rows per instruction at 32 cycles, two waves per SIMD; twice
+  // for FP8's hi + lo), the dense-tile clear and the scatter, a fixed overhead
   const double R = (double)m * -std::expm1(-(double)nnz / (double)m);
   const double blocks = std::ceil(R / P.m_b);
-  const double mf = (double)P.m_b / 16.0 * 2.0 * (fmt == MF_FP8 ? 2.0 : 1.0) * 16.0;
-  const double per_unit_block = mf + 300.0 + (double)nnz / std::max(1.0, blocks) / P.ncr / 4.0;
+  const double mf = (double)P.m_b / 16.0 * 4.0 * 2.0 * 32.0 * (fmt == MF_FP8 ? 2.0 : 1.0) / 4.0;
+  const double per_unit_block = mf + 600.0 + (double)nnz / std::max(1.0, blocks) / P.ncr / 8.0;
   P.cost = blocks * per_unit_block * (double)P.tiles * P.ncr;
   int64_t splits;
   if (tune && tune->splits > 0) {
@@ -303,7 +305,7 @@ bool plan_mfma(int64_t m, int64_t n, int64_t nnz, int64_t d, int fmt, const sk_t
     splits = (int64_t)std::ceil(P.cost / ((double)P.tiles * P.ncr * unit_cycles));
   } else {
     const int64_t units = (int64_t)P.tiles * P.ncr;
-    splits = (3 * 256 * 2 + units - 1) / units;  // about two rounds of three units per CU
+    splits = (2 * 256 * 2 + units - 1) / units;  // about two rounds of two units per CU
     splits = std::min<int64_t>(splits, 64);
   }
   P.splits = (int32_t)std::max<int64_t>(1, std::min<int64_t>(splits, P.nb_max));
@@ -572,7 +574,7 @@ sk_status batch_plan(int32_t count, const sk_csc* A, const int64_t* d, const int
     if (prec != SK_PREC_F32 && dist[i] != SK_RADEMACHER) return SK_EUNSUPPORTED;
     nmax = std::max(nmax, A[i].n);
   }
-  B.variant = nmax <= 512 ? 5 : (nmax <= 2048 ? 0 : 1);
+  B.variant = nmax <= 512 ? 5 : (nmax <= 2048 ? 2 : 1);
   B.plans.resize(count);
   double total_cost = 0.0;
   for (int i = 0; i < count; ++i) {
@@ -1072,7 +1074,7 @@ sk_status sk_sketch_batched(int32_t count, const sk_csc* A, const int64_t* d, co
       hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(V.wgs), B.lds[kind], st, d_outs,
                          d_work + first, (int)B.units[kind], counters + kind);
     } else {
-      const int64_t grid = std::min<int64_t>(B.units[kind], (int64_t)cus * 3);
+      const int64_t grid = std::min<int64_t>(B.units[kind], (int64_t)cus * 2);
       if (kind == 2 + MF_BF16)
         hipLaunchKernelGGL(k_sketch_mfma_persistent<MF_BF16>, dim3((unsigned)grid),
                            dim3(MF_THREADS), 0, st, d_outs, d_work + first, (int)B.units[kind],

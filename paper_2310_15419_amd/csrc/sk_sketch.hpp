@@ -55,7 +55,7 @@ struct SketchParams {
 
 // ---------------------------------------------------------------- S tile
 // Fill S_lds[l * ldS + t] = S(grow0 + t, rows[l]) for l < rb, t < d_b.
-template <int DIST, int WGS>
+template <int DIST, int WGS, int U>
 __device__ __forceinline__ void fill_tile(float* __restrict__ S_lds, const SketchParams& P,
                                           const int32_t* __restrict__ rows, int rb,
                                           uint64_t grow0) {
@@ -82,7 +82,7 @@ __device__ __forceinline__ void fill_tile(float* __restrict__ S_lds, const Sketc
     }
   } else if ((grow0 & 3u) == 0) {
     // aligned: chunk ch of row l is exactly generator group grow0/4 + ch
-    constexpr int U = 4;
+    // U generator calls in flight per thread
     const uint64_t g0 = grow0 >> 2;
     for (int base = tid; base < total; base += U * WGS) {
       int32_t jr[U];
@@ -169,8 +169,11 @@ __device__ __forceinline__ void stage_entries(uint2* __restrict__ E_lds,
 template <int DIST, int DL, int Q, int CS, int WGS>
 __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, int tile, int crange,
                                             unsigned char* __restrict__ smem) {
+  // LDS: S tile (m_b x ldS floats) | entries (e_max + 2) | segment bounds of
+  // the unit's columns (col_per_wg + 1)
   float* S_lds = reinterpret_cast<float*>(smem);
   uint2* E_lds = reinterpret_cast<uint2*>(smem + (size_t)P.m_b * P.ldS * sizeof(float));
+  int32_t* seg_lds = reinterpret_cast<int32_t*>(E_lds + P.e_max + 2);
 
   const int tid = threadIdx.x;
   const int64_t i_tile = (int64_t)tile * P.d_b;
@@ -209,9 +212,13 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
     const int64_t b_lo = first_at((split * T + P.splits - 1) / P.splits);
     const int64_t b_hi =
         split + 1 == P.splits ? nb : first_at(((split + 1) * T + P.splits - 1) / P.splits);
-    // segment bounds of this group's columns in block b: loaded one block
-    // ahead so their latency hides behind the previous block's accumulation
-    int32_t pbn[CS + 1];
+    // segment bounds of the unit's columns in block b: loaded one block ahead
+    // (a few values per thread) so their latency hides behind the previous
+    // block's accumulation, then staged in LDS for the column walk
+    constexpr int KS = ((WGS / Q) * CS + 1 + WGS - 1) / WGS;
+    const int64_t cw0 = (int64_t)crange * P.col_per_wg;
+    const int64_t ncw = P.n - cw0 < P.col_per_wg ? P.n - cw0 : P.col_per_wg;
+    int32_t sreg[KS];
     int32_t beg_n = 0, end_n = 0, dense_n = 0, r0_n = 0, r1_n = 0;
     auto load_bounds = [&](int64_t b) {
       const int32_t* segb = P.seg + b * P.n;
@@ -221,11 +228,12 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
       r1_n = P.bstart[b + 1];
       dense_n = P.dflag ? P.dflag[b] : 0;
 #pragma unroll
-      for (int c = 0; c <= CS; ++c) {
-        const int64_t k = kbase + c;
-        pbn[c] = segb[k < P.n ? k : P.n];
+      for (int k = 0; k < KS; ++k) {
+        const int64_t i = tid + k * WGS;
+        sreg[k] = segb[cw0 + (i < ncw ? i : ncw)];
       }
     };
+    const int cl = cgi * CS;  // the group's first column inside the unit
     if (b_lo < b_hi) load_bounds(b_lo);
     for (int64_t b = b_lo; b < b_hi; ++b) {
       if (dense_n) {  // the block runs on the dense (matrix core) path
@@ -236,16 +244,19 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
       const int rb = r1_n - r0_n;
       const int32_t blk_beg = beg_n;
       const int32_t blk_end = end_n;
-      int32_t pb[CS + 1];
+      __syncthreads();  // the previous block's tile, entries and bounds are consumed
 #pragma unroll
-      for (int c = 0; c <= CS; ++c) pb[c] = active ? pbn[c] : blk_end;
-      __syncthreads();  // the previous block's tile and entries are consumed
+      for (int k = 0; k < KS; ++k) {
+        const int i = tid + k * WGS;
+        if (i <= P.col_per_wg) seg_lds[i] = sreg[k];
+      }
       // pass: entries [sp, s1) are processed; staging starts at the even s0a
       int32_t sp = blk_beg;
       int32_t s0a = sp & ~1;
       int32_t s1 = (blk_end - s0a < P.e_max) ? blk_end : s0a + P.e_max;
       stage_entries<WGS>(E_lds, P.ent, s0a, s1);
-      fill_tile<DIST, WGS>(S_lds, P, P.rowlist + row_beg, rb, grow0);
+      // fewer generator calls in flight when the accumulators are many
+      fill_tile<DIST, WGS, (DL * CS >= 64 ? 2 : 4)>(S_lds, P, P.rowlist + row_beg, rb, grow0);
       bool first_pass = true;
       while (true) {
         __builtin_amdgcn_s_waitcnt(0);
@@ -255,8 +266,9 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
         if (active) {
 #pragma unroll
           for (int c = 0; c < CS; ++c) {
-            const int32_t lo = pb[c] > sp ? pb[c] : sp;
-            const int32_t hi = pb[c + 1] < s1 ? pb[c + 1] : s1;
+            const int32_t pc0 = seg_lds[cl + c], pc1 = seg_lds[cl + c + 1];
+            const int32_t lo = pc0 > sp ? pc0 : sp;
+            const int32_t hi = pc1 < s1 ? pc1 : s1;
             int32_t p = lo - s0a;
             const int32_t pe = hi - s0a;
             for (; p + 1 < pe; p += 2) {
