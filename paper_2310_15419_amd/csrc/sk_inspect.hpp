@@ -79,9 +79,11 @@ struct Item {
   int32_t* bfl;       // r_max + 1, region of a concatenated array
   int32_t* bstart;    // nb_max + 1
   int32_t* vbase;     // n + 1, region of a concatenated array; nullptr: no splitting
-  int32_t* pos;       // (nb_max + 1) * nv
+  int32_t* pos;       // (nb_max + 1) * nv; after the scan: seg - pos (where a
+                      // (block, column)'s entries go, less its first position)
   int32_t* seg;       // nb_max * nv + 1, region of a concatenated array
   uint2* ent;         // nnz + 2
+  int2* rowinfo;      // m: {block, row offset in the S tile in bytes} of row r
   int32_t* bcost;     // nb_max + 1, region of a concatenated array: block costs,
                       // then their exclusive prefix (splits cut it evenly)
   const int32_t* dflag;  // per block: nonzero on the dense path (may be null)
@@ -103,6 +105,7 @@ struct Item {
   int64_t o_seg;      // nb_max * nv + 1
   int64_t o_nnz;      // nnz
   int64_t o_blk;      // nb_max + 1
+  int64_t o_rt;       // row tiles of the counting pass, ceil(m / RT_ROWS)
 };
 
 template <typename T>
@@ -236,10 +239,50 @@ __global__ void k_items(const Item* __restrict__ it, int count, int64_t total) {
   Op::run(it[i], g - it[i].*F);
 }
 
+// One thread per index of an entry-indexed space (field F holds each item's
+// offset); Op::run also gets the column of the entry, found by a search
+// limited to the columns of the workgroup's first and last entries (one
+// column, typically) instead of one over all of colptr.
+template <int64_t Item::*F, class Op>
+__global__ __launch_bounds__(256) void k_items_cols(const Item* __restrict__ it, int count,
+                                                    int64_t total) {
+  __shared__ int s_item[2];
+  __shared__ int64_t s_col[2];
+  const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t g = g0 + threadIdx.x;
+  const int64_t glast = (g0 + blockDim.x < total ? g0 + blockDim.x : total) - 1;
+  if (threadIdx.x < 2) {
+    const int64_t gg = threadIdx.x == 0 ? g0 : glast;
+    const int i = count == 1 ? 0 : find_item<F>(it, count, gg);
+    const Item& I = it[i];
+    int64_t t = gg - I.*F;
+    if (t >= I.nnz) t = I.nnz - 1;
+    s_item[threadIdx.x] = i;
+    s_col[threadIdx.x] = t >= 0 ? column_of(I.colptr, I.n, t) : 0;
+  }
+  __syncthreads();
+  if (g >= total) return;
+  const bool one = s_item[0] == s_item[1];
+  const int i = one ? s_item[0] : find_item<F>(it, count, g);
+  const Item& I = it[i];
+  const int64_t t = g - I.*F;
+  int64_t k = 0;
+  if (t < I.nnz) {
+    int64_t lo = one ? s_col[0] : 0, hi = one ? s_col[1] : I.n - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (I.colptr[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    k = lo;
+  }
+  Op::run(I, t, k);
+}
+
 // Validate, mark occupied rows and count entries per row.  One thread per
-// nonzero (and per colptr entry).
+// nonzero (and per colptr entry); k is the column of nonzero t.
 struct OpValidate {
-  static __device__ void run(const Item& I, int64_t t) {
+  static __device__ void run(const Item& I, int64_t t, int64_t k) {
     int bad = 0;
     if (t <= I.n) {
       const int64_t c = I.colptr[t];
@@ -250,20 +293,53 @@ struct OpValidate {
     }
     if (t < I.nnz) {
       const int32_t r = I.rowidx[t];
-      if (r < 0 || r >= I.m) {
-        bad |= ST_RANGE;
-      } else {
-        I.ridx[r] = 1;
-        atomicAdd(&I.rcnt[r], 1);
-      }
-      if (t > 0) {
-        const int64_t k = column_of(I.colptr, I.n, t);
-        if (I.colptr[k] < t && I.rowidx[t - 1] >= r) bad |= ST_UNSORTED;
-      }
+      if (r < 0 || r >= I.m) bad |= ST_RANGE;
+      if (t > 0 && I.colptr[k] < t && I.rowidx[t - 1] >= r) bad |= ST_UNSORTED;
     }
     if (bad) atomicOr(&I.hdr->status, bad);
   }
 };
+
+// Entries per row without global atomics: one workgroup per tile of RT_ROWS
+// rows of one item.  Rows are sorted inside each column, so the entries of a
+// column that fall in the tile are one run, found by a binary search (one
+// column per lane); they are counted with LDS atomics, then the counts and
+// the occupancy flags are written out in order.  (On malformed input the
+// counts are meaningless, and the validation status stops everything after.)
+constexpr int RT_ROWS = 8192;
+__global__ __launch_bounds__(1024) void k_row_counts(const Item* __restrict__ it, int count,
+                                                      int64_t total_tiles) {
+  __shared__ int32_t cnt[RT_ROWS];
+  const int64_t g = blockIdx.x;
+  if (g >= total_tiles) return;
+  const int i = count == 1 ? 0 : find_item<&Item::o_rt>(it, count, g);
+  const Item& I = it[i];
+  const int64_t r0 = (g - I.o_rt) * RT_ROWS;
+  const int64_t r1 = r0 + RT_ROWS < I.m ? r0 + RT_ROWS : I.m;
+  for (int j = threadIdx.x; j < RT_ROWS; j += blockDim.x) cnt[j] = 0;
+  __syncthreads();
+  for (int64_t k = threadIdx.x; k < I.n; k += blockDim.x) {
+    const int64_t c0 = I.colptr[k], c1 = I.colptr[k + 1];
+    if (c0 < 0 || c1 > I.nnz || c1 < c0) continue;  // malformed (flagged by the validation)
+    int64_t lo = c0, hi = c1;  // first entry with row >= r0
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (I.rowidx[mid] < r0) lo = mid + 1;
+      else hi = mid;
+    }
+    for (int64_t p = lo; p < c1; ++p) {
+      const int32_t r = I.rowidx[p];
+      if (r >= r1 || r < r0) break;
+      atomicAdd(&cnt[r - r0], 1);
+    }
+  }
+  __syncthreads();
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    const int32_t c = cnt[r - r0];
+    I.rcnt[r] = c;
+    I.ridx[r] = c > 0 ? 1 : 0;
+  }
+}
 
 // region bases after a concatenated scan
 enum : int { SCAN_RIDX = 0, SCAN_BFL = 1, SCAN_VBASE = 2, SCAN_SEG = 3, SCAN_COST = 4 };
@@ -454,26 +530,39 @@ struct OpBlockCnt {
   }
 };
 
-// ent[seg[b nv + v] + (position in v - pos[b nv + v])] = {row in block *
-// row_bytes, value}
-struct OpScatter {
-  static __device__ void run(const Item& I, int64_t p) {
+// rowinfo[r] = {block of row r, its offset in the S tile in bytes}
+struct OpRowInfo {
+  static __device__ void run(const Item& I, int64_t r) {
     if (I.hdr->status) return;
-    const int32_t r = I.rowidx[p];
     const int32_t c = I.ridx[r];
+    if (I.ridx[r + 1] == c) return;  // empty row
     const int32_t b = I.bfl[c + 1] - 1;
-    const int32_t l = c - I.bstart[b];
-    const int64_t k = column_of(I.colptr, I.n, p);
+    I.rowinfo[r] = make_int2(b, (c - I.bstart[b]) * I.row_bytes);
+  }
+};
+
+// pos[t] <- seg[t] - pos[t] (t < nb_max nv): an entry at position q of its
+// (virtual) column in block b goes to pos[b nv + v] + q
+struct OpSegPos {
+  static __device__ void run(const Item& I, int64_t t) {
+    if (I.hdr->status) return;
+    I.pos[t] = I.seg[t] - I.pos[t];
+  }
+};
+
+// ent[pos[b nv + v] + position in v] = {row offset in the S tile, value}
+struct OpScatter {
+  static __device__ void run(const Item& I, int64_t p, int64_t k) {
+    if (I.hdr->status) return;
+    const int2 ri = I.rowinfo[I.rowidx[p]];
     int64_t v = k, q = p - I.colptr[k];
     if (I.vbase) {
       const int64_t s = I.vbase[k + 1] - I.vbase[k];
       v = I.vbase[k] + q % s;
       q = q / s;
     }
-    const int64_t bv = (int64_t)b * I.nv + v;
-    const int64_t dest = (int64_t)I.seg[bv] + (q - (int64_t)I.pos[bv]);
-    I.ent[dest] = make_uint2((uint32_t)l * (uint32_t)I.row_bytes,
-                             __float_as_uint(load_value(I.vals, I.vtype, p)));
+    const int64_t dest = (int64_t)I.pos[(int64_t)ri.x * I.nv + v] + q;
+    I.ent[dest] = make_uint2((uint32_t)ri.y, __float_as_uint(load_value(I.vals, I.vtype, p)));
   }
 };
 

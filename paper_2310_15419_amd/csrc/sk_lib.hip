@@ -66,6 +66,7 @@ const Variant kVariants[] = {
     SK_VARIANT(4, 4, 2, 1024),   // 6: few columns, many S rows per workgroup
     SK_VARIANT(16, 1, 4, 512),   // 7: two workgroups per CU, one lane per column group
     SK_VARIANT(8, 2, 8, 512),    // 8: two workgroups per CU, lane pairs
+    SK_VARIANT(4, 8, 16, 1024),  // 9: eight lanes per group (one 128-byte S window per read)
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -324,7 +325,8 @@ bool plan_any(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, int prec,
 // Workspace of one sketch.  The header sits at offset 0 (the status call
 // reads it there).
 struct Layout {
-  int64_t hdr, item, ridx, rcnt, rowlist, rowcnt, bfl, bstart, vbase, pos, seg, ent, bcost, sums;
+  int64_t hdr, item, ridx, rcnt, rowlist, rowcnt, bfl, bstart, vbase, pos, seg, ent, bcost, sums,
+      rowinfo;
   int64_t dflag, dlist, doff, dhdr, drows, dense, part, total;
 };
 
@@ -348,6 +350,7 @@ Layout layout_for(int64_t m, int64_t n, int64_t nnz, int64_t d, const Plan& P) {
   L.seg = off;     off = align_up(off + 4 * (P.nb_max * P.nv + 2));
   L.ent = off;     off = align_up(off + 8 * (nnz + 2));  // +2: 16-byte staging tail
   L.bcost = off;   off = align_up(off + 4 * (P.nb_max + 2));
+  L.rowinfo = off; off = align_up(off + 8 * m);
   const int64_t longest = std::max<int64_t>({m + 1, P.r_max + 1, n + 1, P.nb_max * P.nv + 1});
   L.sums = off;    off = align_up(off + 4 * scan_sums_len(longest));
   L.dflag = off;   off = align_up(off + 4 * P.nb_max);
@@ -401,7 +404,7 @@ sk_status scan_i32(int32_t* a, int64_t count, int32_t* sums, hipStream_t st) {
 // batch of one), and the concatenated arrays the per-item scans run over.
 struct InspectSizes {
   int64_t valid = 0, ridx = 0, m = 0, grp = 0, bfl = 0, rmax = 0, col = 0, vb = 0, pos = 0,
-          cnt = 0, seg = 0, nnz = 0, blk = 0;
+          cnt = 0, seg = 0, nnz = 0, blk = 0, rt = 0;
 };
 
 // offsets of item I in each index space; sizes accumulate into Z
@@ -419,6 +422,7 @@ void item_offsets(Item& I, InspectSizes& Z) {
   I.o_seg = Z.seg;     Z.seg += I.nb_max * I.nv + 1;
   I.o_nnz = Z.nnz;     Z.nnz += I.nnz;
   I.o_blk = Z.blk;     Z.blk += I.nb_max + 1;
+  I.o_rt = Z.rt;       Z.rt += (I.m + RT_ROWS - 1) / RT_ROWS;
 }
 
 struct InspectArrays {
@@ -436,6 +440,13 @@ void launch_items(Item* it, int count, int64_t total, hipStream_t st) {
   if (total > 0)
     hipLaunchKernelGGL((k_items<F, Op>), dim3(blocks_for(total, 256)), dim3(256), 0, st, it, count,
                        total);
+}
+
+template <int64_t Item::*F, class Op>
+void launch_items_cols(Item* it, int count, int64_t total, hipStream_t st) {
+  if (total > 0)
+    hipLaunchKernelGGL((k_items_cols<F, Op>), dim3(blocks_for(total, 256)), dim3(256), 0, st, it,
+                       count, total);
 }
 
 // exclusive scan of a concatenated array, then per-region rebasing
@@ -457,11 +468,10 @@ sk_status run_inspector(Item* it, int count, const InspectSizes& Z, const Inspec
   sk_status s;
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(Z.ridx + 1, 256 * 8)), dim3(256), 0, st,
                      W.ridx, Z.ridx + 1, 0);
-  hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(Z.m, 256 * 8)), dim3(256), 0, st, W.rcnt,
-                     Z.m, 0);
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(Z.bfl + 1, 256 * 8)), dim3(256), 0, st,
                      W.bfl, Z.bfl + 1, 0);
-  launch_items<&Item::o_valid, OpValidate>(it, count, Z.valid, st);
+  launch_items_cols<&Item::o_valid, OpValidate>(it, count, Z.valid, st);
+  hipLaunchKernelGGL(k_row_counts, dim3((unsigned)Z.rt), dim3(1024), 0, st, it, count, Z.rt);
   if ((s = scan_regions<SCAN_RIDX, &Item::o_ridx>(W.ridx, Z.ridx, it, count, W.sums, st)) != SK_OK)
     return s;
   launch_items<&Item::o_m, OpRowlist>(it, count, Z.m, st);
@@ -480,7 +490,9 @@ sk_status run_inspector(Item* it, int count, const InspectSizes& Z, const Inspec
   launch_items<&Item::o_cnt, OpBlockCnt>(it, count, Z.cnt, st);
   if ((s = scan_regions<SCAN_SEG, &Item::o_seg>(W.seg, Z.seg, it, count, W.sums, st)) != SK_OK)
     return s;
-  launch_items<&Item::o_nnz, OpScatter>(it, count, Z.nnz, st);
+  launch_items<&Item::o_cnt, OpSegPos>(it, count, Z.cnt, st);
+  launch_items<&Item::o_m, OpRowInfo>(it, count, Z.m, st);
+  launch_items_cols<&Item::o_nnz, OpScatter>(it, count, Z.nnz, st);
   return launch_ok();
 }
 
@@ -547,7 +559,7 @@ SketchParams make_params(const Plan& P, const Item& I, int64_t d, int64_t row0, 
 struct BatchPlan {
   int variant = 0;
   std::vector<Plan> plans;
-  std::vector<int64_t> rowlist, rowcnt, bstart, pos, ent, part;
+  std::vector<int64_t> rowlist, rowcnt, bstart, pos, ent, part, rowinfo;
   InspectSizes Z;
   int64_t hdrs = 0, items = 0, outs = 0, work = 0, counters = 0;
   int64_t ridx_all = 0, rcnt_all = 0, bfl_all = 0, seg_all = 0, bcost_all = 0, sums = 0;
@@ -624,7 +636,7 @@ sk_status batch_plan(int32_t count, const sk_csc* A, const int64_t* d, const int
   B.sums = off;
   off = align_up(off + 4 * scan_sums_len(std::max({Z.ridx, Z.bfl, Z.seg, Z.blk})));
   B.rowlist.resize(count); B.rowcnt.resize(count); B.bstart.resize(count);
-  B.pos.resize(count); B.ent.resize(count); B.part.resize(count);
+  B.pos.resize(count); B.ent.resize(count); B.part.resize(count); B.rowinfo.resize(count);
   for (int i = 0; i < count; ++i) {
     const Plan& P = B.plans[i];
     const int64_t n = A[i].n, nnz = A[i].nnz;
@@ -633,6 +645,7 @@ sk_status batch_plan(int32_t count, const sk_csc* A, const int64_t* d, const int
     B.bstart[i] = off;  off = align_up(off + 4 * (P.nb_max + 1));
     B.pos[i] = off;     off = align_up(off + 4 * (P.nb_max + 1) * n);
     B.ent[i] = off;     off = align_up(off + 8 * (nnz + 2));
+    B.rowinfo[i] = off; off = align_up(off + 8 * A[i].m);
     B.part[i] = off;
     if (P.slices > 1) off = align_up(off + 4 * (int64_t)P.slices * d[i] * n);
   }
@@ -832,6 +845,7 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
   I.seg = (int32_t*)(w + L.seg);
   I.ent = (uint2*)(w + L.ent);
   I.bcost = (int32_t*)(w + L.bcost);
+  I.rowinfo = (int2*)(w + L.rowinfo);
   I.dflag = P.dense_pct ? (int32_t*)(w + L.dflag) : nullptr;
   InspectSizes Z;
   item_offsets(I, Z);
@@ -1015,6 +1029,7 @@ sk_status sk_sketch_batched(int32_t count, const sk_csc* A, const int64_t* d, co
     I.vbase = nullptr;
     I.pos = (int32_t*)(w + B.pos[i]);
     I.ent = (uint2*)(w + B.ent[i]);
+    I.rowinfo = (int2*)(w + B.rowinfo[i]);
     item_offsets(I, Z);
     BatchOut& O = outs[i];
     std::memset(&O, 0, sizeof O);
