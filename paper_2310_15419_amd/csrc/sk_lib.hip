@@ -67,6 +67,7 @@ const Variant kVariants[] = {
     SK_VARIANT(16, 1, 4, 512),   // 7: two workgroups per CU, one lane per column group
     SK_VARIANT(8, 2, 8, 512),    // 8: two workgroups per CU, lane pairs
     SK_VARIANT(4, 8, 16, 1024),  // 9: eight lanes per group (one 128-byte S window per read)
+    SK_VARIANT(4, 4, 16, 512),   // 10: two workgroups per CU, 2048 columns each
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 

@@ -59,7 +59,7 @@ def test_materialize_bit_exact(B, oracle_lib, dist, row0, d, col0, ncols):
 
 # ------------------------------------------------------------- A_hat
 @pytest.mark.parametrize("dist", DISTS)
-@pytest.mark.parametrize("variant", [0, 1, 3, 4, 5, 6, 8, 9])
+@pytest.mark.parametrize("variant", [0, 1, 3, 4, 5, 6, 8, 9, 10])
 def test_sketch_small_all_variants(B, oracle_lib, dist, variant):
     # several tiles in d, several row blocks, ragged tails everywhere
     m, n, d = 7001, 77, 203
