@@ -49,7 +49,7 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(4))) void k
   while (true) {
     if (threadIdx.x == 0) s_unit = atomicAdd(counter, 1);
     __syncthreads();
-    const int u = s_unit;
+    const int u = __builtin_amdgcn_readfirstlane(s_unit);  // uniform: parameters in SGPRs
     __syncthreads();
     if (u >= total) break;
     const int2 w = work[u];
@@ -66,12 +66,12 @@ template <int FMT>
 __global__ __launch_bounds__(MF_THREADS) void k_sketch_mfma_persistent(
     const BatchOut* __restrict__ it, const int2* __restrict__ work, int total,
     int32_t* __restrict__ counter) {
-  __shared__ __align__(16) unsigned char smem[sizeof(MfmaLds<FMT>)];
+  extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_unit;
   while (true) {
     if (threadIdx.x == 0) s_unit = atomicAdd(counter, 1);
     __syncthreads();
-    const int u = s_unit;
+    const int u = __builtin_amdgcn_readfirstlane(s_unit);  // uniform: parameters in SGPRs
     __syncthreads();
     if (u >= total) break;
     const int2 w = work[u];

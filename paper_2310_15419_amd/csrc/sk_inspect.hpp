@@ -67,6 +67,8 @@ struct Item {
   int32_t m_b;        // rows per row group (S-tile capacity)
   int32_t e_cap;      // entries per block (staging capacity)
   int32_t row_bytes;  // S-tile row stride in bytes
+  int32_t col_tag;    // nonzero: an entry's row offset also carries (column mod
+                      // col_tag) << 16 (the matrix-core kernel's tile column)
   int64_t nv;         // (virtual) columns of the layout
   int64_t nb_max;     // block capacity
   int64_t r_max;      // nonempty-row capacity, min(m, max(nnz, 1))
@@ -562,7 +564,9 @@ struct OpScatter {
       q = q / s;
     }
     const int64_t dest = (int64_t)I.pos[(int64_t)ri.x * I.nv + v] + q;
-    I.ent[dest] = make_uint2((uint32_t)ri.y, __float_as_uint(load_value(I.vals, I.vtype, p)));
+    uint32_t x = (uint32_t)ri.y;
+    if (I.col_tag) x |= (uint32_t)(k % I.col_tag) << 16;
+    I.ent[dest] = make_uint2(x, __float_as_uint(load_value(I.vals, I.vtype, p)));
   }
 };
 

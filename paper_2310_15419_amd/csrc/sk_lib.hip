@@ -292,13 +292,15 @@ bool plan_mfma(int64_t m, int64_t n, int64_t nnz, int64_t d, int fmt, const sk_t
   P.lds = fmt == MF_BF16 ? sizeof(MfmaLds<MF_BF16>) : sizeof(MfmaLds<MF_FP8>);
   P.dense_pct = 0;
   P.kd_max = 0;
-  // cost per unit and block in CU-cycles: MFMA issue (four accumulators per
-  // wave, 16 rows per instruction at 32 cycles, two waves per SIMD; twice
-  // for FP8's hi + lo), the dense-tile clear and the scatter, a fixed overhead
+  // cost per unit and block in CU-cycles: the larger of the MFMA issue (four
+  // accumulators per wave, 16 rows per instruction at 32 cycles, two waves
+  // per SIMD; twice for FP8's hi + lo) and the next block's build that
+  // overlaps it (the dense-tile clear and the scatter), plus the barrier
   const double R = (double)m * -std::expm1(-(double)nnz / (double)m);
   const double blocks = std::ceil(R / P.m_b);
   const double mf = (double)P.m_b / 16.0 * 4.0 * 2.0 * 32.0 * (fmt == MF_FP8 ? 2.0 : 1.0) / 4.0;
-  const double per_unit_block = mf + 600.0 + (double)nnz / std::max(1.0, blocks) / P.ncr / 8.0;
+  const double build = 600.0 + (double)nnz / std::max(1.0, blocks) / P.ncr / 8.0;
+  const double per_unit_block = std::max(mf, build) + 100.0;
   P.cost = blocks * per_unit_block * (double)P.tiles * P.ncr;
   int64_t splits;
   if (tune && tune->splits > 0) {
@@ -518,6 +520,7 @@ Item make_item(const sk_csc* A, const Plan& P, int dist) {
   I.m_b = P.m_b; I.e_cap = P.e_max; I.row_bytes = P.row_bytes;
   I.nv = P.nv; I.nb_max = P.nb_max; I.r_max = P.r_max;
   if (P.mfma) {  // blocks of equal height; the cost follows the rows
+    I.col_tag = MF_TN;
     I.w_row = 16;
     I.w_ent = 1;
     I.w_blk = 16 * 300;
@@ -896,11 +899,18 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
   const int64_t grid = (int64_t)P.tiles * P.ncr * P.splits;
   if (grid >= INT32_MAX) return SK_EUNSUPPORTED;
   if (P.mfma) {
+    const void* kern = P.mfma == MF_BF16 ? (const void*)k_sketch_mfma<MF_BF16>
+                                         : (const void*)k_sketch_mfma<MF_FP8>;
+    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds) !=
+        hipSuccess)
+      return SK_EHIP;
     if (phases & 2) {
       if (P.mfma == MF_BF16)
-        hipLaunchKernelGGL(k_sketch_mfma<MF_BF16>, dim3((unsigned)grid), dim3(MF_THREADS), 0, st, K);
+        hipLaunchKernelGGL(k_sketch_mfma<MF_BF16>, dim3((unsigned)grid), dim3(MF_THREADS), P.lds,
+                           st, K);
       else
-        hipLaunchKernelGGL(k_sketch_mfma<MF_FP8>, dim3((unsigned)grid), dim3(MF_THREADS), 0, st, K);
+        hipLaunchKernelGGL(k_sketch_mfma<MF_FP8>, dim3((unsigned)grid), dim3(MF_THREADS), P.lds,
+                           st, K);
       if ((s = launch_ok()) != SK_OK) return s;
     }
   } else {
@@ -1090,15 +1100,22 @@ sk_status sk_sketch_batched(int32_t count, const sk_csc* A, const int64_t* d, co
       hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(V.wgs), B.lds[kind], st, d_outs,
                          d_work + first, (int)B.units[kind], counters + kind);
     } else {
-      const int64_t grid = std::min<int64_t>(B.units[kind], (int64_t)cus * 2);
-      if (kind == 2 + MF_BF16)
+      // one workgroup per CU: the two tile copies take most of the LDS
+      const int64_t grid = std::min<int64_t>(B.units[kind], (int64_t)cus);
+      const bool bf = kind == 2 + MF_BF16;
+      const void* kern = bf ? (const void*)k_sketch_mfma_persistent<MF_BF16>
+                            : (const void*)k_sketch_mfma_persistent<MF_FP8>;
+      if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)B.lds[kind]) != hipSuccess)
+        return SK_EHIP;
+      if (bf)
         hipLaunchKernelGGL(k_sketch_mfma_persistent<MF_BF16>, dim3((unsigned)grid),
-                           dim3(MF_THREADS), 0, st, d_outs, d_work + first, (int)B.units[kind],
-                           counters + kind);
+                           dim3(MF_THREADS), B.lds[kind], st, d_outs, d_work + first,
+                           (int)B.units[kind], counters + kind);
       else
         hipLaunchKernelGGL(k_sketch_mfma_persistent<MF_FP8>, dim3((unsigned)grid),
-                           dim3(MF_THREADS), 0, st, d_outs, d_work + first, (int)B.units[kind],
-                           counters + kind);
+                           dim3(MF_THREADS), B.lds[kind], st, d_outs, d_work + first,
+                           (int)B.units[kind], counters + kind);
     }
     if ((s = launch_ok()) != SK_OK) return s;
     first += B.units[kind];

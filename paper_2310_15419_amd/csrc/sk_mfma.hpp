@@ -7,13 +7,19 @@
 // blocks are densified on the fly in LDS: nothing dense is written to HBM.
 //
 // One work unit owns an output tile A_hat[i0 : i0 + 128, c0 : c0 + 256] for
-// a run of row blocks (a split); eight waves each hold a 32 x 128 part as four
-// 32 x 32 MFMA accumulators.  Per block of at most MF_MB rows:
-//   1. the S tile (128 S rows x the block's rows) as sign bits, one ballot
-//      per S row; expanded to +-1 operands through a 256-entry table,
-//   2. the block's entries in the unit's 256 columns scattered into a zeroed
-//      dense tile (column-major, the block's rows contiguous),
+// a run of row blocks (a split).  Eight waves run the matrix cores, each
+// holding a 32 x 128 part as four 32 x 32 accumulators; four more waves build
+// the next block's tiles in a second copy meanwhile, so building and
+// multiplying overlap:
+//   1. the S tile (128 S rows x the block's rows) as sign bits: one
+//      generator call per block row gives its 128 bits (four words); each
+//      matrix-core lane turns bit (its S row) of eight words into eight +-1
+//      operands,
+//   2. the block's entries in the unit's 256 columns scattered into the
+//      dense tile (column-major, the block's rows contiguous), after zeros
+//      over the entries the copy held before,
 //   3. for every 16 rows: v_mfma_f32_32x32x16 (bf16 or fp8) per accumulator.
+// One workgroup barrier per block hands the copies over.
 // Both operands use the same lane -> K mapping, so each instruction forms the
 // right dot products whatever the hardware's K order inside a lane group.
 #pragma once
@@ -32,50 +38,73 @@ enum : int { MF_BF16 = 1, MF_FP8 = 2 };
 constexpr int MF_MB = 128;      // rows per block (K extent of one dense tile)
 constexpr int MF_TM = 128;      // S rows per unit
 constexpr int MF_TN = 256;      // columns per unit
-constexpr int MF_THREADS = 512; // eight waves: four S-row quarters x two column halves
+constexpr int MF_CONSUMERS = 8; // waves on the matrix cores (four S-row quarters x two halves)
+constexpr int MF_PRODUCERS = 8; // waves building tiles: two groups (even, odd blocks) of
+                                // four, 64 columns each
+constexpr int MF_THREADS = 64 * (MF_CONSUMERS + MF_PRODUCERS);
+constexpr int MF_EQ = 8;        // entries per producer lane kept in registers
 
 typedef float mf_floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 mf_bf16x8 __attribute__((ext_vector_type(8)));
 
-// S is held as bits (bit k % 8 of byte [i][k / 8]: S row i, block row k;
-// set = -1) and expanded to MFMA operands through a table of the 256 byte
-// values -> eight +-1 operands.
+// Two copies of the per-block tiles (the one the matrix cores read and the
+// one being built).  S is held as the generator's words: S[w][k] bit t is set
+// when S row 32 w + t of the unit is -1 in block row k.
 template <int FMT>
 struct MfmaLds;
 
 template <>
 struct MfmaLds<MF_BF16> {
   static constexpr int LDK = MF_MB + 8;  // elements per dense-tile row (16-byte rows, skewed)
-  uint16_t A[MF_TN][LDK];
-  uint4 lut[256];                        // eight bf16 +-1
-  uint8_t S[MF_TM][MF_MB / 8];
-  int32_t seg[MF_TN + 1];
+  uint16_t A[2][MF_TN][LDK];
+  uint32_t S[2][MF_TM / 32][MF_MB];
+  int32_t rb[2];                         // rows of the block in each copy
 };
 
 template <>
 struct MfmaLds<MF_FP8> {
   static constexpr int LDK = MF_MB + 16;
-  uint8_t Ahi[MF_TN][LDK];
-  uint8_t Alo[MF_TN][LDK];
-  uint2 lut[256];                        // eight fp8 +-1
-  uint8_t S[MF_TM][MF_MB / 8];
-  int32_t seg[MF_TN + 1];
+  uint8_t Ahi[2][MF_TN][LDK];
+  uint8_t Alo[2][MF_TN][LDK];
+  uint32_t S[2][MF_TM / 32][MF_MB];
+  int32_t rb[2];
 };
+
+// Accesses through a generic pointer are flat instructions, which count as
+// LDS traffic in the wait counters too (an LDS wait then also waits for every
+// load in flight).  Parameters read from memory (the batched kernel's) arrive
+// as generic pointers, so the unit addresses its arrays as global memory
+// explicitly.
+template <typename T>
+using global_t = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ global_t<T>* in_global(T* p) {
+  return (global_t<T>*)p;
+}
 
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
   const uint32_t u = __float_as_uint(x);
   return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);  // finite inputs
 }
 
-// first k in [0, cols) with seg[k + 1] > p (seg non-decreasing)
-__device__ __forceinline__ int seg_column(const int32_t* seg, int cols, int32_t p) {
-  int lo = 0, hi = cols - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (seg[mid + 1] > p) hi = mid;
-    else lo = mid + 1;
-  }
-  return lo;
+// Sign bits of the 128 consecutive S rows i..i+127 of column j, word t
+// holding rows i + 32t .. i + 32t + 31 (bit set <=> -1): one generator call
+// when i is a multiple of 128, else two, joined at the offset.
+__host__ __device__ __forceinline__ Words sign_bits128(uint64_t seed, uint64_t i, uint64_t j) {
+  const uint64_t g = i >> 7;
+  const int s = (int)(i & 127);
+  const Words a = gen_words(seed, g, j);
+  if (s == 0) return a;
+  const Words c = gen_words(seed, g + 1, j);
+  const int q = s >> 5, r = s & 31;
+  // words q .. q + 4 of the 256-bit concatenation a, c (q is 0..3)
+  const uint32_t v0 = q == 0 ? a.x0 : q == 1 ? a.x1 : q == 2 ? a.x2 : a.x3;
+  const uint32_t v1 = q == 0 ? a.x1 : q == 1 ? a.x2 : q == 2 ? a.x3 : c.x0;
+  const uint32_t v2 = q == 0 ? a.x2 : q == 1 ? a.x3 : q == 2 ? c.x0 : c.x1;
+  const uint32_t v3 = q == 0 ? a.x3 : q == 1 ? c.x0 : q == 2 ? c.x1 : c.x2;
+  const uint32_t v4 = q == 0 ? c.x0 : q == 1 ? c.x1 : q == 2 ? c.x2 : c.x3;
+  auto join = [r](uint32_t lo, uint32_t hi) { return r ? (lo >> r) | (hi << (32 - r)) : lo; };
+  return Words{join(v0, v1), join(v1, v2), join(v2, v3), join(v3, v4)};
 }
 
 template <int FMT>
@@ -85,171 +114,251 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
   constexpr int LDK = MfmaLds<FMT>::LDK;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int mq = wave & 3, nh = wave >> 2;  // S-row quarter, column half
+  const bool consumer = wave < MF_CONSUMERS;
+  const int mq = wave & 3, nh = (wave >> 2) & 1;  // consumers: S-row quarter, column half
+  // producers: group (the parity of the blocks it builds) and wave in it
+  const int grp = __builtin_amdgcn_readfirstlane((wave - MF_CONSUMERS) >> 2);
+  const int pw = __builtin_amdgcn_readfirstlane(wave & 3);
   const int64_t i0 = (int64_t)tile * MF_TM;
   const int64_t c0 = (int64_t)crange * MF_TN;
   const int cols = (int)(P.n - c0 < MF_TN ? P.n - c0 : MF_TN);
   const uint64_t grow0 = (uint64_t)(P.row0 + i0);
+  const auto* hdr = in_global(P.hdr);
+  const auto* bcost = in_global(P.bcost);
+  const auto* bstart = in_global(P.bstart);
+  const auto* seg = in_global(P.seg);
+  const auto* rowlist = in_global(P.rowlist);
+  const auto* ent64 = in_global(reinterpret_cast<const uint64_t*>(P.ent));
+  auto ent = [ent64](int64_t p) {
+    const uint64_t v = ent64[p];
+    return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+  };
+
+  const int status = hdr->status;
+  int64_t b_lo = 0, b_hi = 0;
+  if (status == 0) {
+    const int64_t nb = hdr->nblocks;
+    const int64_t T = bcost[nb];
+    auto first_at = [&](int64_t x) {
+      int64_t lo = 0, hi = nb;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (bcost[mid] < x) lo = mid + 1;
+        else hi = mid;
+      }
+      return lo;
+    };
+    b_lo = first_at((split * T + P.splits - 1) / P.splits);
+    b_hi = split + 1 == P.splits ? nb : first_at(((split + 1) * T + P.splits - 1) / P.splits);
+  }
+
+  if (!consumer) {
+    // A producer wave builds its share of a copy for one block: the S words
+    // of block rows 32 pw .. + 31 (one generator call each), and the dense
+    // tile of its 64 columns: zeros where that copy's previous block had
+    // entries (or everywhere, when they were not all kept), then the
+    // block's entries.  A wave's LDS writes to its share all come from that
+    // wave, in program order, so the producers never wait on each other.
+    //
+    // Group g builds the blocks of parity g, always into copy g, so it has
+    // two blocks' time on the matrix cores between a build and the next:
+    // right after a build it issues the loads of its next block's rows and
+    // entries (in registers across the barriers) and of the bounds of the
+    // block after that, and memory latency (longer than one block's time)
+    // is covered.  Every build issues the same loads (indices held in range
+    // rather than branched around), so the wait before a build covers only
+    // loads two steps old.
+    const int cw0 = 64 * pw;
+    const int ncw = cols - cw0 < 64 ? cols - cw0 : 64;  // <= 0: past the last column
+    const int cs0 = ncw > 0 ? cw0 : 0, cs1 = ncw > 0 ? cw0 + ncw : 0;
+    const int krow = 32 * pw + (lane & 31);
+    const int64_t nblk = b_hi - b_lo;
+    struct Bounds {
+      int32_t r0, rb, p0, p1;
+    };
+    struct Payload {
+      int32_t row, rb, p0, p1;
+      uint2 e[MF_EQ];
+    };
+    struct Placed {     // where a copy's block put this lane's entries
+      int32_t count;    // the wave's entries; -1: not all kept (clear everything)
+      uint32_t at[MF_EQ];
+    };
+    // bounds of block b_lo + i (any i >= 0: past the end, those of the last
+    // block, unused)
+    auto load_bounds = [&](int64_t i) {
+      const int64_t b = b_lo + (i < nblk ? i : nblk - 1);
+      Bounds x;
+      x.r0 = bstart[b];
+      x.rb = bstart[b + 1];
+      const auto* segb = seg + b * P.n + c0;
+      x.p0 = segb[cs0];
+      x.p1 = segb[cs1];
+      return x;
+    };
+    // rowlist is padded past its last group, so r0 + krow stays in range;
+    // an entry index is clamped to a valid one (the array has at least two)
+    auto load_payload = [&](const Bounds& x) {
+      // (the wave-uniform bounds move to scalar registers, so the next
+      // bounds can load straight into the vector registers just read)
+      Payload y;
+      y.rb = __builtin_amdgcn_readfirstlane(x.rb - x.r0);
+      y.p0 = __builtin_amdgcn_readfirstlane(x.p0);
+      y.p1 = __builtin_amdgcn_readfirstlane(x.p1);
+      y.row = rowlist[x.r0 + krow];
+      const int32_t last = x.p1 > 0 ? x.p1 - 1 : 0;
+#pragma unroll
+      for (int q = 0; q < MF_EQ; ++q) {
+        const int32_t p = x.p0 + lane + 64 * q;
+        y.e[q] = ent(p < last ? p : last);
+      }
+      return y;
+    };
+    // an entry holds its row in the block (low 16 bits) and its tile column
+    // (high 16 bits); its element index in a copy is column * LDK + row
+    auto slot = [](uint32_t ex) {
+      return (uint32_t)(((ex >> 16) & (MF_TN - 1)) * LDK + (ex & (MF_MB - 1)));
+    };
+    auto put = [&](int buf, uint32_t at, float a) {
+      if constexpr (FMT == MF_BF16) {
+        (&L.A[buf][0][0])[at] = bf16_rne(a);
+      } else {
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, a, 0, false) & 0xFFu;
+        const float back = __builtin_amdgcn_cvt_f32_fp8((int)hi, 0);
+        const uint32_t lo =
+            (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a - back, a - back, 0, false) & 0xFFu;
+        (&L.Ahi[buf][0][0])[at] = (uint8_t)hi;
+        (&L.Alo[buf][0][0])[at] = (uint8_t)lo;
+      }
+    };
+    auto zero = [&](int buf, uint32_t at) {
+      if constexpr (FMT == MF_BF16) {
+        (&L.A[buf][0][0])[at] = 0;
+      } else {
+        (&L.Ahi[buf][0][0])[at] = 0;
+        (&L.Alo[buf][0][0])[at] = 0;
+      }
+    };
+    auto build = [&](int buf, const Payload& y, Placed& pl) {
+      if (pw == 0 && lane == 0) L.rb[buf] = y.rb;
+      if (lane < 32) {
+        Words w{0u, 0u, 0u, 0u};
+        if (krow < y.rb) w = sign_bits128(P.seed, grow0, (uint64_t)(uint32_t)y.row);
+        L.S[buf][0][krow] = w.x0;
+        L.S[buf][1][krow] = w.x1;
+        L.S[buf][2][krow] = w.x2;
+        L.S[buf][3][krow] = w.x3;
+      }
+      if (ncw <= 0) return;  // past the last column: never stored
+      if (pl.count >= 0) {
+#pragma unroll
+        for (int q = 0; q < MF_EQ; ++q)
+          if (lane + 64 * q < pl.count) zero(buf, pl.at[q]);
+      } else {
+        constexpr int w16 = (FMT == MF_BF16 ? 64 * LDK * 2 : 64 * LDK) / 16;
+        if constexpr (FMT == MF_BF16) {
+          uint4* z = reinterpret_cast<uint4*>(&L.A[buf][cw0][0]);
+          for (int i = lane; i < w16; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
+        } else {
+          uint4* z = reinterpret_cast<uint4*>(&L.Ahi[buf][cw0][0]);
+          uint4* z2 = reinterpret_cast<uint4*>(&L.Alo[buf][cw0][0]);
+          for (int i = lane; i < w16; i += 64) {
+            z[i] = make_uint4(0u, 0u, 0u, 0u);
+            z2[i] = make_uint4(0u, 0u, 0u, 0u);
+          }
+        }
+      }
+      // the zeros are written before any store of the block's entries
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const int32_t cnt = y.p1 - y.p0;
+      pl.count = cnt <= 64 * MF_EQ ? cnt : -1;
+#pragma unroll
+      for (int q = 0; q < MF_EQ; ++q) {
+        pl.at[q] = slot(y.e[q].x);
+        if (lane + 64 * q < cnt) put(buf, pl.at[q], __uint_as_float(y.e[q].y));
+      }
+      for (int32_t p = y.p0 + lane + 64 * MF_EQ; p < y.p1; p += 64) {
+        const uint2 e = ent(p);
+        put(buf, slot(e.x), __uint_as_float(e.y));
+      }
+    };
+
+    // Block k (relative to b_lo) is built before barrier k and consumed
+    // between barriers k and k + 1; the two roles run separate loops with
+    // the same barriers, and a role is the same for a whole wave.
+    Placed pl{-1, {}};  // copy grp: its last block's entries
+    Payload Y{};        // the group's next block
+    Bounds Bn{};        // the block after that
+    if (grp < nblk) {
+      Y = load_payload(load_bounds(grp));
+      Bn = load_bounds(grp + 2);
+    }
+    for (int64_t k = 0; k <= nblk; ++k) {
+      if ((int)(k & 1) == grp && k < nblk) {
+        build(grp, Y, pl);
+        Y = load_payload(Bn);    // block k + 2
+        Bn = load_bounds(k + 4);
+      }
+      __syncthreads();  // block k is built; block k - 1 consumed
+    }
+    return;
+  }
 
   mf_floatx16 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
-
-  // operand table: byte -> eight +-1 values (bit set: -1)
-  if (tid < 256) {
-    if constexpr (FMT == MF_BF16) {
-      uint32_t w[4];
+  // a +-1 operand: eight block rows of this lane's S row (bit `bs` of eight
+  // consecutive words) as BF16 (sign bit 15) or FP8 (sign bit 7) values
+  const uint32_t bs = lane & 31;
+  const int kq = 8 * (lane >> 5);
+  uint32_t one8 = 0;
+  if constexpr (FMT == MF_FP8)
+    one8 = ((uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(1.0f, 1.0f, 0, false) & 0xFFu) * 0x01010101u;
+  __syncthreads();  // copy 0 holds block b_lo
+  for (int64_t b = b_lo; b < b_hi; ++b) {
+    const int buf = (int)((b - b_lo) & 1);
+    // the matrix cores on block b: 16 block rows per instruction; rows past
+    // rb are zero in the dense tile
+    const int rb = L.rb[buf];
+    for (int k0 = 0; k0 < rb; k0 += 16) {
+      const uint4 w0 = *reinterpret_cast<const uint4*>(&L.S[buf][mq][k0 + kq]);
+      const uint4 w1 = *reinterpret_cast<const uint4*>(&L.S[buf][mq][k0 + kq + 4]);
+      if constexpr (FMT == MF_BF16) {
+        auto pair = [bs](uint32_t e, uint32_t o) {
+          return 0x3F803F80u | (((e >> bs) & 1u) << 15) | (((o >> bs) & 1u) << 31);
+        };
+        const uint4 sv = make_uint4(pair(w0.x, w0.y), pair(w0.z, w0.w), pair(w1.x, w1.y),
+                                    pair(w1.z, w1.w));
+        const mf_bf16x8 a = *reinterpret_cast<const mf_bf16x8*>(&sv);
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const uint32_t lo = (tid >> (2 * h)) & 1u ? 0xBF80u : 0x3F80u;
-        const uint32_t hi = (tid >> (2 * h + 1)) & 1u ? 0xBF80u : 0x3F80u;
-        w[h] = lo | (hi << 16);
-      }
-      L.lut[tid] = make_uint4(w[0], w[1], w[2], w[3]);
-    } else {
-      const uint32_t one = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(1.0f, 1.0f, 0, false) & 0xFFu;
-      const uint32_t neg = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(-1.0f, -1.0f, 0, false) & 0xFFu;
-      uint32_t w[2] = {0u, 0u};
+        for (int t = 0; t < 4; ++t) {
+          const int ncol = 128 * nh + 32 * t + (lane & 31);
+          const mf_bf16x8 bv = *reinterpret_cast<const mf_bf16x8*>(&L.A[buf][ncol][k0 + kq]);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[t], 0, 0, 0);
+        }
+      } else {
+        auto quad = [bs, one8](const uint4 w) {
+          return one8 | (((w.x >> bs) & 1u) << 7) | (((w.y >> bs) & 1u) << 15) |
+                 (((w.z >> bs) & 1u) << 23) | (((w.w >> bs) & 1u) << 31);
+        };
+        const long a = (long)(((uint64_t)quad(w1) << 32) | quad(w0));
 #pragma unroll
-      for (int e = 0; e < 8; ++e) w[e >> 2] |= ((tid >> e) & 1u ? neg : one) << (8 * (e & 3));
-      L.lut[tid] = make_uint2(w[0], w[1]);
-    }
-  }
-
-  const int status = P.hdr->status;
-  if (status == 0) {
-    const int64_t nb = P.hdr->nblocks;
-    const int64_t T = P.bcost[nb];
-    auto first_at = [&](int64_t x) {
-      int64_t lo = 0, hi = nb;
-      while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (P.bcost[mid] < x) lo = mid + 1;
-        else hi = mid;
-      }
-      return lo;
-    };
-    const int64_t b_lo = first_at((split * T + P.splits - 1) / P.splits);
-    const int64_t b_hi =
-        split + 1 == P.splits ? nb : first_at(((split + 1) * T + P.splits - 1) / P.splits);
-    // Software pipeline over the blocks: while block b runs on the matrix
-    // cores, the entries and rows of block b + 1 and the segment bounds of
-    // block b + 2 are in flight to registers.
-    const int krow = 64 * nh + lane;  // the block row whose S bits this thread makes
-    struct Bounds {
-      int32_t r0, rb, segv, p0, p1;
-    };
-    auto load_bounds = [&](int64_t b) {
-      Bounds x;
-      x.r0 = P.bstart[b];
-      x.rb = P.bstart[b + 1] - x.r0;
-      const int32_t* segb = P.seg + b * P.n + c0;
-      x.segv = tid <= cols ? segb[tid] : 0;
-      x.p0 = segb[0];
-      x.p1 = segb[cols];
-      return x;
-    };
-    constexpr int ET = 4;  // entries per thread carried in registers
-    uint2 ent[ET];
-    int32_t row = 0;
-    auto load_payload = [&](const Bounds& x) {
-#pragma unroll
-      for (int q = 0; q < ET; ++q) {
-        const int32_t p = x.p0 + tid + q * MF_THREADS;
-        ent[q] = p < x.p1 ? P.ent[p] : make_uint2(0u, 0u);
-      }
-      row = krow < x.rb ? P.rowlist[x.r0 + krow] : 0;
-    };
-    Bounds cur{}, nxt{};
-    if (b_lo < b_hi) {
-      cur = load_bounds(b_lo);
-      load_payload(cur);
-    }
-    if (b_lo + 1 < b_hi) nxt = load_bounds(b_lo + 1);
-    for (int64_t b = b_lo; b < b_hi; ++b) {
-      const int rb = cur.rb;
-      __syncthreads();  // the previous block's tiles are consumed
-      // zero the dense tile, stage the unit's segment bounds
-      {
-        uint4* z = reinterpret_cast<uint4*>(smem);
-        constexpr int n16 = (FMT == MF_BF16 ? MF_TN * LDK * 2 : 2 * MF_TN * LDK) / 16;
-        for (int i = tid; i < n16; i += MF_THREADS) z[i] = make_uint4(0u, 0u, 0u, 0u);
-      }
-      if (tid <= cols) L.seg[tid] = cur.segv;
-      // S bits: wave w takes S rows 32 (w & 3) .. + 31 and block rows
-      // 64 (w >> 2) .. + 63 (one per lane); one ballot per S row gives the
-      // 64 bits of that row for the wave's block rows
-      {
-        uint32_t bits = 0;
-        if (krow < rb) bits = sign_bits32(P.seed, grow0 + 32u * mq, (uint64_t)(uint32_t)row);
-        for (int u = 0; u < 32; ++u) {
-          const uint64_t srow = __ballot((bits >> u) & 1u);
-          if (lane == u) *reinterpret_cast<uint64_t*>(&L.S[32 * mq + u][8 * nh]) = srow;
+        for (int t = 0; t < 4; ++t) {
+          const int ncol = 128 * nh + 32 * t + (lane & 31);
+          const long bh = *reinterpret_cast<const long*>(&L.Ahi[buf][ncol][k0 + kq]);
+          const long bl = *reinterpret_cast<const long*>(&L.Alo[buf][ncol][k0 + kq]);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, bh, acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, bl, acc[t], 0, 0, 0);
         }
       }
-      __syncthreads();
-      // scatter the entries of the unit's columns (row offset in e.x): those
-      // carried in registers, then any beyond them straight from memory
-      auto put = [&](const uint2 e, int32_t p) {
-        const int c = seg_column(L.seg, cols, p);
-        const float a = __uint_as_float(e.y);
-        if constexpr (FMT == MF_BF16) {
-          L.A[c][e.x] = bf16_rne(a);
-        } else {
-          const uint32_t hi = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, a, 0, false) & 0xFFu;
-          const float back = __builtin_amdgcn_cvt_f32_fp8((int)hi, 0);
-          const uint32_t lo =
-              (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a - back, a - back, 0, false) & 0xFFu;
-          L.Ahi[c][e.x] = (uint8_t)hi;
-          L.Alo[c][e.x] = (uint8_t)lo;
-        }
-      };
-#pragma unroll
-      for (int q = 0; q < ET; ++q) {
-        const int32_t p = cur.p0 + tid + q * MF_THREADS;
-        if (p < cur.p1) put(ent[q], p);
-      }
-      for (int32_t p = cur.p0 + tid + ET * MF_THREADS; p < cur.p1; p += MF_THREADS) put(P.ent[p], p);
-      // prefetch: entries and rows of block b + 1, bounds of block b + 2
-      if (b + 1 < b_hi) load_payload(nxt);
-      Bounds nn{};
-      if (b + 2 < b_hi) nn = load_bounds(b + 2);
-      __syncthreads();
-      // K loop: 16 block rows per instruction; rows past rb are zero in A
-      const int kq = 8 * (lane >> 5);
-      const int mrow = 32 * mq + (lane & 31);
-      for (int k0 = 0; k0 < rb; k0 += 16) {
-        const int sb = L.S[mrow][(k0 + kq) >> 3];
-        if constexpr (FMT == MF_BF16) {
-          const uint4 sv = L.lut[sb];
-          const mf_bf16x8 a = *reinterpret_cast<const mf_bf16x8*>(&sv);
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int ncol = 128 * nh + 32 * t + (lane & 31);
-            const mf_bf16x8 bv = *reinterpret_cast<const mf_bf16x8*>(&L.A[ncol][k0 + kq]);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[t], 0, 0, 0);
-          }
-        } else {
-          const uint2 sv = L.lut[sb];
-          const long a = (long)(((uint64_t)sv.y << 32) | sv.x);
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int ncol = 128 * nh + 32 * t + (lane & 31);
-            const long bh = *reinterpret_cast<const long*>(&L.Ahi[ncol][k0 + kq]);
-            const long bl = *reinterpret_cast<const long*>(&L.Alo[ncol][k0 + kq]);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, bh, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, bl, acc[t], 0, 0, 0);
-          }
-        }
-      }
-      cur = nxt;
-      nxt = nn;
     }
+    __syncthreads();  // block b consumed; the other copy holds block b + 1
   }
   // C[i][j]: j = lane % 32, i = 8 (r / 4) + 4 (lane / 32) + r % 4
-  float* __restrict__ out = P.out + (int64_t)split * P.split_stride;
+  auto* out = in_global(P.out) + (int64_t)split * P.split_stride;
   const float nan = __uint_as_float(0x7FC00000u);
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -264,7 +373,7 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
 
 template <int FMT>
 __global__ __launch_bounds__(MF_THREADS) void k_sketch_mfma(SketchParams P) {
-  __shared__ __align__(16) unsigned char smem[sizeof(MfmaLds<FMT>)];
+  extern __shared__ __align__(16) unsigned char smem[];
   const int bid = blockIdx.x;
   const int split = bid % P.splits;
   const int rest = bid / P.splits;
