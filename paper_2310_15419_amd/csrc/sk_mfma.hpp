@@ -58,7 +58,6 @@ struct MfmaLds<MF_BF16> {
   static constexpr int LDK = MF_MB + 8;  // elements per dense-tile row (16-byte rows, skewed)
   uint16_t A[2][MF_TN][LDK];
   uint32_t S[2][MF_TM / 32][MF_MB];
-  int32_t rb[2];                         // rows of the block in each copy
 };
 
 template <>
@@ -67,7 +66,6 @@ struct MfmaLds<MF_FP8> {
   uint8_t Ahi[2][MF_TN][LDK];
   uint8_t Alo[2][MF_TN][LDK];
   uint32_t S[2][MF_TM / 32][MF_MB];
-  int32_t rb[2];
 };
 
 // Accesses through a generic pointer are flat instructions, which count as
@@ -240,7 +238,6 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
       }
     };
     auto build = [&](int buf, const Payload& y, Placed& pl) {
-      if (pw == 0 && lane == 0) L.rb[buf] = y.rb;
       if (lane < 32) {
         Words w{0u, 0u, 0u, 0u};
         if (krow < y.rb) w = sign_bits128(P.seed, grow0, (uint64_t)(uint32_t)y.row);
@@ -320,15 +317,18 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
   __syncthreads();  // copy 0 holds block b_lo
   for (int64_t b = b_lo; b < b_hi; ++b) {
     const int buf = (int)((b - b_lo) & 1);
-    // the matrix cores on block b: 16 block rows per instruction; rows past
-    // rb are zero in the dense tile
-    const int rb = L.rb[buf];
-    for (int k0 = 0; k0 < rb; k0 += 16) {
-      const uint4 w0 = *reinterpret_cast<const uint4*>(&L.S[buf][mq][k0 + kq]);
-      const uint4 w1 = *reinterpret_cast<const uint4*>(&L.S[buf][mq][k0 + kq + 4]);
-      if constexpr (FMT == MF_BF16) {
-        auto pair = [bs](uint32_t e, uint32_t o) {
-          return 0x3F803F80u | (((e >> bs) & 1u) << 15) | (((o >> bs) & 1u) << 31);
+    // the matrix cores on block b: 16 block rows per instruction, all eight
+    // steps unrolled (rows past the block's end are zero in the dense tile
+    // and their S words are zero, so they add nothing)
+    auto bit = [bs](uint32_t w) { return __builtin_amdgcn_ubfe(w, bs, 1u); };
+    if constexpr (FMT == MF_BF16) {
+#pragma unroll
+      for (int k0 = 0; k0 < MF_MB; k0 += 16) {
+        const uint4 w0 = *reinterpret_cast<const uint4*>(&L.S[buf][mq][k0 + kq]);
+        const uint4 w1 = *reinterpret_cast<const uint4*>(&L.S[buf][mq][k0 + kq + 4]);
+        // elements 2h, 2h + 1: 0x3F80 (+1), sign bit 15 of each half
+        auto pair = [&](uint32_t e, uint32_t o) {
+          return ((bit(e) | (bit(o) << 16)) << 15) | 0x3F803F80u;
         };
         const uint4 sv = make_uint4(pair(w0.x, w0.y), pair(w0.z, w0.w), pair(w1.x, w1.y),
                                     pair(w1.z, w1.w));
@@ -339,10 +339,15 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
           const mf_bf16x8 bv = *reinterpret_cast<const mf_bf16x8*>(&L.A[buf][ncol][k0 + kq]);
           acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[t], 0, 0, 0);
         }
-      } else {
-        auto quad = [bs, one8](const uint4 w) {
-          return one8 | (((w.x >> bs) & 1u) << 7) | (((w.y >> bs) & 1u) << 15) |
-                 (((w.z >> bs) & 1u) << 23) | (((w.w >> bs) & 1u) << 31);
+      }
+    } else {
+#pragma unroll 2
+      for (int k0 = 0; k0 < MF_MB; k0 += 16) {
+        const uint4 w0 = *reinterpret_cast<const uint4*>(&L.S[buf][mq][k0 + kq]);
+        const uint4 w1 = *reinterpret_cast<const uint4*>(&L.S[buf][mq][k0 + kq + 4]);
+        // four elements per word: the +1 byte, sign bit 7 of each byte
+        auto quad = [&](const uint4 w) {
+          return ((bit(w.x) | (bit(w.y) << 8) | (bit(w.z) << 16) | (bit(w.w) << 24)) << 7) | one8;
         };
         const long a = (long)(((uint64_t)quad(w1) << 32) | quad(w0));
 #pragma unroll
