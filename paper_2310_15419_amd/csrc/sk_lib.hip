@@ -257,7 +257,7 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
 // kernel (nnz d FMAs at the VALU rate, with its gather and padding costs).
 // The threshold is a density in percent (the measured crossover of the two
 // kernels on MI355X); dense_min_pct overrides it.
-constexpr double kMfmaAutoPct[3] = {0.0, 3.5, 4.0};  // unused, BF16, FP8
+constexpr double kMfmaAutoPct[3] = {0.0, 1.5, 3.0};  // unused, BF16, FP8
 
 int mfma_format(int64_t m, int64_t n, int64_t nnz, int dist, int prec, const sk_tuning* tune) {
   if (prec == SK_PREC_F32 || dist != SK_RADEMACHER) return 0;
