@@ -200,7 +200,9 @@ def bench_batched(args):
     import torch
     from paper_2310_15419_amd import binding as B, inputs
     t_gen = time.perf_counter()
-    workers = min(16, len(os.sched_getaffinity(0)))
+    # a process pool generates the items (one process under a profiler:
+    # --workers 1)
+    workers = args.workers or min(16, len(os.sched_getaffinity(0)))
     items = inputs.workload_batched(args.batch_count, workers=workers)
     print(f"[bench] {len(items)} items in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr,
           flush=True)
@@ -303,6 +305,8 @@ def main():
     ap.add_argument("--row-pad", type=int, default=0)
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--workers", type=int, default=0,
+                    help="processes generating the batched items (0: up to 16)")
     ap.add_argument("--serve-pool", type=int, default=24)
     ap.add_argument("--serve-requests", type=int, default=150)
     ap.add_argument("--serve-slots", type=int, default=8)
