@@ -232,13 +232,37 @@ __device__ __forceinline__ int find_item(const Item* __restrict__ it, int count,
   return lo;
 }
 
+// The items of a workgroup's first and last indices (s_item[0], s_item[1]);
+// when they are the same (the usual case) the item is uniform, so its
+// descriptor is read with scalar loads rather than once per lane.
+template <int64_t Item::*F>
+__device__ __forceinline__ void workgroup_items(const Item* __restrict__ it, int count,
+                                                int64_t total, int* s_item) {
+  const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t glast = (g0 + blockDim.x < total ? g0 + blockDim.x : total) - 1;
+  if (threadIdx.x < 2) s_item[threadIdx.x] = find_item<F>(it, count, threadIdx.x ? glast : g0);
+  __syncthreads();
+}
+
 // One thread per flattened index: Op::run(item, index inside the item).
 template <int64_t Item::*F, class Op>
-__global__ void k_items(const Item* __restrict__ it, int count, int64_t total) {
+__global__ __launch_bounds__(256) void k_items(const Item* __restrict__ it, int count,
+                                               int64_t total) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (count == 1) {
+    if (g < total) Op::run(it[0], g);
+    return;
+  }
+  __shared__ int s_item[2];
+  workgroup_items<F>(it, count, total, s_item);
   if (g >= total) return;
-  const int i = count == 1 ? 0 : find_item<F>(it, count, g);
-  Op::run(it[i], g - it[i].*F);
+  if (s_item[0] == s_item[1]) {
+    const int i = __builtin_amdgcn_readfirstlane(s_item[0]);
+    Op::run(it[i], g - it[i].*F);
+  } else {
+    const int i = find_item<F>(it, count, g);
+    Op::run(it[i], g - it[i].*F);
+  }
 }
 
 // One thread per index of an entry-indexed space (field F holds each item's
@@ -264,21 +288,28 @@ __global__ __launch_bounds__(256) void k_items_cols(const Item* __restrict__ it,
   }
   __syncthreads();
   if (g >= total) return;
-  const bool one = s_item[0] == s_item[1];
-  const int i = one ? s_item[0] : find_item<F>(it, count, g);
-  const Item& I = it[i];
-  const int64_t t = g - I.*F;
-  int64_t k = 0;
-  if (t < I.nnz) {
-    int64_t lo = one ? s_col[0] : 0, hi = one ? s_col[1] : I.n - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (I.colptr[mid] <= t) lo = mid;
-      else hi = mid - 1;
+  // the column of entry t, searched between the given bounds
+  auto column = [](const Item& I, int64_t t, int64_t lo, int64_t hi) {
+    int64_t k = 0;
+    if (t < I.nnz) {
+      while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (I.colptr[mid] <= t) lo = mid;
+        else hi = mid - 1;
+      }
+      k = lo;
     }
-    k = lo;
+    return k;
+  };
+  if (s_item[0] == s_item[1]) {  // one item: uniform descriptor, narrow search
+    const Item& I = it[__builtin_amdgcn_readfirstlane(s_item[0])];
+    const int64_t t = g - I.*F;
+    Op::run(I, t, column(I, t, s_col[0], s_col[1]));
+  } else {
+    const Item& I = it[find_item<F>(it, count, g)];
+    const int64_t t = g - I.*F;
+    Op::run(I, t, column(I, t, 0, I.n - 1));
   }
-  Op::run(I, t, k);
 }
 
 // Validate, mark occupied rows and count entries per row.  One thread per
@@ -329,10 +360,19 @@ __global__ __launch_bounds__(1024) void k_row_counts(const Item* __restrict__ it
       if (I.rowidx[mid] < r0) lo = mid + 1;
       else hi = mid;
     }
-    for (int64_t p = lo; p < c1; ++p) {
-      const int32_t r = I.rowidx[p];
-      if (r >= r1 || r < r0) break;
-      atomicAdd(&cnt[r - r0], 1);
+    // the column's run in the tile, eight rows per load round (the loads of
+    // a round are independent, so their latencies overlap)
+    for (int64_t p = lo; p < c1; p += 8) {
+      int32_t r[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) r[u] = p + u < c1 ? I.rowidx[p + u] : (int32_t)r1;
+      bool past = false;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (r[u] >= r1 || r[u] < r0) past = true;  // (below r0 only on malformed input)
+        else atomicAdd(&cnt[r[u] - r0], 1);
+      }
+      if (past) break;
     }
   }
   __syncthreads();
