@@ -76,6 +76,8 @@ struct Item {
   Header* hdr;
   int32_t* ridx;      // m + 1, region of a concatenated array
   int32_t* rcnt;      // m
+  int32_t* rpart;     // partial row counts per (row tile, column slab): tiles *
+                      // slabs * RT_ROWS (nullptr when the item has one slab)
   int32_t* rowlist;   // r_max + m_b + 1 (padded for whole-group reads)
   int32_t* rowcnt;    // r_max
   int32_t* bfl;       // r_max + 1, region of a concatenated array
@@ -107,7 +109,7 @@ struct Item {
   int64_t o_seg;      // nb_max * nv + 1
   int64_t o_nnz;      // nnz
   int64_t o_blk;      // nb_max + 1
-  int64_t o_rt;       // row tiles of the counting pass, ceil(m / RT_ROWS)
+  int64_t o_rt;       // (row tile, column slab) pairs of the counting pass
 };
 
 template <typename T>
@@ -333,55 +335,97 @@ struct OpValidate {
   }
 };
 
-// Entries per row without global atomics: one workgroup per tile of RT_ROWS
-// rows of one item.  Rows are sorted inside each column, so the entries of a
-// column that fall in the tile are one run, found by a binary search (one
-// column per lane); they are counted with LDS atomics, then the counts and
-// the occupancy flags are written out in order.  (On malformed input the
-// counts are meaningless, and the validation status stops everything after.)
+// Entries per row without global atomics: one workgroup per (tile of
+// RT_ROWS rows, slab of RT_COLS columns) of one item.  Rows are sorted
+// inside each column, so the entries of a column that fall in the tile are
+// one run, found by a binary search; four lanes walk it (every fourth entry)
+// and count the rows with LDS atomics.  Column slabs spread a tile whose rows
+// are dense (many columns share them) over several workgroups; with more
+// than one slab the counts go to per-slab partials, summed by OpRowReduce.
+// (On malformed input the counts are meaningless, and the validation status
+// stops everything after.)
 constexpr int RT_ROWS = 8192;
+constexpr int RT_COLS = 256;
+
+__host__ __device__ inline int64_t rt_slabs(int64_t n) {
+  return n > RT_COLS ? (n + RT_COLS - 1) / RT_COLS : 1;
+}
+
 __global__ __launch_bounds__(1024) void k_row_counts(const Item* __restrict__ it, int count,
-                                                      int64_t total_tiles) {
+                                                      int64_t total) {
   __shared__ int32_t cnt[RT_ROWS];
   const int64_t g = blockIdx.x;
-  if (g >= total_tiles) return;
+  if (g >= total) return;
   const int i = count == 1 ? 0 : find_item<&Item::o_rt>(it, count, g);
   const Item& I = it[i];
-  const int64_t r0 = (g - I.o_rt) * RT_ROWS;
+  const int64_t slabs = rt_slabs(I.n);
+  const int64_t w = g - I.o_rt;
+  const int64_t tile = w / slabs, slab = w - tile * slabs;
+  const int64_t r0 = tile * RT_ROWS;
   const int64_t r1 = r0 + RT_ROWS < I.m ? r0 + RT_ROWS : I.m;
   for (int j = threadIdx.x; j < RT_ROWS; j += blockDim.x) cnt[j] = 0;
   __syncthreads();
-  for (int64_t k = threadIdx.x; k < I.n; k += blockDim.x) {
-    const int64_t c0 = I.colptr[k], c1 = I.colptr[k + 1];
-    if (c0 < 0 || c1 > I.nnz || c1 < c0) continue;  // malformed (flagged by the validation)
+  const int64_t k = slab * RT_COLS + (threadIdx.x >> 2);
+  const int64_t c0 = k < I.n ? I.colptr[k] : 0, c1 = k < I.n ? I.colptr[k + 1] : 0;
+  if (k < I.n && c0 >= 0 && c1 <= I.nnz && c1 >= c0) {  // (malformed: flagged by the validation)
     int64_t lo = c0, hi = c1;  // first entry with row >= r0
     while (lo < hi) {
       const int64_t mid = (lo + hi) >> 1;
       if (I.rowidx[mid] < r0) lo = mid + 1;
       else hi = mid;
     }
-    // the column's run in the tile, eight rows per load round (the loads of
-    // a round are independent, so their latencies overlap)
-    for (int64_t p = lo; p < c1; p += 8) {
-      int32_t r[8];
+    // entries p, p + 4, ... below `end`, eight per load round (independent
+    // loads, so their latencies overlap), up to the first row past the tile
+    auto run = [&](int64_t p, int64_t end) {
+      for (; p < end; p += 32) {
+        int32_t r[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) r[u] = p + u < c1 ? I.rowidx[p + u] : (int32_t)r1;
-      bool past = false;
+        for (int u = 0; u < 8; ++u) r[u] = p + 4 * u < end ? I.rowidx[p + 4 * u] : (int32_t)r1;
+        bool past = false;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (r[u] >= r1 || r[u] < r0) past = true;  // (below r0 only on malformed input)
-        else atomicAdd(&cnt[r[u] - r0], 1);
+        for (int u = 0; u < 8; ++u) {
+          if (r[u] >= r1 || r[u] < r0) past = true;  // (below r0 only on malformed input)
+          else atomicAdd(&cnt[r[u] - r0], 1);
+        }
+        if (past) break;
       }
-      if (past) break;
-    }
+    };
+    // the lanes of a wave start at staggered points of their runs (then wrap
+    // round to the head), so where columns share rows they add to
+    // different counters at a time
+    const int64_t s0 = lo + (threadIdx.x & 3);
+    const int64_t st = s0 + 4 * ((threadIdx.x >> 2) & 7);
+    const int64_t mid = st < c1 ? st : c1;
+    run(mid, c1);
+    run(s0, mid);
   }
   __syncthreads();
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const int32_t c = cnt[r - r0];
+  if (slabs == 1) {
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+      const int32_t c = cnt[r - r0];
+      I.rcnt[r] = c;
+      I.ridx[r] = c > 0 ? 1 : 0;
+    }
+  } else {
+    int32_t* __restrict__ out = I.rpart + w * RT_ROWS;
+    for (int64_t j = threadIdx.x; j < r1 - r0; j += blockDim.x) out[j] = cnt[j];
+  }
+}
+
+// rows of an item with several column slabs: counts and occupancy flags
+// from the slabs' partial counts (in a fixed order)
+struct OpRowReduce {
+  static __device__ void run(const Item& I, int64_t r) {
+    if (!I.rpart) return;
+    const int64_t slabs = rt_slabs(I.n);
+    const int64_t tile = r / RT_ROWS, j = r - tile * RT_ROWS;
+    const int32_t* __restrict__ p = I.rpart + tile * slabs * RT_ROWS + j;
+    int32_t c = 0;
+    for (int64_t s = 0; s < slabs; ++s) c += p[s * RT_ROWS];
     I.rcnt[r] = c;
     I.ridx[r] = c > 0 ? 1 : 0;
   }
-}
+};
 
 // region bases after a concatenated scan
 enum : int { SCAN_RIDX = 0, SCAN_BFL = 1, SCAN_VBASE = 2, SCAN_SEG = 3, SCAN_COST = 4 };

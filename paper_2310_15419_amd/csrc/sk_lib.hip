@@ -223,9 +223,14 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
   } else if (unit_cycles > 0) {
     splits = (int64_t)std::ceil(best / ((double)P.tiles * P.ncr * unit_cycles));
   } else {
+    // about eight workgroups per CU, rounded to the nearest multiple of four
+    // from eight splits on (the splits then sit on fixed pairs of XCDs).
+    // Fewer splits write and reduce fewer partial slices; more balance
+    // uneven blocks (measured: uniform rows favour 12-16 splits at d = 4000,
+    // power-law columns 24 at d = 3000)
     const int64_t wgs_now = (int64_t)P.tiles * ncr;
-    splits = (2048 + wgs_now - 1) / wgs_now;
-    if (splits >= 8) splits = (splits + 7) / 8 * 8;  // whole XCDs per split
+    splits = std::max<int64_t>(1, (2048 + wgs_now / 2) / wgs_now);
+    if (splits >= 8) splits = (splits + 2) / 4 * 4;
     splits = std::min<int64_t>(splits, 64);
   }
   splits = std::max<int64_t>(1, std::min<int64_t>(splits, P.nb_max));
@@ -327,7 +332,14 @@ bool plan_any(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, int prec,
 
 // Workspace of one sketch.  The header sits at offset 0 (the status call
 // reads it there).
+// partial row counts of an item with several column slabs (ints)
+int64_t rpart_ints(int64_t m, int64_t n) {
+  const int64_t slabs = rt_slabs(n);
+  return slabs > 1 ? (m + RT_ROWS - 1) / RT_ROWS * slabs * RT_ROWS : 0;
+}
+
 struct Layout {
+  int64_t rpart;
   int64_t hdr, item, ridx, rcnt, rowlist, rowcnt, bfl, bstart, vbase, pos, seg, ent, bcost, sums,
       rowinfo;
   int64_t dflag, dlist, doff, dhdr, drows, dense, part, total;
@@ -354,6 +366,7 @@ Layout layout_for(int64_t m, int64_t n, int64_t nnz, int64_t d, const Plan& P) {
   L.ent = off;     off = align_up(off + 8 * (nnz + 2));  // +2: 16-byte staging tail
   L.bcost = off;   off = align_up(off + 4 * (P.nb_max + 2));
   L.rowinfo = off; off = align_up(off + 8 * m);
+  L.rpart = off;   off = align_up(off + 4 * rpart_ints(m, n));
   const int64_t longest = std::max<int64_t>({m + 1, P.r_max + 1, n + 1, P.nb_max * P.nv + 1});
   L.sums = off;    off = align_up(off + 4 * scan_sums_len(longest));
   L.dflag = off;   off = align_up(off + 4 * P.nb_max);
@@ -408,6 +421,7 @@ sk_status scan_i32(int32_t* a, int64_t count, int32_t* sums, hipStream_t st) {
 struct InspectSizes {
   int64_t valid = 0, ridx = 0, m = 0, grp = 0, bfl = 0, rmax = 0, col = 0, vb = 0, pos = 0,
           cnt = 0, seg = 0, nnz = 0, blk = 0, rt = 0;
+  bool slabs = false;  // some item counts its rows in several column slabs
 };
 
 // offsets of item I in each index space; sizes accumulate into Z
@@ -425,7 +439,8 @@ void item_offsets(Item& I, InspectSizes& Z) {
   I.o_seg = Z.seg;     Z.seg += I.nb_max * I.nv + 1;
   I.o_nnz = Z.nnz;     Z.nnz += I.nnz;
   I.o_blk = Z.blk;     Z.blk += I.nb_max + 1;
-  I.o_rt = Z.rt;       Z.rt += (I.m + RT_ROWS - 1) / RT_ROWS;
+  I.o_rt = Z.rt;       Z.rt += (I.m + RT_ROWS - 1) / RT_ROWS * rt_slabs(I.n);
+  if (rt_slabs(I.n) > 1) Z.slabs = true;
 }
 
 struct InspectArrays {
@@ -474,7 +489,9 @@ sk_status run_inspector(Item* it, int count, const InspectSizes& Z, const Inspec
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(Z.bfl + 1, 256 * 8)), dim3(256), 0, st,
                      W.bfl, Z.bfl + 1, 0);
   launch_items_cols<&Item::o_valid, OpValidate>(it, count, Z.valid, st);
-  hipLaunchKernelGGL(k_row_counts, dim3((unsigned)Z.rt), dim3(1024), 0, st, it, count, Z.rt);
+  if (Z.rt > 0)
+    hipLaunchKernelGGL(k_row_counts, dim3((unsigned)Z.rt), dim3(1024), 0, st, it, count, Z.rt);
+  if (Z.slabs) launch_items<&Item::o_m, OpRowReduce>(it, count, Z.m, st);
   if ((s = scan_regions<SCAN_RIDX, &Item::o_ridx>(W.ridx, Z.ridx, it, count, W.sums, st)) != SK_OK)
     return s;
   launch_items<&Item::o_m, OpRowlist>(it, count, Z.m, st);
@@ -563,7 +580,7 @@ SketchParams make_params(const Plan& P, const Item& I, int64_t d, int64_t row0, 
 struct BatchPlan {
   int variant = 0;
   std::vector<Plan> plans;
-  std::vector<int64_t> rowlist, rowcnt, bstart, pos, ent, part, rowinfo;
+  std::vector<int64_t> rowlist, rowcnt, bstart, pos, ent, part, rowinfo, rpart;
   InspectSizes Z;
   int64_t hdrs = 0, items = 0, outs = 0, work = 0, counters = 0;
   int64_t ridx_all = 0, rcnt_all = 0, bfl_all = 0, seg_all = 0, bcost_all = 0, sums = 0;
@@ -641,6 +658,7 @@ sk_status batch_plan(int32_t count, const sk_csc* A, const int64_t* d, const int
   off = align_up(off + 4 * scan_sums_len(std::max({Z.ridx, Z.bfl, Z.seg, Z.blk})));
   B.rowlist.resize(count); B.rowcnt.resize(count); B.bstart.resize(count);
   B.pos.resize(count); B.ent.resize(count); B.part.resize(count); B.rowinfo.resize(count);
+  B.rpart.resize(count);
   for (int i = 0; i < count; ++i) {
     const Plan& P = B.plans[i];
     const int64_t n = A[i].n, nnz = A[i].nnz;
@@ -650,6 +668,7 @@ sk_status batch_plan(int32_t count, const sk_csc* A, const int64_t* d, const int
     B.pos[i] = off;     off = align_up(off + 4 * (P.nb_max + 1) * n);
     B.ent[i] = off;     off = align_up(off + 8 * (nnz + 2));
     B.rowinfo[i] = off; off = align_up(off + 8 * A[i].m);
+    B.rpart[i] = off;   off = align_up(off + 4 * rpart_ints(A[i].m, n));
     B.part[i] = off;
     if (P.slices > 1) off = align_up(off + 4 * (int64_t)P.slices * d[i] * n);
   }
@@ -850,6 +869,7 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
   I.ent = (uint2*)(w + L.ent);
   I.bcost = (int32_t*)(w + L.bcost);
   I.rowinfo = (int2*)(w + L.rowinfo);
+  I.rpart = rpart_ints(A->m, n) ? (int32_t*)(w + L.rpart) : nullptr;
   I.dflag = P.dense_pct ? (int32_t*)(w + L.dflag) : nullptr;
   InspectSizes Z;
   item_offsets(I, Z);
@@ -1041,6 +1061,7 @@ sk_status sk_sketch_batched(int32_t count, const sk_csc* A, const int64_t* d, co
     I.pos = (int32_t*)(w + B.pos[i]);
     I.ent = (uint2*)(w + B.ent[i]);
     I.rowinfo = (int2*)(w + B.rowinfo[i]);
+    I.rpart = rpart_ints(I.m, I.n) ? (int32_t*)(w + B.rpart[i]) : nullptr;
     item_offsets(I, Z);
     BatchOut& O = outs[i];
     std::memset(&O, 0, sizeof O);
