@@ -44,6 +44,7 @@ using PersistentKernel = void (*)(const BatchOut*, const int2*, int, int32_t*);
 struct Variant {
   int dl, q, cs, wgs;
   SketchKernel k[3];      // per distribution
+  SketchKernel kf[3];     // per distribution, adding virtual columns in the kernel
   PersistentKernel p[3];  // persistent (batched) form, per distribution
 };
 
@@ -52,6 +53,9 @@ struct Variant {
     DL, Q, CS, WGS,                                                                          \
         {k_sketch<DIST_RADEMACHER, DL, Q, CS, WGS>, k_sketch<DIST_UNIFORM, DL, Q, CS, WGS>,  \
          k_sketch<DIST_GAUSSIAN, DL, Q, CS, WGS>},                                           \
+        {k_sketch<DIST_RADEMACHER, DL, Q, CS, WGS, true>,                                    \
+         k_sketch<DIST_UNIFORM, DL, Q, CS, WGS, true>,                                       \
+         k_sketch<DIST_GAUSSIAN, DL, Q, CS, WGS, true>},                                     \
         {k_sketch_persistent<DIST_RADEMACHER, DL, Q, CS, WGS>,                               \
          k_sketch_persistent<DIST_UNIFORM, DL, Q, CS, WGS>,                                  \
          k_sketch_persistent<DIST_GAUSSIAN, DL, Q, CS, WGS>}                                 \
@@ -573,7 +577,21 @@ SketchParams make_params(const Plan& P, const Item& I, int64_t d, int64_t row0, 
   K.m_b = P.m_b; K.e_max = P.e_max; K.d_b = P.d_b; K.ldS = P.ldS; K.log2_cpr = P.log2_cpr;
   K.dt = P.dt; K.cg = P.cg; K.tiles = P.tiles; K.splits = P.splits;
   K.col_per_wg = P.col_per_wg;
+  K.vbase = nullptr;
+  K.nreal = P.nv;
   return K;
+}
+
+// The sparse kernel adds virtual columns itself when they all lie in one
+// column range, one row of every lane's S rows fits the LDS at once, and
+// the split is substantial (at least n/4 extra virtual columns: heavy
+// columns with many pieces make the separate reduction's longest sums; with
+// few pieces that reduction is cheap and the kernel's folded writes, one
+// row of DL per pass, cost more)
+bool folds_virtual(const Plan& P, int64_t n) {
+  if (P.mfma || P.nv <= n || P.nv - n < (n + 3) / 4 || P.ncr != 1) return false;
+  const Variant& V = kVariants[P.variant];
+  return (int64_t)(P.d_b / V.dl) * P.col_per_wg * 4 <= (int64_t)P.lds;
 }
 
 // ------------------------------------------------------------------ batch
@@ -913,8 +931,13 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
   // the matrix cores for +-1 S in BF16/FP8)
   SketchParams K = make_params(P, I, d, row0, seed);
   K.dflag = P.dense_pct ? dflag : nullptr;
-  const bool staged = P.slices > 1 || nv != n;  // partials, then the reduction
-  if (staged) { K.out = part; K.ld = d; K.split_stride = d * nv; }
+  // virtual columns: added in the kernel (then it writes the n real
+  // columns) or in the reduction
+  const bool fold = I.vbase != nullptr && folds_virtual(P, n);
+  if (fold) { K.vbase = I.vbase; K.nreal = n; }
+  const int64_t wcols = fold ? n : nv;  // columns of one partial slice
+  const bool staged = P.slices > 1 || wcols != n;  // partials, then the reduction
+  if (staged) { K.out = part; K.ld = d; K.split_stride = d * wcols; }
   else { K.out = Ahat; K.ld = ld; K.split_stride = 0; }
   const int64_t grid = (int64_t)P.tiles * P.ncr * P.splits;
   if (grid >= INT32_MAX) return SK_EUNSUPPORTED;
@@ -935,7 +958,7 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
     }
   } else {
     const Variant& V = kVariants[P.variant];
-    SketchKernel kern = V.k[dist];
+    SketchKernel kern = fold ? V.kf[dist] : V.k[dist];
     if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)P.lds) != hipSuccess)
       return SK_EHIP;
@@ -949,7 +972,7 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
     DenseParams DP{};
     DP.drows = drows; DP.dh = dhdr; DP.hdr = I.hdr; DP.D = dense;
     DP.n = n; DP.d = d; DP.row0 = row0; DP.seed = seed;
-    DP.out = part + (int64_t)P.splits * d * nv;
+    DP.out = part + (int64_t)P.splits * d * wcols;
     const int64_t dgrid = ((d + DT_M - 1) / DT_M) * ((n + DT_N - 1) / DT_N);
     if (dgrid >= INT32_MAX) return SK_EUNSUPPORTED;
     if (dist == SK_RADEMACHER)
@@ -963,8 +986,8 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
   // a6: fixed-order reduction of the partial slices (and virtual columns)
   if ((phases & 4) && staged)
     hipLaunchKernelGGL(k_reduce_virtual, dim3(blocks_for(d * n, 256)), dim3(256), 0, st, part,
-                       P.splits, d, n, nv, I.vbase,
-                       P.dense_pct ? part + (int64_t)P.splits * d * nv : nullptr, Ahat, ld);
+                       P.splits, d, n, wcols, fold ? nullptr : I.vbase,
+                       P.dense_pct ? part + (int64_t)P.splits * d * wcols : nullptr, Ahat, ld);
   return launch_ok();
 }
 

@@ -51,6 +51,11 @@ struct SketchParams {
   float* out;       // A_hat (splits == 1) or the split partials
   int64_t ld;       // leading dimension of out
   int64_t split_stride;
+  // non-null: n counts virtual columns (all in one column range) and the
+  // kernel adds each real column's virtual columns before writing out
+  // (nreal columns); null: out holds the n (virtual) columns
+  const int32_t* vbase;
+  int64_t nreal;
 };
 
 // ---------------------------------------------------------------- S tile
@@ -166,7 +171,10 @@ __device__ __forceinline__ void stage_entries(uint2* __restrict__ E_lds,
 // One work unit: S-row tile `tile`, column range `crange`, row-block split
 // `split` of one sketch.  Used by the plain grid and by the persistent batched
 // kernel.
-template <int DIST, int DL, int Q, int CS, int WGS>
+// FOLD: the columns are virtual (P.vbase) and the unit adds each real
+// column's pieces before writing (a separate instantiation, so the plain
+// kernels keep their own register allocation)
+template <int DIST, int DL, int Q, int CS, int WGS, bool FOLD = false>
 __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, int tile, int crange,
                                             unsigned char* __restrict__ smem) {
   // LDS: S tile (m_b x ldS floats) | entries (e_max + 2) | segment bounds of
@@ -304,31 +312,64 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
       }
     }
   }
-  if (active) {
-    float* __restrict__ out = P.out + (int64_t)split * P.split_stride;
-    const float nan = __uint_as_float(0x7FC00000u);
+  float* __restrict__ out = P.out + (int64_t)split * P.split_stride;
+  const float nan = __uint_as_float(0x7FC00000u);
+  if constexpr (!FOLD) {
+    if (active) {
 #pragma unroll
-    for (int c = 0; c < CS; ++c) {
-      const int64_t k = kbase + c;
-      if (k < P.n && k < (int64_t)(crange + 1) * P.col_per_wg) {
+      for (int c = 0; c < CS; ++c) {
+        const int64_t k = kbase + c;
+        if (k < P.n && k < (int64_t)(crange + 1) * P.col_per_wg) {
 #pragma unroll
-        for (int t = 0; t < DL; ++t) {
-          const int64_t i = i_tile + rofs + t;
-          if (i < P.d) out[i + k * P.ld] = status ? nan : acc[c][t];
+          for (int t = 0; t < DL; ++t) {
+            const int64_t i = i_tile + rofs + t;
+            if (i < P.d) out[i + k * P.ld] = status ? nan : acc[c][t];
+          }
         }
       }
     }
+  } else {
+  if (!P.vbase) return;  // (the host launches this form only with virtual columns)
+  // Heavy columns split into virtual columns, all in this workgroup's one
+  // column range: add each real column's virtual columns (in order) through
+  // LDS, one of every lane's DL rows at a time, and write the real columns.
+  float* __restrict__ V = reinterpret_cast<float*>(smem);  // row slots x col_per_wg
+  const int slots = P.dt * Q;
+  const int cpw = P.col_per_wg;
+  const int slot = dsub * Q + q;  // rofs = slot * DL
+#pragma unroll
+  for (int t = 0; t < DL; ++t) {
+    __syncthreads();  // the tiles (or the previous row) are no longer read
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < CS; ++c) {
+        const int lc = cgi * CS + c;
+        if (lc < cpw) V[slot * cpw + lc] = acc[c][t];
+      }
+    }
+    __syncthreads();
+    for (int64_t x = tid; x < (int64_t)slots * P.nreal; x += WGS) {
+      const int64_t k = x / slots;
+      const int r = (int)(x - k * slots);
+      const int64_t i = i_tile + (int64_t)r * DL + t;
+      if (i >= P.d) continue;
+      const int32_t v0 = P.vbase[k], v1 = P.vbase[k + 1];
+      float sum = 0.0f;
+      for (int32_t v = v0; v < v1; ++v) sum += V[r * cpw + v];
+      out[i + k * P.ld] = status ? nan : sum;
+    }
+  }
   }
 }
 
-template <int DIST, int DL, int Q, int CS, int WGS>
+template <int DIST, int DL, int Q, int CS, int WGS, bool FOLD = false>
 __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(4))) void k_sketch(
     SketchParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int bid = blockIdx.x;
   const int split = bid % P.splits;
   const int rest = bid / P.splits;
-  sketch_unit<DIST, DL, Q, CS, WGS>(P, split, rest % P.tiles, rest / P.tiles, smem);
+  sketch_unit<DIST, DL, Q, CS, WGS, FOLD>(P, split, rest % P.tiles, rest / P.tiles, smem);
 }
 
 // A_hat[i, k] = sum over sparse slices of the virtual columns of k, then the
