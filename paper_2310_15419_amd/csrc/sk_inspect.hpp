@@ -67,6 +67,7 @@ struct Item {
   int32_t m_b;        // rows per row group (S-tile capacity)
   int32_t e_cap;      // entries per block (staging capacity)
   int32_t row_bytes;  // S-tile row stride in bytes
+  int32_t bp_chunk;   // blocks per thread of the block-position search
   int32_t col_tag;    // nonzero: an entry's row offset also carries (column mod
                       // col_tag) << 16 (the matrix-core kernel's tile column)
   int64_t nv;         // (virtual) columns of the layout
@@ -104,7 +105,7 @@ struct Item {
   int64_t o_rmax;     // r_max
   int64_t o_col;      // n
   int64_t o_vb;       // n + 1
-  int64_t o_pos;      // (nb_max + 1) * nv
+  int64_t o_pos;      // ceil((nb_max + 1) / bp_chunk) * nv
   int64_t o_cnt;      // nb_max * nv
   int64_t o_seg;      // nb_max * nv + 1
   int64_t o_nnz;      // nnz
@@ -577,15 +578,21 @@ __device__ __forceinline__ int64_t real_column(const int32_t* __restrict__ vbase
 
 // pos[b*nv + v], b = 0..nb_max, in units of the (virtual) column's own
 // positions: how many of its entries lie above block b (all of them for
-// b >= nblocks)
+// b >= nblocks).  One thread per (virtual column, run of bp_chunk blocks):
+// a binary search for the first block, then, as blocks only move down the
+// column, a galloping search from the previous position for each next one
+// (bp_chunk > 1 where a column has few entries per block, so the gallops
+// are short; else the longer chains would cost more than they save).
 struct OpBlockPos {
   static __device__ void run(const Item& I, int64_t t) {
     if (I.hdr->status) return;
-    const int64_t b = t / I.nv, v = t - b * I.nv;
+    const int64_t bc = t / I.nv, v = t - bc * I.nv;
+    const int chunk = I.bp_chunk;
+    const int64_t b0 = bc * chunk;
     int64_t k = v, s = 1, r = 0;
     if (I.vbase) {
       if (v >= I.vbase[I.n]) {
-        I.pos[t] = 0;
+        for (int j = 0; j < chunk && b0 + j <= I.nb_max; ++j) I.pos[(b0 + j) * I.nv + v] = 0;
         return;
       }
       k = real_column(I.vbase, I.n, v);
@@ -593,19 +600,32 @@ struct OpBlockPos {
       r = v - I.vbase[k];
     }
     const int64_t c0 = I.colptr[k], cnt = I.colptr[k + 1] - c0;
-    const int64_t T = cnt > r ? (cnt - r + s - 1) / s : 0;
-    int64_t lo = 0, hi = T;
-    if (b < I.hdr->nblocks) {
-      const int32_t fr = I.rowlist[I.bstart[b]];
-      while (lo < hi) {  // lower bound of fr among rows c0 + r + t s
-        const int64_t mid = (lo + hi) >> 1;
-        if (I.rowidx[c0 + r + mid * s] < fr) lo = mid + 1;
-        else hi = mid;
+    const int64_t T = cnt > r ? (cnt - r + s - 1) / s : 0;  // entries of v
+    const int32_t* __restrict__ rows = I.rowidx + c0 + r;    // entry j of v: rows[j * s]
+    const int64_t nbk = I.hdr->nblocks;
+    int64_t lo = 0;  // entries of v above the current block
+    for (int j = 0; j < chunk && b0 + j <= I.nb_max; ++j) {
+      const int64_t b = b0 + j;
+      if (b < nbk) {
+        const int32_t fr = I.rowlist[I.bstart[b]];  // the block's first row
+        // first entry at or below fr, at or after lo: gallop, then bisect
+        int64_t hi = lo, step = 1;
+        while (hi < T && rows[hi * s] < fr) {
+          lo = hi + 1;
+          hi += step;
+          step <<= 1;
+        }
+        if (hi > T) hi = T;
+        while (lo < hi) {
+          const int64_t mid = (lo + hi) >> 1;
+          if (rows[mid * s] < fr) lo = mid + 1;
+          else hi = mid;
+        }
+      } else {
+        lo = T;
       }
-    } else {
-      lo = hi;
+      I.pos[b * I.nv + v] = (int32_t)lo;
     }
-    I.pos[t] = (int32_t)lo;
   }
 };
 
