@@ -268,18 +268,24 @@ __global__ __launch_bounds__(256) void k_items(const Item* __restrict__ it, int 
   }
 }
 
-// One thread per index of an entry-indexed space (field F holds each item's
-// offset); Op::run also gets the column of the entry, found by a search
-// limited to the columns of the workgroup's first and last entries (one
-// column, typically) instead of one over all of colptr.
+// An entry-indexed space (field F holds each item's offset), IC_PER indices
+// per thread (strided by the workgroup size, so loads stay coalesced);
+// Op::run also gets the column of the entry, found by a search limited to the
+// columns of the workgroup's first and last entries (a few columns,
+// typically) instead of one over all of colptr.  The workgroup's search for
+// those bounds is the latency every index waits on, so it covers 1024 of
+// them.
+constexpr int IC_THREADS = 256;
+constexpr int IC_PER = 4;
+
 template <int64_t Item::*F, class Op>
-__global__ __launch_bounds__(256) void k_items_cols(const Item* __restrict__ it, int count,
-                                                    int64_t total) {
+__global__ __launch_bounds__(IC_THREADS) void k_items_cols(const Item* __restrict__ it, int count,
+                                                           int64_t total) {
   __shared__ int s_item[2];
   __shared__ int64_t s_col[2];
-  const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
-  const int64_t g = g0 + threadIdx.x;
-  const int64_t glast = (g0 + blockDim.x < total ? g0 + blockDim.x : total) - 1;
+  const int64_t g0 = (int64_t)blockIdx.x * (IC_THREADS * IC_PER);
+  const int64_t span = IC_THREADS * IC_PER;
+  const int64_t glast = (g0 + span < total ? g0 + span : total) - 1;
   if (threadIdx.x < 2) {
     const int64_t gg = threadIdx.x == 0 ? g0 : glast;
     const int i = count == 1 ? 0 : find_item<F>(it, count, gg);
@@ -290,7 +296,6 @@ __global__ __launch_bounds__(256) void k_items_cols(const Item* __restrict__ it,
     s_col[threadIdx.x] = t >= 0 ? column_of(I.colptr, I.n, t) : 0;
   }
   __syncthreads();
-  if (g >= total) return;
   // the column of entry t, searched between the given bounds
   auto column = [](const Item& I, int64_t t, int64_t lo, int64_t hi) {
     int64_t k = 0;
@@ -306,12 +311,21 @@ __global__ __launch_bounds__(256) void k_items_cols(const Item* __restrict__ it,
   };
   if (s_item[0] == s_item[1]) {  // one item: uniform descriptor, narrow search
     const Item& I = it[__builtin_amdgcn_readfirstlane(s_item[0])];
-    const int64_t t = g - I.*F;
-    Op::run(I, t, column(I, t, s_col[0], s_col[1]));
+#pragma unroll
+    for (int j = 0; j < IC_PER; ++j) {
+      const int64_t g = g0 + threadIdx.x + j * IC_THREADS;
+      if (g >= total) break;
+      const int64_t t = g - I.*F;
+      Op::run(I, t, column(I, t, s_col[0], s_col[1]));
+    }
   } else {
-    const Item& I = it[find_item<F>(it, count, g)];
-    const int64_t t = g - I.*F;
-    Op::run(I, t, column(I, t, 0, I.n - 1));
+    for (int j = 0; j < IC_PER; ++j) {
+      const int64_t g = g0 + threadIdx.x + j * IC_THREADS;
+      if (g >= total) break;
+      const Item& I = it[find_item<F>(it, count, g)];
+      const int64_t t = g - I.*F;
+      Op::run(I, t, column(I, t, 0, I.n - 1));
+    }
   }
 }
 

@@ -467,8 +467,8 @@ void launch_items(Item* it, int count, int64_t total, hipStream_t st) {
 template <int64_t Item::*F, class Op>
 void launch_items_cols(Item* it, int count, int64_t total, hipStream_t st) {
   if (total > 0)
-    hipLaunchKernelGGL((k_items_cols<F, Op>), dim3(blocks_for(total, 256)), dim3(256), 0, st, it,
-                       count, total);
+    hipLaunchKernelGGL((k_items_cols<F, Op>), dim3(blocks_for(total, IC_THREADS * IC_PER)),
+                       dim3(IC_THREADS), 0, st, it, count, total);
 }
 
 // exclusive scan of a concatenated array, then per-region rebasing
