@@ -91,8 +91,19 @@ __global__ void k_batch_reduce(const BatchOut* __restrict__ it, int count, int64
   const int64_t t = g - I.o_out;
   const int64_t d = I.d, n = I.n;
   const int64_t k = t / d, r = t - k * d;
-  float s = I.part[t];
-  for (int q = 1; q < I.slices; ++q) s += I.part[(int64_t)q * d * n + t];
+  // eight loads in flight, added in slice order
+  const float* __restrict__ p = I.part + t;
+  const int64_t stride = d * n;
+  float s = p[0];
+  int q = 1;
+  for (; q + 8 <= I.slices; q += 8) {
+    float x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = p[(int64_t)(q + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += x[u];
+  }
+  for (; q < I.slices; ++q) s += p[(int64_t)q * stride];
   I.Ahat[r + k * I.ld] = s;
 }
 

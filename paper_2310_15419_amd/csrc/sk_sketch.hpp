@@ -381,15 +381,33 @@ __global__ void k_reduce_virtual(const float* __restrict__ part, int splits, int
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= d * n) return;
   const int64_t k = t / d, i = t - k * d;
-  const int64_t v0 = vbase ? vbase[k] : k, v1 = vbase ? vbase[k + 1] : k + 1;
   float s = 0.0f;
-  bool first = true;
-  for (int q = 0; q < splits; ++q) {
-    const float* sl = part + (int64_t)q * d * nv;
-    for (int64_t v = v0; v < v1; ++v) {
-      const float x = sl[i + v * d];
-      s = first ? x : s + x;
-      first = false;
+  if (!vbase) {
+    // one value per split: eight loads in flight, added in split order
+    const float* __restrict__ p = part + i + k * d;
+    const int64_t stride = d * nv;
+    int q = 0;
+    for (; q + 8 <= splits; q += 8) {
+      float x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = p[(int64_t)(q + u) * stride];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s = q + u == 0 ? x[u] : s + x[u];
+    }
+    for (; q < splits; ++q) {
+      const float x = p[(int64_t)q * stride];
+      s = q == 0 ? x : s + x;
+    }
+  } else {
+    const int64_t v0 = vbase[k], v1 = vbase[k + 1];
+    bool first = true;
+    for (int q = 0; q < splits; ++q) {
+      const float* sl = part + (int64_t)q * d * nv;
+      for (int64_t v = v0; v < v1; ++v) {
+        const float x = sl[i + v * d];
+        s = first ? x : s + x;
+        first = false;
+      }
     }
   }
   if (dense_slice) s += dense_slice[i + k * d];
