@@ -48,16 +48,82 @@ typedef float mf_floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 mf_bf16x8 __attribute__((ext_vector_type(8)));
 
 // Two copies of the per-block tiles (the one the matrix cores read and the
-// one being built).  S is held as the generator's words: S[w][k] bit t is set
-// when S row 32 w + t of the unit is -1 in block row k.
+// one being built).  S is held per S row: W[h][i][u] holds the signs (bit
+// set: -1) of S row i in the block rows a matrix-core lane of half h needs
+// for steps 4u .. 4u + 3 (block rows 16 s + 8 h + e, e < 8), at the bit
+// positions mf_bit_pos gives, so that each operand word is one shift and
+// one mask away.
 template <int FMT>
 struct MfmaLds;
+
+// Bit position in a W word of element e (block row 16 s + 8 h + e) of step
+// s = 4 u + j: BF16 operands are pairs of 16-bit values, sign bits 15 and 31,
+// taken with a left shift by (e / 2 + 4 j); FP8 operands are four bytes,
+// sign bits 7, 15, 23, 31, taken with a shift by (e / 4 + 2 j).
+template <int FMT>
+__device__ __forceinline__ int mf_bit_pos(int j, int e) {
+  if constexpr (FMT == MF_BF16) return 15 + 16 * (e & 1) - (e >> 1) - 4 * j;
+  else return 7 + 8 * (e & 3) - (e >> 2) - 2 * j;
+}
+
+// (j, e) of bit position r (the inverse of mf_bit_pos)
+template <int FMT>
+__device__ __forceinline__ void mf_bit_owner(int r, int& j, int& e) {
+  if constexpr (FMT == MF_BF16) {
+    const int lo = 15 - (r & 15);
+    j = lo >> 2;
+    e = ((r >> 4) & 1) | ((lo & 3) << 1);
+  } else {
+    const int lo = 7 - (r & 7);
+    j = lo >> 1;
+    e = ((r >> 3) & 3) | ((lo & 1) << 2);
+  }
+}
+
+// x of lane l ^ D (within each 32-lane half).  D = 1, 2, 8 are single DPP
+// moves (quad permutations; a rotation by 8 within a 16-lane row), D = 4
+// takes one of two row rotations (a row rotation by r brings lane l - r mod
+// 16), D = 16 goes through the LDS crossbar; only the last has LDS latency.
+template <int D>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x, int lane) {
+  const int v = (int)x;
+  if constexpr (D == 1) return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+  if constexpr (D == 2) return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+  if constexpr (D == 8) return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);
+  if constexpr (D == 4) {
+    const int dn = __builtin_amdgcn_mov_dpp(v, 0x124, 0xF, 0xF, false);  // from l - 4
+    const int up = __builtin_amdgcn_mov_dpp(v, 0x12C, 0xF, 0xF, false);  // from l + 4
+    return (uint32_t)((lane & 4) ? dn : up);
+  }
+  if constexpr (D == 16) return (uint32_t)__builtin_amdgcn_ds_swizzle(v, 0x1F | (16 << 10));
+}
+
+// One stage of a 32 x 32 bit transpose across the lanes of each 32-lane
+// half: lanes l and l ^ D swap the D x D blocks off the diagonal (M selects
+// the bit positions with bit D clear).
+template <int D, uint32_t M>
+__device__ __forceinline__ uint32_t transpose_stage(uint32_t x, int lane) {
+  const uint32_t p = lane_xor<D>(x, lane);
+  const bool upper = (lane & D) != 0;
+  const uint32_t z = __builtin_amdgcn_alignbit(p, p, upper ? D : 32 - D);  // rotate by -/+ D
+  const uint32_t keep = upper ? ~M : M;
+  return (x & keep) | (z & ~keep);
+}
+
+// After it, lane t's bit r is lane r's bit t (within each 32-lane half).
+__device__ __forceinline__ uint32_t transpose32(uint32_t x, int lane) {
+  x = transpose_stage<16, 0x0000FFFFu>(x, lane);
+  x = transpose_stage<8, 0x00FF00FFu>(x, lane);
+  x = transpose_stage<4, 0x0F0F0F0Fu>(x, lane);
+  x = transpose_stage<2, 0x33333333u>(x, lane);
+  return transpose_stage<1, 0x55555555u>(x, lane);
+}
 
 template <>
 struct MfmaLds<MF_BF16> {
   static constexpr int LDK = MF_MB + 8;  // elements per dense-tile row (16-byte rows, skewed)
   uint16_t A[2][MF_TN][LDK];
-  uint32_t S[2][MF_TM / 32][MF_MB];
+  uint32_t W[2][2][MF_TM][2];
 };
 
 template <>
@@ -65,7 +131,7 @@ struct MfmaLds<MF_FP8> {
   static constexpr int LDK = MF_MB + 16;
   uint8_t Ahi[2][MF_TN][LDK];
   uint8_t Alo[2][MF_TN][LDK];
-  uint32_t S[2][MF_TM / 32][MF_MB];
+  uint32_t W[2][2][MF_TM][2];
 };
 
 // Accesses through a generic pointer are flat instructions, which count as
@@ -169,7 +235,16 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
     const int cw0 = 64 * pw;
     const int ncw = cols - cw0 < 64 ? cols - cw0 : 64;  // <= 0: past the last column
     const int cs0 = ncw > 0 ? cw0 : 0, cs1 = ncw > 0 ? cw0 + ncw : 0;
-    const int krow = 32 * pw + (lane & 31);
+    // the wave's S bits: half hh, words u of the W layout; lane r (of each
+    // 32-lane half) generates block row krow, the one whose sign lands at
+    // bit r after the transpose
+    const int hh = pw & 1, wu = pw >> 1;
+    int krow;
+    {
+      int j, e;
+      mf_bit_owner<FMT>(lane & 31, j, e);
+      krow = 16 * (4 * wu + j) + 8 * hh + e;
+    }
     const int64_t nblk = b_hi - b_lo;
     struct Bounds {
       int32_t r0, rb, p0, p1;
@@ -238,13 +313,19 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
       }
     };
     auto build = [&](int buf, const Payload& y, Placed& pl) {
-      if (lane < 32) {
+      {
+        // 128 signs of block row krow from one generator call (both halves
+        // of the wave make the same call); the lower half transposes words
+        // 0 and 1, the upper half words 2 and 3, which leaves lane t of half
+        // v with S rows 64 v + t and 64 v + 32 + t over the wave's rows
         Words w{0u, 0u, 0u, 0u};
         if (krow < y.rb) w = sign_bits128(P.seed, grow0, (uint64_t)(uint32_t)y.row);
-        L.S[buf][0][krow] = w.x0;
-        L.S[buf][1][krow] = w.x1;
-        L.S[buf][2][krow] = w.x2;
-        L.S[buf][3][krow] = w.x3;
+        const bool up = lane >= 32;
+        const uint32_t ta = transpose32(up ? w.x2 : w.x0, lane);
+        const uint32_t tb = transpose32(up ? w.x3 : w.x1, lane);
+        const int i = 64 * (lane >> 5) + (lane & 31);
+        L.W[buf][hh][i][wu] = ta;
+        L.W[buf][hh][i + 32][wu] = tb;
       }
       if (ncw <= 0) return;  // past the last column: never stored
       if (pl.count >= 0) {
@@ -307,10 +388,11 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
-  // a +-1 operand: eight block rows of this lane's S row (bit `bs` of eight
-  // consecutive words) as BF16 (sign bit 15) or FP8 (sign bit 7) values
-  const uint32_t bs = lane & 31;
+  // a +-1 operand: eight block rows of this lane's S row as BF16 (sign bit
+  // 15 of each half) or FP8 (sign bit 7 of each byte) values, from the
+  // lane's two W words by a shift and a mask
   const int kq = 8 * (lane >> 5);
+  const int srow = 32 * mq + (lane & 31);
   uint32_t one8 = 0;
   if constexpr (FMT == MF_FP8)
     one8 = ((uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(1.0f, 1.0f, 0, false) & 0xFFu) * 0x01010101u;
@@ -320,18 +402,16 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
     // the matrix cores on block b: 16 block rows per instruction, all eight
     // steps unrolled (rows past the block's end are zero in the dense tile
     // and their S words are zero, so they add nothing)
-    auto bit = [bs](uint32_t w) { return __builtin_amdgcn_ubfe(w, bs, 1u); };
+    const uint2 wv = *reinterpret_cast<const uint2*>(&L.W[buf][kq >> 3][srow][0]);
     if constexpr (FMT == MF_BF16) {
 #pragma unroll
       for (int k0 = 0; k0 < MF_MB; k0 += 16) {
-        const uint4 w0 = *reinterpret_cast<const uint4*>(&L.S[buf][mq][k0 + kq]);
-        const uint4 w1 = *reinterpret_cast<const uint4*>(&L.S[buf][mq][k0 + kq + 4]);
-        // elements 2h, 2h + 1: 0x3F80 (+1), sign bit 15 of each half
-        auto pair = [&](uint32_t e, uint32_t o) {
-          return ((bit(e) | (bit(o) << 16)) << 15) | 0x3F803F80u;
-        };
-        const uint4 sv = make_uint4(pair(w0.x, w0.y), pair(w0.z, w0.w), pair(w1.x, w1.y),
-                                    pair(w1.z, w1.w));
+        const int st = k0 >> 4;
+        const uint32_t w = st < 4 ? wv.x : wv.y;
+        const int j = st & 3;
+        // elements 2h, 2h + 1: 0x3F80 (+1) with sign bits 15 and 31
+        auto pair = [&](int h) { return ((w << (h + 4 * j)) & 0x80008000u) | 0x3F803F80u; };
+        const uint4 sv = make_uint4(pair(0), pair(1), pair(2), pair(3));
         const mf_bf16x8 a = *reinterpret_cast<const mf_bf16x8*>(&sv);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -343,13 +423,12 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
     } else {
 #pragma unroll 2
       for (int k0 = 0; k0 < MF_MB; k0 += 16) {
-        const uint4 w0 = *reinterpret_cast<const uint4*>(&L.S[buf][mq][k0 + kq]);
-        const uint4 w1 = *reinterpret_cast<const uint4*>(&L.S[buf][mq][k0 + kq + 4]);
-        // four elements per word: the +1 byte, sign bit 7 of each byte
-        auto quad = [&](const uint4 w) {
-          return ((bit(w.x) | (bit(w.y) << 8) | (bit(w.z) << 16) | (bit(w.w) << 24)) << 7) | one8;
-        };
-        const long a = (long)(((uint64_t)quad(w1) << 32) | quad(w0));
+        const int st = k0 >> 4;
+        const uint32_t w = st < 4 ? wv.x : wv.y;
+        const int j = st & 3;
+        // four elements per word: the +1 byte with sign bits 7, 15, 23, 31
+        auto quad = [&](int g) { return ((w << (g + 2 * j)) & 0x80808080u) | one8; };
+        const long a = (long)(((uint64_t)quad(1) << 32) | quad(0));
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int ncol = 128 * nh + 32 * t + (lane & 31);
