@@ -312,20 +312,21 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
         (&L.Alo[buf][0][0])[at] = 0;
       }
     };
-    auto build = [&](int buf, const Payload& y, Placed& pl) {
+    // 128 signs of block row krow from one generator call (both halves of
+    // the wave make the same call); the lower half transposes words 0 and 1,
+    // the upper half words 2 and 3, which leaves lane t of half v with S
+    // rows 64 v + t and 64 v + 32 + t over the wave's rows
+    auto sign_words = [&](const Payload& y) {
+      Words w{0u, 0u, 0u, 0u};
+      if (krow < y.rb) w = sign_bits128(P.seed, grow0, (uint64_t)(uint32_t)y.row);
+      const bool up = lane >= 32;
+      return make_uint2(transpose32(up ? w.x2 : w.x0, lane), transpose32(up ? w.x3 : w.x1, lane));
+    };
+    auto build = [&](int buf, const Payload& y, const uint2 t, Placed& pl) {
       {
-        // 128 signs of block row krow from one generator call (both halves
-        // of the wave make the same call); the lower half transposes words
-        // 0 and 1, the upper half words 2 and 3, which leaves lane t of half
-        // v with S rows 64 v + t and 64 v + 32 + t over the wave's rows
-        Words w{0u, 0u, 0u, 0u};
-        if (krow < y.rb) w = sign_bits128(P.seed, grow0, (uint64_t)(uint32_t)y.row);
-        const bool up = lane >= 32;
-        const uint32_t ta = transpose32(up ? w.x2 : w.x0, lane);
-        const uint32_t tb = transpose32(up ? w.x3 : w.x1, lane);
         const int i = 64 * (lane >> 5) + (lane & 31);
-        L.W[buf][hh][i][wu] = ta;
-        L.W[buf][hh][i + 32][wu] = tb;
+        L.W[buf][hh][i][wu] = t.x;
+        L.W[buf][hh][i + 32][wu] = t.y;
       }
       if (ncw <= 0) return;  // past the last column: never stored
       if (pl.count >= 0) {
@@ -364,19 +365,28 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
 
     // Block k (relative to b_lo) is built before barrier k and consumed
     // between barriers k and k + 1; the two roles run separate loops with
-    // the same barriers, and a role is the same for a whole wave.
+    // the same barriers, and a role is the same for a whole wave.  A group
+    // makes the sign words of its next block in the window in which it
+    // builds nothing, so only the stores and the dense tile remain for the
+    // window in which it builds.
     Placed pl{-1, {}};  // copy grp: its last block's entries
     Payload Y{};        // the group's next block
     Bounds Bn{};        // the block after that
+    uint2 T{};          // sign words of the group's next block
     if (grp < nblk) {
       Y = load_payload(load_bounds(grp));
       Bn = load_bounds(grp + 2);
+      if (grp == 0) T = sign_words(Y);
     }
     for (int64_t k = 0; k <= nblk; ++k) {
-      if ((int)(k & 1) == grp && k < nblk) {
-        build(grp, Y, pl);
-        Y = load_payload(Bn);    // block k + 2
-        Bn = load_bounds(k + 4);
+      if ((int)(k & 1) == grp) {
+        if (k < nblk) {
+          build(grp, Y, T, pl);
+          Y = load_payload(Bn);    // block k + 2
+          Bn = load_bounds(k + 4);
+        }
+      } else if (k + 1 < nblk) {
+        T = sign_words(Y);         // block k + 1
       }
       __syncthreads();  // block k is built; block k - 1 consumed
     }
