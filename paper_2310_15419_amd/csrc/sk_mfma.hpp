@@ -128,7 +128,7 @@ struct MfmaLds<MF_BF16> {
 
 template <>
 struct MfmaLds<MF_FP8> {
-  static constexpr int LDK = MF_MB + 16;
+  static constexpr int LDK = MF_MB + 8;  // bytes per row: 34 dwords, so 32 lanes' 8-byte reads cover all banks
   uint8_t Ahi[2][MF_TN][LDK];
   uint8_t Alo[2][MF_TN][LDK];
   uint32_t W[2][2][MF_TM][2];
