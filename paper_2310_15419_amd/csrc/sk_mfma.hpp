@@ -8,13 +8,14 @@
 //
 // One work unit owns an output tile A_hat[i0 : i0 + 128, c0 : c0 + 256] for
 // a run of row blocks (a split).  Eight waves run the matrix cores, each
-// holding a 32 x 128 part as four 32 x 32 accumulators; four more waves build
-// the next block's tiles in a second copy meanwhile, so building and
-// multiplying overlap:
+// holding a 32 x 128 part as four 32 x 32 accumulators; eight more waves, in
+// two groups that take turns, build the next block's tiles in a second copy
+// meanwhile, so building and multiplying overlap:
 //   1. the S tile (128 S rows x the block's rows) as sign bits: one
-//      generator call per block row gives its 128 bits (four words); each
-//      matrix-core lane turns bit (its S row) of eight words into eight +-1
-//      operands,
+//      generator call per block row gives its 128 bits (four words), which a
+//      bit transpose across the lanes turns into words per S row; each
+//      matrix-core lane reads its S row's two words once per block and makes
+//      every +-1 operand from them with a shift and a mask,
 //   2. the block's entries in the unit's 256 columns scattered into the
 //      dense tile (column-major, the block's rows contiguous), after zeros
 //      over the entries the copy held before,
@@ -218,7 +219,8 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
 
   if (!consumer) {
     // A producer wave builds its share of a copy for one block: the S words
-    // of block rows 32 pw .. + 31 (one generator call each), and the dense
+    // of its 32 block rows (those of one half h and steps 4 u .. 4 u + 3 of
+    // the W layout, one generator call each), and the dense
     // tile of its 64 columns: zeros where that copy's previous block had
     // entries (or everywhere, when they were not all kept), then the
     // block's entries.  A wave's LDS writes to its share all come from that
