@@ -43,7 +43,31 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace sk {
+
+// Accesses through a generic pointer are flat instructions, which count as
+// LDS traffic in the wait counters too (an LDS wait then also waits for every
+// load in flight).  Pointers read from memory (item descriptors, the batched
+// kernels' parameters) are generic, so the hot loops address their arrays as
+// global memory explicitly.
+template <typename T>
+using global_t = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ global_t<T>* in_global(T* p) {
+  return (global_t<T>*)p;
+}
+// (HIP's vector types cannot be read or written through such pointers; pairs
+// go through 64-bit words, quadruples through a native vector type)
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int2 load_pair(const int2* p, int64_t i) {
+  const uint64_t x = in_global(reinterpret_cast<const uint64_t*>(p))[i];
+  return make_int2((int32_t)(uint32_t)x, (int32_t)(uint32_t)(x >> 32));
+}
+__device__ __forceinline__ void store_pair(uint2* p, int64_t i, uint32_t lo, uint32_t hi) {
+  in_global(reinterpret_cast<uint64_t*>(p))[i] = (uint64_t)lo | ((uint64_t)hi << 32);
+}
 
 // status bits written by the validation kernel
 enum : int { ST_RANGE = 1, ST_UNSORTED = 2, ST_COLPTR = 4, ST_CAPACITY = 8 };
@@ -68,8 +92,9 @@ struct Item {
   int32_t e_cap;      // entries per block (staging capacity)
   int32_t row_bytes;  // S-tile row stride in bytes
   int32_t bp_chunk;   // blocks per thread of the block-position search
-  int32_t col_tag;    // nonzero: an entry's row offset also carries (column mod
-                      // col_tag) << 16 (the matrix-core kernel's tile column)
+  int32_t col_tag;    // 0 or a power of two: an entry's row offset also carries
+                      // (column mod col_tag) << 16 (the matrix-core kernel's tile
+                      // column)
   int64_t nv;         // (virtual) columns of the layout
   int64_t nb_max;     // block capacity
   int64_t r_max;      // nonempty-row capacity, min(m, max(nnz, 1))
@@ -134,9 +159,9 @@ __device__ __forceinline__ int64_t column_of(const int64_t* __restrict__ colptr,
 }
 
 __device__ __forceinline__ float load_value(const void* vals, int vtype, int64_t p) {
-  if (vtype == 0) return (float)((const double*)vals)[p];  // RNE
-  if (vtype == 1) return ((const float*)vals)[p];
-  const uint16_t h = ((const uint16_t*)vals)[p];          // bf16 -> fp32 exact
+  if (vtype == 0) return (float)in_global((const double*)vals)[p];  // RNE
+  if (vtype == 1) return in_global((const float*)vals)[p];
+  const uint16_t h = in_global((const uint16_t*)vals)[p];          // bf16 -> fp32 exact
   return __uint_as_float((uint32_t)h << 16);
 }
 
@@ -253,15 +278,16 @@ __global__ __launch_bounds__(256) void k_items(const Item* __restrict__ it, int 
                                                int64_t total) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (count == 1) {
-    if (g < total) Op::run(it[0], g);
+    const Item I = it[0];  // a copy: the op's stores cannot change it
+    if (g < total) Op::run(I, g);
     return;
   }
   __shared__ int s_item[2];
   workgroup_items<F>(it, count, total, s_item);
   if (g >= total) return;
   if (s_item[0] == s_item[1]) {
-    const int i = __builtin_amdgcn_readfirstlane(s_item[0]);
-    Op::run(it[i], g - it[i].*F);
+    const Item I = it[__builtin_amdgcn_readfirstlane(s_item[0])];
+    Op::run(I, g - I.*F);
   } else {
     const int i = find_item<F>(it, count, g);
     Op::run(it[i], g - it[i].*F);
@@ -277,6 +303,13 @@ __global__ __launch_bounds__(256) void k_items(const Item* __restrict__ it, int 
 // them.
 constexpr int IC_THREADS = 256;
 constexpr int IC_PER = 4;
+
+// An op with run_many takes a thread's IC_PER indices at once (all loads
+// before any store, so their memory latencies overlap).
+template <class Op, class = void>
+struct takes_many : std::false_type {};
+template <class Op>
+struct takes_many<Op, std::void_t<decltype(&Op::template run_many<IC_PER>)>> : std::true_type {};
 
 template <int64_t Item::*F, class Op>
 __global__ __launch_bounds__(IC_THREADS) void k_items_cols(const Item* __restrict__ it, int count,
@@ -300,9 +333,10 @@ __global__ __launch_bounds__(IC_THREADS) void k_items_cols(const Item* __restric
   auto column = [](const Item& I, int64_t t, int64_t lo, int64_t hi) {
     int64_t k = 0;
     if (t < I.nnz) {
+      const auto* colptr = in_global(I.colptr);
       while (lo < hi) {
         const int64_t mid = (lo + hi + 1) >> 1;
-        if (I.colptr[mid] <= t) lo = mid;
+        if (colptr[mid] <= t) lo = mid;
         else hi = mid - 1;
       }
       k = lo;
@@ -310,13 +344,29 @@ __global__ __launch_bounds__(IC_THREADS) void k_items_cols(const Item* __restric
     return k;
   };
   if (s_item[0] == s_item[1]) {  // one item: uniform descriptor, narrow search
-    const Item& I = it[__builtin_amdgcn_readfirstlane(s_item[0])];
+    // (a copy, in scalar registers: the op's stores cannot change it)
+    const Item I = it[__builtin_amdgcn_readfirstlane(s_item[0])];
+    if constexpr (takes_many<Op>::value) {
+      // indices past the end stand in as the workgroup's last one (same
+      // item), so every load is valid; their results are not stored
+      int64_t t[IC_PER], k[IC_PER];
+      bool ok[IC_PER];
 #pragma unroll
-    for (int j = 0; j < IC_PER; ++j) {
-      const int64_t g = g0 + threadIdx.x + j * IC_THREADS;
-      if (g >= total) break;
-      const int64_t t = g - I.*F;
-      Op::run(I, t, column(I, t, s_col[0], s_col[1]));
+      for (int j = 0; j < IC_PER; ++j) {
+        const int64_t g = g0 + threadIdx.x + j * IC_THREADS;
+        ok[j] = g < total;
+        t[j] = (ok[j] ? g : glast) - I.*F;
+        k[j] = column(I, t[j], s_col[0], s_col[1]);
+      }
+      Op::template run_many<IC_PER>(I, t, k, ok);
+    } else {
+#pragma unroll
+      for (int j = 0; j < IC_PER; ++j) {
+        const int64_t g = g0 + threadIdx.x + j * IC_THREADS;
+        if (g >= total) break;
+        const int64_t t = g - I.*F;
+        Op::run(I, t, column(I, t, s_col[0], s_col[1]));
+      }
     }
   } else {
     for (int j = 0; j < IC_PER; ++j) {
@@ -334,17 +384,19 @@ __global__ __launch_bounds__(IC_THREADS) void k_items_cols(const Item* __restric
 struct OpValidate {
   static __device__ void run(const Item& I, int64_t t, int64_t k) {
     int bad = 0;
+    const auto* colptr = in_global(I.colptr);
+    const auto* rowidx = in_global(I.rowidx);
     if (t <= I.n) {
-      const int64_t c = I.colptr[t];
+      const int64_t c = colptr[t];
       if (t == 0 && c != 0) bad |= ST_COLPTR;
       if (t == I.n && c != I.nnz) bad |= ST_COLPTR;
-      if (t < I.n && I.colptr[t + 1] < c) bad |= ST_COLPTR;
+      if (t < I.n && colptr[t + 1] < c) bad |= ST_COLPTR;
       if (c < 0 || c > I.nnz) bad |= ST_COLPTR;
     }
     if (t < I.nnz) {
-      const int32_t r = I.rowidx[t];
+      const int32_t r = rowidx[t];
       if (r < 0 || r >= I.m) bad |= ST_RANGE;
-      if (t > 0 && I.colptr[k] < t && I.rowidx[t - 1] >= r) bad |= ST_UNSORTED;
+      if (t > 0 && colptr[k] < t && rowidx[t - 1] >= r) bad |= ST_UNSORTED;
     }
     if (bad) atomicOr(&I.hdr->status, bad);
   }
@@ -381,12 +433,14 @@ __global__ __launch_bounds__(1024) void k_row_counts(const Item* __restrict__ it
   for (int j = threadIdx.x; j < RT_ROWS; j += blockDim.x) cnt[j] = 0;
   __syncthreads();
   const int64_t k = slab * RT_COLS + (threadIdx.x >> 2);
-  const int64_t c0 = k < I.n ? I.colptr[k] : 0, c1 = k < I.n ? I.colptr[k + 1] : 0;
+  const auto* rowidx = in_global(I.rowidx);
+  const int64_t c0 = k < I.n ? in_global(I.colptr)[k] : 0;
+  const int64_t c1 = k < I.n ? in_global(I.colptr)[k + 1] : 0;
   if (k < I.n && c0 >= 0 && c1 <= I.nnz && c1 >= c0) {  // (malformed: flagged by the validation)
     int64_t lo = c0, hi = c1;  // first entry with row >= r0
     while (lo < hi) {
       const int64_t mid = (lo + hi) >> 1;
-      if (I.rowidx[mid] < r0) lo = mid + 1;
+      if (rowidx[mid] < r0) lo = mid + 1;
       else hi = mid;
     }
     // entries p, p + 4, ... below `end`, eight per load round (independent
@@ -395,7 +449,7 @@ __global__ __launch_bounds__(1024) void k_row_counts(const Item* __restrict__ it
       for (; p < end; p += 32) {
         int32_t r[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) r[u] = p + 4 * u < end ? I.rowidx[p + 4 * u] : (int32_t)r1;
+        for (int u = 0; u < 8; ++u) r[u] = p + 4 * u < end ? rowidx[p + 4 * u] : (int32_t)r1;
         bool past = false;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -606,24 +660,29 @@ constexpr int BP_P = 8;          // probes per search step
 constexpr int BP_W = 16;         // entries per window
 struct OpBlockPos {
   static __device__ void run(const Item& I, int64_t t) {
-    if (I.hdr->status) return;
+    if (in_global(I.hdr)->status) return;
+    const auto* vbase = in_global(I.vbase);
+    const auto* colptr = in_global(I.colptr);
+    const auto* rowlist = in_global(I.rowlist);
+    const auto* bstart = in_global(I.bstart);
+    auto* pos = in_global(I.pos);
     const int64_t bc = t / I.nv, v = t - bc * I.nv;
     const int chunk = I.bp_chunk;
     const int64_t b0 = bc * chunk;
     int64_t k = v, s = 1, r = 0;
-    if (I.vbase) {
-      if (v >= I.vbase[I.n]) {
-        for (int j = 0; j < chunk && b0 + j <= I.nb_max; ++j) I.pos[(b0 + j) * I.nv + v] = 0;
+    if (vbase) {
+      if (v >= vbase[I.n]) {
+        for (int j = 0; j < chunk && b0 + j <= I.nb_max; ++j) pos[(b0 + j) * I.nv + v] = 0;
         return;
       }
       k = real_column(I.vbase, I.n, v);
-      s = I.vbase[k + 1] - I.vbase[k];
-      r = v - I.vbase[k];
+      s = vbase[k + 1] - vbase[k];
+      r = v - vbase[k];
     }
-    const int64_t c0 = I.colptr[k], cnt = I.colptr[k + 1] - c0;
+    const int64_t c0 = colptr[k], cnt = colptr[k + 1] - c0;
     const int64_t T = cnt > r ? (cnt - r + s - 1) / s : 0;  // entries of v
-    const int32_t* __restrict__ rows = I.rowidx + c0 + r;    // entry j of v: rows[j * s]
-    const int64_t nbk = I.hdr->nblocks;
+    const auto* rows = in_global(I.rowidx) + c0 + r;        // entry j of v: rows[j * s]
+    const int64_t nbk = in_global(I.hdr)->nblocks;
     const int64_t jn64 = I.nb_max + 1 - b0;
     const int jn = jn64 < chunk ? (int)jn64 : chunk;  // blocks of the run with a pos row
     // first row of each block (past the last block: above every row)
@@ -631,7 +690,7 @@ struct OpBlockPos {
 #pragma unroll
     for (int j = 0; j < BP_MAX_CHUNK; ++j) {
       const int64_t b = b0 + j;
-      fr[j] = (j < jn && b < nbk) ? I.rowlist[I.bstart[b]] : INT32_MAX;
+      fr[j] = (j < jn && b < nbk) ? rowlist[bstart[b]] : INT32_MAX;
     }
     // the first entry at or below fr[0] lies in [lo, hi]
     int64_t lo = 0, hi = T;
@@ -660,10 +719,10 @@ struct OpBlockPos {
     int32_t w[BP_W];
     auto load_window = [&]() {
       if (wide && wl >= 0 && wl + BP_W <= T) {
-        const int4* q = reinterpret_cast<const int4*>(I.rowidx + c0 + wl);
+        const auto* q = in_global(reinterpret_cast<const i32x4*>(I.rowidx + c0 + wl));
 #pragma unroll
         for (int i = 0; i < BP_W / 4; ++i) {
-          const int4 x = q[i];
+          const i32x4 x = q[i];
           w[4 * i] = x.x; w[4 * i + 1] = x.y; w[4 * i + 2] = x.z; w[4 * i + 3] = x.w;
         }
       } else {
@@ -684,7 +743,7 @@ struct OpBlockPos {
 #pragma unroll
         for (int i = 0; i < BP_W; ++i) c += w[i] < f ? 1 : 0;
         if (c < BP_W) {
-          I.pos[(b0 + j) * I.nv + v] = (int32_t)(wl + c);
+          pos[(b0 + j) * I.nv + v] = (int32_t)(wl + c);
           break;
         }
         wl += BP_W;  // all 16 slots lie above f, so wl + 16 <= T
@@ -723,19 +782,61 @@ struct OpSegPos {
 
 // ent[pos[b nv + v] + position in v] = {row offset in the S tile, value}
 struct OpScatter {
-  static __device__ void run(const Item& I, int64_t p, int64_t k) {
-    if (I.hdr->status) return;
-    const int2 ri = I.rowinfo[I.rowidx[p]];
-    int64_t v = k, q = p - I.colptr[k];
+  // (v, position in v) of entry p of column k; a position inside one
+  // column fits 32 bits (pos holds int32)
+  static __device__ __forceinline__ void virt(const Item& I, int64_t p, int64_t k, int64_t c0,
+                                              int64_t& v, int64_t& q) {
+    v = k;
+    q = p - c0;
     if (I.vbase) {
-      const int64_t s = I.vbase[k + 1] - I.vbase[k];
-      v = I.vbase[k] + q % s;
-      q = q / s;
+      const auto* vbase = in_global(I.vbase);
+      const uint32_t s = (uint32_t)(vbase[k + 1] - vbase[k]);
+      const uint32_t q32 = (uint32_t)q;
+      const uint32_t qs = q32 / s;
+      v = vbase[k] + (q32 - qs * s);
+      q = qs;
     }
-    const int64_t dest = (int64_t)I.pos[(int64_t)ri.x * I.nv + v] + q;
+  }
+  static __device__ __forceinline__ uint32_t tagged(const Item& I, int2 ri, int64_t k) {
     uint32_t x = (uint32_t)ri.y;
-    if (I.col_tag) x |= (uint32_t)(k % I.col_tag) << 16;
-    I.ent[dest] = make_uint2(x, __float_as_uint(load_value(I.vals, I.vtype, p)));
+    if (I.col_tag) x |= ((uint32_t)k & (uint32_t)(I.col_tag - 1)) << 16;
+    return x;
+  }
+  static __device__ void run(const Item& I, int64_t p, int64_t k) {
+    if (in_global(I.hdr)->status) return;
+    const int2 ri = load_pair(I.rowinfo, in_global(I.rowidx)[p]);
+    int64_t v, q;
+    virt(I, p, k, in_global(I.colptr)[k], v, q);
+    const int64_t dest = (int64_t)in_global(I.pos)[(int64_t)ri.x * I.nv + v] + q;
+    store_pair(I.ent, dest, tagged(I, ri, k), __float_as_uint(load_value(I.vals, I.vtype, p)));
+  }
+  // the same for N entries, stage by stage: rows and values, the rows'
+  // block and offset, the (block, column) positions, then the stores
+  template <int N>
+  static __device__ void run_many(const Item& I, const int64_t (&p)[N], const int64_t (&k)[N],
+                                  const bool (&ok)[N]) {
+    if (in_global(I.hdr)->status) return;
+    const auto* rowidx = in_global(I.rowidx);
+    const auto* colptr = in_global(I.colptr);
+    const auto* pos = in_global(I.pos);
+    int32_t row[N];
+    float a[N];
+    int64_t v[N], q[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      row[j] = rowidx[p[j]];
+      a[j] = load_value(I.vals, I.vtype, p[j]);
+      virt(I, p[j], k[j], colptr[k[j]], v[j], q[j]);
+    }
+    int2 ri[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) ri[j] = load_pair(I.rowinfo, row[j]);
+    int32_t base[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) base[j] = pos[(int64_t)ri[j].x * I.nv + v[j]];
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (ok[j]) store_pair(I.ent, (int64_t)base[j] + q[j], tagged(I, ri[j], k[j]), __float_as_uint(a[j]));
   }
 };
 

@@ -547,6 +547,7 @@ Item make_item(const sk_csc* A, const Plan& P, int dist) {
   }
   I.nv = P.nv; I.nb_max = P.nb_max; I.r_max = P.r_max;
   if (P.mfma) {  // blocks of equal height; the cost follows the rows
+    static_assert((MF_TN & (MF_TN - 1)) == 0, "the tile-column tag is taken by a mask");
     I.col_tag = MF_TN;
     I.w_row = 16;
     I.w_ent = 1;

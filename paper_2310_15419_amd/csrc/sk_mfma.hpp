@@ -135,17 +135,8 @@ struct MfmaLds<MF_FP8> {
   uint32_t W[2][2][MF_TM][2];
 };
 
-// Accesses through a generic pointer are flat instructions, which count as
-// LDS traffic in the wait counters too (an LDS wait then also waits for every
-// load in flight).  Parameters read from memory (the batched kernel's) arrive
-// as generic pointers, so the unit addresses its arrays as global memory
-// explicitly.
-template <typename T>
-using global_t = __attribute__((address_space(1))) T;
-template <typename T>
-__device__ __forceinline__ global_t<T>* in_global(T* p) {
-  return (global_t<T>*)p;
-}
+// (Parameters read from memory, as the batched kernel's are, arrive as
+// generic pointers; the unit addresses its arrays through in_global.)
 
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
   const uint32_t u = __float_as_uint(x);
