@@ -145,19 +145,6 @@ __global__ void k_fill(T* __restrict__ p, int64_t count, T v) {
     p[i] = v;
 }
 
-// largest k in [0, n) with colptr[k] <= p (colptr assumed non-decreasing;
-// stays in range even when it is not)
-__device__ __forceinline__ int64_t column_of(const int64_t* __restrict__ colptr, int64_t n,
-                                             int64_t p) {
-  int64_t lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (colptr[mid] <= p) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 __device__ __forceinline__ float load_value(const void* vals, int vtype, int64_t p) {
   if (vtype == 0) return (float)in_global((const double*)vals)[p];  // RNE
   if (vtype == 1) return in_global((const float*)vals)[p];
@@ -260,37 +247,92 @@ __device__ __forceinline__ int find_item(const Item* __restrict__ it, int count,
   return lo;
 }
 
+// The largest q in [lo, hi] with key(q) <= x (lo when there is none), found
+// by the 32 lanes of a half wave together: each step loads 32 evenly spaced
+// keys at once and keeps the stretch between the last one at or below x and
+// the next, so a search over n keys takes about log32(n) load round trips.
+// The keys ascend (where they do not, as in malformed input, the result is
+// still some q in [lo, hi]).  Every lane of the half wave passes the same
+// arguments.
+template <class Key>
+__device__ __forceinline__ int64_t halfwave_last_le(int64_t lo, int64_t hi, int64_t x, Key key) {
+  const int l = threadIdx.x & 31;
+  const int half = threadIdx.x & 32;  // this half's bits in a ballot
+  while (hi > lo) {
+    const int64_t step = (hi - lo + 32) / 32;  // ceil of (hi - lo + 1) / 32
+    const int64_t q = lo + l * step;
+    const bool le = q <= hi && (l == 0 || key(q) <= x);  // (lane 0: lo, kept)
+    const uint32_t m = (uint32_t)(__ballot(le) >> half);
+    const int c = m == 0xFFFFFFFFu ? 32 : __builtin_ctz(~m);  // probes before the first above x
+    const int64_t nlo = lo + (int64_t)(c - 1) * step;
+    const int64_t nhi = lo + (int64_t)c * step - 1;
+    lo = nlo;
+    hi = nhi < hi ? nhi : hi;
+  }
+  return lo;
+}
+
 // The items of a workgroup's first and last indices (s_item[0], s_item[1]);
 // when they are the same (the usual case) the item is uniform, so its
 // descriptor is read with scalar loads rather than once per lane.
 template <int64_t Item::*F>
 __device__ __forceinline__ void workgroup_items(const Item* __restrict__ it, int count,
-                                                int64_t total, int* s_item) {
-  const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
-  const int64_t glast = (g0 + blockDim.x < total ? g0 + blockDim.x : total) - 1;
-  if (threadIdx.x < 2) s_item[threadIdx.x] = find_item<F>(it, count, threadIdx.x ? glast : g0);
+                                                int64_t total, int64_t g0, int64_t span,
+                                                int* s_item) {
+  const int64_t glast = (g0 + span < total ? g0 + span : total) - 1;
+  if (threadIdx.x < 64) {  // half wave h finds the item of index h ? glast : g0
+    const int h = threadIdx.x >> 5;
+    const int i = (int)halfwave_last_le(0, count - 1, h ? glast : g0,
+                                        [&](int64_t q) { return it[q].*F; });
+    if ((threadIdx.x & 31) == 0) s_item[h] = i;
+  }
   __syncthreads();
 }
 
-// One thread per flattened index: Op::run(item, index inside the item).
+// Indices per thread of k_items: 4 (strided by the workgroup size, so the
+// accesses stay coalesced), which spreads a workgroup's item lookup over
+// 1024 of them; an op whose per-index work is long sets kPerThread.
+constexpr int KI_THREADS = 256;
+template <class Op, class = void>
+struct per_thread {
+  static constexpr int value = 4;
+};
+template <class Op>
+struct per_thread<Op, std::void_t<decltype(Op::kPerThread)>> {
+  static constexpr int value = Op::kPerThread;
+};
+
+// Op::run(item, index inside the item) for every flattened index.
 template <int64_t Item::*F, class Op>
-__global__ __launch_bounds__(256) void k_items(const Item* __restrict__ it, int count,
-                                               int64_t total) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(KI_THREADS) void k_items(const Item* __restrict__ it, int count,
+                                                      int64_t total) {
+  constexpr int PER = per_thread<Op>::value;
+  const int64_t g0 = (int64_t)blockIdx.x * (KI_THREADS * PER);
   if (count == 1) {
     const Item I = it[0];  // a copy: the op's stores cannot change it
-    if (g < total) Op::run(I, g);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int64_t g = g0 + threadIdx.x + j * KI_THREADS;
+      if (g < total) Op::run(I, g);
+    }
     return;
   }
   __shared__ int s_item[2];
-  workgroup_items<F>(it, count, total, s_item);
-  if (g >= total) return;
+  workgroup_items<F>(it, count, total, g0, KI_THREADS * PER, s_item);
   if (s_item[0] == s_item[1]) {
     const Item I = it[__builtin_amdgcn_readfirstlane(s_item[0])];
-    Op::run(I, g - I.*F);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int64_t g = g0 + threadIdx.x + j * KI_THREADS;
+      if (g < total) Op::run(I, g - I.*F);
+    }
   } else {
-    const int i = find_item<F>(it, count, g);
-    Op::run(it[i], g - it[i].*F);
+    for (int j = 0; j < PER; ++j) {
+      const int64_t g = g0 + threadIdx.x + j * KI_THREADS;
+      if (g >= total) break;
+      const int i = find_item<F>(it, count, g);
+      Op::run(it[i], g - it[i].*F);
+    }
   }
 }
 
@@ -319,14 +361,22 @@ __global__ __launch_bounds__(IC_THREADS) void k_items_cols(const Item* __restric
   const int64_t g0 = (int64_t)blockIdx.x * (IC_THREADS * IC_PER);
   const int64_t span = IC_THREADS * IC_PER;
   const int64_t glast = (g0 + span < total ? g0 + span : total) - 1;
-  if (threadIdx.x < 2) {
-    const int64_t gg = threadIdx.x == 0 ? g0 : glast;
-    const int i = count == 1 ? 0 : find_item<F>(it, count, gg);
+  if (threadIdx.x < 64) {  // half wave h: the item and column of index h ? glast : g0
+    const int h = threadIdx.x >> 5;
+    const int64_t gg = h ? glast : g0;
+    const int i = count == 1 ? 0
+                             : (int)halfwave_last_le(0, count - 1, gg,
+                                                     [&](int64_t q) { return it[q].*F; });
     const Item& I = it[i];
     int64_t t = gg - I.*F;
     if (t >= I.nnz) t = I.nnz - 1;
-    s_item[threadIdx.x] = i;
-    s_col[threadIdx.x] = t >= 0 ? column_of(I.colptr, I.n, t) : 0;
+    const auto* colptr = in_global(I.colptr);
+    const int64_t col =
+        t >= 0 ? halfwave_last_le(0, I.n - 1, t, [&](int64_t q) { return colptr[q]; }) : 0;
+    if ((threadIdx.x & 31) == 0) {
+      s_item[h] = i;
+      s_col[h] = col;
+    }
   }
   __syncthreads();
   // the column of entry t, searched between the given bounds
@@ -397,6 +447,45 @@ struct OpValidate {
       const int32_t r = rowidx[t];
       if (r < 0 || r >= I.m) bad |= ST_RANGE;
       if (t > 0 && colptr[k] < t && rowidx[t - 1] >= r) bad |= ST_UNSORTED;
+    }
+    if (bad) atomicOr(&I.hdr->status, bad);
+  }
+  // the same for N indices: every load first (indices clamped into range,
+  // results of the clamped ones unused), then the checks, one status update
+  template <int N>
+  static __device__ void run_many(const Item& I, const int64_t (&t)[N], const int64_t (&k)[N],
+                                  const bool (&ok)[N]) {
+    const auto* colptr = in_global(I.colptr);
+    const auto* rowidx = in_global(I.rowidx);
+    int64_t c[N], c1[N], ck[N];
+    int32_t r[N], rp[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int64_t tc = t[j] < I.n ? t[j] : I.n;
+      c[j] = colptr[tc];
+      c1[j] = colptr[tc < I.n ? tc + 1 : I.n];
+      ck[j] = colptr[k[j]];
+      r[j] = rp[j] = 0;
+      if (I.nnz > 0) {
+        const int64_t te = t[j] < I.nnz ? t[j] : I.nnz - 1;
+        r[j] = rowidx[te];
+        rp[j] = rowidx[te > 0 ? te - 1 : 0];
+      }
+    }
+    int bad = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if (!ok[j]) continue;
+      if (t[j] <= I.n) {
+        if (t[j] == 0 && c[j] != 0) bad |= ST_COLPTR;
+        if (t[j] == I.n && c[j] != I.nnz) bad |= ST_COLPTR;
+        if (t[j] < I.n && c1[j] < c[j]) bad |= ST_COLPTR;
+        if (c[j] < 0 || c[j] > I.nnz) bad |= ST_COLPTR;
+      }
+      if (t[j] < I.nnz) {
+        if (r[j] < 0 || r[j] >= I.m) bad |= ST_RANGE;
+        if (t[j] > 0 && ck[j] < t[j] && rp[j] >= r[j]) bad |= ST_UNSORTED;
+      }
     }
     if (bad) atomicOr(&I.hdr->status, bad);
   }
@@ -659,6 +748,7 @@ constexpr int BP_MAX_CHUNK = 8;  // bp_chunk at most
 constexpr int BP_P = 8;          // probes per search step
 constexpr int BP_W = 16;         // entries per window
 struct OpBlockPos {
+  static constexpr int kPerThread = 1;
   static __device__ void run(const Item& I, int64_t t) {
     if (in_global(I.hdr)->status) return;
     const auto* vbase = in_global(I.vbase);

@@ -460,8 +460,8 @@ struct InspectArrays {
 template <int64_t Item::*F, class Op>
 void launch_items(Item* it, int count, int64_t total, hipStream_t st) {
   if (total > 0)
-    hipLaunchKernelGGL((k_items<F, Op>), dim3(blocks_for(total, 256)), dim3(256), 0, st, it, count,
-                       total);
+    hipLaunchKernelGGL((k_items<F, Op>), dim3(blocks_for(total, KI_THREADS * per_thread<Op>::value)),
+                       dim3(KI_THREADS), 0, st, it, count, total);
 }
 
 template <int64_t Item::*F, class Op>
