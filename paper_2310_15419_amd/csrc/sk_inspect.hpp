@@ -289,13 +289,13 @@ __device__ __forceinline__ void workgroup_items(const Item* __restrict__ it, int
   __syncthreads();
 }
 
-// Indices per thread of k_items: 4 (strided by the workgroup size, so the
+// Indices per thread of k_items: 8 (strided by the workgroup size, so the
 // accesses stay coalesced), which spreads a workgroup's item lookup over
-// 1024 of them; an op whose per-index work is long sets kPerThread.
+// 2048 of them; an op whose per-index work is long sets kPerThread.
 constexpr int KI_THREADS = 256;
 template <class Op, class = void>
 struct per_thread {
-  static constexpr int value = 4;
+  static constexpr int value = 8;
 };
 template <class Op>
 struct per_thread<Op, std::void_t<decltype(Op::kPerThread)>> {
