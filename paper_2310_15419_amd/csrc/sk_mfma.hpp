@@ -8,7 +8,9 @@
 //
 // One work unit owns an output tile A_hat[i0 : i0 + 128, c0 : c0 + 256] for
 // a run of row blocks (a split).  Eight waves run the matrix cores, each
-// holding a 32 x 128 part as four 32 x 32 accumulators; eight more waves, in
+// holding four 32 x 32 accumulators (a 32 x 128 part in BF16, 64 x 64 in
+// FP8, where each operand read from LDS then feeds two instructions); eight
+// more waves, in
 // two groups that take turns, build the next block's tiles in a second copy
 // meanwhile, so building and multiplying overlap:
 //   1. the S tile (128 S rows x the block's rows) as sign bits: one
@@ -39,7 +41,7 @@ enum : int { MF_BF16 = 1, MF_FP8 = 2 };
 constexpr int MF_MB = 128;      // rows per block (K extent of one dense tile)
 constexpr int MF_TM = 128;      // S rows per unit
 constexpr int MF_TN = 256;      // columns per unit
-constexpr int MF_CONSUMERS = 8; // waves on the matrix cores (four S-row quarters x two halves)
+constexpr int MF_CONSUMERS = 8; // waves on the matrix cores
 constexpr int MF_PRODUCERS = 8; // waves building tiles: two groups (even, odd blocks) of
                                 // four, 64 columns each
 constexpr int MF_THREADS = 64 * (MF_CONSUMERS + MF_PRODUCERS);
@@ -171,7 +173,12 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const bool consumer = wave < MF_CONSUMERS;
-  const int mq = wave & 3, nh = (wave >> 2) & 1;  // consumers: S-row quarter, column half
+  // consumers: a wave holds RA x TB accumulators of 32 x 32, S-row group rg
+  // (32 RA rows) and column group cg (32 TB columns); BF16 takes one S
+  // operand per step across four column tiles (its operand VALU is the
+  // larger cost), FP8 two S operands across two (its LDS reads are)
+  constexpr int RA = FMT == MF_BF16 ? 1 : 2, TB = 4 / RA;
+  const int rg = wave % (4 / RA), cg = (wave / (4 / RA)) % (8 / TB);
   // producers: group (the parity of the blocks it builds) and wave in it
   const int grp = __builtin_amdgcn_readfirstlane((wave - MF_CONSUMERS) >> 2);
   const int pw = __builtin_amdgcn_readfirstlane(wave & 3);
@@ -386,61 +393,86 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
     return;
   }
 
+  // acc[TB a + t]: S rows 32 (RA rg + a) + (0..31) x columns 32 (TB cg + t) + (0..31)
   mf_floatx16 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
-  // a +-1 operand: eight block rows of this lane's S row as BF16 (sign bit
-  // 15 of each half) or FP8 (sign bit 7 of each byte) values, from the
-  // lane's two W words by a shift and a mask
+  // a +-1 operand: eight block rows of one S row as BF16 (sign bit 15 of
+  // each half) or FP8 (sign bit 7 of each byte) values, from that row's two
+  // W words by a shift and a mask
   const int kq = 8 * (lane >> 5);
-  const int srow = 32 * mq + (lane & 31);
+  const int srow = 32 * RA * rg + (lane & 31);  // + 32 a
+  const int ncol = 32 * TB * cg + (lane & 31);  // + 32 t
   uint32_t one8 = 0;
   if constexpr (FMT == MF_FP8)
     one8 = ((uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(1.0f, 1.0f, 0, false) & 0xFFu) * 0x01010101u;
   __syncthreads();  // copy 0 holds block b_lo
   for (int64_t b = b_lo; b < b_hi; ++b) {
     const int buf = (int)((b - b_lo) & 1);
-    // the matrix cores on block b: 16 block rows per instruction, all eight
-    // steps unrolled (rows past the block's end are zero in the dense tile
-    // and their S words are zero, so they add nothing)
-    const uint2 wv = *reinterpret_cast<const uint2*>(&L.W[buf][kq >> 3][srow][0]);
+    // the matrix cores on block b: 16 block rows per instruction (rows past
+    // the block's end are zero in the dense tile and their S words are
+    // zero, so they add nothing); steps 4 u + j take word u of each S row
+    // (u unrolled, so the word is picked at compile time)
+    uint2 wv[RA];
+#pragma unroll
+    for (int a = 0; a < RA; ++a)
+      wv[a] = *reinterpret_cast<const uint2*>(&L.W[buf][kq >> 3][srow + 32 * a][0]);
     if constexpr (FMT == MF_BF16) {
 #pragma unroll
-      for (int k0 = 0; k0 < MF_MB; k0 += 16) {
-        const int st = k0 >> 4;
-        const uint32_t w = st < 4 ? wv.x : wv.y;
-        const int j = st & 3;
-        // elements 2h, 2h + 1: 0x3F80 (+1) with sign bits 15 and 31
-        auto pair = [&](int h) { return ((w << (h + 4 * j)) & 0x80008000u) | 0x3F803F80u; };
-        const uint4 sv = make_uint4(pair(0), pair(1), pair(2), pair(3));
-        const mf_bf16x8 a = *reinterpret_cast<const mf_bf16x8*>(&sv);
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int ncol = 128 * nh + 32 * t + (lane & 31);
-          const mf_bf16x8 bv = *reinterpret_cast<const mf_bf16x8*>(&L.A[buf][ncol][k0 + kq]);
-          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[t], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) {
+          const int k0 = 16 * (4 * u + j);
+          mf_bf16x8 sa[RA], bv[TB];
+#pragma unroll
+          for (int a = 0; a < RA; ++a) {
+            const uint32_t w = u ? wv[a].y : wv[a].x;
+            // elements 2h, 2h + 1: 0x3F80 (+1) with sign bits 15 and 31
+            auto pair = [&](int h) { return ((w << (h + 4 * j)) & 0x80008000u) | 0x3F803F80u; };
+            const uint4 sv = make_uint4(pair(0), pair(1), pair(2), pair(3));
+            sa[a] = *reinterpret_cast<const mf_bf16x8*>(&sv);
+          }
+#pragma unroll
+          for (int t = 0; t < TB; ++t)
+            bv[t] = *reinterpret_cast<const mf_bf16x8*>(&L.A[buf][ncol + 32 * t][k0 + kq]);
+#pragma unroll
+          for (int a = 0; a < RA; ++a)
+#pragma unroll
+            for (int t = 0; t < TB; ++t)
+              acc[TB * a + t] =
+                  __builtin_amdgcn_mfma_f32_32x32x16_bf16(sa[a], bv[t], acc[TB * a + t], 0, 0, 0);
         }
-      }
     } else {
-#pragma unroll 2
-      for (int k0 = 0; k0 < MF_MB; k0 += 16) {
-        const int st = k0 >> 4;
-        const uint32_t w = st < 4 ? wv.x : wv.y;
-        const int j = st & 3;
-        // four elements per word: the +1 byte with sign bits 7, 15, 23, 31
-        auto quad = [&](int g) { return ((w << (g + 2 * j)) & 0x80808080u) | one8; };
-        const long a = (long)(((uint64_t)quad(1) << 32) | quad(0));
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int ncol = 128 * nh + 32 * t + (lane & 31);
-          const long bh = *reinterpret_cast<const long*>(&L.Ahi[buf][ncol][k0 + kq]);
-          const long bl = *reinterpret_cast<const long*>(&L.Alo[buf][ncol][k0 + kq]);
-          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, bh, acc[t], 0, 0, 0);
-          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, bl, acc[t], 0, 0, 0);
+      for (int u = 0; u < 2; ++u)
+#pragma unroll 2
+        for (int j = 0; j < 4; ++j) {
+          const int k0 = 16 * (4 * u + j);
+          long sa[RA], bh[TB], bl[TB];
+#pragma unroll
+          for (int a = 0; a < RA; ++a) {
+            const uint32_t w = u ? wv[a].y : wv[a].x;
+            // four elements per word: the +1 byte with sign bits 7, 15, 23, 31
+            auto quad = [&](int g) { return ((w << (g + 2 * j)) & 0x80808080u) | one8; };
+            sa[a] = (long)(((uint64_t)quad(1) << 32) | quad(0));
+          }
+#pragma unroll
+          for (int t = 0; t < TB; ++t) {
+            bh[t] = *reinterpret_cast<const long*>(&L.Ahi[buf][ncol + 32 * t][k0 + kq]);
+            bl[t] = *reinterpret_cast<const long*>(&L.Alo[buf][ncol + 32 * t][k0 + kq]);
+          }
+#pragma unroll
+          for (int a = 0; a < RA; ++a)
+#pragma unroll
+            for (int t = 0; t < TB; ++t) {
+              acc[TB * a + t] =
+                  __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(sa[a], bh[t], acc[TB * a + t], 0, 0, 0);
+              acc[TB * a + t] =
+                  __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(sa[a], bl[t], acc[TB * a + t], 0, 0, 0);
+            }
         }
-      }
     }
     __syncthreads();  // block b consumed; the other copy holds block b + 1
   }
@@ -448,14 +480,16 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
   auto* out = in_global(P.out) + (int64_t)split * P.split_stride;
   const float nan = __uint_as_float(0x7FC00000u);
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int64_t j = c0 + 128 * nh + 32 * t + (lane & 31);
+  for (int a = 0; a < RA; ++a)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int64_t i = i0 + 32 * mq + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      if (i < P.d && j < P.n) out[i + j * P.ld] = status ? nan : acc[t][r];
+    for (int t = 0; t < TB; ++t) {
+      const int64_t j = c0 + ncol + 32 * t;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t i = i0 + 32 * RA * rg + 32 * a + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (i < P.d && j < P.n) out[i + j * P.ld] = status ? nan : acc[TB * a + t][r];
+      }
     }
-  }
 }
 
 template <int FMT>
