@@ -289,9 +289,10 @@ __device__ __forceinline__ void workgroup_items(const Item* __restrict__ it, int
   __syncthreads();
 }
 
-// Indices per thread of k_items: 8 (strided by the workgroup size, so the
-// accesses stay coalesced), which spreads a workgroup's item lookup over
-// 2048 of them; an op whose per-index work is long sets kPerThread.
+// Indices per thread of k_items in a batch: 8 (strided by the workgroup
+// size, so the accesses stay coalesced), which spreads a workgroup's item
+// lookup over 2048 of them; an op whose per-index work is long sets
+// kPerThread.  A single item has no lookup and takes one per thread.
 constexpr int KI_THREADS = 256;
 template <class Op, class = void>
 struct per_thread {
@@ -302,11 +303,11 @@ struct per_thread<Op, std::void_t<decltype(Op::kPerThread)>> {
   static constexpr int value = Op::kPerThread;
 };
 
-// Op::run(item, index inside the item) for every flattened index.
-template <int64_t Item::*F, class Op>
+// Op::run(item, index inside the item) for every flattened index, PER per
+// thread.
+template <int64_t Item::*F, class Op, int PER>
 __global__ __launch_bounds__(KI_THREADS) void k_items(const Item* __restrict__ it, int count,
                                                       int64_t total) {
-  constexpr int PER = per_thread<Op>::value;
   const int64_t g0 = (int64_t)blockIdx.x * (KI_THREADS * PER);
   if (count == 1) {
     const Item I = it[0];  // a copy: the op's stores cannot change it

@@ -459,9 +459,15 @@ struct InspectArrays {
 
 template <int64_t Item::*F, class Op>
 void launch_items(Item* it, int count, int64_t total, hipStream_t st) {
-  if (total > 0)
-    hipLaunchKernelGGL((k_items<F, Op>), dim3(blocks_for(total, KI_THREADS * per_thread<Op>::value)),
+  if (total <= 0) return;
+  if (count == 1) {
+    hipLaunchKernelGGL((k_items<F, Op, 1>), dim3(blocks_for(total, KI_THREADS)), dim3(KI_THREADS),
+                       0, st, it, count, total);
+  } else {
+    constexpr int per = per_thread<Op>::value;
+    hipLaunchKernelGGL((k_items<F, Op, per>), dim3(blocks_for(total, KI_THREADS * per)),
                        dim3(KI_THREADS), 0, st, it, count, total);
+  }
 }
 
 template <int64_t Item::*F, class Op>
