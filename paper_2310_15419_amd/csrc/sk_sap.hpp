@@ -156,8 +156,12 @@ __global__ __launch_bounds__(SAP_THREADS) void k_qr_panel(double* __restrict__ A
 }
 
 // The same factorisation with the panel (rows j0..d-1, nb <= QR_NB_LDS
-// columns) held in LDS: one workgroup of 1024 threads, every step's
-// reductions and updates on LDS data.
+// columns) held in LDS, by one workgroup of 1024 threads.  Thread t keeps
+// rows t, t + 1024, ... for the whole panel, and a column takes three
+// barriers: its norm (summed from the previous column's update pass), its
+// dot products with the other panel columns (taken while the reflector is
+// scaled), and their totals; the update of the later columns then computes
+// the next column's norm on the way.
 constexpr int QR_NB_LDS = 8;
 constexpr int QR_LDS_ROWS = 2304;  // panel rows that fit: 2304 * 8 * 8 B = 144 KiB
 __global__ __launch_bounds__(1024) void k_qr_panel_lds(double* __restrict__ A, int64_t lda,
@@ -165,20 +169,46 @@ __global__ __launch_bounds__(1024) void k_qr_panel_lds(double* __restrict__ A, i
                                                         double* __restrict__ tau,
                                                         double* __restrict__ T) {
   extern __shared__ double P[];  // (d - j0) x nb, column-major, ld = rows
-  __shared__ double sh[16];
+  __shared__ double s_norm[16];
   __shared__ double s_dot[QR_NB_LDS][16];
   __shared__ double s_w[QR_NB_LDS];
+  __shared__ double s_t[QR_NB_LDS][QR_NB_LDS];  // T[i][j] (the panel's T, kept here)
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int rows = (int)(d - j0);
-  for (int j = 0; j < nb; ++j)
-    for (int r = tid; r < rows; r += 1024) P[r + j * rows] = A[j0 + r + (j0 + j) * lda];
-  __syncthreads();
+  {
+    // the thread's (at most three) rows of every column, loaded together
+    constexpr int RPT = (QR_LDS_ROWS + 1023) / 1024;
+    double v[QR_NB_LDS][RPT];
+#pragma unroll
+    for (int j = 0; j < QR_NB_LDS; ++j)
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int r = tid + 1024 * q;
+        v[j][q] = j < nb && r < rows ? A[j0 + r + (j0 + j) * lda] : 0.0;
+      }
+#pragma unroll
+    for (int j = 0; j < QR_NB_LDS; ++j)
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int r = tid + 1024 * q;
+        if (j < nb && r < rows) P[r + j * rows] = v[j][q];
+      }
+  }
+  // per-wave partial sums of squares of column 0 below its diagonal (the
+  // thread's own rows)
+  {
+    double ss = 0.0;
+    for (int r = tid; r < rows; r += 1024)
+      if (r > 0) ss += P[r] * P[r];
+    ss = wave_sum(ss);
+    if (lane == 0) s_norm[wave] = ss;
+  }
   for (int k = 0; k < nb; ++k) {
     double* col = P + k * rows;  // row c = j0 + k is local row k
-    double ss = 0.0;
-    for (int r = k + 1 + tid; r < rows; r += 1024) ss += col[r] * col[r];
-    const double sigma = block_sum(ss, sh);
+    __syncthreads();             // column k and its norm partials are final
+    double sigma = 0.0;
+    for (int w = 0; w < 16; ++w) sigma += s_norm[w];  // fixed order
     const double alpha = col[k];
     double t_k, beta, scale;
     if (sigma == 0.0) {
@@ -191,13 +221,14 @@ __global__ __launch_bounds__(1024) void k_qr_panel_lds(double* __restrict__ A, i
       t_k = (beta - alpha) / beta;
       scale = 1.0 / (alpha - beta);
     }
-    for (int r = k + 1 + tid; r < rows; r += 1024) col[r] *= scale;
-    __syncthreads();
+    // v = the scaled column below row k, and its dots with the other columns
     double part[QR_NB_LDS];
 #pragma unroll
     for (int j = 0; j < QR_NB_LDS; ++j) part[j] = 0.0;
-    for (int r = k + 1 + tid; r < rows; r += 1024) {
-      const double vr = col[r];
+    for (int r = tid; r < rows; r += 1024) {
+      if (r <= k) continue;
+      const double vr = col[r] * scale;
+      col[r] = vr;
 #pragma unroll
       for (int j = 0; j < QR_NB_LDS; ++j)
         if (j < nb && j != k) part[j] += P[r + j * rows] * vr;
@@ -214,27 +245,45 @@ __global__ __launch_bounds__(1024) void k_qr_panel_lds(double* __restrict__ A, i
       s_w[tid] = sj + P[k + tid * rows];  // row c: v[c] = 1
     }
     __syncthreads();
+    // columns j > k: a_j -= t_k w_j v (the thread's rows), and the partial
+    // norm of column k + 1 below its diagonal
+    double ss = 0.0;
     for (int j = k + 1; j < nb; ++j) {
       const double wj = t_k * s_w[j];
       double* cj = P + j * rows;
-      for (int r = k + 1 + tid; r < rows; r += 1024) cj[r] -= wj * col[r];
+      for (int r = tid; r < rows; r += 1024) {
+        if (r <= k) continue;
+        const double x = cj[r] - wj * col[r];
+        cj[r] = x;
+        if (j == k + 1 && r > k + 1) ss += x * x;
+      }
       if (tid == 0) cj[k] -= wj;
+    }
+    if (k + 1 < nb) {
+      ss = wave_sum(ss);
+      if (lane == 0) s_norm[wave] = ss;
+    }
+    // T column k: thread i < k takes T[i][k] (T's earlier columns were
+    // written by the same thread)
+    if (tid < k) {
+      double si = 0.0;
+      for (int j = tid; j < k; ++j) si += s_t[tid][j] * s_w[j];
+      s_t[tid][k] = -t_k * si;
     }
     if (tid == 0) {
       col[k] = beta;
       tau[j0 + k] = t_k;
-      for (int i = 0; i < k; ++i) {
-        double si = 0.0;
-        for (int j = i; j < k; ++j) si += T[i + j * QR_NB] * s_w[j];
-        T[i + k * QR_NB] = -t_k * si;
-      }
-      T[k + k * QR_NB] = t_k;
-      for (int i = k + 1; i < QR_NB; ++i) T[i + k * QR_NB] = 0.0;
+      s_t[k][k] = t_k;
     }
-    __syncthreads();
   }
+  __syncthreads();
   for (int j = 0; j < nb; ++j)
     for (int r = tid; r < rows; r += 1024) A[j0 + r + (j0 + j) * lda] = P[r + j * rows];
+  // T (ldt = QR_NB): the upper triangle, zeros below
+  if (tid < QR_NB * nb) {
+    const int i = tid % QR_NB, j = tid / QR_NB;
+    T[i + j * QR_NB] = i <= j ? s_t[i][j] : 0.0;
+  }
 }
 
 // C <- C - V T^T (V^T C) for the trailing columns j >= j0 + nb, rows >= j0;
