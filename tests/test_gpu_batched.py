@@ -124,3 +124,31 @@ def test_batched_precision_path(B, oracle_lib, prec):
         assert mf == (A.nnz / (A.m * A.n) >= 0.015 * (prec == 1) + 0.03 * (prec == 2)), i
         single = B.sketch(dA, d, dist, sd, prec=prec, tune=plan).cpu().numpy().astype(np.float64)
         assert np.array_equal(single, got), i
+
+
+def test_batched_many_small_items(B, oracle_lib):
+    # 300 small items: workgroups of the item-indexed inspector kernels span
+    # many items at once, and finding a workgroup's items takes more than
+    # one step of the 32-way search
+    rng = np.random.default_rng(11)
+    items = []
+    for b in range(300):
+        m = int(rng.integers(50, 5000))
+        n = int(rng.integers(1, 81))
+        d = int(rng.integers(2 * n, 4 * n + 1))
+        nnz = int(round(float(rng.uniform(0.0, 0.06)) * m * n))
+        A = inputs.uniform_positions(m, n, nnz, int(rng.integers(1 << 30)), "uniform", np.float32)
+        items.append((A, d, ["rademacher", "uniform", "gaussian"][b % 3], 7000 + b))
+    batch, mats, outs, ws = _run_batch(B, items)
+    assert batch.status(ws) == [0] * len(items)
+    plans = batch.plan()
+    check = set(int(i) for i in rng.choice(len(items), 12, replace=False))
+    for i, ((A, d, dist, sd), dA, out, plan) in enumerate(zip(items, mats, outs, plans)):
+        got = out.t().cpu().numpy().astype(np.float64)
+        single = B.sketch(dA, d, dist, sd, tune=plan).cpu().numpy().astype(np.float64)
+        assert np.array_equal(single, got), (i, A.m, A.n, A.nnz, d, dist)
+        if i in check:
+            ref = oracle_lib.sketch(A.m, A.n, A.colptr, A.rowidx, A.vals.astype(np.float64), d,
+                                    dist, sd) if A.nnz else np.zeros((d, A.n))
+            norm, col = _rel(got, ref)
+            assert norm <= TOL_NORM and col <= TOL_COL, (i, norm, col)
