@@ -287,7 +287,13 @@ __global__ __launch_bounds__(1024) void k_qr_panel_lds(double* __restrict__ A, i
 }
 
 // C <- C - V T^T (V^T C) for the trailing columns j >= j0 + nb, rows >= j0;
-// one workgroup per trailing column.
+// one workgroup per trailing column.  Rows go in chunks of QU_R per thread
+// (strided by the workgroup): a chunk's column values, then each
+// reflector's values in the chunk, are loaded together, so a pass waits on
+// a few memory round trips rather than one per row step; with one chunk
+// (d - j0 <= QU_R * SAP_THREADS) the column stays in registers between the
+// passes.
+constexpr int QU_R = 8;
 __global__ __launch_bounds__(SAP_THREADS) void k_qr_update(double* __restrict__ A, int64_t lda,
                                                             int64_t d, int64_t n, int64_t j0,
                                                             int nb, const double* __restrict__ T) {
@@ -299,18 +305,34 @@ __global__ __launch_bounds__(SAP_THREADS) void k_qr_update(double* __restrict__ 
   const int64_t j = j0 + nb + blockIdx.x;
   if (j >= n) return;
   double* cj = A + j * lda;
-  // W = V^T C[:, j]; V_i has 1 at row j0 + i, zeros above, A[r, j0 + i] below
+  constexpr int64_t CH = (int64_t)QU_R * SAP_THREADS;  // rows per chunk
+  // V_i has 1 at row j0 + i, zeros above, A[r, j0 + i] below
+  auto vval = [&](int i, int64_t r) {
+    const int64_t ri = j0 + i;
+    return r > ri ? A[r + ri * lda] : (r == ri ? 1.0 : 0.0);
+  };
+  double c[QU_R];
+  // W = V^T C[:, j]
   double part[QR_NB];
 #pragma unroll
   for (int i = 0; i < QR_NB; ++i) part[i] = 0.0;
-  for (int64_t r = j0 + tid; r < d; r += SAP_THREADS) {
-    const double cr = cj[r];
+  for (int64_t r0 = j0; r0 < d; r0 += CH) {
+#pragma unroll
+    for (int q = 0; q < QU_R; ++q) {
+      const int64_t r = r0 + tid + (int64_t)q * SAP_THREADS;
+      c[q] = r < d ? cj[r] : 0.0;
+    }
 #pragma unroll
     for (int i = 0; i < QR_NB; ++i) {
       if (i < nb) {
-        const int64_t ri = j0 + i;
-        const double vi = r > ri ? A[r + ri * lda] : (r == ri ? 1.0 : 0.0);
-        part[i] += vi * cr;
+        double v[QU_R];
+#pragma unroll
+        for (int q = 0; q < QU_R; ++q) {
+          const int64_t r = r0 + tid + (int64_t)q * SAP_THREADS;
+          v[q] = r < d ? vval(i, r) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < QU_R; ++q) part[i] += v[q] * c[q];
       }
     }
   }
@@ -334,15 +356,39 @@ __global__ __launch_bounds__(SAP_THREADS) void k_qr_update(double* __restrict__ 
   }
   __syncthreads();
   // C -= V W2
-  for (int64_t r = j0 + tid; r < d; r += SAP_THREADS) {
-    double s = 0.0;
-    for (int i = 0; i < nb; ++i) {
-      const int64_t ri = j0 + i;
-      if (r < ri) break;
-      const double vi = r > ri ? A[r + ri * lda] : 1.0;
-      s += vi * s_w2[i];
+  double w2[QR_NB];
+#pragma unroll
+  for (int i = 0; i < QR_NB; ++i) w2[i] = i < nb ? s_w2[i] : 0.0;
+  const bool one_chunk = d - j0 <= CH;
+  for (int64_t r0 = j0; r0 < d; r0 += CH) {
+    if (!one_chunk) {
+#pragma unroll
+      for (int q = 0; q < QU_R; ++q) {
+        const int64_t r = r0 + tid + (int64_t)q * SAP_THREADS;
+        c[q] = r < d ? cj[r] : 0.0;
+      }
     }
-    cj[r] -= s;
+    double acc[QU_R];
+#pragma unroll
+    for (int q = 0; q < QU_R; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int i = 0; i < QR_NB; ++i) {
+      if (i < nb) {
+        double v[QU_R];
+#pragma unroll
+        for (int q = 0; q < QU_R; ++q) {
+          const int64_t r = r0 + tid + (int64_t)q * SAP_THREADS;
+          v[q] = r < d ? vval(i, r) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < QU_R; ++q) acc[q] += v[q] * w2[i];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < QU_R; ++q) {
+      const int64_t r = r0 + tid + (int64_t)q * SAP_THREADS;
+      if (r < d) cj[r] = c[q] - acc[q];
+    }
   }
 }
 
