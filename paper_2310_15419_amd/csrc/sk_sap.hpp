@@ -35,10 +35,32 @@ constexpr int SAP_THREADS = 256;
 constexpr int SAP_CHUNK = 2048;    // entries per A^T u chunk
 
 // ---------------------------------------------------------------- helpers
+// v from another lane by a DPP move (the two halves of a double apart);
+// lanes outside row_mask get 0
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xF, false);
+  return __builtin_bit_cast(double, (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32));
+}
+
+// Sum over the 64 lanes of a wave (all active), every lane gets it: pairs
+// and quads by quad permutations, 8- and 16-lane rows by mirrors, then
+// lane 15 of each row into the next (rows 1, 3) and lane 31 into rows 2, 3,
+// so lane 63 holds the total.  DPP moves stay in the VALU, so no step waits
+// on the LDS crossbar.  (The order of the additions is fixed.)
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;  // lane 0 holds the sum
+  v += dpp_f64<0xB1, 0xF>(v);   // quad_perm 1,0,3,2
+  v += dpp_f64<0x4E, 0xF>(v);   // quad_perm 2,3,0,1
+  v += dpp_f64<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_f64<0x140, 0xF>(v);  // row_mirror
+  v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15
+  v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+  return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));  // in every lane
 }
 
 // sum over the workgroup (blockDim.x a multiple of 64, <= 1024); every
