@@ -611,6 +611,7 @@ __global__ void k_gemv_upper(const double* __restrict__ Rit, int64_t n,
   if (i >= n) return;
   const double* row = Rit + i * n;
   double acc = 0.0;
+#pragma unroll 4
   for (int64_t j = i + lane; j < n; j += 64) acc += row[j] * v[j];
   acc = wave_sum(acc);
   if (lane == 0) t[i] = acc;
@@ -625,6 +626,7 @@ __global__ void k_gemv_upper_t(const double* __restrict__ Ri, int64_t ldi, int64
   const int lane = threadIdx.x & 63;
   if (j >= n) return;
   double acc = 0.0;
+#pragma unroll 4
   for (int64_t i = lane; i <= j; i += 64) acc += Ri[i + j * ldi] * s[i];
   acc = wave_sum(acc);
   if (lane == 0) t[j] = acc;
@@ -674,6 +676,7 @@ __global__ __launch_bounds__(SAP_THREADS) void k_lsqr_av_long(
   if (li < lidx[m]) {
     const int32_t r = lrows[li];
     double s = 0.0;
+#pragma unroll 4
     for (int32_t p = rowptr[r] + lane; p < rowptr[r + 1]; p += 64) s += cval[p] * z[ccol[p]];
     s = wave_sum(s);
     if (lane == 0) {
@@ -717,18 +720,15 @@ __global__ void k_lsqr_atu(const int64_t* __restrict__ colptr, const int32_t* __
   const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (g >= cbase[n]) return;
-  int64_t lo = 0, hi = n - 1;  // column of chunk g
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (cbase[mid] <= g) lo = mid;
-    else hi = mid - 1;
-  }
-  const int64_t k = lo;
+  // column of chunk g (both half waves search for the same g)
+  const int64_t k = halfwave_last_le(0, n - 1, g, [&](int64_t q) { return (int64_t)cbase[q]; });
   const int64_t p0 = colptr[k] + (g - cbase[k]) * SAP_CHUNK;
   const int64_t p1 = p0 + SAP_CHUNK < colptr[k + 1] ? p0 + SAP_CHUNK : colptr[k + 1];
   double acc = 0.0;
-  if (valid)
+  if (valid) {
+#pragma unroll 4
     for (int64_t p = p0 + lane; p < p1; p += 64) acc += v64[p] * u[rowidx[p]];
+  }
   acc = wave_sum(acc);
   if (lane == 0) cpart[g] = acc / (st->beta > 0.0 ? st->beta : 1.0);
 }
