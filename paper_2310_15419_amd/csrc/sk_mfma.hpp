@@ -216,9 +216,9 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
   }
 
   if (!consumer) {
-    // A producer wave builds its share of a copy for one block: the S words
-    // of its 32 block rows (those of one half h and steps 4 u .. 4 u + 3 of
-    // the W layout, one generator call each), and the dense
+    // A producer wave builds its share of a copy for one block: waves 0 and
+    // 1 the S words of 64 block rows each (one half h of the W layout, one
+    // generator call per row), and every wave the dense
     // tile of its 64 columns: zeros where that copy's previous block had
     // entries (or everywhere, when they were not all kept), then the
     // block's entries.  A wave's LDS writes to its share all come from that
@@ -235,10 +235,12 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
     const int cw0 = 64 * pw;
     const int ncw = cols - cw0 < 64 ? cols - cw0 : 64;  // <= 0: past the last column
     const int cs0 = ncw > 0 ? cw0 : 0, cs1 = ncw > 0 ? cw0 + ncw : 0;
-    // the wave's S bits: half hh, words u of the W layout; lane r (of each
-    // 32-lane half) generates block row krow, the one whose sign lands at
-    // bit r after the transpose
-    const int hh = pw & 1, wu = pw >> 1;
+    // the group's S bits come from its waves 0 and 1: wave hh makes half
+    // hh of the W layout, and lane r of its 32-lane half u generates block
+    // row krow, whose sign lands at bit r of word u after the transpose
+    // (one distinct generator call per lane)
+    const bool signs = pw < 2;
+    const int hh = pw & 1, wu = lane >> 5;
     int krow;
     {
       int j, e;
@@ -312,21 +314,22 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
         (&L.Alo[buf][0][0])[at] = 0;
       }
     };
-    // 128 signs of block row krow from one generator call (both halves of
-    // the wave make the same call); the lower half transposes words 0 and 1,
-    // the upper half words 2 and 3, which leaves lane t of half v with S
-    // rows 64 v + t and 64 v + 32 + t over the wave's rows
+    // 128 signs of block row krow from one generator call; transposing its
+    // four words across the half wave leaves lane t with S rows 32 q + t
+    // (word q) over the half's 32 block rows
     auto sign_words = [&](const Payload& y) {
       Words w{0u, 0u, 0u, 0u};
       if (krow < y.rb) w = sign_bits128(P.seed, grow0, (uint64_t)(uint32_t)y.row);
-      const bool up = lane >= 32;
-      return make_uint2(transpose32(up ? w.x2 : w.x0, lane), transpose32(up ? w.x3 : w.x1, lane));
+      return make_uint4(transpose32(w.x0, lane), transpose32(w.x1, lane),
+                        transpose32(w.x2, lane), transpose32(w.x3, lane));
     };
-    auto build = [&](int buf, const Payload& y, const uint2 t, Placed& pl) {
-      {
-        const int i = 64 * (lane >> 5) + (lane & 31);
+    auto build = [&](int buf, const Payload& y, const uint4 t, Placed& pl) {
+      if (signs) {
+        const int i = lane & 31;
         L.W[buf][hh][i][wu] = t.x;
-        L.W[buf][hh][i + 32][wu] = t.y;
+        L.W[buf][hh][32 + i][wu] = t.y;
+        L.W[buf][hh][64 + i][wu] = t.z;
+        L.W[buf][hh][96 + i][wu] = t.w;
       }
       if (ncw <= 0) return;  // past the last column: never stored
       if (pl.count >= 0) {
@@ -372,11 +375,11 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
     Placed pl{-1, {}};  // copy grp: its last block's entries
     Payload Y{};        // the group's next block
     Bounds Bn{};        // the block after that
-    uint2 T{};          // sign words of the group's next block
+    uint4 T{};          // sign words of the group's next block (waves 0, 1)
     if (grp < nblk) {
       Y = load_payload(load_bounds(grp));
       Bn = load_bounds(grp + 2);
-      if (grp == 0) T = sign_words(Y);
+      if (grp == 0 && signs) T = sign_words(Y);
     }
     for (int64_t k = 0; k <= nblk; ++k) {
       if ((int)(k & 1) == grp) {
@@ -385,7 +388,7 @@ __device__ __forceinline__ void mfma_unit(const SketchParams& P, int split, int 
           Y = load_payload(Bn);    // block k + 2
           Bn = load_bounds(k + 4);
         }
-      } else if (k + 1 < nblk) {
+      } else if (k + 1 < nblk && signs) {
         T = sign_words(Y);         // block k + 1
       }
       __syncthreads();  // block k is built; block k - 1 consumed
