@@ -18,8 +18,10 @@
 // staging passes.
 //
 // Every kernel here runs over a flattened index space that concatenates the
-// items of a batch (a single sketch is a batch of one): a thread finds its
-// item by binary search over the items' prefix offsets.  Per-item exclusive
+// items of a batch (a single sketch is a batch of one): a workgroup finds
+// the items of its first and last index by a search over the items' prefix
+// offsets (all its threads share one item in the usual case; else each
+// thread searches).  Per-item exclusive
 // scans are one scan over the concatenated regions, followed by subtraction
 // of each item's value at its region start.
 //
@@ -341,9 +343,9 @@ __global__ __launch_bounds__(KI_THREADS) void k_items(const Item* __restrict__ i
 // per thread (strided by the workgroup size, so loads stay coalesced);
 // Op::run also gets the column of the entry, found by a search limited to the
 // columns of the workgroup's first and last entries (a few columns,
-// typically) instead of one over all of colptr.  The workgroup's search for
-// those bounds is the latency every index waits on, so it covers 1024 of
-// them.
+// typically) instead of one over all of colptr.  The workgroup's searches
+// for those bounds (on 32 lanes each) are the latency every index waits on,
+// so they cover 1024 of them.
 constexpr int IC_THREADS = 256;
 constexpr int IC_PER = 4;
 
