@@ -18,7 +18,10 @@ def B():
     return binding
 
 
-@pytest.mark.parametrize("d,n", [(300, 77), (64, 64), (40, 1), (1000, 513), (33, 17), (257, 32)])
+# (2600, 40): every panel outside LDS and the trailing update in several row
+# chunks; (2400, 200): the first panels outside LDS, the rest in it
+@pytest.mark.parametrize("d,n", [(300, 77), (64, 64), (40, 1), (1000, 513), (33, 17), (257, 32),
+                                 (2600, 40), (2400, 200)])
 def test_qr_against_numpy(B, d, n):
     import torch
     rng = np.random.default_rng(d * 1000 + n)
