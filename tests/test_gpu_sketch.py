@@ -329,3 +329,24 @@ def test_precision_path_rules(B):
     a = B.sketch(dA, 80, "rademacher", 1, prec=1, tune={"dense_min_pct": 50}).cpu().numpy()
     b = B.sketch(dA, 80, "rademacher", 1, prec=0).cpu().numpy()
     assert np.array_equal(a, b)
+
+
+def test_unaligned_row_indices(B, oracle_lib):
+    # row indices and values that start 4 bytes past a 16-byte boundary (a
+    # view into a larger tensor): the block-position search then reads its
+    # windows one entry at a time; the result must not depend on it
+    import torch
+    A = inputs.uniform_positions(30_000, 60, 60_000, 3, "uniform", np.float32)
+    aligned = B.DeviceCsc.from_host(A)
+    big_r = torch.zeros(A.nnz + 1, dtype=torch.int32, device="cuda")
+    big_v = torch.zeros(A.nnz + 1, dtype=torch.float32, device="cuda")
+    big_r[1:] = aligned.rowidx
+    big_v[1:] = aligned.vals
+    shifted = B.DeviceCsc(A.m, A.n, aligned.colptr, big_r[1:], big_v[1:])
+    assert shifted.rowidx.data_ptr() % 16 == 4
+    for dist in DISTS:
+        a = B.sketch(aligned, 150, dist, 9).cpu().numpy()
+        s = B.sketch(shifted, 150, dist, 9).cpu().numpy()
+        assert np.array_equal(a, s), dist
+        norm, col = rel_errors(s.astype(np.float64), run_oracle(oracle_lib, A, 150, dist, 9))
+        assert norm <= TOL_NORM and col <= TOL_COL, dist
