@@ -104,6 +104,7 @@ __global__ __launch_bounds__(SAP_THREADS) void k_qr_panel(double* __restrict__ A
   __shared__ double sh[16];
   __shared__ double s_dot[QR_NB][SAP_THREADS / 64];
   __shared__ double s_w[QR_NB];
+  __shared__ double s_t[QR_NB][QR_NB];  // T[i][j] (the panel's T, kept here)
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   for (int k = 0; k < nb; ++k) {
@@ -163,17 +164,21 @@ __global__ __launch_bounds__(SAP_THREADS) void k_qr_panel(double* __restrict__ A
       for (int64_t r = c + 1 + tid; r < d; r += SAP_THREADS) cj[r] -= wj * col[r];
       if (tid == 0) cj[c] -= wj;
     }
-    // T[0:k, k] = -tau_k T[0:k, 0:k] z, z_j = V_j^T v (j < k); T[k, k] = tau_k
-    if (tid == 0) {
-      for (int i = 0; i < k; ++i) {
-        double s = 0.0;
-        for (int j = i; j < k; ++j) s += T[i + j * QR_NB] * s_w[j];
-        T[i + k * QR_NB] = -t_k * s;
-      }
-      T[k + k * QR_NB] = t_k;
-      for (int i = k + 1; i < QR_NB; ++i) T[i + k * QR_NB] = 0.0;
+    // T[0:k, k] = -tau_k T[0:k, 0:k] z, z_j = V_j^T v (j < k); T[k, k] =
+    // tau_k.  Thread i < k takes T[i][k] (T's earlier columns of row i were
+    // written by the same thread).
+    if (tid < k) {
+      double s = 0.0;
+      for (int j = tid; j < k; ++j) s += s_t[tid][j] * s_w[j];
+      s_t[tid][k] = -t_k * s;
     }
+    if (tid == 0) s_t[k][k] = t_k;
     __syncthreads();
+  }
+  // T (ldt = QR_NB): the upper triangle, zeros below
+  if (tid < QR_NB * nb) {
+    const int i = tid % QR_NB, j = tid / QR_NB;
+    T[i + j * QR_NB] = i <= j ? s_t[i][j] : 0.0;
   }
 }
 
