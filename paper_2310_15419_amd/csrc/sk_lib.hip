@@ -797,7 +797,10 @@ sk_status qr_launch(int64_t d, int64_t n, double* A, int64_t lda, double* R, int
 
 sk_status trinv_launch(int64_t n, const double* R, int64_t ldr, double* Ri, int64_t ldi,
                        hipStream_t st) {
-  hipLaunchKernelGGL(k_trinv_upper, dim3((unsigned)n), dim3(SAP_THREADS), (size_t)(8 * n), st, R,
+  if (hipFuncSetAttribute((const void*)k_trinv_upper, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          16 * SAP_MAX_N) != hipSuccess)
+    return SK_EHIP;
+  hipLaunchKernelGGL(k_trinv_upper, dim3((unsigned)n), dim3(SAP_THREADS), (size_t)(16 * n), st, R,
                      ldr, n, Ri, ldi);
   return launch_ok();
 }

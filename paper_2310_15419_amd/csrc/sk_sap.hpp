@@ -430,29 +430,63 @@ __global__ void k_qr_extract_r(const double* __restrict__ A, int64_t lda, int64_
 
 // Rinv = R^{-1} (upper triangular); one workgroup per column j: solve
 // R x = e_j by column-oriented back substitution with the right-hand side
-// in LDS (n <= SAP_MAX_N).
+// and R's diagonal in LDS (n <= SAP_MAX_N); each step's column of R is
+// loaded the step before.
 constexpr int SAP_MAX_N = 8192;
+constexpr int TRI_Q = 4;  // rows per thread held in registers (n <= 1024 all of them)
 __global__ __launch_bounds__(SAP_THREADS) void k_trinv_upper(const double* __restrict__ R,
                                                               int64_t ldr, int64_t n,
                                                               double* __restrict__ Ri,
                                                               int64_t ldi) {
-  extern __shared__ double rhs[];  // n doubles
+  extern __shared__ double rhs[];  // 2 n doubles: the right-hand side, then R's diagonal
+  double* diag = rhs + n;
   const int tid = threadIdx.x;
   const int64_t j = blockIdx.x;
   if (j >= n) return;
-  for (int64_t i = tid; i < n; i += SAP_THREADS) rhs[i] = i == j ? 1.0 : 0.0;
-  __syncthreads();
-  for (int64_t i = j; i >= 0; --i) {
-    const double xi = rhs[i] / R[i + i * ldr];
+  for (int64_t i = tid; i < n; i += SAP_THREADS) {
+    rhs[i] = i == j ? 1.0 : 0.0;
+    diag[i] = i <= j ? R[i + i * ldr] : 1.0;
+  }
+  // the thread's rows of column c (rows < c) into v; up to TRI_Q rows per
+  // thread are held in registers, the rest (n > TRI_Q * SAP_THREADS) read
+  // when used
+  auto load_col = [&](int64_t c, double (&v)[TRI_Q]) {
+#pragma unroll
+    for (int q = 0; q < TRI_Q; ++q) {
+      const int64_t r = tid + (int64_t)SAP_THREADS * q;
+      v[q] = r < c ? R[r + c * ldr] : 0.0;
+    }
+  };
+  auto step = [&](int64_t i, const double (&v)[TRI_Q]) {
+    const double xi = rhs[i] / diag[i];
     __syncthreads();  // every thread has read rhs[i]
     if (tid == 0) rhs[i] = xi;
+#pragma unroll
+    for (int q = 0; q < TRI_Q; ++q) {
+      const int64_t r = tid + (int64_t)SAP_THREADS * q;
+      if (r < i) rhs[r] -= xi * v[q];
+    }
     const double* ci = R + i * ldr;
-    for (int64_t r = tid; r < i; r += SAP_THREADS) rhs[r] -= xi * ci[r];
+    for (int64_t r = tid + (int64_t)SAP_THREADS * TRI_Q; r < i; r += SAP_THREADS)
+      rhs[r] -= xi * ci[r];
     __syncthreads();
+  };
+  __syncthreads();
+  // two register buffers in turn: a column's loads are issued one step
+  // before it is used, and no copy of in-flight registers is made
+  double ca[TRI_Q], cb[TRI_Q];
+  load_col(j, ca);
+  for (int64_t i = j; i >= 0; i -= 2) {
+    load_col(i - 1, cb);
+    step(i, ca);
+    if (i == 0) break;
+    load_col(i - 2, ca);
+    step(i - 1, cb);
   }
   double* out = Ri + j * ldi;
   for (int64_t i = tid; i < n; i += SAP_THREADS) out[i] = i <= j ? rhs[i] : 0.0;
 }
+
 
 // ------------------------------------------------------------- A copies
 // The kernels that index by A's structure run only on input the sketch's

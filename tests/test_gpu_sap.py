@@ -38,7 +38,7 @@ def test_qr_against_numpy(B, d, n):
     assert np.linalg.norm(R - sgn[:, None] * Rn) <= 1e-12 * n * np.linalg.norm(Rn)
 
 
-@pytest.mark.parametrize("n", [1, 5, 64, 300, 1001])
+@pytest.mark.parametrize("n", [1, 5, 64, 300, 1001, 1100])  # 1100: the workgroup form
 def test_trinv_against_numpy(B, n):
     import torch
     rng = np.random.default_rng(n)
