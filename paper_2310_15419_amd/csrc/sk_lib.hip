@@ -779,7 +779,7 @@ sk_status qr_launch(int64_t d, int64_t n, double* A, int64_t lda, double* R, int
     const bool in_lds = d - j0 <= QR_LDS_ROWS;
     const int nb = (int)std::min<int64_t>(in_lds ? QR_NB_LDS : QR_NB, n - j0);
     if (in_lds)
-      hipLaunchKernelGGL(k_qr_panel_lds, dim3(1), dim3(1024), (size_t)(8 * nb * (d - j0)), st, A,
+      hipLaunchKernelGGL(k_qr_panel_lds, dim3(1), dim3(QR_PT), (size_t)(8 * nb * (d - j0)), st, A,
                          lda, d, j0, nb, tau, T);
     else
       hipLaunchKernelGGL(k_qr_panel, dim3(1), dim3(SAP_THREADS), 0, st, A, lda, d, j0, nb, tau,

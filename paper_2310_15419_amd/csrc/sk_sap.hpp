@@ -183,21 +183,22 @@ __global__ __launch_bounds__(SAP_THREADS) void k_qr_panel(double* __restrict__ A
 }
 
 // The same factorisation with the panel (rows j0..d-1, nb <= QR_NB_LDS
-// columns) held in LDS, by one workgroup of 1024 threads.  Thread t keeps
-// rows t, t + 1024, ... for the whole panel, and a column takes three
+// columns) held in LDS, by one workgroup of QR_PT threads.  Thread t keeps
+// rows t, t + QR_PT, ... for the whole panel, and a column takes three
 // barriers: its norm (summed from the previous column's update pass), its
 // dot products with the other panel columns (taken while the reflector is
 // scaled), and their totals; the update of the later columns then computes
 // the next column's norm on the way.
 constexpr int QR_NB_LDS = 8;
 constexpr int QR_LDS_ROWS = 2304;  // panel rows that fit: 2304 * 8 * 8 B = 144 KiB
-__global__ __launch_bounds__(1024) void k_qr_panel_lds(double* __restrict__ A, int64_t lda,
+constexpr int QR_PT = 1024;        // threads of the panel workgroup (measured: 256 and 512 slower)
+__global__ __launch_bounds__(QR_PT) void k_qr_panel_lds(double* __restrict__ A, int64_t lda,
                                                         int64_t d, int64_t j0, int nb,
                                                         double* __restrict__ tau,
                                                         double* __restrict__ T) {
   extern __shared__ double P[];  // (d - j0) x nb, column-major, ld = rows
-  __shared__ double s_norm[16];
-  __shared__ double s_dot[QR_NB_LDS][16];
+  __shared__ double s_norm[QR_PT / 64];
+  __shared__ double s_dot[QR_NB_LDS][QR_PT / 64];
   __shared__ double s_w[QR_NB_LDS];
   __shared__ double s_t[QR_NB_LDS][QR_NB_LDS];  // T[i][j] (the panel's T, kept here)
   const int tid = threadIdx.x;
@@ -205,20 +206,20 @@ __global__ __launch_bounds__(1024) void k_qr_panel_lds(double* __restrict__ A, i
   const int rows = (int)(d - j0);
   {
     // the thread's (at most three) rows of every column, loaded together
-    constexpr int RPT = (QR_LDS_ROWS + 1023) / 1024;
+    constexpr int RPT = (QR_LDS_ROWS + QR_PT - 1) / QR_PT;
     double v[QR_NB_LDS][RPT];
 #pragma unroll
     for (int j = 0; j < QR_NB_LDS; ++j)
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
-        const int r = tid + 1024 * q;
+        const int r = tid + QR_PT * q;
         v[j][q] = j < nb && r < rows ? A[j0 + r + (j0 + j) * lda] : 0.0;
       }
 #pragma unroll
     for (int j = 0; j < QR_NB_LDS; ++j)
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
-        const int r = tid + 1024 * q;
+        const int r = tid + QR_PT * q;
         if (j < nb && r < rows) P[r + j * rows] = v[j][q];
       }
   }
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(1024) void k_qr_panel_lds(double* __restrict__ A, i
   // thread's own rows)
   {
     double ss = 0.0;
-    for (int r = tid; r < rows; r += 1024)
+    for (int r = tid; r < rows; r += QR_PT)
       if (r > 0) ss += P[r] * P[r];
     ss = wave_sum(ss);
     if (lane == 0) s_norm[wave] = ss;
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(1024) void k_qr_panel_lds(double* __restrict__ A, i
     double* col = P + k * rows;  // row c = j0 + k is local row k
     __syncthreads();             // column k and its norm partials are final
     double sigma = 0.0;
-    for (int w = 0; w < 16; ++w) sigma += s_norm[w];  // fixed order
+    for (int w = 0; w < QR_PT / 64; ++w) sigma += s_norm[w];  // fixed order
     const double alpha = col[k];
     double t_k, beta, scale;
     if (sigma == 0.0) {
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(1024) void k_qr_panel_lds(double* __restrict__ A, i
     double part[QR_NB_LDS];
 #pragma unroll
     for (int j = 0; j < QR_NB_LDS; ++j) part[j] = 0.0;
-    for (int r = tid; r < rows; r += 1024) {
+    for (int r = tid; r < rows; r += QR_PT) {
       if (r <= k) continue;
       const double vr = col[r] * scale;
       col[r] = vr;
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(1024) void k_qr_panel_lds(double* __restrict__ A, i
     __syncthreads();
     if (tid < nb && tid != k) {
       double sj = 0.0;
-      for (int w = 0; w < 16; ++w) sj += s_dot[tid][w];
+      for (int w = 0; w < QR_PT / 64; ++w) sj += s_dot[tid][w];
       s_w[tid] = sj + P[k + tid * rows];  // row c: v[c] = 1
     }
     __syncthreads();
@@ -278,7 +279,7 @@ __global__ __launch_bounds__(1024) void k_qr_panel_lds(double* __restrict__ A, i
     for (int j = k + 1; j < nb; ++j) {
       const double wj = t_k * s_w[j];
       double* cj = P + j * rows;
-      for (int r = tid; r < rows; r += 1024) {
+      for (int r = tid; r < rows; r += QR_PT) {
         if (r <= k) continue;
         const double x = cj[r] - wj * col[r];
         cj[r] = x;
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(1024) void k_qr_panel_lds(double* __restrict__ A, i
   }
   __syncthreads();
   for (int j = 0; j < nb; ++j)
-    for (int r = tid; r < rows; r += 1024) A[j0 + r + (j0 + j) * lda] = P[r + j * rows];
+    for (int r = tid; r < rows; r += QR_PT) A[j0 + r + (j0 + j) * lda] = P[r + j * rows];
   // T (ldt = QR_NB): the upper triangle, zeros below
   if (tid < QR_NB * nb) {
     const int i = tid % QR_NB, j = tid / QR_NB;
