@@ -771,15 +771,13 @@ sk_status sap_layout(const sk_csc* A, const sk_sap_params* p, SapLayout& L) {
 
 sk_status qr_launch(int64_t d, int64_t n, double* A, int64_t lda, double* R, int64_t ldr,
                     double* tau, double* T, hipStream_t st) {
-  if (hipFuncSetAttribute((const void*)k_qr_panel_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          8 * QR_NB_LDS * QR_LDS_ROWS) != hipSuccess)
-    return SK_EHIP;
   for (int64_t j0 = 0; j0 < n;) {
-    // panels whose rows fit in LDS are factored there, eight columns at a time
-    const bool in_lds = d - j0 <= QR_LDS_ROWS;
-    const int nb = (int)std::min<int64_t>(in_lds ? QR_NB_LDS : QR_NB, n - j0);
-    if (in_lds)
-      hipLaunchKernelGGL(k_qr_panel_lds, dim3(1), dim3(QR_PT), (size_t)(8 * nb * (d - j0)), st, A,
+    // panels of at most QR_REG_ROWS rows are factored in registers, eight
+    // columns at a time
+    const bool in_regs = d - j0 <= QR_REG_ROWS;
+    const int nb = (int)std::min<int64_t>(in_regs ? QR_NB_REG : QR_NB, n - j0);
+    if (in_regs)
+      hipLaunchKernelGGL(k_qr_panel_regs, dim3(1), dim3(QR_PT), 0, st, A,
                          lda, d, j0, nb, tau, T);
     else
       hipLaunchKernelGGL(k_qr_panel, dim3(1), dim3(SAP_THREADS), 0, st, A, lda, d, j0, nb, tau,

@@ -182,62 +182,63 @@ __global__ __launch_bounds__(SAP_THREADS) void k_qr_panel(double* __restrict__ A
   }
 }
 
-// The same factorisation with the panel (rows j0..d-1, nb <= QR_NB_LDS
-// columns) held in LDS, by one workgroup of QR_PT threads.  Thread t keeps
-// rows t, t + QR_PT, ... for the whole panel, and a column takes three
-// barriers: its norm (summed from the previous column's update pass), its
+// The same factorisation for a panel of rows j0..d-1 (at most QR_REG_ROWS)
+// and nb <= QR_NB_REG columns, by one workgroup of QR_PT threads that keep
+// the panel in registers: thread t holds rows t, t + QR_PT, ... of every
+// panel column for the whole panel.  Only the partial sums, the T factor and
+// row k (published by its owner, thread k) go through LDS.  A column takes
+// three barriers: its norm (summed from the previous column's update), its
 // dot products with the other panel columns (taken while the reflector is
-// scaled), and their totals; the update of the later columns then computes
-// the next column's norm on the way.
-constexpr int QR_NB_LDS = 8;
-constexpr int QR_LDS_ROWS = 2304;  // panel rows that fit: 2304 * 8 * 8 B = 144 KiB
+// scaled), and their totals; the update of the later columns computes the
+// next column's norm on the way.
+constexpr int QR_NB_REG = 8;
+constexpr int QR_REG_ROWS = 2304;  // panel rows held: 3 per thread
 constexpr int QR_PT = 1024;        // threads of the panel workgroup (measured: 256 and 512 slower)
-__global__ __launch_bounds__(QR_PT) void k_qr_panel_lds(double* __restrict__ A, int64_t lda,
+__global__ __launch_bounds__(QR_PT) void k_qr_panel_regs(double* __restrict__ A, int64_t lda,
                                                         int64_t d, int64_t j0, int nb,
                                                         double* __restrict__ tau,
                                                         double* __restrict__ T) {
-  extern __shared__ double P[];  // (d - j0) x nb, column-major, ld = rows
+  constexpr int RPT = (QR_REG_ROWS + QR_PT - 1) / QR_PT;
+  static_assert(QR_NB_REG <= QR_PT, "row k of the panel is owned by thread k");
   __shared__ double s_norm[QR_PT / 64];
-  __shared__ double s_dot[QR_NB_LDS][QR_PT / 64];
-  __shared__ double s_w[QR_NB_LDS];
-  __shared__ double s_t[QR_NB_LDS][QR_NB_LDS];  // T[i][j] (the panel's T, kept here)
+  __shared__ double s_dot[QR_NB_REG][QR_PT / 64];
+  __shared__ double s_w[QR_NB_REG];
+  __shared__ double s_row[QR_NB_REG];           // row k of the panel's columns
+  __shared__ double s_t[QR_NB_REG][QR_NB_REG];  // T[i][j] (the panel's T, kept here)
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int rows = (int)(d - j0);
+  // x[j][q]: row tid + QR_PT q of panel column j
+  double x[QR_NB_REG][RPT];
+#pragma unroll
+  for (int j = 0; j < QR_NB_REG; ++j)
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = tid + QR_PT * q;
+      x[j][q] = j < nb && r < rows ? A[j0 + r + (j0 + j) * lda] : 0.0;
+    }
   {
-    // the thread's (at most three) rows of every column, loaded together
-    constexpr int RPT = (QR_LDS_ROWS + QR_PT - 1) / QR_PT;
-    double v[QR_NB_LDS][RPT];
-#pragma unroll
-    for (int j = 0; j < QR_NB_LDS; ++j)
-#pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int r = tid + QR_PT * q;
-        v[j][q] = j < nb && r < rows ? A[j0 + r + (j0 + j) * lda] : 0.0;
-      }
-#pragma unroll
-    for (int j = 0; j < QR_NB_LDS; ++j)
-#pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int r = tid + QR_PT * q;
-        if (j < nb && r < rows) P[r + j * rows] = v[j][q];
-      }
-  }
-  // per-wave partial sums of squares of column 0 below its diagonal (the
-  // thread's own rows)
-  {
+    // per-wave partial sums of squares of column 0 below its diagonal, and
+    // row 0 published
     double ss = 0.0;
-    for (int r = tid; r < rows; r += QR_PT)
-      if (r > 0) ss += P[r] * P[r];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = tid + QR_PT * q;
+      if (r > 0 && r < rows) ss += x[0][q] * x[0][q];
+    }
     ss = wave_sum(ss);
     if (lane == 0) s_norm[wave] = ss;
+    if (tid == 0)
+#pragma unroll
+      for (int j = 0; j < QR_NB_REG; ++j) s_row[j] = x[j][0];
   }
-  for (int k = 0; k < nb; ++k) {
-    double* col = P + k * rows;  // row c = j0 + k is local row k
-    __syncthreads();             // column k and its norm partials are final
+#pragma unroll
+  for (int k = 0; k < QR_NB_REG; ++k) {
+    if (k >= nb) break;
+    __syncthreads();  // norm partials and row k are final
     double sigma = 0.0;
     for (int w = 0; w < QR_PT / 64; ++w) sigma += s_norm[w];  // fixed order
-    const double alpha = col[k];
+    const double alpha = s_row[k];
     double t_k, beta, scale;
     if (sigma == 0.0) {
       t_k = 0.0;
@@ -250,19 +251,22 @@ __global__ __launch_bounds__(QR_PT) void k_qr_panel_lds(double* __restrict__ A, 
       scale = 1.0 / (alpha - beta);
     }
     // v = the scaled column below row k, and its dots with the other columns
-    double part[QR_NB_LDS];
+    double part[QR_NB_REG];
 #pragma unroll
-    for (int j = 0; j < QR_NB_LDS; ++j) part[j] = 0.0;
-    for (int r = tid; r < rows; r += QR_PT) {
-      if (r <= k) continue;
-      const double vr = col[r] * scale;
-      col[r] = vr;
+    for (int j = 0; j < QR_NB_REG; ++j) part[j] = 0.0;
 #pragma unroll
-      for (int j = 0; j < QR_NB_LDS; ++j)
-        if (j < nb && j != k) part[j] += P[r + j * rows] * vr;
+    for (int q = 0; q < RPT; ++q) {
+      const int r = tid + QR_PT * q;
+      if (r > k && r < rows) {
+        const double vr = x[k][q] * scale;
+        x[k][q] = vr;
+#pragma unroll
+        for (int j = 0; j < QR_NB_REG; ++j)
+          if (j < nb && j != k) part[j] += x[j][q] * vr;
+      }
     }
 #pragma unroll
-    for (int j = 0; j < QR_NB_LDS; ++j) {
+    for (int j = 0; j < QR_NB_REG; ++j) {
       const double sj = wave_sum(part[j]);
       if (lane == 0) s_dot[j][wave] = sj;
     }
@@ -270,43 +274,57 @@ __global__ __launch_bounds__(QR_PT) void k_qr_panel_lds(double* __restrict__ A, 
     if (tid < nb && tid != k) {
       double sj = 0.0;
       for (int w = 0; w < QR_PT / 64; ++w) sj += s_dot[tid][w];
-      s_w[tid] = sj + P[k + tid * rows];  // row c: v[c] = 1
+      s_w[tid] = sj + s_row[tid];  // row c: v[c] = 1
     }
     __syncthreads();
-    // columns j > k: a_j -= t_k w_j v (the thread's rows), and the partial
-    // norm of column k + 1 below its diagonal
+    // columns j > k: a_j -= t_k w_j v (row k: v = 1), and the partial norm
+    // of column k + 1 below its diagonal
     double ss = 0.0;
-    for (int j = k + 1; j < nb; ++j) {
-      const double wj = t_k * s_w[j];
-      double* cj = P + j * rows;
-      for (int r = tid; r < rows; r += QR_PT) {
-        if (r <= k) continue;
-        const double x = cj[r] - wj * col[r];
-        cj[r] = x;
-        if (j == k + 1 && r > k + 1) ss += x * x;
+#pragma unroll
+    for (int j = 0; j < QR_NB_REG; ++j) {
+      if (j > k && j < nb) {
+        const double wj = t_k * s_w[j];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int r = tid + QR_PT * q;
+          if (r > k && r < rows) {
+            const double y = x[j][q] - wj * x[k][q];
+            x[j][q] = y;
+            if (j == k + 1 && r > k + 1) ss += y * y;
+          } else if (r == k) {
+            x[j][q] -= wj;
+          }
+        }
       }
-      if (tid == 0) cj[k] -= wj;
     }
+    if (tid == k) x[k][0] = beta;  // (row k of column k: R's diagonal)
     if (k + 1 < nb) {
       ss = wave_sum(ss);
       if (lane == 0) s_norm[wave] = ss;
+      if (tid == k + 1)
+#pragma unroll
+        for (int j = 0; j < QR_NB_REG; ++j) s_row[j] = x[j][0];
     }
-    // T column k: thread i < k takes T[i][k] (T's earlier columns were
-    // written by the same thread)
+    // T column k: thread i < k takes T[i][k] (T's earlier columns of row i
+    // were written by the same thread)
     if (tid < k) {
       double si = 0.0;
       for (int j = tid; j < k; ++j) si += s_t[tid][j] * s_w[j];
       s_t[tid][k] = -t_k * si;
     }
     if (tid == 0) {
-      col[k] = beta;
       tau[j0 + k] = t_k;
       s_t[k][k] = t_k;
     }
   }
   __syncthreads();
-  for (int j = 0; j < nb; ++j)
-    for (int r = tid; r < rows; r += QR_PT) A[j0 + r + (j0 + j) * lda] = P[r + j * rows];
+#pragma unroll
+  for (int j = 0; j < QR_NB_REG; ++j)
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = tid + QR_PT * q;
+      if (j < nb && r < rows) A[j0 + r + (j0 + j) * lda] = x[j][q];
+    }
   // T (ldt = QR_NB): the upper triangle, zeros below
   if (tid < QR_NB * nb) {
     const int i = tid % QR_NB, j = tid / QR_NB;

@@ -18,8 +18,8 @@ def B():
     return binding
 
 
-# (2600, 40): every panel outside LDS and the trailing update in several row
-# chunks; (2400, 200): the first panels outside LDS, the rest in it
+# (2600, 40): every panel in global memory and the trailing update in several row
+# chunks; (2400, 200): the first panels in global memory, the rest in registers
 @pytest.mark.parametrize("d,n", [(300, 77), (64, 64), (40, 1), (1000, 513), (33, 17), (257, 32),
                                  (2600, 40), (2400, 200)])
 def test_qr_against_numpy(B, d, n):
