@@ -755,9 +755,12 @@ __global__ __launch_bounds__(1024) void k_lsqr_beta(const double* __restrict__ p
   __shared__ double sh[16];
   if (st->done) return;
   double s = 0.0;
+#pragma unroll 4
   for (int64_t i = threadIdx.x; i < np; i += blockDim.x) s += partial[i];
-  if (!INIT)
+  if (!INIT) {
+#pragma unroll 4
     for (int64_t i = threadIdx.x; i < np2; i += blockDim.x) s += partial2[i];
+  }
   const double tot = block_sum(s, sh);
   if (threadIdx.x == 0) {
     const double beta = sqrt(tot);
