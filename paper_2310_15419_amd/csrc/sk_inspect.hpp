@@ -747,7 +747,7 @@ __device__ __forceinline__ int64_t real_column(const int32_t* __restrict__ vbase
 //   - each block's position by counting, in a window of 16 consecutive
 //     entries, those above its first row; the window moves down the column
 //     while a block's first row lies below all of it.
-constexpr int BP_MAX_CHUNK = 8;  // bp_chunk at most
+constexpr int BP_MAX_CHUNK = 16;  // bp_chunk at most
 constexpr int BP_P = 8;          // probes per search step
 constexpr int BP_W = 16;         // entries per window
 struct OpBlockPos {

@@ -546,10 +546,10 @@ Item make_item(const sk_csc* A, const Plan& P, int dist) {
   I.colptr = A->colptr; I.rowidx = A->rowidx; I.vals = A->vals; I.vtype = A->vtype;
   I.m_b = P.m_b; I.e_cap = P.e_max; I.row_bytes = P.row_bytes;
   // block-position search: blocks per thread from the expected entries per
-  // (column, block) (measured: 8 at ~4 entries, 1-2 at ~14)
+  // (column, block) (measured: 16 at ~3.7 entries, 8 at ~4-6, 1-2 at ~14)
   {
     const double per = (double)A->nnz / std::max(1.0, (double)A->n * (double)P.ngroups);
-    I.bp_chunk = per <= 6.0 ? 8 : (per <= 24.0 ? 2 : 1);
+    I.bp_chunk = per <= 4.0 ? 16 : (per <= 6.0 ? 8 : (per <= 24.0 ? 2 : 1));
   }
   I.nv = P.nv; I.nb_max = P.nb_max; I.r_max = P.r_max;
   if (P.mfma) {  // blocks of equal height; the cost follows the rows
