@@ -382,9 +382,12 @@ __global__ void k_reduce_virtual(const float* __restrict__ part, int splits, int
   if (t >= d * n) return;
   const int64_t k = t / d, i = t - k * d;
   float s = 0.0f;
-  if (!vbase) {
+  // the slice column(s) of real column k
+  const int64_t col = vbase ? vbase[k] : k;
+  const int64_t ncol = vbase ? vbase[k + 1] - col : 1;
+  if (ncol == 1) {
     // one value per split: eight loads in flight, added in split order
-    const float* __restrict__ p = part + i + k * d;
+    const float* __restrict__ p = part + i + col * d;
     const int64_t stride = d * nv;
     int q = 0;
     for (; q + 8 <= splits; q += 8) {
@@ -399,7 +402,7 @@ __global__ void k_reduce_virtual(const float* __restrict__ part, int splits, int
       s = q == 0 ? x : s + x;
     }
   } else {
-    const int64_t v0 = vbase[k], v1 = vbase[k + 1];
+    const int64_t v0 = col, v1 = col + ncol;
     bool first = true;
     for (int q = 0; q < splits; ++q) {
       const float* sl = part + (int64_t)q * d * nv;
