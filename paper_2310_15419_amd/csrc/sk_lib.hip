@@ -267,11 +267,18 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
 // The threshold is a density in percent (the measured crossover of the two
 // kernels on MI355X); dense_min_pct overrides it.
 constexpr double kMfmaAutoPct[3] = {0.0, 1.5, 3.0};  // unused, BF16, FP8
+// In a batch the matrix-core items share one launch with the others and pay
+// no per-item launch, so the crossover is lower (measured on the 512-item
+// workload: 1% beats 1.5% in BF16 and 3% in FP8).  Whole percents: a batch
+// reports them as its items' tuning.
+constexpr int kMfmaBatchPct[3] = {0, 1, 1};
 
-int mfma_format(int64_t m, int64_t n, int64_t nnz, int dist, int prec, const sk_tuning* tune) {
+int mfma_format(int64_t m, int64_t n, int64_t nnz, int dist, int prec, const sk_tuning* tune,
+                bool batch = false) {
   if (prec == SK_PREC_F32 || dist != SK_RADEMACHER) return 0;
   const double pct = tune && tune->dense_min_pct > 0 ? (double)tune->dense_min_pct
-                                                     : kMfmaAutoPct[prec];
+                     : batch                          ? (double)kMfmaBatchPct[prec]
+                                                      : kMfmaAutoPct[prec];
   if (pct > 100.0) return 0;
   const double density = 100.0 * (double)nnz / ((double)m * (double)n);
   if (density < pct) return 0;
@@ -328,8 +335,9 @@ bool plan_mfma(int64_t m, int64_t n, int64_t nnz, int64_t d, int fmt, const sk_t
 
 // the plan a request runs with: the matrix-core path or the sparse kernel
 bool plan_any(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, int prec,
-              const sk_tuning* tune, Plan& P, int forced_variant = -1, double unit_cycles = 0.0) {
-  const int fmt = mfma_format(m, n, nnz, dist, prec, tune);
+              const sk_tuning* tune, Plan& P, int forced_variant = -1, double unit_cycles = 0.0,
+              bool batch = false) {
+  const int fmt = mfma_format(m, n, nnz, dist, prec, tune, batch);
   if (fmt) return plan_mfma(m, n, nnz, d, fmt, tune, P, unit_cycles);
   return plan_for(m, n, nnz, d, dist, tune, P, forced_variant, unit_cycles);
 }
@@ -643,7 +651,8 @@ sk_status batch_plan(int32_t count, const sk_csc* A, const int64_t* d, const int
   double total_cost = 0.0;
   for (int i = 0; i < count; ++i) {
     const sk_tuning* t = tune ? &tune[i] : nullptr;
-    if (!plan_any(A[i].m, A[i].n, A[i].nnz, d[i], dist[i], prec, t, B.plans[i], B.variant, 0.0))
+    if (!plan_any(A[i].m, A[i].n, A[i].nnz, d[i], dist[i], prec, t, B.plans[i], B.variant, 0.0,
+                  true))
       return SK_EINVAL;
     total_cost += B.plans[i].cost;
   }
@@ -652,7 +661,8 @@ sk_status batch_plan(int32_t count, const sk_csc* A, const int64_t* d, const int
   const double unit = std::max(1.0, total_cost / ((double)cus * kBatchUnitsPerSlot));
   for (int i = 0; i < count; ++i) {
     const sk_tuning* t = tune ? &tune[i] : nullptr;
-    if (!plan_any(A[i].m, A[i].n, A[i].nnz, d[i], dist[i], prec, t, B.plans[i], B.variant, unit))
+    if (!plan_any(A[i].m, A[i].n, A[i].nnz, d[i], dist[i], prec, t, B.plans[i], B.variant, unit,
+                  true))
       return SK_EINVAL;
     const Plan& P = B.plans[i];
     if ((int64_t)(P.nb_max + 1) * P.nv >= INT32_MAX) return SK_EUNSUPPORTED;
@@ -1199,8 +1209,11 @@ sk_status sk_sketch_batched_plan(int32_t count, const sk_csc* A, const int64_t* 
     chosen[i].splits = P.splits;
     chosen[i].variant = P.mfma ? 0 : P.variant + 1;
     // sparse items: no dense blocks (and no matrix-core path); matrix-core
-    // items: the caller's threshold (0 = the automatic one) picks it again
-    chosen[i].dense_min_pct = P.mfma ? (tune ? tune[i].dense_min_pct : 0) : 101;
+    // items: the threshold that picked it (the caller's, else the batch's),
+    // so a single call with this tuning takes the same path
+    chosen[i].dense_min_pct =
+        P.mfma ? (tune && tune[i].dense_min_pct > 0 ? tune[i].dense_min_pct : kMfmaBatchPct[prec])
+               : 101;
     chosen[i].tile_rows = P.mfma ? 0 : P.d_b;
     chosen[i].col_split = 1;
   }

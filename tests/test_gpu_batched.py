@@ -121,7 +121,7 @@ def test_batched_precision_path(B, oracle_lib, prec):
                                 sd)
         norm, col = _rel(got, ref)
         assert norm <= (1e-2 if mf else TOL_NORM), (i, norm)
-        assert mf == (A.nnz / (A.m * A.n) >= 0.015 * (prec == 1) + 0.03 * (prec == 2)), i
+        assert mf == (A.nnz / (A.m * A.n) >= 0.01), i  # the batch's threshold
         single = B.sketch(dA, d, dist, sd, prec=prec, tune=plan).cpu().numpy().astype(np.float64)
         assert np.array_equal(single, got), i
 
