@@ -192,8 +192,8 @@ __global__ __launch_bounds__(SAP_THREADS) void k_qr_panel(double* __restrict__ A
 // scaled), and their totals; the update of the later columns computes the
 // next column's norm on the way.
 constexpr int QR_NB_REG = 8;
-constexpr int QR_REG_ROWS = 2304;  // panel rows held: 3 per thread
 constexpr int QR_PT = 1024;        // threads of the panel workgroup (measured: 256 and 512 slower)
+constexpr int QR_REG_ROWS = 3 * QR_PT;  // panel rows held: 3 per thread
 __global__ __launch_bounds__(QR_PT) void k_qr_panel_regs(double* __restrict__ A, int64_t lda,
                                                         int64_t d, int64_t j0, int nb,
                                                         double* __restrict__ tau,

@@ -18,10 +18,11 @@ def B():
     return binding
 
 
-# (2600, 40): every panel in global memory and the trailing update in several row
-# chunks; (2400, 200): the first panels in global memory, the rest in registers
+# (2600, 40): panels in registers and the trailing update in several row
+# chunks; (3300, 30): every panel in global memory; (3100, 100): the first
+# panels in global memory, the rest in registers
 @pytest.mark.parametrize("d,n", [(300, 77), (64, 64), (40, 1), (1000, 513), (33, 17), (257, 32),
-                                 (2600, 40), (2400, 200)])
+                                 (2600, 40), (3300, 30), (3100, 100)])
 def test_qr_against_numpy(B, d, n):
     import torch
     rng = np.random.default_rng(d * 1000 + n)
