@@ -12,7 +12,8 @@
  *
  * Conventions common to every call:
  *  - All matrix/vector pointers are DEVICE pointers owned by the caller; the
- *    library never allocates device memory (the caller passes a workspace),
+ *    library never allocates device memory (the caller passes a workspace;
+ *    the one exception is the fixed per-device array of sk_sketch_noalloc),
  *    so device-memory accounting by the caller is exact.
  *  - Indices are 0-based (the paper's pseudocode is 1-based).
  *  - A is CSC: colptr int64[n+1] (colptr[0] = 0, colptr[n] = nnz, non-
@@ -28,8 +29,9 @@
  *    NaN into the output and record a status in the workspace, which
  *    sk_sketch_status() returns (it synchronises the stream).
  *  - HIP launch failures map to SK_EHIP.
- *  - The library holds no mutable global state; concurrent calls on
- *    different streams with different workspaces are independent.
+ *  - The library holds no mutable global state besides the fixed device
+ *    array of sk_sketch_noalloc (below); concurrent calls on different
+ *    streams with different workspaces are independent.
  */
 #ifndef SKETCH_H
 #define SKETCH_H
@@ -120,6 +122,25 @@ sk_status sk_sketch_workspace(const sk_csc* A, int64_t d, int32_t dist, int32_t 
 sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint64_t seed,
                     int32_t prec, const sk_tuning* tune, float* Ahat, int64_t ld, void* ws,
                     size_t ws_bytes, void* hip_stream);
+
+/* Allocation-free form of sk_sketch, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same computation and result as sk_sketch with the
+ * same arguments, but the workspace is a fixed device array inside the
+ * library, SK_NOALLOC_SCRATCH_BYTES per device, which every GPU the library
+ * runs on holds until the process ends.  The caller still owns A and A_hat.
+ * The call allocates nothing and frees nothing; it resolves the array's
+ * device address on its first call on each device (the current device).
+ * Returns SK_EWORKSPACE when sk_sketch_workspace() for these arguments
+ * exceeds SK_NOALLOC_SCRATCH_BYTES.  All calls on one device share its one
+ * array: calls that overlap on a device (different streams, or other host
+ * threads) race and must be serialised by the caller.  Every call clears
+ * what must start at zero itself.  Errors in the CSC contents give NaN in
+ * A_hat (the status record sits in the shared array, with no reader call). */
+#define SK_NOALLOC_SCRATCH_BYTES (64ull << 20)
+sk_status sk_sketch_noalloc(const sk_csc* A, int64_t row0, int64_t d, int32_t dist,
+                            uint64_t seed, int32_t prec, const sk_tuning* tune, float* Ahat,
+                            int64_t ld, void* hip_stream);
 
 /* Status of the last sk_sketch that used this workspace (synchronises
  * hip_stream).  Also reports the inspector's counts when the pointers are

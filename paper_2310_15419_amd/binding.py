@@ -75,6 +75,8 @@ def lib():
         L.sk_sketch_workspace.argtypes = [P(SkCsc), i64, i32, i32, P(SkTuning), P(ctypes.c_size_t)]
         L.sk_sketch.argtypes = [P(SkCsc), i64, i64, i32, u64, i32, P(SkTuning), vp, i64, vp,
                                 ctypes.c_size_t, vp]
+        L.sk_sketch_noalloc.argtypes = [P(SkCsc), i64, i64, i32, u64, i32, P(SkTuning), vp, i64,
+                                        vp]
         L.sk_sketch_status.argtypes = [vp, vp, P(i64), P(i64)]
         L.sk_materialize_s.argtypes = [i64, i64, i64, i64, i32, u64, vp, i64, vp]
         L.sk_autotune.argtypes = [P(SkCsc), i64, i32, P(SkTuning)]
@@ -96,7 +98,8 @@ def lib():
         L.sk_sap_finish.argtypes = [P(SkCsc), P(SapParams), vp, vp, ctypes.c_size_t, vp]
         L.sk_sap_read_info.argtypes = [P(SkCsc), P(SapParams), vp, ctypes.c_size_t, vp,
                                        P(SapInfo)]
-        for name in ("sk_sketch_workspace", "sk_sketch", "sk_sketch_status", "sk_materialize_s",
+        for name in ("sk_sketch_workspace", "sk_sketch", "sk_sketch_noalloc", "sk_sketch_status",
+                     "sk_materialize_s",
                      "sk_autotune", "sk_sketch_batched_workspace", "sk_sketch_batched",
                      "sk_sketch_batched_plan", "sk_sketch_batched_status", "sk_qr_f64_workspace",
                      "sk_qr_f64", "sk_trinv_f64", "sk_sap_workspace", "sk_sap_begin",
@@ -194,6 +197,21 @@ def sketch_into(A: DeviceCsc, d: int, dist, seed: int, out, ws, row0: int = 0,
     _check(lib().sk_sketch(ctypes.byref(c), row0, d, _dist(dist), seed, prec, _tuning(tune),
                            out.data_ptr(), ld, ws.data_ptr(), ws.numel(), _stream(stream)),
            "sk_sketch")
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # SK_NOALLOC_SCRATCH_BYTES
+
+
+def sketch_noalloc_into(A: DeviceCsc, d: int, dist, seed: int, out, row0: int = 0,
+                        prec: int = PREC_F32, tune=None, stream=None,
+                        ld: int | None = None) -> None:
+    """sk_sketch_noalloc: like ``sketch_into`` with the library's fixed device
+    array as the workspace (no workspace argument, nothing allocated)."""
+    c = A.c_struct()
+    ld = d if ld is None else ld
+    _check(lib().sk_sketch_noalloc(ctypes.byref(c), row0, d, _dist(dist), seed, prec,
+                                   _tuning(tune), out.data_ptr(), ld, _stream(stream)),
+           "sk_sketch_noalloc")
 
 
 def sketch(A: DeviceCsc, d: int, dist, seed: int, row0: int = 0, prec: int = PREC_F32,

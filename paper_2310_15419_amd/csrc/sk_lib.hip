@@ -11,6 +11,7 @@
 #include <cstdint>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 
 #include "sk_batch.hpp"
 #include "sk_dense.hpp"
@@ -849,6 +850,34 @@ void lsqr_iteration(const sk_csc* A, const SapLayout& L, char* w, hipStream_t st
 }
 }  // namespace
 
+// ------------------------------------------------- allocation-free form
+// Workspace of sk_sketch_noalloc: a fixed device array, one copy per device
+// (the loader gives each GPU its own), held until the process ends.  Host
+// code never passes the array's name to a kernel: that name is a host-side
+// stand-in, not a device address.  The device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[SK_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+sk_status scratch_for_current_device(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SK_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return SK_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SK_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SK_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* sk_status_string(int s) {
@@ -1013,6 +1042,20 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
                        P.splits, d, n, wcols, fold ? nullptr : I.vbase,
                        P.dense_pct ? part + (int64_t)P.splits * d * wcols : nullptr, Ahat, ld);
   return launch_ok();
+}
+
+sk_status sk_sketch_noalloc(const sk_csc* A, int64_t row0, int64_t d, int32_t dist,
+                            uint64_t seed, int32_t prec, const sk_tuning* tune, float* Ahat,
+                            int64_t ld, void* hip_stream) {
+  size_t need = 0;
+  sk_status s = sk_sketch_workspace(A, d, dist, prec, tune, &need);
+  if (s != SK_OK) return s;
+  if (need > (size_t)SK_NOALLOC_SCRATCH_BYTES) return SK_EWORKSPACE;
+  void* ws = nullptr;
+  if ((s = scratch_for_current_device(&ws)) != SK_OK) return s;
+  // sk_sketch itself allocates nothing and clears what must start at zero
+  // (the header, the scanned flags) with fill kernels on the stream
+  return sk_sketch(A, row0, d, dist, seed, prec, tune, Ahat, ld, ws, need, hip_stream);
 }
 
 sk_status sk_sketch_status(const void* ws, void* hip_stream, int64_t* nonempty_rows,

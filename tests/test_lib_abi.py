@@ -115,3 +115,15 @@ def test_autotune_host_only():
     c = _csc(m=2_000_000, n=2000, nnz=20_000_000)
     assert lib.sk_autotune(ctypes.byref(c), 4000, 1, ctypes.byref(t)) == 0
     assert t.tile_rows >= 16 and t.rows_per_block > 100 and t.splits >= 1
+
+
+def test_noalloc_oversize_refused_on_host():
+    # the allocation-free form checks its fixed array's size before any
+    # device work (dummy device pointers are never read)
+    lib = binding.lib()
+    big = _csc(m=2_000_000, n=2000, nnz=20_000_000)
+    out = ctypes.c_void_p(8)
+    assert lib.sk_sketch_noalloc(ctypes.byref(big), 0, 4000, 1, 1, 0, None, out, 4000,
+                                 None) == -4
+    assert lib.sk_sketch_noalloc(ctypes.byref(_csc(m=0)), 0, 64, 1, 1, 0, None, out, 64,
+                                 None) == -1
