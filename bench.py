@@ -93,12 +93,24 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(A, d, dist, seed, target_s: float):
-    """The oracle, untouched, on the first rows of A (all columns)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(A, d, dist, seed, target_s: float, threads: int = 0):
+    """The oracle, untouched, on the first rows of A (all columns).  Returns
+    the baseline record, the oracle's A_hat and the sampled matrix."""
     import oracle
     oracle.build()
     from paper_2310_15419_amd import inputs
-    threads = len(os.sched_getaffinity(0))
+    threads = threads or len(os.sched_getaffinity(0))
 
     def sample(rows):
         keep = A.rowidx < rows
@@ -113,10 +125,22 @@ def cpu_baseline(A, d, dist, seed, target_s: float):
     rows = int(min(A.m, max(rows, rows * target_s / max(dt, 1e-3))))
     S = sample(rows)
     t0 = time.perf_counter()
-    oracle.sketch(S.m, S.n, S.colptr, S.rowidx, S.vals, d, dist, seed, threads=threads)
+    ref = oracle.sketch(S.m, S.n, S.colptr, S.rowidx, S.vals, d, dist, seed, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": S.nnz * d / dt, "unit": "nnz*d/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {rows} rows of A (nnz={S.nnz}), full d={d}, {dt:.1f} s"}
+    rec = {"value": S.nnz * d / dt, "unit": "nnz*d/s", "cores": threads, "kind": "oracle",
+           "cpu": cpu_model(),
+           "sample": f"first {rows} rows of A (nnz={S.nnz}), full d={d}, {dt:.1f} s"}
+    return rec, ref, S
+
+
+def parity_record(got, ref, S, dist, what: str):
+    """The oracle's error measures for a GPU result on the oracle's sample."""
+    import oracle
+    p = oracle.parity(got, ref, S.colptr, S.vals, dist)
+    p.update({"compared": what, "elem_bound": oracle.ELEM_TOL, "norm_bound": 1e-5})
+    p["pass"] = bool(p["nonfinite"] == 0 and p["normwise"] <= 1e-5 and
+                     p["max_elem_scaled"] <= oracle.ELEM_TOL)
+    return p
 
 
 def bench_serving(args):
@@ -416,8 +440,25 @@ def main():
                      "kernel_ms": kms},
         "wall_s_timed": wall,
     }
+    res["config"]["input_sha256"] = A.sha256()
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(A, d, dist, seed, args.cpu_seconds)
+        rec, ref, S = cpu_baseline(A, d, dist, seed, args.cpu_seconds)
+        if S.m == A.m:
+            # the whole workload: the timed output itself
+            got = out.t().cpu().numpy()
+            what = "the timed output, every element"
+        else:
+            # a row sample: the same call on the sampled rows
+            vdt = None if A.vals.dtype == np.float64 else np.float32  # as the timed input
+            got = B.sketch(B.DeviceCsc.from_host(S, dtype=vdt), d, dist, seed).cpu().numpy()
+            what = f"a GPU sketch of the oracle's sample ({S.m} rows), every element"
+        res["parity"] = parity_record(got, ref, S, dist, what)
+        del ref, got
+        if args.workload == "plain_small":
+            # one thread too, beside the paper's sequential tables
+            one, _, _ = cpu_baseline(A, d, dist, seed, args.cpu_seconds, threads=1)
+            rec["one_thread"] = one
+        res["cpu_baseline"] = rec
     print(json.dumps(res), flush=True)
 
 

@@ -10,9 +10,12 @@ something other than itself):
   philox        -- against an independent Philox4x32-10 (PyTorch's header
                    engine, compiled into a test harness)
   s_entry / materialize_s -- against the generator words (independent Philox)
-                   for +-1 and (-1,1); Gaussian against FP64 libm Box-Muller
+                   for +-1 and (-1,1) exactly; Gaussian against FP64 libm
+                   Box-Muller
   sketch        -- brute force, identity blocks, linearity, concatenation,
                    E[A_hat^T A_hat] = d sigma^2 A^T A, subspace embedding
+  parity        -- error measures only (no part of the method); pinned by a
+                   brute-force recomputation on a small case
   ls_*          -- numpy least squares on dense inputs
 """
 from __future__ import annotations
@@ -142,6 +145,42 @@ def tables():
     mc = np.empty(3, np.float32)
     lib().or_tables(lc.ctypes.data, sc.ctypes.data, cc.ctypes.data, mc.ctypes.data)
     return {"log": lc, "sin": sc, "cos": cc, "misc": mc}
+
+
+# largest |S| entry per distribution: +-1, the open interval (-1,1), and the
+# largest radius the Gaussian transform can produce, sqrt(-2 ln 2^-24)
+S_MAX = {RADEMACHER: 1.0, UNIFORM: 1.0, GAUSSIAN: float(np.sqrt(48.0 * np.log(2.0)))}
+# element-wise bar of the FP32 path, relative to the scale of the terms summed
+# into the element (see ``parity``)
+ELEM_TOL = 2.0 ** -20
+
+
+def parity(got, ref, colptr, vals, dist) -> dict:
+    """Errors of a sketch ``got`` (d x n) against the oracle's ``ref``:
+    normwise ||got - ref||_F / ||ref||_F, the largest per-column relative
+    2-norm error, and the largest element-wise error scaled by the size of
+    the terms summed into that element, |got_ik - ref_ik| / (max|S| sum_j
+    |a_jk|) (an FP32 sum of K terms is off by at most about K u of that
+    scale, and typically by sqrt(K) u)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    if got.shape != ref.shape:
+        raise ValueError(f"shape {got.shape} != {ref.shape}")
+    diff = np.abs(got - ref)
+    rnorm = np.linalg.norm(ref)
+    normwise = float(np.linalg.norm(diff) / rnorm) if rnorm > 0 else float(np.linalg.norm(diff))
+    cref = np.linalg.norm(ref, axis=0)
+    cdiff = np.linalg.norm(diff, axis=0)
+    col = np.where(cref > 0, cdiff / np.where(cref > 0, cref, 1.0), cdiff)
+    colptr = np.asarray(colptr, dtype=np.int64)
+    n = colptr.size - 1
+    owner = np.repeat(np.arange(n), np.diff(colptr))
+    scale = np.bincount(owner, weights=np.abs(np.asarray(vals, dtype=np.float64)), minlength=n)
+    scale = scale * S_MAX[_dist(dist)]
+    elem = np.where(scale > 0, diff / np.where(scale > 0, scale, 1.0), diff)
+    return {"normwise": normwise, "max_col": float(col.max()) if col.size else 0.0,
+            "max_elem_scaled": float(elem.max()) if elem.size else 0.0,
+            "nonfinite": int(np.count_nonzero(~np.isfinite(got)))}
 
 
 def max_threads() -> int:

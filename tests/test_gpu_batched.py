@@ -32,6 +32,14 @@ def _items(seed, count, n_hi=500):
     return out
 
 
+def _check(got, ref, A, dist, what):
+    """The FP32 path's bar, element by element (see test_gpu_sketch)."""
+    import oracle
+    p = oracle.parity(got, ref, A.colptr, A.vals, dist)
+    assert p["nonfinite"] == 0 and p["normwise"] <= TOL_NORM and p["max_col"] <= TOL_COL, (what, p)
+    assert p["max_elem_scaled"] <= oracle.ELEM_TOL, (what, p)
+
+
 def _rel(got, ref):
     diff = got - ref
     norm = np.linalg.norm(diff) / max(np.linalg.norm(ref), 1e-300)
@@ -64,8 +72,7 @@ def test_batched_matches_oracle_and_single(B, oracle_lib, seed, n_hi):
         got = out.t().cpu().numpy().astype(np.float64)
         ref = oracle_lib.sketch(A.m, A.n, A.colptr, A.rowidx, A.vals.astype(np.float64), d, dist,
                                 sd)
-        norm, col = _rel(got, ref)
-        assert norm <= TOL_NORM and col <= TOL_COL, (i, norm, col)
+        _check(got, ref, A, dist, i)
         single = B.sketch(dA, d, dist, sd, tune=plan).cpu().numpy().astype(np.float64)
         assert np.array_equal(single, got), i
 
@@ -91,8 +98,7 @@ def test_batched_edge_items_and_validation(B, oracle_lib):
         got = out.t().cpu().numpy().astype(np.float64)
         ref = oracle_lib.sketch(A.m, A.n, A.colptr, A.rowidx, A.vals.astype(np.float64), d, dist,
                                 sd) if A.nnz else np.zeros((d, A.n))
-        norm, col = _rel(got, ref)
-        assert norm <= TOL_NORM and col <= TOL_COL
+        _check(got, ref, A, dist, (A.m, A.n, d))
 
 
 @pytest.mark.parametrize("prec", [1, 2])  # BF16, FP8
@@ -150,5 +156,4 @@ def test_batched_many_small_items(B, oracle_lib):
         if i in check:
             ref = oracle_lib.sketch(A.m, A.n, A.colptr, A.rowidx, A.vals.astype(np.float64), d,
                                     dist, sd) if A.nnz else np.zeros((d, A.n))
-            norm, col = _rel(got, ref)
-            assert norm <= TOL_NORM and col <= TOL_COL, (i, norm, col)
+            _check(got, ref, A, dist, i)

@@ -142,3 +142,23 @@ def test_coefficient_tables_from_their_definition(oracle_lib):
     hi, lo, s2 = t["misc"]
     assert float(hi) == 22713 / 32768 and abs(float(hi) + float(lo) - math.log(2)) < 1e-12
     assert s2 == np.float32(math.sqrt(2))
+
+
+@pytest.mark.parametrize("seed", [31, 0xFEDC_BA98_7654_3210])
+def test_s_entry_against_independent_words(oracle_lib, seed):
+    # S(i, j) one entry at a time, pinned on words from the independent engine:
+    # +-1 and (-1,1) exactly, the Gaussian against FP64 libm Box-Muller
+    cases = [(0, 0), (127, 3), (128, 3), (255, 2**31 - 1), (4001, 2**31 + 5), (9, 2**40 + 1)]
+    for i, j in cases:
+        x = refgen.words_for(seed, i // 128, j)
+        b = (int(x[(i % 128) // 32]) >> (i % 32)) & 1
+        assert oracle_lib.s_entry("rademacher", seed, i, j) == (-1.0 if b else 1.0)
+        x = refgen.words_for(seed, i // 4, j)
+        t = int(np.int32(np.uint32(x[i % 4]))) >> 8
+        assert oracle_lib.s_entry("uniform", seed, i, j) == (2 * t + 1) * 2.0**-24
+        pair = (x[0], x[1]) if i % 4 < 2 else (x[2], x[3])
+        z0, z1, r = refgen.box_muller_f64(np.array([pair[0]], np.uint32),
+                                          np.array([pair[1]], np.uint32))
+        z = (z0 if i % 2 == 0 else z1)[0]
+        got = oracle_lib.s_entry("gaussian", seed, i, j)
+        assert abs(got - z) <= 2.0**-20 * max(r[0], 1.0), (i, j, got, z)

@@ -144,3 +144,26 @@ def test_nonempty_rows_expectation():
     # per-sample sd <= sqrt(m p (1-p)), p = 1-(1-rho)^n
     p = 1 - (1 - rho) ** n
     assert abs(np.mean(counts) - expect) < 5 * np.sqrt(m * p * (1 - p) / 5) + 50
+
+
+def test_parity_measures_by_brute_force(oracle_lib):
+    # the error measures on a tiny case, recomputed element by element
+    from paper_2310_15419_amd import inputs
+    A = inputs.uniform_positions(50, 4, 30, 2, "normal", np.float64)
+    rng = np.random.default_rng(0)
+    ref = rng.standard_normal((6, 4))
+    got = ref + 1e-3 * rng.standard_normal((6, 4))
+    p = oracle_lib.parity(got, ref, A.colptr, A.vals, "gaussian")
+    smax = np.sqrt(-2.0 * np.log(2.0**-24))
+    worst = 0.0
+    for k in range(4):
+        s = sum(abs(A.vals[e]) for e in range(A.colptr[k], A.colptr[k + 1])) * smax
+        for i in range(6):
+            e = abs(got[i, k] - ref[i, k])
+            worst = max(worst, e / s if s > 0 else e)
+    assert np.isclose(p["max_elem_scaled"], worst, rtol=1e-12)
+    assert np.isclose(p["normwise"], np.sqrt(((got - ref) ** 2).sum() / (ref ** 2).sum()))
+    cols = [np.sqrt(((got[:, k] - ref[:, k]) ** 2).sum() / (ref[:, k] ** 2).sum())
+            for k in range(4)]
+    assert np.isclose(p["max_col"], max(cols))
+    assert p["nonfinite"] == 0
