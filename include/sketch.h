@@ -98,6 +98,10 @@ typedef struct {
   int32_t row_pad;        /* S-tile row padding in floats: 0 = none (rows of
                              d_b floats), else this many extra floats per row
                              (a multiple of 4)                                */
+  int32_t count_rng;      /* nonzero: run the sparse kernel's call-counting
+                             instantiation, which also adds up its generator
+                             calls (read with sk_sketch_rng_calls; same
+                             A_hat; for checks, not for speed)                */
 } sk_tuning;
 
 /* Human-readable name of a status code (static storage). */
@@ -148,6 +152,15 @@ sk_status sk_sketch_noalloc(const sk_csc* A, int64_t row0, int64_t d, int32_t di
  * SK_ERANGE, SK_ECOLPTR or SK_EHIP. */
 sk_status sk_sketch_status(const void* ws, void* hip_stream, int64_t* nonempty_rows,
                            int64_t* row_blocks);
+
+/* Generator calls the last sk_sketch on this workspace made in its sparse
+ * kernel, counted only when it ran with sk_tuning.count_rng set (else 0).
+ * Each S tile is generated once per row block, so the count is
+ * sum over (tile, block) of |rows of the block| x (generator groups the
+ * tile's S rows touch): 4 rows per group for (-1,1) and the Gaussian, 128
+ * for +-1 (Sec. III-B counts the random numbers a blocked sketch draws).
+ * Synchronises hip_stream. */
+sk_status sk_sketch_rng_calls(const void* ws, void* hip_stream, uint64_t* calls);
 
 /* Autotuner: the tuning sk_sketch would choose for this shape (a cost model
  * over S-row tile height, rows per block and splits; the kernel shape follows

@@ -31,7 +31,8 @@ class SkTuning(ctypes.Structure):
     _fields_ = [("rows_per_block", ctypes.c_int32), ("splits", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("dense_min_pct", ctypes.c_int32),
                 ("phases", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-                ("col_split", ctypes.c_int32), ("row_pad", ctypes.c_int32)]
+                ("col_split", ctypes.c_int32), ("row_pad", ctypes.c_int32),
+                ("count_rng", ctypes.c_int32)]
 
 
 class SapParams(ctypes.Structure):
@@ -78,6 +79,7 @@ def lib():
         L.sk_sketch_noalloc.argtypes = [P(SkCsc), i64, i64, i32, u64, i32, P(SkTuning), vp, i64,
                                         vp]
         L.sk_sketch_status.argtypes = [vp, vp, P(i64), P(i64)]
+        L.sk_sketch_rng_calls.argtypes = [vp, vp, P(ctypes.c_uint64)]
         L.sk_materialize_s.argtypes = [i64, i64, i64, i64, i32, u64, vp, i64, vp]
         L.sk_autotune.argtypes = [P(SkCsc), i64, i32, P(SkTuning)]
         L.sk_sketch_batched_workspace.argtypes = [i32, P(SkCsc), P(i64), P(i32), i32, P(SkTuning),
@@ -99,6 +101,7 @@ def lib():
         L.sk_sap_read_info.argtypes = [P(SkCsc), P(SapParams), vp, ctypes.c_size_t, vp,
                                        P(SapInfo)]
         for name in ("sk_sketch_workspace", "sk_sketch", "sk_sketch_noalloc", "sk_sketch_status",
+                     "sk_sketch_rng_calls",
                      "sk_materialize_s",
                      "sk_autotune", "sk_sketch_batched_workspace", "sk_sketch_batched",
                      "sk_sketch_batched_plan", "sk_sketch_batched_status", "sk_qr_f64_workspace",
@@ -136,7 +139,8 @@ def _tuning(tune):
     t = SkTuning(int(tune.get("rows_per_block", 0)), int(tune.get("splits", 0)),
                  int(tune.get("variant", 0)), int(tune.get("dense_min_pct", 0)),
                  int(tune.get("phases", 0)), int(tune.get("tile_rows", 0)),
-                 int(tune.get("col_split", 0)), int(tune.get("row_pad", 0)))
+                 int(tune.get("col_split", 0)), int(tune.get("row_pad", 0)),
+                 int(tune.get("count_rng", 0)))
     return ctypes.byref(t)
 
 
@@ -225,6 +229,14 @@ def sketch(A: DeviceCsc, d: int, dist, seed: int, row0: int = 0, prec: int = PRE
         st = sketch_status(ws, stream)
         _check(st["status"], "sk_sketch (device validation)")
     return out.t()
+
+
+def sketch_rng_calls(ws, stream=None) -> int:
+    """Generator calls of the last call-counting sketch on this workspace."""
+    out = ctypes.c_uint64()
+    _check(lib().sk_sketch_rng_calls(ws.data_ptr(), _stream(stream), ctypes.byref(out)),
+           "sk_sketch_rng_calls")
+    return int(out.value)
 
 
 def sketch_status(ws, stream=None) -> dict:

@@ -164,14 +164,26 @@ __device__ __forceinline__ void dense_fill_s(float* __restrict__ Ss, const int32
                                              int nk, uint64_t grow0, uint64_t seed) {
   const int tid = threadIdx.x;
   if (DIST == DIST_RADEMACHER) {
-    // 32 rows x 2 words of 32 sign bits
-    if (tid < 2 * DT_K) {
-      const int kk = tid >> 1, half = tid & 1;
-      uint32_t bits = 0;
-      if (kk < nk) bits = sign_bits32(seed, grow0 + 32u * half, (uint64_t)(uint32_t)rows[kk]);
-      for (int u = 0; u < 32; ++u)
-        Ss[(32 * half + u) * (DT_K + 1) + kk] =
-            kk < nk ? ((bits >> u) & 1u ? -1.0f : 1.0f) : 0.0f;
+    // one generator call per (row, 128-row group the 64 tile rows touch: one,
+    // or two when the tile straddles a group boundary); each word of a call
+    // holds 32 consecutive rows' signs
+    const uint64_t g0 = grow0 >> 7;
+    const int ng = (int)(((grow0 + DT_M - 1) >> 7) - g0 + 1);
+    if (tid < ng * DT_K) {
+      const int kk = tid / ng, gi = tid - kk * ng;
+      const uint64_t g = g0 + (uint64_t)gi;
+      Words x{0u, 0u, 0u, 0u};
+      if (kk < nk) x = gen_words(seed, g, (uint64_t)(uint32_t)rows[kk]);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const uint32_t bits = word_at(x, w);
+        const int64_t r_w = (int64_t)(g * 128u) + 32 * w;
+        for (int u = 0; u < 32; ++u) {
+          const int64_t i = r_w + u - (int64_t)grow0;
+          if (i >= 0 && i < DT_M)
+            Ss[i * (DT_K + 1) + kk] = kk < nk ? ((bits >> u) & 1u ? -1.0f : 1.0f) : 0.0f;
+        }
+      }
     }
   } else {
     // 64 S rows span 16 generator groups (17 when grow0 is not 4-aligned)

@@ -46,7 +46,8 @@ struct Variant {
   int dl, q, cs, wgs;
   SketchKernel k[3];      // per distribution
   SketchKernel kf[3];     // per distribution, adding virtual columns in the kernel
-  PersistentKernel p[3];  // persistent (batched) form, per distribution
+  SketchKernel kc[3];     // per distribution, counting the generator calls
+  PersistentKernel p[3];  // persistent (batched) form, per distribution (none: null)
 };
 
 #define SK_VARIANT(DL, Q, CS, WGS)                                                           \
@@ -57,6 +58,9 @@ struct Variant {
         {k_sketch<DIST_RADEMACHER, DL, Q, CS, WGS, true>,                                    \
          k_sketch<DIST_UNIFORM, DL, Q, CS, WGS, true>,                                       \
          k_sketch<DIST_GAUSSIAN, DL, Q, CS, WGS, true>},                                     \
+        {k_sketch<DIST_RADEMACHER, DL, Q, CS, WGS, false, true>,                             \
+         k_sketch<DIST_UNIFORM, DL, Q, CS, WGS, false, true>,                                \
+         k_sketch<DIST_GAUSSIAN, DL, Q, CS, WGS, false, true>},                              \
         {k_sketch_persistent<DIST_RADEMACHER, DL, Q, CS, WGS>,                               \
          k_sketch_persistent<DIST_UNIFORM, DL, Q, CS, WGS>,                                  \
          k_sketch_persistent<DIST_GAUSSIAN, DL, Q, CS, WGS>}                                 \
@@ -109,7 +113,8 @@ double plan_cost(const Plan& P, const Variant& V, int64_t m, int64_t n, int64_t 
   const double R = (double)m * (1.0 - std::exp(-(double)nnz / (double)m));
   const double tiles = (double)P.tiles * P.ncr;
   const double d_eff = (double)P.tiles * P.d_b;
-  const int rpc = dist == DIST_RADEMACHER ? std::min(32, P.d_b) : 4;
+  // S rows per generator call (+-1: 128, one call per 128-row group a tile touches)
+  const int rpc = dist == DIST_RADEMACHER ? std::min(128, P.d_b) : 4;
   const double call_ops = dist == DIST_GAUSSIAN ? 200.0 : (dist == DIST_UNIFORM ? 75.0 : 70.0);
   const double rng = R * (double)P.ncr * (d_eff / rpc) * call_ops / 64.0;
   const double lambda = std::max(1e-3, (double)P.m_b * ((double)nnz / R) / (double)n);
@@ -577,7 +582,7 @@ Item make_item(const sk_csc* A, const Plan& P, int dist) {
   // row, multiply-adds (with the lockstep padding) and staging per entry, a
   // fixed cost per block
   const Variant& V = kVariants[P.variant];
-  const int rpc = dist == DIST_RADEMACHER ? std::min(32, P.d_b) : 4;
+  const int rpc = dist == DIST_RADEMACHER ? std::min(128, P.d_b) : 4;
   const double call_ops = dist == DIST_GAUSSIAN ? 200.0 : (dist == DIST_UNIFORM ? 75.0 : 70.0);
   I.w_row = (int32_t)std::max(1.0, std::round(16.0 * (P.d_b / rpc) * call_ops / 64.0));
   I.w_ent = (int32_t)std::max(
@@ -986,7 +991,9 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
   K.dflag = P.dense_pct ? dflag : nullptr;
   // virtual columns: added in the kernel (then it writes the n real
   // columns) or in the reduction
-  const bool fold = I.vbase != nullptr && folds_virtual(P, n);
+  // the call-counting instantiation leaves virtual columns to the reduction
+  const bool counting = tune && tune->count_rng && !P.mfma;
+  const bool fold = !counting && I.vbase != nullptr && folds_virtual(P, n);
   if (fold) { K.vbase = I.vbase; K.nreal = n; }
   const int64_t wcols = fold ? n : nv;  // columns of one partial slice
   const bool staged = P.slices > 1 || wcols != n;  // partials, then the reduction
@@ -1011,7 +1018,7 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
     }
   } else {
     const Variant& V = kVariants[P.variant];
-    SketchKernel kern = fold ? V.kf[dist] : V.k[dist];
+    SketchKernel kern = counting ? V.kc[dist] : (fold ? V.kf[dist] : V.k[dist]);
     if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)P.lds) != hipSuccess)
       return SK_EHIP;
@@ -1071,6 +1078,16 @@ sk_status sk_sketch_status(const void* ws, void* hip_stream, int64_t* nonempty_r
   if (h.status & ST_RANGE) return SK_ERANGE;
   if (h.status & ST_UNSORTED) return SK_EUNSORTED;
   if (h.status & ST_CAPACITY) return SK_EUNSUPPORTED;  // block capacity (a planning bound) exceeded
+  return SK_OK;
+}
+
+sk_status sk_sketch_rng_calls(const void* ws, void* hip_stream, uint64_t* calls) {
+  if (!ws || !calls) return SK_EINVAL;
+  Header h;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (hipMemcpyAsync(&h, ws, sizeof h, hipMemcpyDeviceToHost, st) != hipSuccess) return SK_EHIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return SK_EHIP;
+  *calls = (uint64_t)h.reserved[0];
   return SK_OK;
 }
 

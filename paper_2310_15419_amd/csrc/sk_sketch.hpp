@@ -3,10 +3,10 @@
 // One workgroup owns an output tile A_hat[i0 : i0 + d_b, column range] for a
 // range of row blocks (a "split" of the nonempty rows).  Per row block it
 //   1. regenerates the S tile S[i0 : i0 + d_b, rows of the block] into LDS,
-//      one generator call per (row, 4 S rows) -- every S entry is generated
-//      once per tile and reused by every column that has a nonzero in that
-//      row (the reuse of Algorithm 4, Sec. II-B; generation count of
-//      Sec. III-B),
+//      one generator call per (row, 4 S rows), or per (row, 128 S rows) for
+//      the +-1 distribution -- every S entry is generated once per tile and
+//      reused by every column that has a nonzero in that row (the reuse of
+//      Algorithm 4, Sec. II-B; generation count of Sec. III-B),
 //   2. stages the block's entries (ordered by column, then row) into LDS,
 //   3. accumulates: lanes are grouped Q at a time; a group owns CS columns
 //      and, inside the tile, Q*DL consecutive S rows (DL per lane).  For each
@@ -59,75 +59,99 @@ struct SketchParams {
 };
 
 // ---------------------------------------------------------------- S tile
-// Fill S_lds[l * ldS + t] = S(grow0 + t, rows[l]) for l < rb, t < d_b.
-template <int DIST, int WGS, int U>
-__device__ __forceinline__ void fill_tile(float* __restrict__ S_lds, const SketchParams& P,
-                                          const int32_t* __restrict__ rows, int rb,
-                                          uint64_t grow0) {
-  const int tid = threadIdx.x;
-  const int log2_cpr = P.log2_cpr;
-  const int cmask = (1 << log2_cpr) - 1;
-  const int total = rb << log2_cpr;
+// S_lds[l * ldS + t] = S(grow0 + t, rows[l]) for l < rb, t < d_b, by the PT
+// threads ptid = 0 .. PT-1, U generator calls in flight per thread.  COUNT:
+// add the number of generator calls made to *calls (the call-count check's
+// instantiation; the product has no atomics).
+template <int DIST, int PT, int U, bool COUNT>
+__device__ __forceinline__ void produce_tile(float* __restrict__ S_lds, const SketchParams& P,
+                                             const int32_t* __restrict__ rows, int rb,
+                                             uint64_t grow0, int ptid,
+                                             unsigned long long* calls) {
+  uint32_t ncalls = 0;
+  const int d_b = P.d_b;
   if (DIST == DIST_RADEMACHER) {
-    const int rpc = P.d_b < 32 ? P.d_b : 32;  // S rows per chunk
-    for (int idx = tid; idx < total; idx += WGS) {
-      const int l = idx >> log2_cpr;
-      const int ch = idx & cmask;
-      const uint64_t j = (uint64_t)(uint32_t)rows[l];
-      const uint32_t bits = sign_bits32(P.seed, grow0 + (uint64_t)ch * 32u, j);
-      float4* dst = reinterpret_cast<float4*>(S_lds + l * P.ldS + ch * 32);
-      for (int t = 0; t < rpc; t += 4) {
-        float4 v;
-        v.x = (bits >> (t + 0)) & 1u ? -1.0f : 1.0f;
-        v.y = (bits >> (t + 1)) & 1u ? -1.0f : 1.0f;
-        v.z = (bits >> (t + 2)) & 1u ? -1.0f : 1.0f;
-        v.w = (bits >> (t + 3)) & 1u ? -1.0f : 1.0f;
-        dst[t >> 2] = v;
+    // one call per (row, 128-row group the tile touches): its four words give
+    // 128 consecutive S rows, bit b of word w being row 128 g + 32 w + b.
+    // Tile row t of group gi sits at bit position t + off - 128 gi.
+    const uint64_t g0 = grow0 >> 7;
+    const int off = (int)(grow0 & 127u);
+    const int ng = (off + d_b + 127) >> 7;
+    const int total = rb * ng;
+    for (int idx = ptid; idx < total; idx += PT) {
+      const int l = idx / ng;
+      const int gi = idx - l * ng;
+      const Words x = gen_words(P.seed, g0 + (uint64_t)gi, (uint64_t)(uint32_t)rows[l]);
+      ++ncalls;
+      float* row = S_lds + l * P.ldS;
+      const int t_lo = 128 * gi - off > 0 ? 128 * gi - off : 0;
+      const int t_hi = 128 * (gi + 1) - off < d_b ? 128 * (gi + 1) - off : d_b;
+      if (((off | d_b) & 3) == 0) {
+        // four rows per store: sign bit into the sign of 1.0f
+        for (int t = t_lo; t < t_hi; t += 4) {
+          const int bp = t + off - 128 * gi;
+          const uint32_t w = word_at(x, bp >> 5) >> (bp & 31);
+          float4 v;
+          v.x = __uint_as_float(((w << 31) & 0x80000000u) | 0x3F800000u);
+          v.y = __uint_as_float(((w << 30) & 0x80000000u) | 0x3F800000u);
+          v.z = __uint_as_float(((w << 29) & 0x80000000u) | 0x3F800000u);
+          v.w = __uint_as_float(((w << 28) & 0x80000000u) | 0x3F800000u);
+          *reinterpret_cast<float4*>(row + t) = v;
+        }
+      } else {
+        for (int t = t_lo; t < t_hi; ++t) {
+          const int bp = t + off - 128 * gi;
+          const uint32_t w = word_at(x, bp >> 5) >> (bp & 31);
+          row[t] = __uint_as_float(((w << 31) & 0x80000000u) | 0x3F800000u);
+        }
       }
     }
   } else if ((grow0 & 3u) == 0) {
-    // aligned: chunk ch of row l is exactly generator group grow0/4 + ch
-    // U generator calls in flight per thread
+    // aligned: chunk ch of row l is generator group grow0/4 + ch
     const uint64_t g0 = grow0 >> 2;
-    for (int base = tid; base < total; base += U * WGS) {
+    const int lg = P.log2_cpr;
+    const int cmask = (1 << lg) - 1;
+    const int total = rb << lg;
+    for (int base = ptid; base < total; base += U * PT) {
       int32_t jr[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int idx = base + u * WGS;
-        jr[u] = idx < total ? rows[idx >> log2_cpr] : 0;
+        const int idx = base + u * PT;
+        jr[u] = idx < total ? rows[idx >> lg] : 0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int idx = base + u * WGS;
+        const int idx = base + u * PT;
         if (idx < total) {
-          const int l = idx >> log2_cpr;
-          const int ch = idx & cmask;
           float v[4];
-          quad_values<DIST>(P.seed, g0 + (uint64_t)ch, (uint64_t)(uint32_t)jr[u], v);
-          *reinterpret_cast<float4*>(S_lds + l * P.ldS + ch * 4) =
+          quad_values<DIST>(P.seed, g0 + (uint64_t)(idx & cmask), (uint64_t)(uint32_t)jr[u], v);
+          ++ncalls;
+          *reinterpret_cast<float4*>(S_lds + (idx >> lg) * P.ldS + (idx & cmask) * 4) =
               make_float4(v[0], v[1], v[2], v[3]);
         }
       }
     }
   } else {
-    // misaligned tile start: the tile's rows touch d_b/4 + 1 generator
-    // groups; each group is generated once and its rows inside the tile kept
-    const int ng = (P.d_b >> 2) + 1;
+    // misaligned tile start: d_b/4 + 1 generator groups per row, each
+    // generated once, its rows inside the tile kept
+    const int ng = (d_b >> 2) + 1;
     const uint64_t g0 = grow0 >> 2;
     const int shift = (int)(grow0 & 3u);
     const int tot = rb * ng;
-    for (int idx = tid; idx < tot; idx += WGS) {
+    for (int idx = ptid; idx < tot; idx += PT) {
       const int l = idx / ng;
       const int gi = idx - l * ng;
       float v[4];
       quad_values<DIST>(P.seed, g0 + (uint64_t)gi, (uint64_t)(uint32_t)rows[l], v);
+      ++ncalls;
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
-        const int t = gi * 4 + w - shift;  // row inside the tile
-        if (t >= 0 && t < P.d_b) S_lds[l * P.ldS + t] = v[w];
+        const int t = gi * 4 + w - shift;
+        if (t >= 0 && t < d_b) S_lds[l * P.ldS + t] = v[w];
       }
     }
   }
+  if (COUNT && ncalls) atomicAdd(calls, (unsigned long long)ncalls);
 }
 
 // DL consecutive S values of one tile row (rows start 16-byte aligned).
@@ -174,7 +198,7 @@ __device__ __forceinline__ void stage_entries(uint2* __restrict__ E_lds,
 // FOLD: the columns are virtual (P.vbase) and the unit adds each real
 // column's pieces before writing (a separate instantiation, so the plain
 // kernels keep their own register allocation)
-template <int DIST, int DL, int Q, int CS, int WGS, bool FOLD = false>
+template <int DIST, int DL, int Q, int CS, int WGS, bool FOLD = false, bool COUNT = false>
 __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, int tile, int crange,
                                             unsigned char* __restrict__ smem) {
   // LDS: S tile (m_b x ldS floats) | entries (e_max + 2) | segment bounds of
@@ -264,7 +288,9 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
       int32_t s1 = (blk_end - s0a < P.e_max) ? blk_end : s0a + P.e_max;
       stage_entries<WGS>(E_lds, P.ent, s0a, s1);
       // fewer generator calls in flight when the accumulators are many
-      fill_tile<DIST, WGS, (DL * CS >= 64 ? 2 : 4)>(S_lds, P, P.rowlist + row_beg, rb, grow0);
+      produce_tile<DIST, WGS, (DL * CS >= 64 ? 2 : 4), COUNT>(
+          S_lds, P, P.rowlist + row_beg, rb, grow0, tid,
+          reinterpret_cast<unsigned long long*>(const_cast<int64_t*>(&P.hdr->reserved[0])));
       bool first_pass = true;
       while (true) {
         __builtin_amdgcn_s_waitcnt(0);
@@ -362,14 +388,14 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
   }
 }
 
-template <int DIST, int DL, int Q, int CS, int WGS, bool FOLD = false>
+template <int DIST, int DL, int Q, int CS, int WGS, bool FOLD = false, bool COUNT = false>
 __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(4))) void k_sketch(
     SketchParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int bid = blockIdx.x;
   const int split = bid % P.splits;
   const int rest = bid / P.splits;
-  sketch_unit<DIST, DL, Q, CS, WGS, FOLD>(P, split, rest % P.tiles, rest / P.tiles, smem);
+  sketch_unit<DIST, DL, Q, CS, WGS, FOLD, COUNT>(P, split, rest % P.tiles, rest / P.tiles, smem);
 }
 
 // A_hat[i, k] = sum over sparse slices of the virtual columns of k, then the

@@ -382,3 +382,47 @@ def test_unaligned_row_indices(B, oracle_lib):
         assert np.array_equal(a, s), dist
         assert_parity(s.astype(np.float64), run_oracle(oracle_lib, A, 150, dist, 9), A, dist,
                       "unaligned")
+
+
+# ------------------------------------------------- generator call count
+def expected_calls(R, row0, d, d_b, e):
+    """Generator calls of a sketch whose every row block regenerates its S
+    tiles once: each nonempty row of A is generated once per S-row tile, one
+    call per group of e S rows (e = 128 for +-1, 4 otherwise) that the tile's
+    rows [row0 + t d_b, row0 + (t + 1) d_b) touch."""
+    total = 0
+    for t in range(-(-d // d_b)):
+        g0 = row0 + t * d_b
+        total += (g0 + d_b - 1) // e - g0 // e + 1
+    return R * total
+
+
+@pytest.mark.parametrize("dist", DISTS)
+@pytest.mark.parametrize("variant,tile_rows", [(3, 32), (5, 64), (5, 128), (2, 16), (6, 64)])
+@pytest.mark.parametrize("row0", [0, 100, 3])
+def test_generator_call_count(B, oracle_lib, dist, variant, tile_rows, row0):
+    # the S tile of a row block is generated once and reused by every column:
+    # the call count is exactly R x (generator groups per tile), summed over
+    # the tiles (no dense blocks here)
+    import torch
+    m, n, d = 7001, 77, 203
+    A = inputs.uniform_positions(m, n, 9000, 5, "normal", np.float64)
+    R = int(np.unique(A.rowidx).size)
+    tune = {"variant": variant, "tile_rows": tile_rows, "rows_per_block": 97,
+            "dense_min_pct": 101, "count_rng": 1}
+    print(f"call count {dist} variant={variant} d_b={tile_rows} row0={row0}", flush=True)
+    dA = B.DeviceCsc.from_host(A)
+    ws = B.alloc_workspace(B.workspace_bytes(dA, d, dist, tune=tune))
+    out = torch.empty((n, d), dtype=torch.float32, device="cuda")
+    B.sketch_into(dA, d, dist, 42, out, ws, row0=row0, tune=tune)
+    calls = B.sketch_rng_calls(ws)
+    e = 128 if dist == "rademacher" else 4
+    assert calls == expected_calls(R, row0, d, tile_rows, e), (calls, R)
+    got = out.t().cpu().numpy().astype(np.float64)
+    assert_parity(got, run_oracle(oracle_lib, A, d, dist, 42, row0=row0), A, dist, "counted")
+    # the product instantiation gives the same A_hat bit for bit
+    plain = dict(tune, count_rng=0)
+    out2 = torch.empty_like(out)
+    B.sketch_into(dA, d, dist, 42, out2, ws, row0=row0, tune=plain)
+    assert torch.equal(out, out2)
+    assert B.sketch_rng_calls(ws) == 0
