@@ -190,7 +190,7 @@ def bench_serving(args):
             reqs = srv.run(requests(args.serve_requests, arr, 7))
             st = S.latency_stats(reqs)
             st["peak_inflight"] = srv.peak_inflight
-            st["converged"] = sum(r.info["istop"] in (1, 2) for r in reqs)
+            st["converged"] = sum(bool(r.info) and r.info["istop"] in (1, 2) for r in reqs)
             row[name] = st
             print(f"[bench] rate {frac:.2f}x {name}: p50 {st['p50_ms']:.1f} ms, p99 "
                   f"{st['p99_ms']:.1f} ms, {st['solves_per_s']:.1f} solves/s",

@@ -176,9 +176,12 @@ sk_status sk_autotune(const sk_csc* A, int64_t d, int32_t dist, sk_tuning* out);
  * persistent launch per distribution runs every item's work units from a
  * longest-first list (the only shared state is one atomic work counter);
  * each item's result is bitwise the one sk_sketch gives with the tuning
- * sk_sketch_batched_plan reports for it.  prec must be SK_PREC_F32.
- * Asynchronous on hip_stream; per-item device validation status via
- * sk_sketch_batched_status. */
+ * sk_sketch_batched_plan reports for it.  prec SK_PREC_BF16 / SK_PREC_FP8
+ * (all items +-1, else SK_EUNSUPPORTED): items of density >= 1% (or the
+ * item's dense_min_pct) run as a dense contraction on the matrix cores with
+ * +-1 S exact in that format, in their own persistent launch; the others run
+ * the FP32 sparse kernel.  Asynchronous on hip_stream; per-item device
+ * validation status via sk_sketch_batched_status. */
 sk_status sk_sketch_batched_workspace(int32_t count, const sk_csc* A, const int64_t* d,
                                       const int32_t* dist, int32_t prec, const sk_tuning* tune,
                                       size_t* bytes);
@@ -247,7 +250,9 @@ typedef struct {
 /* Solver info; the first sizeof(sk_sap_info) bytes of an SAP workspace hold it
  * (device memory) from sk_sap_begin on.  istop follows LSQR's codes: 0 running,
  * 1 residual small, 2 normal-equation residual small, 3 condition limit,
- * 4-6 the same at machine precision, 7 iteration limit. */
+ * 4-6 the same at machine precision, 7 iteration limit; and 8: the sketch's
+ * device validation rejected A (done is set at once, no iteration runs and x
+ * is not meaningful; sk_sap_read_info returns the input error). */
 typedef struct {
   int32_t iterations, istop, done, iter_lim;
   double rnorm;   /* ||b - A x|| estimate               */

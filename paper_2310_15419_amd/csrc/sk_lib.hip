@@ -638,6 +638,17 @@ struct BatchPlan {
 
 int unit_kind(const Plan& P, int dist) { return P.mfma ? 2 + P.mfma : dist; }
 
+// compute units of the caller's current device (256 on MI355X when it cannot
+// be queried, e.g. planning on a host without a GPU)
+int current_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    return 256;
+  return cus;
+}
+
 constexpr int kBatchUnitsPerSlot = 8;  // work units per persistent workgroup, for balance
 
 sk_status batch_plan(int32_t count, const sk_csc* A, const int64_t* d, const int32_t* dist,
@@ -662,8 +673,7 @@ sk_status batch_plan(int32_t count, const sk_csc* A, const int64_t* d, const int
       return SK_EINVAL;
     total_cost += B.plans[i].cost;
   }
-  int cus = 256;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess) cus = 256;
+  const int cus = current_cus();
   const double unit = std::max(1.0, total_cost / ((double)cus * kBatchUnitsPerSlot));
   for (int i = 0; i < count; ++i) {
     const sk_tuning* t = tune ? &tune[i] : nullptr;
@@ -1213,8 +1223,7 @@ sk_status sk_sketch_batched(int32_t count, const sk_csc* A, const int64_t* d, co
   if ((s = run_inspector(d_items, count, Z, W, st)) != SK_OK) return s;
   if ((s = run_block_costs(d_items, count, Z, W, st)) != SK_OK) return s;
   // a7: one persistent launch per kind of work unit present
-  int cus = 256;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess) cus = 256;
+  const int cus = current_cus();
   int64_t first = 0;
   for (int kind = 0; kind < 5; ++kind) {
     if (B.units[kind] == 0) continue;
@@ -1436,6 +1445,7 @@ sk_status sk_sap_begin(const sk_csc* A, const double* b, const sk_sap_params* p,
   hipLaunchKernelGGL(k_lsqr_update<true>, dim3(1), dim3(1024), 0, st, n,
                      (const double*)(w + L.t2), (double*)(w + L.v), (double*)(w + L.w),
                      (double*)(w + L.y), state);
+  hipLaunchKernelGGL(k_lsqr_input_check, dim3(1), dim3(64), 0, st, state, skh);
   return launch_ok();
 }
 

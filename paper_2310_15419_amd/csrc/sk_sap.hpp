@@ -919,6 +919,18 @@ __global__ void k_gemv_upper_final(const double* __restrict__ Ri, int64_t ldi, i
   x[i] = s;
 }
 
+// LSQR stop code of a request whose A failed the sketch's device validation
+constexpr int32_t LSQR_ISTOP_INPUT = 8;
+
+// a request whose A failed validation stops before its first iteration (the
+// info prefix then tells an asynchronous reader without another call)
+__global__ void k_lsqr_input_check(LsqrState* __restrict__ st, const Header* __restrict__ skh) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && skh->status) {
+    st->istop = LSQR_ISTOP_INPUT;
+    st->done = 1;
+  }
+}
+
 __global__ void k_lsqr_set(LsqrState* __restrict__ st, double atol, double btol, double ctol,
                            int32_t iter_lim) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {

@@ -14,6 +14,12 @@ the same loop is the plain per-request path (one solve at a time).
 
 Every request's kernels depend only on its own data and tuning, so a result is
 the same alone and in the mix.
+
+A request that cannot be served fails alone: one whose arguments the library
+refuses, or whose footprint exceeds the whole budget, is rejected at arrival;
+one whose A fails the sketch's device validation stops before its first LSQR
+iteration (stop code 8).  Its ``error`` says why and its ``x`` stays None; the
+others are served as if it were not there.
 """
 from __future__ import annotations
 
@@ -39,6 +45,7 @@ class Request:
     done: float = math.nan
     x: object = None
     info: dict | None = None
+    error: str | None = None  # set when the request failed alone (x is None)
 
     @property
     def footprint(self) -> int:
@@ -86,11 +93,19 @@ class Server:
     def run(self, requests: list[Request], idle_sleep: float = 2e-5) -> list[Request]:
         """Serve the requests (sorted by arrival); returns them with timings."""
         torch = self.torch
+        servable = []
         for r in requests:
-            r.ws_bytes = B.SapSolve.workspace_bytes(r.A, r.params)
+            try:
+                r.ws_bytes = B.SapSolve.workspace_bytes(r.A, r.params)
+            except B.SketchError as e:
+                self._reject(r, f"refused by the library: {e}")
+                continue
             if r.footprint > self.budget:
-                raise ValueError(f"request {r.rid} needs {r.footprint} B, over the budget")
-        pending = sorted(requests, key=lambda r: r.arrival)
+                self._reject(r, f"needs {r.footprint} B of device memory, more than the "
+                                f"whole budget of {self.budget} B")
+                continue
+            servable.append(r)
+        pending = sorted(servable, key=lambda r: r.arrival)
         head = 0
         used = 0
         t0 = time.perf_counter()
@@ -103,17 +118,22 @@ class Server:
                 progressed = True
                 if s.phase == "iterate":
                     info = B.SapSolve.parse_info(bytes(s.info_host.numpy()))
-                    if info["done"]:
+                    if info["done"] and info["istop"] == ISTOP_INPUT:
+                        # A failed the device validation: no x to compute
+                        s.req.info = info
+                        s.req.error = "A failed the sketch's device validation"
+                        s.phase = "failed"
+                    elif info["done"]:
                         s.req.info = info
                         s.solve.finish(s.stream)
                         s.event.record(s.stream)
                         s.phase = "finish"
                     else:
                         self._enqueue_chunk(s)
-                else:  # finished
+                if s.phase in ("finish", "failed") and s.event.query():
                     r = s.req
                     r.done = time.perf_counter() - t0
-                    r.x = s.solve.x
+                    r.x = s.solve.x if s.phase == "finish" else None
                     used -= r.footprint
                     s.req, s.solve, s.phase = None, None, ""
                     active -= 1
@@ -147,16 +167,29 @@ class Server:
         torch.cuda.synchronize()
         return requests
 
+    @staticmethod
+    def _reject(r: Request, why: str):
+        r.error = why
+        r.admitted = r.done = r.arrival
+
+
+# LSQR stop code of a request whose A failed the sketch's device validation
+ISTOP_INPUT = 8
+
 
 def latency_stats(reqs: list[Request]) -> dict:
-    lat = np.array([r.latency for r in reqs])
-    t_first = min(r.arrival for r in reqs)
-    t_last = max(r.done for r in reqs)
-    return {"requests": len(reqs), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+    """Latency and throughput over the served requests (failed ones counted
+    apart)."""
+    ok = [r for r in reqs if r.error is None]
+    lat = np.array([r.latency for r in ok])
+    t_first = min(r.arrival for r in ok)
+    t_last = max(r.done for r in ok)
+    return {"requests": len(ok), "failed": len(reqs) - len(ok),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_ms": float(lat.mean() * 1e3),
-            "solves_per_s": len(reqs) / max(t_last - t_first, 1e-9),
-            "iterations_mean": float(np.mean([r.info["iterations"] for r in reqs]))}
+            "solves_per_s": len(ok) / max(t_last - t_first, 1e-9),
+            "iterations_mean": float(np.mean([r.info["iterations"] for r in ok]))}
 
 
 def poisson_arrivals(count: int, rate: float, seed: int) -> np.ndarray:

@@ -75,3 +75,44 @@ def test_admission_respects_budget(env):
     # in arrival order: nobody is admitted before an earlier request
     order = sorted(reqs, key=lambda r: r.admitted)
     assert [r.rid for r in order] == sorted(r.rid for r in reqs)
+
+
+def test_bad_requests_fail_alone(env):
+    # one request whose A has unsorted rows in a column (caught by the
+    # sketch's device validation) and one that needs more memory than the
+    # whole budget sit among good ones: each bad one fails with its own
+    # error, the server goes on, and the good results equal their alone runs
+    import torch
+    B, S = env
+    reqs = make_requests(B, S, 4, 21)
+    alone = [B.SapSolve(r.A, r.b, r.params).solve(chunk=4)[0].cpu().numpy()
+             for _, _, r in reqs]
+    A, b, _ = inputs.ls_request(777, 8_000, 40, dense_rows=80)
+    rows = A.rowidx.copy()
+    lo = A.colptr[5]
+    rows[lo], rows[lo + 1] = rows[lo + 1], rows[lo]
+    bad = B.DeviceCsc(A.m, A.n, torch.from_numpy(A.colptr).cuda(),
+                      torch.from_numpy(rows).cuda(), torch.from_numpy(A.vals).cuda())
+    malformed = S.Request(100, bad, torch.from_numpy(b).cuda(), B.sap_params(80, "gaussian", 5))
+    Ab, bb, _ = inputs.ls_request(778, 400_000, 150, dense_rows=300)
+    huge = S.Request(101, B.DeviceCsc.from_host(Ab), torch.from_numpy(bb).cuda(),
+                     B.sap_params(300, "rademacher", 6))
+    mix = [r for _, _, r in reqs]
+    mix.insert(1, malformed)
+    mix.insert(3, huge)
+    for k, r in enumerate(mix):
+        r.arrival = 0.001 * k
+        r.ws_bytes = B.SapSolve.workspace_bytes(r.A, r.params)
+    budget = int(max(r.footprint for r in mix if r is not huge) * 1.5)
+    assert huge.footprint > budget, (huge.footprint, budget)
+    server = S.Server(hbm_budget=budget, slots=3, chunk=4)
+    print("mix with a malformed and an over-budget request", flush=True)
+    server.run(mix)
+    assert malformed.error and "validation" in malformed.error and malformed.x is None
+    assert malformed.info["istop"] == S.ISTOP_INPUT and malformed.info["iterations"] == 0
+    assert huge.error and "budget" in huge.error and huge.x is None
+    for (_, _, r), xa in zip(reqs, alone):
+        assert r.error is None and r.info["istop"] in (1, 2)
+        assert np.array_equal(r.x.cpu().numpy(), xa), r.rid
+    st = S.latency_stats(mix)
+    assert st["requests"] == len(reqs) and st["failed"] == 2

@@ -102,8 +102,13 @@ def test_batched_plan_host_only():
     assert len({c.variant for c in chosen}) == 1
     for c in chosen:
         assert c.rows_per_block >= 1 and c.splits >= 1 and c.tile_rows >= 1
-    # precision path is single-sketch only; bad count; bad d
+    # BF16/FP8 operands hold only +-1 S exactly: a batch with (-1,1) or
+    # Gaussian items is refused, an all-+-1 batch is planned; bad count; bad d
     assert lib.sk_sketch_batched_workspace(n, mats, ds, dist, 1, None, ctypes.byref(out)) == -6
+    pm1 = (ctypes.c_int32 * n)(*([0] * n))
+    for prec in (1, 2):
+        assert lib.sk_sketch_batched_workspace(n, mats, ds, pm1, prec, None,
+                                               ctypes.byref(out)) == 0
     assert lib.sk_sketch_batched_workspace(0, mats, ds, dist, 0, None, ctypes.byref(out)) == -1
     ds[2] = 0
     assert lib.sk_sketch_batched_workspace(n, mats, ds, dist, 0, None, ctypes.byref(out)) == -1
