@@ -102,6 +102,16 @@ typedef struct {
                              instantiation, which also adds up its generator
                              calls (read with sk_sketch_rng_calls; same
                              A_hat; for checks, not for speed)                */
+  int32_t rng_mode;       /* generator of the distribution-cost ablation
+                             (Sec. III-A's cost h of a random number; Sec. V's
+                             "junk" generator): 0 = Philox4x32-10 (the
+                             product); 1 = a junk counter hash (NOT random:
+                             times the sketch without the generator's cost;
+                             A_hat is not S A); 3 = (-1,1) only: S kept as
+                             the integers 2^24 s, A_hat scaled by 2^-24 at the
+                             end (the integer-scaling trick; same A_hat as 0).
+                             Modes 1 and 3 run on the kernel shapes 3 and 6
+                             without dense blocks; else SK_EUNSUPPORTED.    */
 } sk_tuning;
 
 /* Human-readable name of a status code (static storage). */
@@ -145,6 +155,27 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
 sk_status sk_sketch_noalloc(const sk_csc* A, int64_t row0, int64_t d, int32_t dist,
                             uint64_t seed, int32_t prec, const sk_tuning* tune, float* Ahat,
                             int64_t ld, void* hip_stream);
+
+/* The sketch with S given explicitly instead of generated (the stored-S
+ * sparse product of the distribution-cost ablation: what regenerating S
+ * saves against reading it from memory): A_hat[0:d, 0:n] = S A with S
+ * device FP32, column-major d x m, leading dimension lds >= d rounded up to a
+ * multiple of 128 (rows past d are read but never used), 16-byte aligned.
+ * Same workspace as sk_sketch(A, d, SK_UNIFORM, SK_PREC_F32, tune), same
+ * kernel shapes as sk_tuning.rng_mode.  Asynchronous on hip_stream. */
+sk_status sk_sketch_stored(const sk_csc* A, int64_t d, const float* S, int64_t lds,
+                           const sk_tuning* tune, float* Ahat, int64_t ld, void* ws,
+                           size_t ws_bytes, void* hip_stream);
+
+/* Generator throughput, for measuring the cost of one call (the h of Sec.
+ * III-A): blocks x 256 threads each make `calls` calls of the generator
+ * (gen 0 = Philox4x32-10, 1 = the junk hash of sk_tuning.rng_mode) with the
+ * transform of `dist` (+-1: the raw words), for counters (call index, thread
+ * index), fold all outputs of a thread into one word and write it to
+ * sink[thread] (device, blocks * 256 words).  Asynchronous on hip_stream; the
+ * caller times it. */
+sk_status sk_rng_throughput(int32_t dist, int32_t gen, int64_t calls, int32_t blocks,
+                            uint64_t seed, uint32_t* sink, void* hip_stream);
 
 /* Status of the last sk_sketch that used this workspace (synchronises
  * hip_stream).  Also reports the inspector's counts when the pointers are

@@ -32,7 +32,7 @@ class SkTuning(ctypes.Structure):
                 ("variant", ctypes.c_int32), ("dense_min_pct", ctypes.c_int32),
                 ("phases", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("col_split", ctypes.c_int32), ("row_pad", ctypes.c_int32),
-                ("count_rng", ctypes.c_int32)]
+                ("count_rng", ctypes.c_int32), ("rng_mode", ctypes.c_int32)]
 
 
 class SapParams(ctypes.Structure):
@@ -80,6 +80,9 @@ def lib():
                                         vp]
         L.sk_sketch_status.argtypes = [vp, vp, P(i64), P(i64)]
         L.sk_sketch_rng_calls.argtypes = [vp, vp, P(ctypes.c_uint64)]
+        L.sk_sketch_stored.argtypes = [P(SkCsc), i64, vp, i64, P(SkTuning), vp, i64, vp,
+                                       ctypes.c_size_t, vp]
+        L.sk_rng_throughput.argtypes = [i32, i32, i64, i32, u64, vp, vp]
         L.sk_materialize_s.argtypes = [i64, i64, i64, i64, i32, u64, vp, i64, vp]
         L.sk_autotune.argtypes = [P(SkCsc), i64, i32, P(SkTuning)]
         L.sk_sketch_batched_workspace.argtypes = [i32, P(SkCsc), P(i64), P(i32), i32, P(SkTuning),
@@ -101,7 +104,7 @@ def lib():
         L.sk_sap_read_info.argtypes = [P(SkCsc), P(SapParams), vp, ctypes.c_size_t, vp,
                                        P(SapInfo)]
         for name in ("sk_sketch_workspace", "sk_sketch", "sk_sketch_noalloc", "sk_sketch_status",
-                     "sk_sketch_rng_calls",
+                     "sk_sketch_rng_calls", "sk_sketch_stored", "sk_rng_throughput",
                      "sk_materialize_s",
                      "sk_autotune", "sk_sketch_batched_workspace", "sk_sketch_batched",
                      "sk_sketch_batched_plan", "sk_sketch_batched_status", "sk_qr_f64_workspace",
@@ -140,7 +143,7 @@ def _tuning(tune):
                  int(tune.get("variant", 0)), int(tune.get("dense_min_pct", 0)),
                  int(tune.get("phases", 0)), int(tune.get("tile_rows", 0)),
                  int(tune.get("col_split", 0)), int(tune.get("row_pad", 0)),
-                 int(tune.get("count_rng", 0)))
+                 int(tune.get("count_rng", 0)), int(tune.get("rng_mode", 0)))
     return ctypes.byref(t)
 
 
@@ -229,6 +232,23 @@ def sketch(A: DeviceCsc, d: int, dist, seed: int, row0: int = 0, prec: int = PRE
         st = sketch_status(ws, stream)
         _check(st["status"], "sk_sketch (device validation)")
     return out.t()
+
+
+def sketch_stored_into(A: DeviceCsc, S, out, ws, tune=None, stream=None) -> None:
+    """sk_sketch_stored: A_hat = S A with S given (a torch FP32 tensor of shape
+    (m, lds), i.e. column-major d x m with leading dimension lds)."""
+    c = A.c_struct()
+    d = out.shape[1]
+    _check(lib().sk_sketch_stored(ctypes.byref(c), d, S.data_ptr(), S.shape[1], _tuning(tune),
+                                  out.data_ptr(), d, ws.data_ptr(), ws.numel(), _stream(stream)),
+           "sk_sketch_stored")
+
+
+def rng_throughput(dist, gen: int, calls: int, blocks: int, seed: int, sink,
+                   stream=None) -> None:
+    """sk_rng_throughput into a device uint32/int32 tensor of blocks * 256 words."""
+    _check(lib().sk_rng_throughput(_dist(dist), gen, calls, blocks, seed, sink.data_ptr(),
+                                   _stream(stream)), "sk_rng_throughput")
 
 
 def sketch_rng_calls(ws, stream=None) -> int:

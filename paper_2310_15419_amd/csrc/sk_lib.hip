@@ -80,6 +80,39 @@ const Variant kVariants[] = {
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
+// Generator-ablation forms of two kernel shapes (index 2: the shape of
+// columns in the thousands; index 5: a few hundred columns): junk generator
+// per distribution, S read from memory, and the (-1,1) scaled integers.
+struct AblationKernels {
+  int variant;
+  SketchKernel junk[3];
+  SketchKernel stored;
+  SketchKernel scaled;
+};
+
+#define SK_ABLATION(V, DL, Q, CS, WGS)                                                        \
+  AblationKernels {                                                                          \
+    V,                                                                                       \
+        {k_sketch<DIST_RADEMACHER, DL, Q, CS, WGS, false, false, GEN_JUNK>,                  \
+         k_sketch<DIST_UNIFORM, DL, Q, CS, WGS, false, false, GEN_JUNK>,                     \
+         k_sketch<DIST_GAUSSIAN, DL, Q, CS, WGS, false, false, GEN_JUNK>},                   \
+        k_sketch<DIST_UNIFORM, DL, Q, CS, WGS, false, false, GEN_STORED>,                    \
+        k_sketch<DIST_UNIFORM, DL, Q, CS, WGS, false, false, GEN_SCALED>                     \
+  }
+
+const AblationKernels kAblation[] = {SK_ABLATION(2, 8, 4, 8, 1024), SK_ABLATION(5, 4, 4, 2, 1024)};
+
+// the ablation kernel of a plan's shape for a generator mode (null: none)
+SketchKernel ablation_kernel(int variant, int gen, int dist) {
+  for (const AblationKernels& a : kAblation) {
+    if (a.variant != variant) continue;
+    if (gen == GEN_JUNK) return a.junk[dist];
+    if (gen == GEN_STORED) return a.stored;
+    if (gen == GEN_SCALED && dist == DIST_UNIFORM) return a.scaled;
+  }
+  return nullptr;
+}
+
 struct Plan {
   int variant;  // index into kVariants
   int32_t m_b, e_max, d_b, ldS, dt, cg, tiles, splits, col_per_wg, ncr, log2_cpr;
@@ -893,40 +926,14 @@ sk_status scratch_for_current_device(void** out) {
 }
 }  // namespace
 
-extern "C" {
-
-const char* sk_status_string(int s) {
-  switch (s) {
-    case SK_OK: return "ok";
-    case SK_EINVAL: return "invalid argument";
-    case SK_EUNSORTED: return "row indices not strictly increasing within a column";
-    case SK_ERANGE: return "row index out of range";
-    case SK_EWORKSPACE: return "workspace missing or too small";
-    case SK_EHIP: return "HIP runtime error";
-    case SK_EUNSUPPORTED: return "unsupported request";
-    case SK_ECOLPTR: return "column pointers malformed";
-    default: return "unknown status";
-  }
-}
-
-int sk_variant_count(void) { return kNumVariants; }
-
-sk_status sk_sketch_workspace(const sk_csc* A, int64_t d, int32_t dist, int32_t prec,
-                              const sk_tuning* tune, size_t* bytes) {
-  if (!bytes) return SK_EINVAL;
-  sk_status s = check_csc(A);
-  if (s != SK_OK) return s;
-  if (d < 1 || dist < 0 || dist > 2 || prec < 0 || prec > 2) return SK_EINVAL;
-  if (prec != SK_PREC_F32 && dist != SK_RADEMACHER) return SK_EUNSUPPORTED;
-  Plan P;
-  if (!plan_any(A->m, A->n, A->nnz, d, dist, prec, tune, P)) return SK_EINVAL;
-  *bytes = (size_t)layout_for(A->m, A->n, A->nnz, d, P).total;
-  return SK_OK;
-}
-
-sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint64_t seed,
-                    int32_t prec, const sk_tuning* tune, float* Ahat, int64_t ld, void* ws,
-                    size_t ws_bytes, void* hip_stream) {
+namespace {
+// The sketch with generator mode `gen` (GEN_PHILOX for the product; the
+// others are the distribution-cost ablation's, on the shapes that have them,
+// without the dense path or the folded virtual columns).
+sk_status sketch_impl(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint64_t seed,
+                      int32_t prec, const sk_tuning* tune, float* Ahat, int64_t ld, void* ws,
+                      size_t ws_bytes, void* hip_stream, int gen, const float* s_pre,
+                      int64_t s_ld) {
   sk_status s = check_csc(A);
   if (s != SK_OK) return s;
   if (d < 1 || row0 < 0 || !Ahat || ld < d || dist < 0 || dist > 2) return SK_EINVAL;
@@ -935,6 +942,13 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
   Plan P;
   if (!plan_any(A->m, A->n, A->nnz, d, dist, prec, tune, P)) return SK_EINVAL;
   if ((int64_t)(P.nb_max + 1) * P.nv >= INT32_MAX) return SK_EUNSUPPORTED;
+  if (gen != GEN_PHILOX) {
+    if (P.mfma || !ablation_kernel(P.variant, gen, dist) || (tune && tune->count_rng))
+      return SK_EUNSUPPORTED;
+    P.dense_pct = 0;
+    P.kd_max = 0;
+    P.slices = P.splits;
+  }
   const Layout L = layout_for(A->m, A->n, A->nnz, d, P);
   if (!ws || ws_bytes < (size_t)L.total) return SK_EWORKSPACE;
   hipStream_t st = (hipStream_t)hip_stream;
@@ -998,12 +1012,14 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
   // a3 + a4: S tiles and sparse accumulation (or the whole contraction on
   // the matrix cores for +-1 S in BF16/FP8)
   SketchParams K = make_params(P, I, d, row0, seed);
+  K.s_pre = s_pre;
+  K.s_ld = s_ld;
   K.dflag = P.dense_pct ? dflag : nullptr;
   // virtual columns: added in the kernel (then it writes the n real
   // columns) or in the reduction
   // the call-counting instantiation leaves virtual columns to the reduction
   const bool counting = tune && tune->count_rng && !P.mfma;
-  const bool fold = !counting && I.vbase != nullptr && folds_virtual(P, n);
+  const bool fold = !counting && gen == GEN_PHILOX && I.vbase != nullptr && folds_virtual(P, n);
   if (fold) { K.vbase = I.vbase; K.nreal = n; }
   const int64_t wcols = fold ? n : nv;  // columns of one partial slice
   const bool staged = P.slices > 1 || wcols != n;  // partials, then the reduction
@@ -1028,7 +1044,10 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
     }
   } else {
     const Variant& V = kVariants[P.variant];
-    SketchKernel kern = counting ? V.kc[dist] : (fold ? V.kf[dist] : V.k[dist]);
+    SketchKernel kern = gen != GEN_PHILOX ? ablation_kernel(P.variant, gen, dist)
+                        : counting        ? V.kc[dist]
+                        : fold            ? V.kf[dist]
+                                          : V.k[dist];
     if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)P.lds) != hipSuccess)
       return SK_EHIP;
@@ -1058,6 +1077,72 @@ sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint
     hipLaunchKernelGGL(k_reduce_virtual, dim3(blocks_for(d * n, 256)), dim3(256), 0, st, part,
                        P.splits, d, n, wcols, fold ? nullptr : I.vbase,
                        P.dense_pct ? part + (int64_t)P.splits * d * wcols : nullptr, Ahat, ld);
+  return launch_ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sk_status_string(int s) {
+  switch (s) {
+    case SK_OK: return "ok";
+    case SK_EINVAL: return "invalid argument";
+    case SK_EUNSORTED: return "row indices not strictly increasing within a column";
+    case SK_ERANGE: return "row index out of range";
+    case SK_EWORKSPACE: return "workspace missing or too small";
+    case SK_EHIP: return "HIP runtime error";
+    case SK_EUNSUPPORTED: return "unsupported request";
+    case SK_ECOLPTR: return "column pointers malformed";
+    default: return "unknown status";
+  }
+}
+
+int sk_variant_count(void) { return kNumVariants; }
+
+sk_status sk_sketch_workspace(const sk_csc* A, int64_t d, int32_t dist, int32_t prec,
+                              const sk_tuning* tune, size_t* bytes) {
+  if (!bytes) return SK_EINVAL;
+  sk_status s = check_csc(A);
+  if (s != SK_OK) return s;
+  if (d < 1 || dist < 0 || dist > 2 || prec < 0 || prec > 2) return SK_EINVAL;
+  if (prec != SK_PREC_F32 && dist != SK_RADEMACHER) return SK_EUNSUPPORTED;
+  Plan P;
+  if (!plan_any(A->m, A->n, A->nnz, d, dist, prec, tune, P)) return SK_EINVAL;
+  *bytes = (size_t)layout_for(A->m, A->n, A->nnz, d, P).total;
+  return SK_OK;
+}
+
+sk_status sk_sketch(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint64_t seed,
+                    int32_t prec, const sk_tuning* tune, float* Ahat, int64_t ld, void* ws,
+                    size_t ws_bytes, void* hip_stream) {
+  return sketch_impl(A, row0, d, dist, seed, prec, tune, Ahat, ld, ws, ws_bytes, hip_stream,
+                     tune ? tune->rng_mode : GEN_PHILOX, nullptr, 0);
+}
+
+sk_status sk_sketch_stored(const sk_csc* A, int64_t d, const float* S, int64_t lds,
+                           const sk_tuning* tune, float* Ahat, int64_t ld, void* ws,
+                           size_t ws_bytes, void* hip_stream) {
+  if (!S || d < 1 || lds < (d + 127) / 128 * 128 || (reinterpret_cast<uintptr_t>(S) & 15))
+    return SK_EINVAL;
+  if (tune && tune->rng_mode) return SK_EINVAL;
+  return sketch_impl(A, 0, d, SK_UNIFORM, 0, SK_PREC_F32, tune, Ahat, ld, ws, ws_bytes,
+                     hip_stream, GEN_STORED, S, lds);
+}
+
+sk_status sk_rng_throughput(int32_t dist, int32_t gen, int64_t calls, int32_t blocks,
+                            uint64_t seed, uint32_t* sink, void* hip_stream) {
+  if (dist < 0 || dist > 2 || (gen != GEN_PHILOX && gen != GEN_JUNK) || calls < 1 ||
+      blocks < 1 || !sink)
+    return SK_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  using RK = void (*)(int64_t, uint64_t, uint32_t*);
+  const RK table[2][3] = {
+      {k_rng_throughput<DIST_RADEMACHER, GEN_PHILOX>, k_rng_throughput<DIST_UNIFORM, GEN_PHILOX>,
+       k_rng_throughput<DIST_GAUSSIAN, GEN_PHILOX>},
+      {k_rng_throughput<DIST_RADEMACHER, GEN_JUNK>, k_rng_throughput<DIST_UNIFORM, GEN_JUNK>,
+       k_rng_throughput<DIST_GAUSSIAN, GEN_JUNK>}};
+  hipLaunchKernelGGL(table[gen][dist], dim3(blocks), dim3(256), 0, st, calls, seed, sink);
   return launch_ok();
 }
 

@@ -194,12 +194,48 @@ __host__ __device__ __forceinline__ void box_muller(uint32_t we, uint32_t wo, fl
   z1 = r * float_of(st_bits);
 }
 
+// ------------------------------------------- distribution-cost ablation
+// Generator modes of the ablation of the paper's cost model (Sec. III-A: the
+// cost h of one random number; Sec. V: the sketch with a "junk" generator):
+//   GEN_PHILOX -- the product generator;
+//   GEN_JUNK   -- a counter hash of one multiply-add and three xors per call,
+//                 NOT a usable random source: it only measures the sketch
+//                 without the generator's cost;
+//   GEN_STORED -- S read from memory (a materialised S, the stored-S SpMM);
+//   GEN_SCALED -- (-1,1) only: S kept as the odd integers (2t + 1) of the
+//                 uniform transform, A_hat scaled by 2^-24 once at the end
+//                 (the paper's (S f)(A / f) integer-scaling trick; every FP32
+//                 rounding scales exactly, so A_hat is unchanged).
+enum : int { GEN_PHILOX = 0, GEN_JUNK = 1, GEN_STORED = 2, GEN_SCALED = 3 };
+
+__host__ __device__ __forceinline__ Words junk_words(uint64_t g, uint64_t j) {
+  const uint32_t b = (uint32_t)j * 0x9E3779B9u + (uint32_t)g;
+  return Words{b, b ^ 0x6C8E9CF5u, b ^ 0xB5297A4Du, b ^ 0x1B56C4E9u};
+}
+
+template <int GEN>
+__host__ __device__ __forceinline__ Words words_of(uint64_t seed, uint64_t g, uint64_t j) {
+  if (GEN == GEN_JUNK) return junk_words(g, j);
+  return gen_words(seed, g, j);
+}
+
+// 2^24 times the uniform value of word w: the odd integer 2t + 1 with
+// t = (int32)w >> 8 (bit 7 of w is the low bit of w >> 7, replaced by 1)
+__host__ __device__ __forceinline__ float uniform_scaled_of(uint32_t w) {
+  return (float)((((int32_t)w) >> 7) | 1);
+}
+
 // Four consecutive S rows 4g..4g+3 of column j (uniform or Gaussian).
-template <int DIST>
+template <int DIST, int GEN = GEN_PHILOX>
 __host__ __device__ __forceinline__ void quad_values(uint64_t seed, uint64_t g, uint64_t j,
                                                      float v[4]) {
-  const Words x = gen_words(seed, g, j);
-  if (DIST == DIST_UNIFORM) {
+  const Words x = words_of<GEN>(seed, g, j);
+  if (DIST == DIST_UNIFORM && GEN == GEN_SCALED) {
+    v[0] = uniform_scaled_of(x.x0);
+    v[1] = uniform_scaled_of(x.x1);
+    v[2] = uniform_scaled_of(x.x2);
+    v[3] = uniform_scaled_of(x.x3);
+  } else if (DIST == DIST_UNIFORM) {
     v[0] = uniform_of(x.x0);
     v[1] = uniform_of(x.x1);
     v[2] = uniform_of(x.x2);

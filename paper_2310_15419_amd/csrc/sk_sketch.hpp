@@ -56,6 +56,10 @@ struct SketchParams {
   // (nreal columns); null: out holds the n (virtual) columns
   const int32_t* vbase;
   int64_t nreal;
+  // GEN_STORED only: S itself, column-major with leading dimension s_ld
+  // (S(i, j) at s_pre[i + j * s_ld]; s_ld and the address multiples of 4)
+  const float* s_pre;
+  int64_t s_ld;
 };
 
 // ---------------------------------------------------------------- S tile
@@ -63,7 +67,7 @@ struct SketchParams {
 // threads ptid = 0 .. PT-1, U generator calls in flight per thread.  COUNT:
 // add the number of generator calls made to *calls (the call-count check's
 // instantiation; the product has no atomics).
-template <int DIST, int PT, int U, bool COUNT>
+template <int DIST, int PT, int U, bool COUNT, int GEN = GEN_PHILOX>
 __device__ __forceinline__ void produce_tile(float* __restrict__ S_lds, const SketchParams& P,
                                              const int32_t* __restrict__ rows, int rb,
                                              uint64_t grow0, int ptid,
@@ -81,7 +85,7 @@ __device__ __forceinline__ void produce_tile(float* __restrict__ S_lds, const Sk
     for (int idx = ptid; idx < total; idx += PT) {
       const int l = idx / ng;
       const int gi = idx - l * ng;
-      const Words x = gen_words(P.seed, g0 + (uint64_t)gi, (uint64_t)(uint32_t)rows[l]);
+      const Words x = words_of<GEN>(P.seed, g0 + (uint64_t)gi, (uint64_t)(uint32_t)rows[l]);
       ++ncalls;
       float* row = S_lds + l * P.ldS;
       const int t_lo = 128 * gi - off > 0 ? 128 * gi - off : 0;
@@ -123,11 +127,18 @@ __device__ __forceinline__ void produce_tile(float* __restrict__ S_lds, const Sk
       for (int u = 0; u < U; ++u) {
         const int idx = base + u * PT;
         if (idx < total) {
-          float v[4];
-          quad_values<DIST>(P.seed, g0 + (uint64_t)(idx & cmask), (uint64_t)(uint32_t)jr[u], v);
+          float4 v4;
+          if (GEN == GEN_STORED) {
+            v4 = *reinterpret_cast<const float4*>(P.s_pre + (int64_t)(uint32_t)jr[u] * P.s_ld +
+                                                  (int64_t)grow0 + (idx & cmask) * 4);
+          } else {
+            float v[4];
+            quad_values<DIST, GEN>(P.seed, g0 + (uint64_t)(idx & cmask),
+                                   (uint64_t)(uint32_t)jr[u], v);
+            v4 = make_float4(v[0], v[1], v[2], v[3]);
+          }
           ++ncalls;
-          *reinterpret_cast<float4*>(S_lds + (idx >> lg) * P.ldS + (idx & cmask) * 4) =
-              make_float4(v[0], v[1], v[2], v[3]);
+          *reinterpret_cast<float4*>(S_lds + (idx >> lg) * P.ldS + (idx & cmask) * 4) = v4;
         }
       }
     }
@@ -142,7 +153,16 @@ __device__ __forceinline__ void produce_tile(float* __restrict__ S_lds, const Sk
       const int l = idx / ng;
       const int gi = idx - l * ng;
       float v[4];
-      quad_values<DIST>(P.seed, g0 + (uint64_t)gi, (uint64_t)(uint32_t)rows[l], v);
+      if (GEN == GEN_STORED) {
+        const float* col = P.s_pre + (int64_t)(uint32_t)rows[l] * P.s_ld;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const int64_t i = (int64_t)(g0 + (uint64_t)gi) * 4 + w;
+          v[w] = i >= (int64_t)grow0 && i < (int64_t)grow0 + d_b ? col[i] : 0.0f;
+        }
+      } else {
+        quad_values<DIST, GEN>(P.seed, g0 + (uint64_t)gi, (uint64_t)(uint32_t)rows[l], v);
+      }
       ++ncalls;
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
@@ -198,7 +218,8 @@ __device__ __forceinline__ void stage_entries(uint2* __restrict__ E_lds,
 // FOLD: the columns are virtual (P.vbase) and the unit adds each real
 // column's pieces before writing (a separate instantiation, so the plain
 // kernels keep their own register allocation)
-template <int DIST, int DL, int Q, int CS, int WGS, bool FOLD = false, bool COUNT = false>
+template <int DIST, int DL, int Q, int CS, int WGS, bool FOLD = false, bool COUNT = false,
+          int GEN = GEN_PHILOX>
 __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, int tile, int crange,
                                             unsigned char* __restrict__ smem) {
   // LDS: S tile (m_b x ldS floats) | entries (e_max + 2) | segment bounds of
@@ -288,7 +309,7 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
       int32_t s1 = (blk_end - s0a < P.e_max) ? blk_end : s0a + P.e_max;
       stage_entries<WGS>(E_lds, P.ent, s0a, s1);
       // fewer generator calls in flight when the accumulators are many
-      produce_tile<DIST, WGS, (DL * CS >= 64 ? 2 : 4), COUNT>(
+      produce_tile<DIST, WGS, (DL * CS >= 64 ? 2 : 4), COUNT, GEN>(
           S_lds, P, P.rowlist + row_beg, rb, grow0, tid,
           reinterpret_cast<unsigned long long*>(const_cast<int64_t*>(&P.hdr->reserved[0])));
       bool first_pass = true;
@@ -349,7 +370,9 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
 #pragma unroll
           for (int t = 0; t < DL; ++t) {
             const int64_t i = i_tile + rofs + t;
-            if (i < P.d) out[i + k * P.ld] = status ? nan : acc[c][t];
+            // (the scaled mode's S is 2^24 S: one exact rescaling here)
+            const float v = GEN == GEN_SCALED ? acc[c][t] * 0x1.0p-24f : acc[c][t];
+            if (i < P.d) out[i + k * P.ld] = status ? nan : v;
           }
         }
       }
@@ -388,14 +411,39 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
   }
 }
 
-template <int DIST, int DL, int Q, int CS, int WGS, bool FOLD = false, bool COUNT = false>
+template <int DIST, int DL, int Q, int CS, int WGS, bool FOLD = false, bool COUNT = false,
+          int GEN = GEN_PHILOX>
 __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(4))) void k_sketch(
     SketchParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int bid = blockIdx.x;
   const int split = bid % P.splits;
   const int rest = bid / P.splits;
-  sketch_unit<DIST, DL, Q, CS, WGS, FOLD, COUNT>(P, split, rest % P.tiles, rest / P.tiles, smem);
+  sketch_unit<DIST, DL, Q, CS, WGS, FOLD, COUNT, GEN>(P, split, rest % P.tiles, rest / P.tiles,
+                                                      smem);
+}
+
+// Generator throughput (the measured cost h of the ablation): each thread
+// makes `calls` generator calls for distinct counters (group c, column =
+// global thread index) and folds every output into one word, written once,
+// so that nothing is stored but nothing can be skipped either.
+template <int DIST, int GEN>
+__global__ __launch_bounds__(256) void k_rng_throughput(int64_t calls, uint64_t seed,
+                                                        uint32_t* __restrict__ sink) {
+  const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t acc = 0;
+  for (int64_t c = 0; c < calls; ++c) {
+    if (DIST == DIST_RADEMACHER) {
+      const Words x = words_of<GEN>(seed, (uint64_t)c, j);
+      acc ^= x.x0 ^ x.x1 ^ x.x2 ^ x.x3;
+    } else {
+      float v[4];
+      quad_values<DIST, GEN>(seed, (uint64_t)c, j, v);
+      acc ^= __float_as_uint(v[0]) ^ __float_as_uint(v[1]) ^ __float_as_uint(v[2]) ^
+             __float_as_uint(v[3]);
+    }
+  }
+  sink[j] = acc;
 }
 
 // A_hat[i, k] = sum over sparse slices of the virtual columns of k, then the
