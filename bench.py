@@ -1,15 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the sketch A_hat = S A on one MI355X.
 
-A step is one full sk_sketch call (device validation, inspector, S tiles +
-sparse accumulation, split reduction) on the plain-at-scale workload: A is
-CSC FP32, m = 2e6, n = 2000, 10 distinct uniform columns per row (nnz = 2e7),
-values U(-1,1); S uniform(-1,1) from Philox4x32-10 (seed 21); d = 4000.
-Inputs are resident in HBM before the timed region.
-
-Prints one JSON line: throughput in nnz*d/s, the ALU roofline of the
-dominant kernel (timed alone with HIP events on the stream it runs on), and
-the CPU oracle timed on a bounded row sample of the same workload.
+Default (``python bench.py``): the plain-at-scale workload.  A step is one
+full sk_sketch call (device validation, inspector, S tiles + sparse
+accumulation, split reduction): A is CSC FP32, m = 2e6, n = 2000, 10 distinct
+uniform columns per row (nnz = 2e7), values U(-1,1); S uniform(-1,1) from
+Philox4x32-10 (seed 21); d = 4000.  Inputs are resident in HBM before the
+timed region.  One JSON line carries:
+  - throughput in nnz*d/s and the step time;
+  - the ALU roofline of the sketch kernel, timed alone with HIP events on the
+    stream it runs on, with the generator's cost per call and per S value
+    measured in the same run by the generator-throughput probe;
+  - the FMA-only bound (the kernel with the junk generator), the inspector
+    and reduction times, and the distribution-cost ablation (junk generator,
+    integer-scaled (-1,1), S stored in HBM);
+  - element-wise parity of the timed output against the CPU oracle, and the
+    oracle's own throughput on the host cores (cpu_baseline);
+  - ``batched``: 64 items of the batched workload, plain FP32 launches
+    against one batched launch (FP32, and +-1 S in BF16 / FP8 on the matrix
+    cores), every item checked against the oracle;
+  - ``serving``: a Poisson stream of sketch-and-precondition least-squares
+    solves at 0.9x capacity, plain (one at a time) against continuous
+    batching: p50/p99 latency and solves/s.
+``--workload batched`` / ``serving`` / ``skewed`` / ``plain_small`` run the
+other workloads on their own (the batched and serving ones at full size);
+``table1`` / ``abnormal`` run the S-tile kernel and the Algorithm 3
+loop-order kernel on stand-ins for the paper's SpMM matrices.
 """
 from __future__ import annotations
 
@@ -26,14 +42,10 @@ sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = full-rate 32-bit VALU lane-ops/s
 VALU_PEAK = 256 * 64 * 2.4e9
-# VALU issue slots (full-rate equivalents) per generator call / per S entry:
-# Philox4x32-10 is 10 rounds of two 32x32->64 multiplies (v_mad_u64_u32, which
-# issues at full rate on gfx950), four xors and the key bumps: about 60 slots
-PHILOX_SLOTS = 60
-# transform slots per S entry: uniform = shift, convert, multiply-add; Gaussian
-# = half a Box-Muller pair (logarithm, square root, sine/cosine polynomials)
-TRANSFORM_SLOTS = {"rademacher": 0.0, "uniform": 4.0, "gaussian": 30.0}
-FMA_SLOTS = 1           # one v_fma_f32 per multiply-add (packed FP32 disabled)
+# the generator's cost per call as the cost model of the sketch counts it:
+# 10 rounds of two 32x32 -> 64-bit multiply-adds and two three-input xors,
+# one issue slot each
+PHILOX_SLOTS_MODEL = 40
 # HBM traffic of the sketch kernel on the default workload, from hardware
 # counters, valid while the kernel sources are the ones it was measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sketch_plain_scale_traffic.txt")
@@ -41,8 +53,8 @@ KERNEL_SOURCES = ["paper_2310_15419_amd/csrc/sk_sketch.hpp",
                   "paper_2310_15419_amd/csrc/sk_rng.hpp"]
 
 
-def valu_work(dist: str, calls: float, entries: float, fmas: float) -> float:
-    return calls * PHILOX_SLOTS + entries * TRANSFORM_SLOTS[dist] + fmas * FMA_SLOTS
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_sources_sha() -> str:
@@ -73,6 +85,22 @@ def counter_traffic(workload: str):
         return None
 
 
+def timed_ms(fn, reps: int, stream, warm: bool = True) -> float:
+    """Average time of fn() over reps calls, HIP events on `stream`."""
+    import torch
+    if warm:
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def make_workload(name: str):
     from paper_2310_15419_amd import inputs
     if name == "plain_scale":
@@ -93,6 +121,34 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+# ---------------------------------------------------------------- generator
+def generator_costs(B, dist: str, stream) -> dict:
+    """Generator calls/s of the throughput probe, as full-rate VALU issue
+    slots per call (Philox and the junk hash), and the transform's slots per
+    S value (the probe with the distribution's transform against the raw
+    words)."""
+    import torch
+    blocks, calls = 256 * 8, 512
+    sink = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    n_calls = blocks * 256 * calls
+
+    def slots(d, gen):
+        ms = timed_ms(lambda: B.rng_throughput(d, gen, calls, blocks, 7, sink, stream), 5, stream)
+        return VALU_PEAK * ms * 1e-3 / n_calls
+
+    words = slots("rademacher", 0)
+    rec = {"philox_slots_per_call": words, "junk_slots_per_call": slots("rademacher", 1),
+           "probe": f"{blocks} x 256 threads x {calls} calls, counters (call, thread)"}
+    if dist != "rademacher":
+        full = slots(dist, 0)
+        rec[f"{dist}_slots_per_call"] = full
+        rec["transform_slots_per_value"] = max(0.0, (full - words) / 4.0)
+    else:
+        rec["transform_slots_per_value"] = 0.0
+    return rec
+
+
+# -------------------------------------------------------------- plain runs
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -143,93 +199,159 @@ def parity_record(got, ref, S, dist, what: str):
     return p
 
 
-def bench_serving(args):
-    """Config 5: a Poisson stream of sketch-and-precondition least-squares
-    requests; p50/p99 latency and solves/s of continuous batching (several
-    slots) against the plain per-request path (one slot), at arrival rates
-    that are fractions of the measured single-request capacity."""
+def ablation(B, dA, A, d, dist, seed, tune, stream, steps, entries) -> dict:
+    """The sketch kernel with the junk generator (the FMA-only analogue), the
+    integer-scaled (-1,1) S and S stored in HBM, on the same input and tiling
+    (no dense path here).  h: generator time per S value (product minus
+    junk), and the generator's share of the product kernel's time."""
     import torch
-    from paper_2310_15419_amd import binding as B, inputs, serving as S
-    rng = np.random.default_rng(50)
-    pool = []
+    base = {k: v for k, v in tune.items() if v}
+    base["dense_min_pct"] = 101
+    out = torch.empty((A.n, d), dtype=torch.float32, device="cuda")
+    rec = {}
+    try:
+        ws = B.alloc_workspace(B.workspace_bytes(dA, d, dist, tune=base))
+        modes = [("philox", 0), ("junk", 1)] + ([("scaled", 3)] if dist == "uniform" else [])
+        for name, mode in modes:
+            t = dict(base, rng_mode=mode)
+            B.sketch_into(dA, d, dist, seed, out, ws, tune=t)  # inspector for this tuning
+            t["phases"] = 2
+            rec[f"{name}_kernel_ms"] = timed_ms(
+                lambda: B.sketch_into(dA, d, dist, seed, out, ws, tune=t), steps, stream)
+        if dist == "uniform":
+            # S itself in HBM (d rounded up to 128 rows per column)
+            lds = -(-d // 128) * 128
+            S = torch.empty((A.m, lds), dtype=torch.float32, device="cuda")
+            B.lib().sk_materialize_s(0, d, 0, A.m, 1, seed, S.data_ptr(), lds, B._stream(stream))
+            t = dict(base)
+            B.sketch_stored_into(dA, S, out, ws, tune=t)
+            t["phases"] = 2
+            rec["stored_kernel_ms"] = timed_ms(
+                lambda: B.sketch_stored_into(dA, S, out, ws, tune=t), steps, stream)
+            rec["stored_s_bytes"] = float(S.numel() * 4)
+            del S
+        del ws
+    except (B.SketchError, torch.cuda.OutOfMemoryError) as e:
+        rec["error"] = str(e)
+        return rec
+    gen_ms = rec["philox_kernel_ms"] - rec["junk_kernel_ms"]
+    rec["h_ns_per_value"] = gen_ms * 1e6 / entries
+    rec["generator_share"] = gen_ms / rec["philox_kernel_ms"]
+    return rec
+
+
+def bench_plain(args, B):
+    import torch
     t_gen = time.perf_counter()
-    for i in range(args.serve_pool):
-        m = int(np.exp(rng.uniform(np.log(1e5), np.log(args.serve_m_hi))))
-        n = int(rng.integers(100, args.serve_n_hi + 1))
-        A, b, _ = inputs.ls_request(500 + i, m, n, dense_rows=2000)
-        pool.append((B.DeviceCsc.from_host(A), torch.from_numpy(b).cuda(), m, n, A.nnz))
-    print(f"[bench] {len(pool)} request matrices in {time.perf_counter() - t_gen:.1f} s",
-          file=sys.stderr, flush=True)
+    A, d, dist, seed, desc = make_workload(args.workload)
+    log(f"workload generated in {time.perf_counter() - t_gen:.1f} s "
+        f"(m={A.m}, n={A.n}, nnz={A.nnz}, d={d})")
+    dA = B.DeviceCsc.from_host(A, dtype=np.float32 if A.vals.dtype != np.float64 else None)
+    tune = {"variant": args.variant, "rows_per_block": args.rows_per_block,
+            "splits": args.splits, "dense_min_pct": args.dense_min_pct,
+            "col_split": args.col_split, "row_pad": args.row_pad, "tile_rows": args.tile_rows}
+    ws = B.alloc_workspace(B.workspace_bytes(dA, d, dist, tune=tune))
+    out = torch.empty((A.n, d), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
 
-    def requests(count, arrivals, seed):
-        r = np.random.default_rng(seed)
-        out = []
-        for k in range(count):
-            dA, db, m, n, _ = pool[int(r.integers(0, len(pool)))]
-            p = B.sap_params(2 * n, "rademacher", 60000 + k, atol=1e-10, btol=1e-10)
-            out.append(S.Request(k, dA, db, p, arrival=float(arrivals[k])))
-        return out
+    for _ in range(args.warmup):
+        B.sketch_into(dA, d, dist, seed, out, ws, tune=tune)
+    st = B.sketch_status(ws)
+    if st["status"] != 0:
+        raise SystemExit(f"sketch failed: {st}")
+    R, nb = st["nonempty_rows"], st["row_blocks"]
 
-    budget = int(args.serve_budget_gb * (1 << 30))
-    # warm-up, then the single-request service time (one slot, all queued)
-    S.Server(budget, 1).run(requests(2, np.zeros(2), 1))
-    probe = requests(len(pool), np.zeros(len(pool)), 2)
-    t0 = time.perf_counter()
-    S.Server(budget, 1).run(probe)
-    service = (time.perf_counter() - t0) / len(probe)
-    capacity = 1.0 / service
-    print(f"[bench] single-request service {service * 1e3:.2f} ms -> capacity {capacity:.1f}/s",
-          file=sys.stderr, flush=True)
-    points = []
-    for frac in args.serve_rates:
-        rate = frac * capacity
-        arr = S.poisson_arrivals(args.serve_requests, rate, seed=int(frac * 1000))
-        row = {"rate_frac": frac, "rate_per_s": rate}
-        for name, slots in (("plain", 1), ("batched", args.serve_slots)):
-            srv = S.Server(budget, slots, chunk=16)
-            reqs = srv.run(requests(args.serve_requests, arr, 7))
-            st = S.latency_stats(reqs)
-            st["peak_inflight"] = srv.peak_inflight
-            st["converged"] = sum(bool(r.info) and r.info["istop"] in (1, 2) for r in reqs)
-            row[name] = st
-            print(f"[bench] rate {frac:.2f}x {name}: p50 {st['p50_ms']:.1f} ms, p99 "
-                  f"{st['p99_ms']:.1f} ms, {st['solves_per_s']:.1f} solves/s",
-                  file=sys.stderr, flush=True)
-        points.append(row)
-    head = next((p for p in points if abs(p["rate_frac"] - 0.9) < 1e-9), points[-1])
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ms = timed_ms(lambda: B.sketch_into(dA, d, dist, seed, out, ws, tune=tune), args.steps,
+                  stream, warm=False)
+    wall = time.perf_counter() - wall0
+    # the phases alone (same stream, same workspace): the sketch kernel, the
+    # validation + inspector, the split reduction
+    phase_ms = {}
+    for name, mask in (("kernel", 2), ("inspector", 1), ("reduction", 4)):
+        t = dict(tune, phases=mask)
+        phase_ms[name] = timed_ms(lambda: B.sketch_into(dA, d, dist, seed, out, ws, tune=t),
+                                  args.steps, stream, warm=False)
+    B.sketch_into(dA, d, dist, seed, out, ws, tune=tune)  # the full result again
+    kms = phase_ms["kernel"]
+
+    nnz = A.nnz
+    e = 128 if dist == "rademacher" else 4
+    calls = R * -(-d // e)
+    entries = R * d
+    fmas = nnz * d
+    gen = generator_costs(B, dist, stream)
+    work = calls * gen["philox_slots_per_call"] + entries * gen["transform_slots_per_value"] + fmas
+    work_model = calls * PHILOX_SLOTS_MODEL + entries * gen["transform_slots_per_value"] + fmas
+    achieved = work / (kms * 1e-3)
+    value = nnz * d / (ms * 1e-3)
     res = {
-        "metric": "p99 latency of served sketch-and-precondition least-squares solves",
-        "value": head["batched"]["p99_ms"], "unit": "ms", "n_gpus": 1,
-        "steps": args.serve_requests, "warmup": 2,
-        "ms_per_step": head["batched"]["mean_ms"], "higher_is_better": False,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (sketch f32)",
+        "metric": "sketched nnz·d per sec (% of roofline); batched vs plain at fixed error; "
+                  "p99 latency",
+        "value": value,
+        "unit": "nnz*d/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "serving: Poisson stream of min ||Ax-b||, A from the power-law "
-                               f"generator with a dense 2000-row block, m log-uniform in [1e5, "
-                               f"{args.serve_m_hi:.0e}], n in [100, {args.serve_n_hi}], d = 2n, "
-                               "S +-1, LSQR to 1e-10, "
-                               f"{len(pool)} distinct matrices, HBM budget "
-                               f"{args.serve_budget_gb} GiB, {args.serve_slots} slots",
-                   "single_request_ms": service * 1e3, "capacity_per_s": capacity,
-                   "points": points},
+        "config": {"workload": desc, "nnz": nnz, "d": d, "nonempty_rows": R, "row_blocks": nb,
+                   "input_sha256": A.sha256()},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                     "unit": "TOP/s (full-rate VALU lane-ops)", "frac": achieved / VALU_PEAK,
+                     "traffic": counter_traffic(args.workload), "kernel": "k_sketch",
+                     "kernel_ms": kms,
+                     "work": {"generator_calls": calls, "s_values": entries, "fma": fmas,
+                              "lane_ops": work},
+                     "generator": gen,
+                     "frac_at_40_slots_per_call": work_model / (kms * 1e-3) / VALU_PEAK,
+                     "fma_only_bound_ms": fmas / VALU_PEAK * 1e3},
+        "phases_ms": phase_ms,
+        "wall_s_timed": wall,
     }
-    print(json.dumps(res), flush=True)
+    if not args.no_ablation and args.workload in ("plain_scale", "skewed"):
+        res["ablation"] = ablation(B, dA, A, d, dist, seed, tune, stream, args.steps, entries)
+        if "junk_kernel_ms" in res["ablation"]:
+            res["roofline"]["fma_only_kernel_ms"] = res["ablation"]["junk_kernel_ms"]
+    del ws
+    if not args.no_cpu_baseline:
+        rec, ref, S = cpu_baseline(A, d, dist, seed, args.cpu_seconds)
+        if S.m == A.m:
+            got = out.t().cpu().numpy()  # the whole workload: the timed output itself
+            what = "the timed output, every element"
+        else:
+            vdt = None if A.vals.dtype == np.float64 else np.float32  # as the timed input
+            got = B.sketch(B.DeviceCsc.from_host(S, dtype=vdt), d, dist, seed).cpu().numpy()
+            what = f"a GPU sketch of the oracle's sample ({S.m} rows), every element"
+        res["parity"] = parity_record(got, ref, S, dist, what)
+        del ref, got
+        if args.workload == "plain_small":
+            # one thread too, beside the paper's sequential tables
+            one, _, _ = cpu_baseline(A, d, dist, seed, args.cpu_seconds, threads=1)
+            rec["one_thread"] = one
+        res["cpu_baseline"] = rec
+    return res
 
 
-def bench_batched(args):
-    """Config 4: 512 uneven +-1 sketches, A values BF16; plain launches (one
-    sk_sketch per item) against one batched launch, with S in FP32 on the
-    sparse kernel and in BF16 / FP8 on the matrix cores, each checked against
-    the FP64 oracle on a sample of items."""
+# ----------------------------------------------------------------- batched
+def bench_batched(B, count: int, steps: int, dense_min_pct: int = 0, workers: int = 0,
+                  oracle_all: bool = True) -> dict:
+    """The batched workload's first `count` items (m log-uniform in [1e4,
+    5e5], n in [50, 500], d in [2n, 4n], density U(0.5%, 5%), values BF16,
+    S +-1): plain per-item launches against one batched launch, with S in FP32
+    on the sparse kernel and in BF16 / FP8 on the matrix cores; every item (or
+    a sample) checked against the FP64 oracle."""
     import torch
-    from paper_2310_15419_amd import binding as B, inputs
+    from paper_2310_15419_amd import inputs
     t_gen = time.perf_counter()
-    # a process pool generates the items (one process under a profiler:
-    # --workers 1)
-    workers = args.workers or min(16, len(os.sched_getaffinity(0)))
-    items = inputs.workload_batched(args.batch_count, workers=workers)
-    print(f"[bench] {len(items)} items in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr,
-          flush=True)
+    workers = workers or min(16, len(os.sched_getaffinity(0)))
+    items = inputs.workload_batched(count, workers=workers)
+    log(f"{len(items)} batched items in {time.perf_counter() - t_gen:.1f} s")
     mats, host = [], []
     for it in items:
         vb = torch.from_numpy(it.A.vals).to(torch.bfloat16)
@@ -241,76 +363,175 @@ def bench_batched(args):
     seeds = [it.seed for it in items]
     work = float(sum(h.nnz * d for h, d in zip(host, ds)))
     outs = [torch.empty((A.n, d), dtype=torch.float32, device="cuda") for A, d in zip(mats, ds)]
-    # oracle sample: the cheapest items and a few mid-size ones
-    order = sorted(range(len(items)), key=lambda i: host[i].nnz * ds[i])
-    sample = order[:6] + order[len(order) // 2: len(order) // 2 + 2]
+    if oracle_all:
+        checked = list(range(len(items)))
+    else:  # the cheapest items and a few mid-size ones
+        order = sorted(range(len(items)), key=lambda i: host[i].nnz * ds[i])
+        checked = order[:6] + order[len(order) // 2: len(order) // 2 + 2]
     import oracle
     oracle.build()
+    t_or = time.perf_counter()
     refs = {i: oracle.sketch(host[i].m, host[i].n, host[i].colptr, host[i].rowidx, host[i].vals,
-                             ds[i], "rademacher", seeds[i]) for i in sample}
+                             ds[i], "rademacher", seeds[i]) for i in checked}
+    log(f"oracle on {len(checked)} items in {time.perf_counter() - t_or:.1f} s")
 
-    def err():
-        e = 0.0
-        for i in sample:
+    def errors():
+        worst = {"normwise": 0.0, "max_elem_scaled": 0.0}
+        for i in checked:
             got = outs[i].t().cpu().numpy().astype(np.float64)
-            e = max(e, float(np.linalg.norm(got - refs[i]) / np.linalg.norm(refs[i])))
-        return e
+            p = oracle.parity(got, refs[i], host[i].colptr, host[i].vals, "rademacher")
+            worst["normwise"] = max(worst["normwise"], p["normwise"])
+            worst["max_elem_scaled"] = max(worst["max_elem_scaled"], p["max_elem_scaled"])
+        return worst
 
-    def timed(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        best = []
-        for _ in range(reps):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            fn()
-            e1.record()
-            torch.cuda.synchronize()
-            best.append(e0.elapsed_time(e1))
-        return float(np.median(best))
-
+    stream = torch.cuda.current_stream()
     modes = {}
-    # --dense-min-pct: the density (percent) from which items run on the
-    # matrix cores in the BF16/FP8 modes (0: the library's measured threshold)
     for prec, pname in ((0, "f32"), (1, "bf16"), (2, "fp8")):
-        tune = {"dense_min_pct": args.dense_min_pct} if args.dense_min_pct and prec else None
-        wss = [B.alloc_workspace(B.workspace_bytes(A, d, "rademacher", prec, tune))
-               for A, d in zip(mats, ds)]
+        tune = {"dense_min_pct": dense_min_pct} if dense_min_pct and prec else None
+        if prec == 0:
+            wss = [B.alloc_workspace(B.workspace_bytes(A, d, "rademacher", prec, tune))
+                   for A, d in zip(mats, ds)]
 
-        def plain():
-            for A, d, sd, o, w in zip(mats, ds, seeds, outs, wss):
-                B.sketch_into(A, d, "rademacher", sd, o, w, prec=prec, tune=tune)
-        ms = timed(plain, args.steps)
-        modes[f"plain_{pname}"] = {"ms": ms, "nnz_d_per_s": work / (ms * 1e-3), "error": err()}
-        del wss
+            def plain():
+                for A, d, sd, o, w in zip(mats, ds, seeds, outs, wss):
+                    B.sketch_into(A, d, "rademacher", sd, o, w, prec=prec, tune=tune)
+            ms = timed_ms(plain, steps, stream)
+            modes["plain_f32"] = {"ms": ms, "nnz_d_per_s": work / (ms * 1e-3), **errors()}
+            del wss
         batch = B.Batch(mats, ds, ["rademacher"] * len(mats), seeds,
                         tunes=[tune] * len(mats) if tune else None, prec=prec)
         ws = B.alloc_workspace(batch.workspace_bytes())
-        ms = timed(lambda: batch.run(outs, ws), args.steps)
+        ms = timed_ms(lambda: batch.run(outs, ws), steps, stream)
         st = batch.status(ws)
         assert all(c == 0 for c in st), st
-        modes[f"batched_{pname}"] = {"ms": ms, "nnz_d_per_s": work / (ms * 1e-3), "error": err(),
+        modes[f"batched_{pname}"] = {"ms": ms, "nnz_d_per_s": work / (ms * 1e-3), **errors(),
                                      "matrix_core_items": sum(p["variant"] == 0
                                                               for p in batch.plan())}
         del ws
-        for k in (f"plain_{pname}", f"batched_{pname}"):
-            print(f"[bench] {k}: {modes[k]['ms']:.2f} ms, {modes[k]['nnz_d_per_s']:.3e} nnz*d/s, "
-                  f"max rel error {modes[k]['error']:.2e}", file=sys.stderr, flush=True)
-    best = max((v["nnz_d_per_s"], k) for k, v in modes.items() if v["error"] <= 1e-2)
-    res = {
-        "metric": "batched vs plain at fixed error (512 sketches)",
-        "value": modes["batched_bf16"]["nnz_d_per_s"], "unit": "nnz*d/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": 1, "ms_per_step": modes["batched_bf16"]["ms"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16 operands, f32 accumulate", "data": "synthetic",
-        "config": {"workload": f"batched: {len(items)} sketches, m log-uniform [1e4, 5e5], n in "
-                               "[50, 500], d in [2n, 4n], density U(0.5%, 5%), A values BF16, "
-                               "S +-1 (seeds 40000+b)",
-                   "sum_nnz_d": work, "modes": modes, "best_within_1e-2": best[1],
-                   "oracle_sample_items": len(sample)},
-    }
-    print(json.dumps(res), flush=True)
+    for k, v in modes.items():
+        log(f"{k}: {v['ms']:.2f} ms, {v['nnz_d_per_s']:.3e} nnz*d/s, normwise error "
+            f"{v['normwise']:.2e}")
+    best = max((v["nnz_d_per_s"], k) for k, v in modes.items() if v["normwise"] <= 1e-2)
+    return {"workload": f"batched: {len(items)} sketches, m log-uniform [1e4, 5e5], n in "
+                        "[50, 500], d in [2n, 4n], density U(0.5%, 5%), A values BF16, "
+                        "S +-1 (seeds 40000+b)",
+            "items": len(items), "sum_nnz_d": work, "modes": modes,
+            "speedup_batched_bf16_vs_plain_f32": modes["plain_f32"]["ms"] /
+                                                 modes["batched_bf16"]["ms"],
+            "best_within_1e-2": best[1], "oracle_items": len(checked),
+            "error_bound": {"f32": 1e-5, "bf16_fp8": 1e-2}}
+
+
+# ----------------------------------------------------------------- serving
+def bench_serving(B, pool: int, count: int, rates, slots: int, m_hi: float, n_hi: int,
+                  budget_gb: float) -> dict:
+    """A Poisson stream of sketch-and-precondition least-squares requests over
+    `pool` distinct matrices (power-law columns with a dense block, m
+    log-uniform in [1e5, m_hi], n in [100, n_hi], d = 2n, S +-1, LSQR to
+    1e-10): p50/p99 latency and solves/s of continuous batching (`slots`
+    requests in flight) against the plain per-request path (one slot), at
+    arrival rates that are fractions of the measured single-request capacity."""
+    import torch
+    from paper_2310_15419_amd import inputs, serving as S
+    rng = np.random.default_rng(50)
+    mats = []
+    t_gen = time.perf_counter()
+    for i in range(pool):
+        m = int(np.exp(rng.uniform(np.log(1e5), np.log(m_hi))))
+        n = int(rng.integers(100, n_hi + 1))
+        A, b, _ = inputs.ls_request(500 + i, m, n, dense_rows=2000)
+        mats.append((B.DeviceCsc.from_host(A), torch.from_numpy(b).cuda(), m, n, A.nnz))
+    log(f"{len(mats)} request matrices in {time.perf_counter() - t_gen:.1f} s")
+
+    def requests(k_count, arrivals, seed):
+        r = np.random.default_rng(seed)
+        out = []
+        for k in range(k_count):
+            dA, db, m, n, _ = mats[int(r.integers(0, len(mats)))]
+            p = B.sap_params(2 * n, "rademacher", 60000 + k, atol=1e-10, btol=1e-10)
+            out.append(S.Request(k, dA, db, p, arrival=float(arrivals[k])))
+        return out
+
+    budget = int(budget_gb * (1 << 30))
+    S.Server(budget, 1).run(requests(2, np.zeros(2), 1))  # warm-up
+    probe = requests(len(mats), np.zeros(len(mats)), 2)
+    t0 = time.perf_counter()
+    S.Server(budget, 1).run(probe)
+    service = (time.perf_counter() - t0) / len(probe)
+    capacity = 1.0 / service
+    log(f"single-request service {service * 1e3:.2f} ms -> capacity {capacity:.1f}/s")
+    points = []
+    for frac in rates:
+        rate = frac * capacity
+        arr = S.poisson_arrivals(count, rate, seed=int(frac * 1000))
+        row = {"rate_frac": frac, "rate_per_s": rate}
+        for name, k_slots in (("plain", 1), ("batched", slots)):
+            srv = S.Server(budget, k_slots, chunk=16)
+            reqs = srv.run(requests(count, arr, 7))
+            st = S.latency_stats(reqs)
+            st["peak_inflight"] = srv.peak_inflight
+            st["converged"] = sum(bool(r.info) and r.info["istop"] in (1, 2) for r in reqs)
+            row[name] = st
+            log(f"rate {frac:.2f}x {name}: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms, "
+                f"{st['solves_per_s']:.1f} solves/s")
+        points.append(row)
+    return {"workload": "serving: Poisson stream of min ||Ax-b||, A from the power-law generator "
+                        f"with a dense 2000-row block, m log-uniform in [1e5, {m_hi:.0e}], n in "
+                        f"[100, {n_hi}], d = 2n, S +-1, LSQR to 1e-10, {len(mats)} distinct "
+                        f"matrices, HBM budget {budget_gb} GiB, {slots} slots",
+            "requests_per_point": count, "single_request_ms": service * 1e3,
+            "capacity_per_s": capacity, "points": points}
+
+
+# ------------------------------------------- the paper's SpMM workloads
+def bench_spmm_shapes(B, which: str, steps: int) -> dict:
+    """Stand-ins for the paper's SpMM test matrices (Table I shapes, or the
+    Table VI patterns), d = 3n, (-1,1) S: the S-tile kernel (the whole
+    sk_sketch step) beside the Algorithm 3 loop-order kernel, nnz*d/s each,
+    their roofline fractions against each kernel's own ALU work (the tile
+    kernel generates each S value once per row block, the kji kernel once per
+    nonzero), and their agreement (normwise difference of the two A_hat)."""
+    import torch
+    from paper_2310_15419_amd import inputs
+    stream = torch.cuda.current_stream()
+    gen = generator_costs(B, "uniform", stream)
+    c_call, c_val = gen["philox_slots_per_call"], gen["transform_slots_per_value"]
+    names = list(inputs.TABLE1) if which == "table1" else ["A", "B", "C"]
+    rows = []
+    for name in names:
+        if which == "table1":
+            A, d = inputs.table1_standin(name)
+        else:
+            A = inputs.abnormal(name)
+            d = 3 * A.n
+        dA = B.DeviceCsc.from_host(A)
+        out_t = torch.empty((A.n, d), dtype=torch.float32, device="cuda")
+        out_c = torch.empty_like(out_t)
+        ws = B.alloc_workspace(B.workspace_bytes(dA, d, "uniform"))
+        wc = B.alloc_workspace(B.colwise_workspace_bytes(dA))
+        t_ms = timed_ms(lambda: B.sketch_into(dA, d, "uniform", 5, out_t, ws), steps, stream)
+        R = B.sketch_status(ws)["nonempty_rows"]
+        c_ms = timed_ms(lambda: B.sketch_colwise_into(dA, d, "uniform", 5, out_c, wc), steps,
+                        stream)
+        diff = float(torch.linalg.norm(out_t - out_c) / torch.linalg.norm(out_c))
+        nnzd = A.nnz * d
+        work_t = R * -(-d // 4) * c_call + R * d * c_val + nnzd
+        work_c = A.nnz * -(-d // 4) * c_call + A.nnz * d * c_val + nnzd
+        row = {"matrix": name, "m": A.m, "n": A.n, "nnz": A.nnz, "d": d, "nonempty_rows": R,
+               "tile_ms": t_ms, "tile_nnz_d_per_s": nnzd / (t_ms * 1e-3),
+               "tile_frac": work_t / (t_ms * 1e-3) / VALU_PEAK,
+               "kji_ms": c_ms, "kji_nnz_d_per_s": nnzd / (c_ms * 1e-3),
+               "kji_frac": work_c / (c_ms * 1e-3) / VALU_PEAK,
+               "kji_over_tile": c_ms / t_ms, "normwise_difference": diff}
+        log(f"{name}: tile {t_ms:.2f} ms ({row['tile_nnz_d_per_s']:.3e} nnz*d/s), kji "
+            f"{c_ms:.2f} ms ({row['kji_nnz_d_per_s']:.3e}), difference {diff:.1e}")
+        rows.append(row)
+        del ws, wc, out_t, out_c
+    return {"workload": ("Table I stand-ins" if which == "table1" else "Table VI patterns") +
+                        ": shapes and nonzero counts of the paper's matrices, uniform random "
+                        "columns (Table I) or the exotic patterns (m=1e5, n=1e4, density 1e-3), "
+                        "d = 3n, S (-1,1) Philox4x32-10 seed 5",
+            "generator": gen, "matrices": rows}
 
 
 def main():
@@ -318,9 +539,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plain_scale")
+    ap.add_argument("--workload", default="plain_scale",
+                    help="plain_scale (default), plain_small, skewed, batched, serving, "
+                         "table1, abnormal")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: leave out the batched and serving sub-objects")
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--rows-per-block", type=int, default=0)
     ap.add_argument("--splits", type=int, default=0)
@@ -361,104 +587,45 @@ def main():
         return
 
     if args.workload == "serving":
-        bench_serving(args)
+        sv = bench_serving(B, args.serve_pool, args.serve_requests, args.serve_rates,
+                           args.serve_slots, args.serve_m_hi, args.serve_n_hi,
+                           args.serve_budget_gb)
+        head = next((p for p in sv["points"] if abs(p["rate_frac"] - 0.9) < 1e-9),
+                    sv["points"][-1])
+        print(json.dumps({
+            "metric": "p99 latency of served sketch-and-precondition least-squares solves",
+            "value": head["batched"]["p99_ms"], "unit": "ms", "n_gpus": 1,
+            "steps": args.serve_requests, "warmup": 2, "ms_per_step": head["batched"]["mean_ms"],
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64 (sketch f32)", "data": "synthetic", "config": sv}), flush=True)
+        return
+    if args.workload in ("table1", "abnormal"):
+        sp = bench_spmm_shapes(B, args.workload, args.steps)
+        tot = sum(r["nnz"] * r["d"] for r in sp["matrices"])
+        t_ms = sum(r["tile_ms"] for r in sp["matrices"])
+        print(json.dumps({
+            "metric": "sketched nnz·d per sec on stand-ins for the paper's SpMM matrices",
+            "value": tot / (t_ms * 1e-3), "unit": "nnz*d/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": 1, "ms_per_step": t_ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": sp}), flush=True)
         return
     if args.workload == "batched":
-        bench_batched(args)
+        bt = bench_batched(B, args.batch_count, args.steps, args.dense_min_pct, args.workers,
+                           oracle_all=False)
+        print(json.dumps({
+            "metric": f"batched vs plain at fixed error ({args.batch_count} sketches)",
+            "value": bt["modes"]["batched_bf16"]["nnz_d_per_s"], "unit": "nnz*d/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": 1,
+            "ms_per_step": bt["modes"]["batched_bf16"]["ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16 operands, f32 accumulate",
+            "data": "synthetic", "config": bt}), flush=True)
         return
 
-    t_gen = time.perf_counter()
-    A, d, dist, seed, desc = make_workload(args.workload)
-    print(f"[bench] workload generated in {time.perf_counter() - t_gen:.1f} s "
-          f"(m={A.m}, n={A.n}, nnz={A.nnz}, d={d})", file=sys.stderr, flush=True)
-    dA = B.DeviceCsc.from_host(A, dtype=np.float32 if A.vals.dtype != np.float64 else None)
-    tune = {"variant": args.variant, "rows_per_block": args.rows_per_block,
-            "splits": args.splits, "dense_min_pct": args.dense_min_pct,
-            "col_split": args.col_split, "row_pad": args.row_pad, "tile_rows": args.tile_rows}
-    ws = B.alloc_workspace(B.workspace_bytes(dA, d, dist, tune=tune))
-    out = torch.empty((A.n, d), dtype=torch.float32, device="cuda")
-    stream = torch.cuda.current_stream()
-
-    for _ in range(args.warmup):
-        B.sketch_into(dA, d, dist, seed, out, ws, tune=tune)
-    st = B.sketch_status(ws)
-    if st["status"] != 0:
-        raise SystemExit(f"sketch failed: {st}")
-    R, nb = st["nonempty_rows"], st["row_blocks"]
-
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        B.sketch_into(dA, d, dist, seed, out, ws, tune=tune)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = e0.elapsed_time(e1) / args.steps
-
-    # the dominant kernel alone (S tiles + sparse accumulation), same stream,
-    # same workspace
-    ktune = dict(tune, phases=2)
-    k0 = torch.cuda.Event(enable_timing=True)
-    k1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    k0.record(stream)
-    for _ in range(args.steps):
-        B.sketch_into(dA, d, dist, seed, out, ws, tune=ktune)
-    k1.record(stream)
-    torch.cuda.synchronize()
-    kms = k0.elapsed_time(k1) / args.steps
-
-    nnz = A.nnz
-    rpc = 128 if dist == "rademacher" else 4
-    calls = R * -(-d // rpc)
-    entries = R * d
-    work = valu_work(dist, calls, entries, nnz * d)
-    achieved = work / (kms * 1e-3)
-    value = nnz * d / (ms * 1e-3)
-
-    res = {
-        "metric": "sketched nnz·d per sec (% of roofline); batched vs plain at fixed error; "
-                  "p99 latency",
-        "value": value,
-        "unit": "nnz*d/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": desc, "nnz": nnz, "d": d, "nonempty_rows": R, "row_blocks": nb},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "TOP/s (full-rate VALU lane-ops)", "frac": achieved / VALU_PEAK,
-                     "traffic": counter_traffic(args.workload), "kernel": "k_sketch",
-                     "kernel_ms": kms},
-        "wall_s_timed": wall,
-    }
-    res["config"]["input_sha256"] = A.sha256()
-    if not args.no_cpu_baseline:
-        rec, ref, S = cpu_baseline(A, d, dist, seed, args.cpu_seconds)
-        if S.m == A.m:
-            # the whole workload: the timed output itself
-            got = out.t().cpu().numpy()
-            what = "the timed output, every element"
-        else:
-            # a row sample: the same call on the sampled rows
-            vdt = None if A.vals.dtype == np.float64 else np.float32  # as the timed input
-            got = B.sketch(B.DeviceCsc.from_host(S, dtype=vdt), d, dist, seed).cpu().numpy()
-            what = f"a GPU sketch of the oracle's sample ({S.m} rows), every element"
-        res["parity"] = parity_record(got, ref, S, dist, what)
-        del ref, got
-        if args.workload == "plain_small":
-            # one thread too, beside the paper's sequential tables
-            one, _, _ = cpu_baseline(A, d, dist, seed, args.cpu_seconds, threads=1)
-            rec["one_thread"] = one
-        res["cpu_baseline"] = rec
+    res = bench_plain(args, B)
+    if args.workload == "plain_scale" and not args.no_extras:
+        res["batched"] = bench_batched(B, 64, max(2, args.steps // 2), workers=args.workers)
+        res["serving"] = bench_serving(B, pool=6, count=60, rates=[0.9], slots=8, m_hi=1e6,
+                                       n_hi=500, budget_gb=64.0)
     print(json.dumps(res), flush=True)
 
 

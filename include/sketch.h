@@ -167,6 +167,21 @@ sk_status sk_sketch_stored(const sk_csc* A, int64_t d, const float* S, int64_t l
                            const sk_tuning* tune, float* Ahat, int64_t ld, void* ws,
                            size_t ws_bytes, void* hip_stream);
 
+/* The sketch in the loop order of Algorithm 3 (variant kji, Sec. II-B):
+ * A_hat[0:d, 0:n] = S[row0 : row0+d, :] A where every nonzero a_jk
+ * regenerates its S column segment S[row0 : row0+d, j] and adds a_jk times
+ * it into column k; no S tile is reused across columns and A is used as the
+ * given CSC (validated on the device, no inspector).  Same S, so the same
+ * A_hat as sk_sketch up to FP32 summation order (each entry here sums the
+ * column's nonzeros in row order).  Generator calls: nnz x (groups of 4, or
+ * of 128 for +-1, that the rows touch per 256 / 2048 rows).  Workspace:
+ * sk_sketch_colwise_workspace bytes (the validation status, read with
+ * sk_sketch_status).  Asynchronous on hip_stream. */
+sk_status sk_sketch_colwise_workspace(const sk_csc* A, size_t* bytes);
+sk_status sk_sketch_colwise(const sk_csc* A, int64_t row0, int64_t d, int32_t dist,
+                            uint64_t seed, float* Ahat, int64_t ld, void* ws, size_t ws_bytes,
+                            void* hip_stream);
+
 /* Generator throughput, for measuring the cost of one call (the h of Sec.
  * III-A): blocks x 256 threads each make `calls` calls of the generator
  * (gen 0 = Philox4x32-10, 1 = the junk hash of sk_tuning.rng_mode) with the

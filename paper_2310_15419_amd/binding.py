@@ -83,6 +83,9 @@ def lib():
         L.sk_sketch_stored.argtypes = [P(SkCsc), i64, vp, i64, P(SkTuning), vp, i64, vp,
                                        ctypes.c_size_t, vp]
         L.sk_rng_throughput.argtypes = [i32, i32, i64, i32, u64, vp, vp]
+        L.sk_sketch_colwise_workspace.argtypes = [P(SkCsc), P(ctypes.c_size_t)]
+        L.sk_sketch_colwise.argtypes = [P(SkCsc), i64, i64, i32, u64, vp, i64, vp,
+                                        ctypes.c_size_t, vp]
         L.sk_materialize_s.argtypes = [i64, i64, i64, i64, i32, u64, vp, i64, vp]
         L.sk_autotune.argtypes = [P(SkCsc), i64, i32, P(SkTuning)]
         L.sk_sketch_batched_workspace.argtypes = [i32, P(SkCsc), P(i64), P(i32), i32, P(SkTuning),
@@ -105,6 +108,7 @@ def lib():
                                        P(SapInfo)]
         for name in ("sk_sketch_workspace", "sk_sketch", "sk_sketch_noalloc", "sk_sketch_status",
                      "sk_sketch_rng_calls", "sk_sketch_stored", "sk_rng_throughput",
+                     "sk_sketch_colwise_workspace", "sk_sketch_colwise",
                      "sk_materialize_s",
                      "sk_autotune", "sk_sketch_batched_workspace", "sk_sketch_batched",
                      "sk_sketch_batched_plan", "sk_sketch_batched_status", "sk_qr_f64_workspace",
@@ -242,6 +246,34 @@ def sketch_stored_into(A: DeviceCsc, S, out, ws, tune=None, stream=None) -> None
     _check(lib().sk_sketch_stored(ctypes.byref(c), d, S.data_ptr(), S.shape[1], _tuning(tune),
                                   out.data_ptr(), d, ws.data_ptr(), ws.numel(), _stream(stream)),
            "sk_sketch_stored")
+
+
+def colwise_workspace_bytes(A: DeviceCsc) -> int:
+    out = ctypes.c_size_t()
+    c = A.c_struct()
+    _check(lib().sk_sketch_colwise_workspace(ctypes.byref(c), ctypes.byref(out)),
+           "sk_sketch_colwise_workspace")
+    return int(out.value)
+
+
+def sketch_colwise_into(A: DeviceCsc, d: int, dist, seed: int, out, ws, row0: int = 0,
+                        stream=None) -> None:
+    """sk_sketch_colwise (the Algorithm 3 loop order) into ``out`` (n, d)."""
+    c = A.c_struct()
+    _check(lib().sk_sketch_colwise(ctypes.byref(c), row0, d, _dist(dist), seed, out.data_ptr(),
+                                   d, ws.data_ptr(), ws.numel(), _stream(stream)),
+           "sk_sketch_colwise")
+
+
+def sketch_colwise(A: DeviceCsc, d: int, dist, seed: int, row0: int = 0, check: bool = True):
+    """A_hat in the Algorithm 3 loop order, as a torch FP32 tensor of shape (d, n)."""
+    import torch
+    ws = alloc_workspace(colwise_workspace_bytes(A), A.colptr.device)
+    out = torch.empty((A.n, d), dtype=torch.float32, device=A.colptr.device)
+    sketch_colwise_into(A, d, dist, seed, out, ws, row0)
+    if check:
+        _check(sketch_status(ws)["status"], "sk_sketch_colwise (device validation)")
+    return out.t()
 
 
 def rng_throughput(dist, gen: int, calls: int, blocks: int, seed: int, sink,

@@ -1,0 +1,111 @@
+// sk_colwise.hpp -- the sketch in the loop order of Algorithm 3 (variant
+// kji): for every column k of A and every nonzero a_jk of it, the segment
+// S[r : r + d, j] is generated anew and a_jk S[:, j] is added into
+// A_hat[:, k].  Nothing is reused across columns (every nonzero pays its own
+// generator calls: Sec. III-A's cost of the kji order), no inspector runs
+// (the CSC input is used as given), and the cost does not depend on where the
+// nonzeros sit (Table VI's observation).  It is the GPU counterpart of the
+// paper's Algorithm 3 beside the S-tile kernel (the counterpart of Algorithm
+// 4's reuse).
+//
+// A wave owns A_hat[tile rows, k]: its 64 lanes hold DL consecutive S rows
+// each (DL = 4: one generator call per lane per nonzero for (-1,1) and the
+// Gaussian; DL = 32: one word of a call per lane for +-1).  The nonzeros of
+// column k are the same for the whole wave, so their row indices and values
+// are scalar loads.  Every A_hat entry is one lane's FP32 sum in row order of
+// the column: no atomics, a fixed summation order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sk_inspect.hpp"
+#include "sk_rng.hpp"
+
+namespace sk {
+
+struct ColwiseParams {
+  const int64_t* colptr;
+  const int32_t* rowidx;
+  const void* vals;
+  int32_t vtype;
+  const Header* hdr;  // validation status of A (set by the validation pass)
+  int64_t n, d, row0;
+  uint64_t seed;
+  float* out;
+  int64_t ld;
+  int32_t tiles;      // S-row tiles of 64 * DL rows
+};
+
+constexpr int CW_WAVES = 4;  // waves (tiles of one column) per workgroup
+
+// S(gi + t, j) for t < DL (gi: the lane's first global S row)
+template <int DIST, int DL>
+__device__ __forceinline__ void colwise_values(uint64_t seed, uint64_t gi, uint64_t j,
+                                               float (&s)[DL]) {
+  if constexpr (DIST == DIST_RADEMACHER) {
+    static_assert(DL == 32, "+-1: one 32-bit word per lane");
+    // rows gi .. gi + 31: bits of one word when gi is a multiple of 32, else
+    // the tail of one word and the head of the next (perhaps the next call's)
+    const uint64_t g = gi >> 7;
+    const int w = (int)((gi >> 5) & 3);
+    const int b = (int)(gi & 31);
+    const Words x = gen_words(seed, g, j);
+    uint32_t bits = word_at(x, w);
+    if (b) {
+      const uint32_t hi = w < 3 ? word_at(x, w + 1) : gen_words(seed, g + 1, j).x0;
+      bits = (bits >> b) | (hi << (32 - b));
+    }
+#pragma unroll
+    for (int t = 0; t < 32; ++t)
+      s[t] = __uint_as_float((((bits >> t) & 1u) << 31) | 0x3F800000u);
+  } else {
+    static_assert(DL == 4, "(-1,1) and Gaussian: one call (four rows) per lane");
+    const uint64_t g = gi >> 2;
+    const int sh = (int)(gi & 3);
+    float v[4];
+    quad_values<DIST>(seed, g, j, v);
+    if (sh == 0) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) s[t] = v[t];
+    } else {
+      float u[4];
+      quad_values<DIST>(seed, g + 1, j, u);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) s[t] = t + sh < 4 ? v[t + sh] : u[t + sh - 4];
+    }
+  }
+}
+
+template <int DIST, int DL>
+__global__ __launch_bounds__(64 * CW_WAVES) void k_sketch_colwise(ColwiseParams P) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t tgroups = (P.tiles + CW_WAVES - 1) / CW_WAVES;
+  const int64_t k = blockIdx.x / tgroups;
+  const int64_t tile = (blockIdx.x - k * tgroups) * CW_WAVES + wave;
+  if (tile >= P.tiles) return;
+  const int64_t i0 = tile * (64 * DL) + (int64_t)lane * DL;  // the lane's first row
+  float acc[DL];
+#pragma unroll
+  for (int t = 0; t < DL; ++t) acc[t] = 0.0f;
+  const int status = P.hdr->status;
+  if (status == 0 && i0 < P.d) {
+    const uint64_t gi = (uint64_t)(P.row0 + i0);
+    const int64_t p0 = P.colptr[k], p1 = P.colptr[k + 1];
+    for (int64_t p = p0; p < p1; ++p) {
+      const uint64_t j = (uint64_t)(uint32_t)P.rowidx[p];
+      const float a = load_value(P.vals, P.vtype, p);
+      float s[DL];
+      colwise_values<DIST, DL>(P.seed, gi, j, s);
+#pragma unroll
+      for (int t = 0; t < DL; ++t) acc[t] = __builtin_fmaf(a, s[t], acc[t]);
+    }
+  }
+  const float nan = __uint_as_float(0x7FC00000u);
+#pragma unroll
+  for (int t = 0; t < DL; ++t)
+    if (i0 + t < P.d) P.out[i0 + t + k * P.ld] = status ? nan : acc[t];
+}
+
+}  // namespace sk

@@ -14,6 +14,7 @@
 #include <mutex>
 
 #include "sk_batch.hpp"
+#include "sk_colwise.hpp"
 #include "sk_dense.hpp"
 #include "sk_inspect.hpp"
 #include "sk_mfma.hpp"
@@ -1128,6 +1129,58 @@ sk_status sk_sketch_stored(const sk_csc* A, int64_t d, const float* S, int64_t l
   if (tune && tune->rng_mode) return SK_EINVAL;
   return sketch_impl(A, 0, d, SK_UNIFORM, 0, SK_PREC_F32, tune, Ahat, ld, ws, ws_bytes,
                      hip_stream, GEN_STORED, S, lds);
+}
+
+// ------------------------------------------- Algorithm 3 (kji) order
+sk_status sk_sketch_colwise_workspace(const sk_csc* A, size_t* bytes) {
+  if (!bytes) return SK_EINVAL;
+  sk_status s = check_csc(A);
+  if (s != SK_OK) return s;
+  *bytes = (size_t)(align_up((int64_t)sizeof(Header)) + align_up((int64_t)sizeof(Item)));
+  return SK_OK;
+}
+
+sk_status sk_sketch_colwise(const sk_csc* A, int64_t row0, int64_t d, int32_t dist,
+                            uint64_t seed, float* Ahat, int64_t ld, void* ws, size_t ws_bytes,
+                            void* hip_stream) {
+  sk_status s = check_csc(A);
+  if (s != SK_OK) return s;
+  if (d < 1 || row0 < 0 || !Ahat || ld < d || dist < 0 || dist > 2) return SK_EINVAL;
+  size_t need = 0;
+  if ((s = sk_sketch_colwise_workspace(A, &need)) != SK_OK) return s;
+  if (!ws || ws_bytes < need) return SK_EWORKSPACE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  char* w = (char*)ws;
+  Header* hdr = (Header*)w;
+  Item* d_item = (Item*)(w + align_up((int64_t)sizeof(Header)));
+  // validation only: the CSC input is used as given
+  Item I;
+  std::memset(&I, 0, sizeof I);
+  I.m = A->m; I.n = A->n; I.nnz = A->nnz;
+  I.colptr = A->colptr; I.rowidx = A->rowidx; I.vals = A->vals; I.vtype = A->vtype;
+  I.hdr = hdr;
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, (int32_t*)hdr,
+                     (int64_t)(sizeof(Header) / 4), 0);
+  hipLaunchKernelGGL(k_put_item, dim3(1), dim3(64), 0, st, I, d_item);
+  launch_items_cols<&Item::o_valid, OpValidate>(d_item, 1, std::max<int64_t>(A->nnz, A->n + 1),
+                                                st);
+  ColwiseParams P{};
+  P.colptr = A->colptr; P.rowidx = A->rowidx; P.vals = A->vals; P.vtype = A->vtype;
+  P.hdr = hdr; P.n = A->n; P.d = d; P.row0 = row0; P.seed = seed; P.out = Ahat; P.ld = ld;
+  const int dl = dist == SK_RADEMACHER ? 32 : 4;
+  P.tiles = (int32_t)((d + 64 * dl - 1) / (64 * dl));
+  const int64_t grid = A->n * ((P.tiles + CW_WAVES - 1) / CW_WAVES);
+  if (grid >= INT32_MAX) return SK_EUNSUPPORTED;
+  if (dist == SK_RADEMACHER)
+    hipLaunchKernelGGL((k_sketch_colwise<DIST_RADEMACHER, 32>), dim3((unsigned)grid),
+                       dim3(64 * CW_WAVES), 0, st, P);
+  else if (dist == SK_UNIFORM)
+    hipLaunchKernelGGL((k_sketch_colwise<DIST_UNIFORM, 4>), dim3((unsigned)grid),
+                       dim3(64 * CW_WAVES), 0, st, P);
+  else
+    hipLaunchKernelGGL((k_sketch_colwise<DIST_GAUSSIAN, 4>), dim3((unsigned)grid),
+                       dim3(64 * CW_WAVES), 0, st, P);
+  return launch_ok();
 }
 
 sk_status sk_rng_throughput(int32_t dist, int32_t gen, int64_t calls, int32_t blocks,

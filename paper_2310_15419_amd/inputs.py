@@ -173,6 +173,85 @@ def workload_skewed(seed: int = 30, m: int = 4_000_000, n: int = 1000, dense_row
     return power_law_columns(m, n, seed, 0.05, dense_rows, np.float32)
 
 
+# ------------------------------------------- the paper's SpMM test shapes
+# (m, n, nnz) of the matrices of Table I (SuiteSparse; the sketch has d = 3n
+# rows there).  The matrices themselves are not available: the stand-ins keep
+# the shape, the nonzero count and the nonzeros per row (3, 4, 3, 3.65 and 5),
+# with the columns uniform at random.
+TABLE1 = {
+    "mk-12": (13860, 1485, 41580),
+    "ch7-9-b3": (105840, 17640, 423360),
+    "shar_te2-b2": (200200, 17160, 600600),
+    "mesh_deform": (234023, 9393, 853829),
+    "cis-n4c6-b4": (20058, 5970, 100290),
+}
+
+
+def row_count_columns(m: int, n: int, nnz: int, seed: int, dtype=np.float32) -> Csc:
+    """nnz nonzeros spread over the rows as evenly as possible (floor or ceil
+    of nnz/m per row, the extra ones on random rows), distinct uniformly random
+    columns in each row; values U(-1,1)."""
+    rng = np.random.default_rng(seed)
+    base = nnz // m
+    extra = np.zeros(m, dtype=bool)
+    extra[rng.choice(m, size=nnz - base * m, replace=False)] = True
+    k = base + 1
+    cols = rng.integers(0, n, size=(m, k), dtype=np.int64)
+    while True:
+        cs = np.sort(cols, axis=1)
+        bad = np.any(cs[:, 1:] == cs[:, :-1], axis=1)
+        if not bad.any():
+            break
+        cols[bad] = rng.integers(0, n, size=(int(bad.sum()), k), dtype=np.int64)
+    keep = np.ones((m, k), dtype=bool)
+    keep[~extra, k - 1] = False
+    rows = np.repeat(np.arange(m, dtype=np.int64), k).reshape(m, k)[keep]
+    cols = cols[keep]
+    vals = rng.uniform(-1.0, 1.0, rows.size).astype(dtype)
+    return from_coo(m, n, rows, cols, vals)
+
+
+def table1_standin(name: str, seed: int = 60) -> tuple[Csc, int]:
+    """The stand-in for a Table I matrix and its sketch size d = 3n."""
+    m, n, nnz = TABLE1[name]
+    return row_count_columns(m, n, nnz, seed), 3 * n
+
+
+def abnormal(kind: str, m: int = 100_000, n: int = 10_000, seed: int = 70,
+             dtype=np.float32) -> Csc:
+    """The exotic sparsity patterns of Table VI (density about 1e-3):
+    A -- every 1000th row dense, all other rows empty;
+    B -- about 2998/3000 of the nonzeros in the middle third of the columns
+         (uniform there), the rest uniform over the other columns;
+    C -- every 1000th column dense, all other columns empty.
+    Values U(-1,1)."""
+    rng = np.random.default_rng(seed)
+    step = 1000
+    if kind == "A":
+        r = np.arange(0, m, step, dtype=np.int64)
+        rows = np.repeat(r, n)
+        cols = np.tile(np.arange(n, dtype=np.int64), r.size)
+    elif kind == "C":
+        c = np.arange(0, n, step, dtype=np.int64)
+        rows = np.tile(np.arange(m, dtype=np.int64), c.size)
+        cols = np.repeat(c, m)
+    elif kind == "B":
+        nnz = int(round(1e-3 * m * n))
+        mid = int(round(nnz * 2998 / 3000))
+        c0, c1 = n // 3, 2 * n // 3
+        inside = c0 * m + _distinct_ints(rng, (c1 - c0) * m, mid)
+        outside_n = n - (c1 - c0)
+        o = _distinct_ints(rng, outside_n * m, nnz - mid)
+        oc = o // m
+        oc = np.where(oc < c0, oc, oc + (c1 - c0))  # skip the middle block
+        flat = np.concatenate([inside, oc * m + o % m])
+        rows, cols = flat % m, flat // m
+    else:
+        raise ValueError(kind)
+    vals = rng.uniform(-1.0, 1.0, rows.size).astype(dtype)
+    return from_coo(m, n, rows, cols, vals)
+
+
 @dataclasses.dataclass
 class BatchItem:
     A: Csc
