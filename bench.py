@@ -507,13 +507,27 @@ def bench_spmm_shapes(B, which: str, steps: int) -> dict:
         dA = B.DeviceCsc.from_host(A)
         out_t = torch.empty((A.n, d), dtype=torch.float32, device="cuda")
         out_c = torch.empty_like(out_t)
-        ws = B.alloc_workspace(B.workspace_bytes(dA, d, "uniform"))
+        tile = {"kernel": B.KERNEL_TILE}
+        ws = B.alloc_workspace(B.workspace_bytes(dA, d, "uniform", tune=tile))
         wc = B.alloc_workspace(B.colwise_workspace_bytes(dA))
-        t_ms = timed_ms(lambda: B.sketch_into(dA, d, "uniform", 5, out_t, ws), steps, stream)
+        t_ms = timed_ms(lambda: B.sketch_into(dA, d, "uniform", 5, out_t, ws, tune=tile), steps,
+                        stream)
         R = B.sketch_status(ws)["nonempty_rows"]
         c_ms = timed_ms(lambda: B.sketch_colwise_into(dA, d, "uniform", 5, out_c, wc), steps,
                         stream)
         diff = float(torch.linalg.norm(out_t - out_c) / torch.linalg.norm(out_c))
+        # the library's own choice: the cost model's (no tuning), then the
+        # measured tuner's (cached for the shape class, so tune=None runs it)
+        B.plan_cache_clear()
+        pick = B.plan_info(dA, d, "uniform")["kernel"]
+        wa = B.alloc_workspace(B.workspace_bytes(dA, d, "uniform"))
+        a_ms = timed_ms(lambda: B.sketch_into(dA, d, "uniform", 5, out_c, wa), steps, stream)
+        t0 = time.perf_counter()
+        tuned, _ = B.autotune_measure(dA, d, "uniform", 5, out_c)
+        tune_s = time.perf_counter() - t0
+        wt = B.alloc_workspace(B.workspace_bytes(dA, d, "uniform"))
+        u_ms = timed_ms(lambda: B.sketch_into(dA, d, "uniform", 5, out_c, wt), steps, stream)
+        B.plan_cache_clear()
         nnzd = A.nnz * d
         work_t = R * -(-d // 4) * c_call + R * d * c_val + nnzd
         work_c = A.nnz * -(-d // 4) * c_call + A.nnz * d * c_val + nnzd
@@ -522,16 +536,70 @@ def bench_spmm_shapes(B, which: str, steps: int) -> dict:
                "tile_frac": work_t / (t_ms * 1e-3) / VALU_PEAK,
                "kji_ms": c_ms, "kji_nnz_d_per_s": nnzd / (c_ms * 1e-3),
                "kji_frac": work_c / (c_ms * 1e-3) / VALU_PEAK,
-               "kji_over_tile": c_ms / t_ms, "normwise_difference": diff}
+               "kji_over_tile": c_ms / t_ms, "normwise_difference": diff,
+               "model_kernel": pick, "model_ms": a_ms, "tuned": tuned, "tuned_ms": u_ms,
+               "tuner_seconds": tune_s}
         log(f"{name}: tile {t_ms:.2f} ms ({row['tile_nnz_d_per_s']:.3e} nnz*d/s), kji "
-            f"{c_ms:.2f} ms ({row['kji_nnz_d_per_s']:.3e}), difference {diff:.1e}")
+            f"{c_ms:.2f} ms ({row['kji_nnz_d_per_s']:.3e}), difference {diff:.1e}; model "
+            f"kernel {pick} {a_ms:.2f} ms, tuned {u_ms:.2f} ms {tuned}")
         rows.append(row)
-        del ws, wc, out_t, out_c
+        del ws, wc, wa, wt, out_t, out_c
     return {"workload": ("Table I stand-ins" if which == "table1" else "Table VI patterns") +
                         ": shapes and nonzero counts of the paper's matrices, uniform random "
                         "columns (Table I) or the exotic patterns (m=1e5, n=1e4, density 1e-3), "
                         "d = 3n, S (-1,1) Philox4x32-10 seed 5",
             "generator": gen, "matrices": rows}
+
+
+def bench_tuner(B, names, steps: int) -> dict:
+    """The measured tuner against an exhaustive sweep of the same space
+    (Algorithm 3 kernel; every S-tile kernel shape x splits 1..64) timed
+    the bench's way (event-timed average of `steps` calls), per workload."""
+    import torch
+    stream = torch.cuda.current_stream()
+    res = []
+    for name in names:
+        A, d, dist, seed, _ = make_workload(name)
+        dA = B.DeviceCsc.from_host(A)
+        out = torch.empty((A.n, d), dtype=torch.float32, device="cuda")
+        B.plan_cache_clear()
+
+        def run(tune):
+            ws = B.alloc_workspace(B.workspace_bytes(dA, d, dist, tune=tune))
+            ms = timed_ms(lambda: B.sketch_into(dA, d, dist, seed, out, ws, tune=tune), steps,
+                          stream)
+            del ws
+            return ms
+        model_ms = run(None)
+        model = B.autotune(dA, d, dist)
+        t0 = time.perf_counter()
+        tuned, tuner_ms = B.autotune_measure(dA, d, dist, seed, out)
+        tune_s = time.perf_counter() - t0
+        tuned_ms = run(tuned)
+        sweep = [{"kernel": 2, "ms": run({"kernel": 2})}]
+        for v in range(1, B.variant_count() + 1):
+            for sp in (1, 2, 4, 6, 8, 12, 16, 20, 24, 32, 48, 64):
+                t = {"kernel": 1, "variant": v, "splits": sp}
+                try:
+                    ms = run(t)
+                except (B.SketchError, RuntimeError) as e:  # too many partial slices, ...
+                    log(f"{name}: sweep point {t} skipped: {e}")
+                    continue
+                sweep.append(dict(t, ms=ms))
+            log(f"{name}: swept variant {v}")
+        best = min(sweep, key=lambda r: r["ms"])
+        row = {"workload": name, "d": d, "dist": dist, "model_tuning": model,
+               "model_ms": model_ms, "tuned": tuned, "tuner_own_ms": tuner_ms,
+               "tuned_ms": tuned_ms, "tuner_seconds": tune_s, "best_swept": best,
+               "tuned_over_best": tuned_ms / best["ms"], "model_over_best": model_ms / best["ms"],
+               "sweep_points": len(sweep),
+               "sweep": sorted(sweep, key=lambda r: r["ms"])[:12]}
+        log(f"{name}: model {model_ms:.3f} ms, tuned {tuned} {tuned_ms:.3f} ms, best swept "
+            f"{best} -> tuned/best {row['tuned_over_best']:.3f}")
+        res.append(row)
+        B.plan_cache_clear()
+        del dA, out
+    return {"workloads": res}
 
 
 def main():
@@ -541,7 +609,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plain_scale",
                     help="plain_scale (default), plain_small, skewed, batched, serving, "
-                         "table1, abnormal")
+                         "table1, abnormal, tuner")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
@@ -599,12 +667,22 @@ def main():
             "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64 (sketch f32)", "data": "synthetic", "config": sv}), flush=True)
         return
+    if args.workload == "tuner":
+        tr = bench_tuner(B, ["plain_scale", "skewed"], args.steps)
+        worst = max(r["tuned_over_best"] for r in tr["workloads"])
+        print(json.dumps({
+            "metric": "measured-tuner pick over the best point of an exhaustive sweep",
+            "value": worst, "unit": "ratio (worst workload)", "n_gpus": 1, "steps": args.steps,
+            "warmup": 1, "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": tr}), flush=True)
+        return
     if args.workload in ("table1", "abnormal"):
         sp = bench_spmm_shapes(B, args.workload, args.steps)
         tot = sum(r["nnz"] * r["d"] for r in sp["matrices"])
-        t_ms = sum(r["tile_ms"] for r in sp["matrices"])
+        t_ms = sum(r["tuned_ms"] for r in sp["matrices"])
         print(json.dumps({
-            "metric": "sketched nnz·d per sec on stand-ins for the paper's SpMM matrices",
+            "metric": "sketched nnz·d per sec on stand-ins for the paper's SpMM matrices "
+                      "(measured-tuner plans)",
             "value": tot / (t_ms * 1e-3), "unit": "nnz*d/s", "n_gpus": 1, "steps": args.steps,
             "warmup": 1, "ms_per_step": t_ms, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": sp}), flush=True)

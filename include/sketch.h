@@ -112,6 +112,16 @@ typedef struct {
                              end (the integer-scaling trick; same A_hat as 0).
                              Modes 1 and 3 run on the kernel shapes 3 and 6
                              without dense blocks; else SK_EUNSUPPORTED.    */
+  int32_t kernel;         /* 0 = auto, 1 = the S-tile kernel (Algorithm 4's
+                             reuse of an S tile across a row block; every
+                             field above applies to it), 2 = the Algorithm 3
+                             loop-order kernel of sk_sketch_colwise (FP32,
+                             Philox only; the fields above are ignored except
+                             count_rng and rng_mode, which it refuses with
+                             SK_EUNSUPPORTED).  Auto takes the Algorithm 3
+                             kernel only for FP32 requests that set no other
+                             field, when its predicted time (from the shape
+                             alone) is under half the S-tile kernel's.     */
 } sk_tuning;
 
 /* Human-readable name of a status code (static storage). */
@@ -161,8 +171,9 @@ sk_status sk_sketch_noalloc(const sk_csc* A, int64_t row0, int64_t d, int32_t di
  * saves against reading it from memory): A_hat[0:d, 0:n] = S A with S
  * device FP32, column-major d x m, leading dimension lds >= d rounded up to a
  * multiple of 128 (rows past d are read but never used), 16-byte aligned.
- * Same workspace as sk_sketch(A, d, SK_UNIFORM, SK_PREC_F32, tune), same
- * kernel shapes as sk_tuning.rng_mode.  Asynchronous on hip_stream. */
+ * Same workspace as sk_sketch(A, d, SK_UNIFORM, SK_PREC_F32, tune) on the
+ * S-tile kernel (tune->kernel = 1), which it always runs; same kernel shapes
+ * as sk_tuning.rng_mode.  Asynchronous on hip_stream. */
 sk_status sk_sketch_stored(const sk_csc* A, int64_t d, const float* S, int64_t lds,
                            const sk_tuning* tune, float* Ahat, int64_t ld, void* ws,
                            size_t ws_bytes, void* hip_stream);
@@ -208,10 +219,53 @@ sk_status sk_sketch_status(const void* ws, void* hip_stream, int64_t* nonempty_r
  * Synchronises hip_stream. */
 sk_status sk_sketch_rng_calls(const void* ws, void* hip_stream, uint64_t* calls);
 
-/* Autotuner: the tuning sk_sketch would choose for this shape (a cost model
- * over S-row tile height, rows per block and splits; the kernel shape follows
- * the column count).  Host-only. */
+/* Autotuner, model form: the tuning sk_sketch(prec SK_PREC_F32) would choose
+ * for this shape with tune NULL (the cached plan of the shape class if
+ * sk_autotune_measure filled one; else the cost model: the kernel, then for
+ * the S-tile kernel the S-row tile height and rows per block by cost, the
+ * kernel shape by column count, the splits by occupancy).  Host-only. */
 sk_status sk_autotune(const sk_csc* A, int64_t d, int32_t dist, sk_tuning* out);
+
+/* The cost model's view of a request, for inspection (host-only): info[0] =
+ * predicted S-tile kernel time (us), info[1] = predicted Algorithm 3 kernel
+ * time (us), info[2] = the kernel auto picks (1 or 2), info[3] = the S-tile
+ * plan's cost (CU-cycles), info[4] = its kernel shape (1-based); the first
+ * ninfo of these are written.  tune as for sk_sketch (NULL: the cached
+ * plan, else the model). */
+sk_status sk_plan_info(const sk_csc* A, int64_t d, int32_t dist, int32_t prec,
+                       const sk_tuning* tune, double* info, int32_t ninfo);
+
+/* Autotuner, measured form: runs the candidates on the device and keeps the
+ * fastest.  Stage one times the Algorithm 3 kernel (FP32 only) and every
+ * S-tile kernel shape at the model's splits (the matrix-core path: its one
+ * shape); stage two times splits 1..64 for the two fastest S-tile shapes.
+ * Each candidate: one untimed call, then the best of up to three calls timed
+ * with events on hip_stream (one when already 1.5x slower than the best).
+ * The winner (fields kernel, variant, splits; the rest 0) is written to *out,
+ * its time in ms to *best_ms (may be NULL), and stored in the process-wide
+ * plan cache under the request's shape class: distribution, precision and
+ * the sizes m, n, nnz, d each rounded to half an octave.  From then on
+ * sk_sketch, sk_sketch_workspace, sk_sketch_noalloc and sk_autotune called
+ * with tune NULL on a request of that class use it (query the workspace
+ * after tuning).  The class does not see where the nonzeros sit: matrices of
+ * one size class but different structure (Table VI) should pass their own
+ * tuning.  Synchronises hip_stream; on return A_hat (device FP32, ld >= d)
+ * holds the sketch with the winning tuning (S from seed, rows 0..d-1).  ws:
+ * device workspace of sk_autotune_workspace bytes (the largest any candidate
+ * takes).  An A that fails validation returns its status code and caches
+ * nothing. */
+sk_status sk_autotune_workspace(const sk_csc* A, int64_t d, int32_t dist, int32_t prec,
+                                size_t* bytes);
+sk_status sk_autotune_measure(const sk_csc* A, int64_t d, int32_t dist, uint64_t seed,
+                              int32_t prec, float* Ahat, int64_t ld, void* ws, size_t ws_bytes,
+                              void* hip_stream, sk_tuning* out, double* best_ms);
+
+/* The plan cache (host-only; guarded by one mutex): lookup returns 1 and
+ * writes the cached tuning of the request's shape class, or 0 when there is
+ * none (SK_EINVAL on NULL arguments); clear empties it. */
+int sk_plan_cache_lookup(const sk_csc* A, int64_t d, int32_t dist, int32_t prec,
+                         sk_tuning* out);
+void sk_plan_cache_clear(void);
 
 /* Many independent sketches in one pass (the batched form of sk_sketch):
  * item i computes Ahat[i] = S_i[0:d[i], :] A[i] with S_i from seed[i] and

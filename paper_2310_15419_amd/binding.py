@@ -32,7 +32,8 @@ class SkTuning(ctypes.Structure):
                 ("variant", ctypes.c_int32), ("dense_min_pct", ctypes.c_int32),
                 ("phases", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("col_split", ctypes.c_int32), ("row_pad", ctypes.c_int32),
-                ("count_rng", ctypes.c_int32), ("rng_mode", ctypes.c_int32)]
+                ("count_rng", ctypes.c_int32), ("rng_mode", ctypes.c_int32),
+                ("kernel", ctypes.c_int32)]
 
 
 class SapParams(ctypes.Structure):
@@ -88,6 +89,13 @@ def lib():
                                         ctypes.c_size_t, vp]
         L.sk_materialize_s.argtypes = [i64, i64, i64, i64, i32, u64, vp, i64, vp]
         L.sk_autotune.argtypes = [P(SkCsc), i64, i32, P(SkTuning)]
+        L.sk_plan_info.argtypes = [P(SkCsc), i64, i32, i32, P(SkTuning), P(ctypes.c_double), i32]
+        L.sk_autotune_workspace.argtypes = [P(SkCsc), i64, i32, i32, P(ctypes.c_size_t)]
+        L.sk_autotune_measure.argtypes = [P(SkCsc), i64, i32, u64, i32, vp, i64, vp,
+                                          ctypes.c_size_t, vp, P(SkTuning), P(ctypes.c_double)]
+        L.sk_plan_cache_lookup.argtypes = [P(SkCsc), i64, i32, i32, P(SkTuning)]
+        L.sk_plan_cache_clear.argtypes = []
+        L.sk_plan_cache_clear.restype = None
         L.sk_sketch_batched_workspace.argtypes = [i32, P(SkCsc), P(i64), P(i32), i32, P(SkTuning),
                                                   P(ctypes.c_size_t)]
         L.sk_sketch_batched.argtypes = [i32, P(SkCsc), P(i64), P(i32), P(u64), i32, P(SkTuning),
@@ -110,7 +118,9 @@ def lib():
                      "sk_sketch_rng_calls", "sk_sketch_stored", "sk_rng_throughput",
                      "sk_sketch_colwise_workspace", "sk_sketch_colwise",
                      "sk_materialize_s",
-                     "sk_autotune", "sk_sketch_batched_workspace", "sk_sketch_batched",
+                     "sk_autotune", "sk_plan_info", "sk_autotune_workspace",
+                     "sk_autotune_measure", "sk_plan_cache_lookup",
+                     "sk_sketch_batched_workspace", "sk_sketch_batched",
                      "sk_sketch_batched_plan", "sk_sketch_batched_status", "sk_qr_f64_workspace",
                      "sk_qr_f64", "sk_trinv_f64", "sk_sap_workspace", "sk_sap_begin",
                      "sk_sap_iterate", "sk_sap_finish", "sk_sap_read_info"):
@@ -143,11 +153,10 @@ def _tuning(tune):
         return None
     if isinstance(tune, SkTuning):
         return ctypes.byref(tune)
-    t = SkTuning(int(tune.get("rows_per_block", 0)), int(tune.get("splits", 0)),
-                 int(tune.get("variant", 0)), int(tune.get("dense_min_pct", 0)),
-                 int(tune.get("phases", 0)), int(tune.get("tile_rows", 0)),
-                 int(tune.get("col_split", 0)), int(tune.get("row_pad", 0)),
-                 int(tune.get("count_rng", 0)), int(tune.get("rng_mode", 0)))
+    unknown = set(tune) - {f[0] for f in SkTuning._fields_}
+    if unknown:
+        raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+    t = SkTuning(**{k: int(v) for k, v in tune.items()})
     return ctypes.byref(t)
 
 
@@ -329,6 +338,53 @@ def autotune(A: DeviceCsc, d: int, dist) -> dict:
     return tuning_dict(t)
 
 
+KERNEL_AUTO, KERNEL_TILE, KERNEL_KJI = 0, 1, 2
+
+
+def plan_info(A: DeviceCsc, d: int, dist, prec: int = PREC_F32, tune=None) -> dict:
+    """The cost model's view of a request (sk_plan_info)."""
+    info = (ctypes.c_double * 5)()
+    c = A.c_struct()
+    _check(lib().sk_plan_info(ctypes.byref(c), d, _dist(dist), prec, _tuning(tune), info, 5),
+           "sk_plan_info")
+    return {"tile_us": info[0], "kji_us": info[1], "kernel": int(info[2]),
+            "tile_cost": info[3], "variant": int(info[4])}
+
+
+def autotune_measure(A: DeviceCsc, d: int, dist, seed: int, out, prec: int = PREC_F32,
+                     ws=None, stream=None):
+    """sk_autotune_measure: time the candidates on the device, cache the winner for
+    the shape class; ``out`` (n, d) FP32 then holds the sketch with it.  Returns
+    (tuning dict, ms)."""
+    c = A.c_struct()
+    if ws is None:
+        need = ctypes.c_size_t()
+        _check(lib().sk_autotune_workspace(ctypes.byref(c), d, _dist(dist), prec,
+                                           ctypes.byref(need)), "sk_autotune_workspace")
+        ws = alloc_workspace(int(need.value), out.device)
+    t = SkTuning()
+    ms = ctypes.c_double()
+    _check(lib().sk_autotune_measure(ctypes.byref(c), d, _dist(dist), seed, prec,
+                                     out.data_ptr(), d, ws.data_ptr(), ws.numel(),
+                                     _stream(stream), ctypes.byref(t), ctypes.byref(ms)),
+           "sk_autotune_measure")
+    return tuning_dict(t), float(ms.value)
+
+
+def plan_cache_lookup(A: DeviceCsc, d: int, dist, prec: int = PREC_F32):
+    """The cached tuning of the request's shape class, or None."""
+    t = SkTuning()
+    c = A.c_struct()
+    r = lib().sk_plan_cache_lookup(ctypes.byref(c), d, _dist(dist), prec, ctypes.byref(t))
+    if r < 0 or r > 1:
+        raise SketchError(r, "sk_plan_cache_lookup")
+    return tuning_dict(t) if r == 1 else None
+
+
+def plan_cache_clear() -> None:
+    lib().sk_plan_cache_clear()
+
+
 def tuning_dict(t: SkTuning) -> dict:
     return {f[0]: int(getattr(t, f[0])) for f in SkTuning._fields_}
 
@@ -491,4 +547,5 @@ EXPORTED = ["sk_status_string", "sk_variant_count", "sk_sketch_workspace", "sk_s
             "sk_sketch_batched_workspace", "sk_sketch_batched", "sk_sketch_batched_plan",
             "sk_sketch_batched_status", "sk_qr_f64_workspace", "sk_qr_f64", "sk_trinv_f64",
             "sk_sap_workspace", "sk_sap_begin", "sk_sap_iterate", "sk_sap_finish",
-            "sk_sap_read_info"]
+            "sk_sap_read_info", "sk_plan_info", "sk_autotune_workspace", "sk_autotune_measure",
+            "sk_plan_cache_lookup", "sk_plan_cache_clear"]

@@ -11,7 +11,9 @@
 #include <cstdint>
 #include <cstddef>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 
 #include "sk_batch.hpp"
 #include "sk_colwise.hpp"
@@ -373,6 +375,39 @@ bool plan_mfma(int64_t m, int64_t n, int64_t nnz, int64_t d, int fmt, const sk_t
   return true;
 }
 
+// Predicted time of the Algorithm 3 loop-order kernel (sk_colwise.hpp), in
+// microseconds: every nonzero pays, per tile of 64 DL rows, one lane's
+// generator call(s), transform and DL multiply-adds (measured issue costs on
+// MI355X: a Philox4x32-10 call about 48 full-rate slots, the (-1,1)
+// transform about 2 per value, a Gaussian call with Box-Muller about 180),
+// spread over the 1024 SIMDs; fewer waves than four per SIMD leave the
+// dependent generator chains exposed.  Columns are taken as balanced (the
+// plan sees only the shape).
+double kji_time_us(int64_t n, int64_t nnz, int64_t d, int dist) {
+  const int dl = dist == DIST_RADEMACHER ? 32 : 4;
+  const double per_entry = dist == DIST_RADEMACHER ? 48.0 + 32.0 * 3.0
+                           : dist == DIST_UNIFORM  ? 48.0 + 4.0 * 2.2 + 8.0
+                                                   : 180.0 + 8.0;
+  const double tiles = std::ceil((double)d / (64.0 * dl));
+  const double clk = (double)nnz * tiles * per_entry * 4.0 / 1024.0;  // per SIMD
+  const double waves = std::min<double>((double)n, std::max(1.0, (double)nnz)) * tiles;
+  const double eff = std::min(1.0, waves / 4096.0);
+  return clk / eff / 2400.0 + 5.0;
+}
+
+// Predicted time of the S-tile kernel's plan: its cost model (CU-cycles on
+// 256 CUs at 2.4 GHz) times a factor fitted to measured runs, plus the fixed
+// cost of the inspector and reduction launches.  The model counts issue
+// slots; the column walk's LDS bank conflicts and the lockstep padding it
+// leaves out make the measured time 1.7-2.1x the count on matrices with
+// uniform nonzero positions (the Table I stand-ins, Table VI's B and the
+// 2e6 x 2000 uniform case), hence the factor 2.
+constexpr double kTileCostFactor = 2.0;
+constexpr double kTileFixedUs = 40.0;
+double tile_time_us(const Plan& P) {
+  return kTileCostFactor * P.cost / (256.0 * 2400.0) + kTileFixedUs;
+}
+
 // the plan a request runs with: the matrix-core path or the sparse kernel
 bool plan_any(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, int prec,
               const sk_tuning* tune, Plan& P, int forced_variant = -1, double unit_cycles = 0.0,
@@ -441,6 +476,76 @@ sk_status check_csc(const sk_csc* A) {
   if (A->m >= INT32_MAX || A->nnz >= INT32_MAX) return SK_EUNSUPPORTED;
   if (A->vtype < SK_F64 || A->vtype > SK_BF16) return SK_EINVAL;
   return SK_OK;
+}
+
+// ------------------------------------------------- kernel choice and cache
+enum { KERNEL_AUTO = 0, KERNEL_TILE = 1, KERNEL_KJI = 2 };
+
+// The model takes the Algorithm 3 kernel only when it predicts it twice as
+// fast: the model sees the shape alone and takes the nonzero positions as
+// uniform, while structure it cannot see (most nonzeros in a few rows, as in
+// Table VI's A or a dense row block) gives the S-tile kernel reuse of S
+// that the estimate misses (measured: 2x on A, 1.5x on a 4e6 x 1000 matrix
+// with a dense 2000-row block).  The measured tuner decides the rest.
+constexpr double kKjiMargin = 2.0;
+
+// any field that only the S-tile kernel has
+bool tile_fields_set(const sk_tuning* t) {
+  return t && (t->rows_per_block || t->splits || t->variant || t->dense_min_pct || t->phases ||
+               t->tile_rows || t->col_split || t->row_pad || t->count_rng || t->rng_mode);
+}
+
+// KERNEL_TILE or KERNEL_KJI for a request (FP32 only for the latter); an
+// out-of-range tune->kernel is returned as is (the caller rejects it)
+int choose_kernel(const sk_csc* A, int64_t d, int dist, int prec, const sk_tuning* tune) {
+  if (tune && tune->kernel != KERNEL_AUTO) return tune->kernel;
+  if (prec != SK_PREC_F32 || tile_fields_set(tune)) return KERNEL_TILE;
+  Plan P;
+  if (!plan_for(A->m, A->n, A->nnz, d, dist, tune, P)) return KERNEL_TILE;
+  return kji_time_us(A->n, A->nnz, d, dist) * kKjiMargin < tile_time_us(P) ? KERNEL_KJI
+                                                                              : KERNEL_TILE;
+}
+
+// Plan cache: the tuning sk_autotune_measure found best, per shape class
+// (distribution, precision and the half-octave classes of m, n, nnz and d).
+// The only process-wide mutable state besides the no-allocation scratch
+// array; guarded by one mutex.
+struct ShapeKey {
+  int32_t dist, prec, m, n, nnz, d;
+  bool operator<(const ShapeKey& o) const {
+    return std::tie(dist, prec, m, n, nnz, d) < std::tie(o.dist, o.prec, o.m, o.n, o.nnz, o.d);
+  }
+};
+
+int32_t size_class(int64_t v) {
+  return (int32_t)std::lround(2.0 * std::log2((double)std::max<int64_t>(v, 1)));
+}
+
+ShapeKey shape_key(const sk_csc* A, int64_t d, int dist, int prec) {
+  return ShapeKey{dist, prec, size_class(A->m), size_class(A->n), size_class(A->nnz),
+                  size_class(d)};
+}
+
+std::mutex g_plan_mu;
+std::map<ShapeKey, sk_tuning> g_plans;
+
+// The tuning a request runs with: the caller's if given, else the cached one
+// of its shape class, else none (the model's choice).  A cached entry holds
+// only the searched fields (kernel, kernel shape, splits), so it plans for
+// any matrix of the class.
+const sk_tuning* effective_tuning(const sk_csc* A, int64_t d, int dist, int prec,
+                                  const sk_tuning* tune, sk_tuning& buf) {
+  if (tune) return tune;
+  std::lock_guard<std::mutex> g(g_plan_mu);
+  if (g_plans.empty()) return nullptr;
+  const auto it = g_plans.find(shape_key(A, d, dist, prec));
+  if (it == g_plans.end()) return nullptr;
+  buf = it->second;
+  return &buf;
+}
+
+size_t colwise_bytes() {
+  return (size_t)(align_up((int64_t)sizeof(Header)) + align_up((int64_t)sizeof(Item)));
 }
 
 int blocks_for(int64_t count, int threads) {
@@ -928,6 +1033,45 @@ sk_status scratch_for_current_device(void** out) {
 }  // namespace
 
 namespace {
+// The Algorithm 3 (kji) kernel after the validation pass (arguments checked
+// by the caller).
+sk_status colwise_impl(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint64_t seed,
+                       float* Ahat, int64_t ld, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (!ws || ws_bytes < colwise_bytes()) return SK_EWORKSPACE;
+  const int dl = dist == SK_RADEMACHER ? 32 : 4;
+  const int64_t tiles = (d + 64 * dl - 1) / (64 * dl);
+  const int64_t grid = A->n * ((tiles + CW_WAVES - 1) / CW_WAVES);
+  if (grid >= INT32_MAX) return SK_EUNSUPPORTED;
+  char* w = (char*)ws;
+  Header* hdr = (Header*)w;
+  Item* d_item = (Item*)(w + align_up((int64_t)sizeof(Header)));
+  // validation only: the CSC input is used as given
+  Item I;
+  std::memset(&I, 0, sizeof I);
+  I.m = A->m; I.n = A->n; I.nnz = A->nnz;
+  I.colptr = A->colptr; I.rowidx = A->rowidx; I.vals = A->vals; I.vtype = A->vtype;
+  I.hdr = hdr;
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, (int32_t*)hdr,
+                     (int64_t)(sizeof(Header) / 4), 0);
+  hipLaunchKernelGGL(k_put_item, dim3(1), dim3(64), 0, st, I, d_item);
+  launch_items_cols<&Item::o_valid, OpValidate>(d_item, 1, std::max<int64_t>(A->nnz, A->n + 1),
+                                                st);
+  ColwiseParams P{};
+  P.colptr = A->colptr; P.rowidx = A->rowidx; P.vals = A->vals; P.vtype = A->vtype;
+  P.hdr = hdr; P.n = A->n; P.d = d; P.row0 = row0; P.seed = seed; P.out = Ahat; P.ld = ld;
+  P.tiles = (int32_t)tiles;
+  if (dist == SK_RADEMACHER)
+    hipLaunchKernelGGL((k_sketch_colwise<DIST_RADEMACHER, 32>), dim3((unsigned)grid),
+                       dim3(64 * CW_WAVES), 0, st, P);
+  else if (dist == SK_UNIFORM)
+    hipLaunchKernelGGL((k_sketch_colwise<DIST_UNIFORM, 4>), dim3((unsigned)grid),
+                       dim3(64 * CW_WAVES), 0, st, P);
+  else
+    hipLaunchKernelGGL((k_sketch_colwise<DIST_GAUSSIAN, 4>), dim3((unsigned)grid),
+                       dim3(64 * CW_WAVES), 0, st, P);
+  return launch_ok();
+}
+
 // The sketch with generator mode `gen` (GEN_PHILOX for the product; the
 // others are the distribution-cost ablation's, on the shapes that have them,
 // without the dense path or the folded virtual columns).
@@ -940,6 +1084,18 @@ sk_status sketch_impl(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, ui
   if (d < 1 || row0 < 0 || !Ahat || ld < d || dist < 0 || dist > 2) return SK_EINVAL;
   if (prec < 0 || prec > 2) return SK_EINVAL;
   if (prec != SK_PREC_F32 && dist != SK_RADEMACHER) return SK_EUNSUPPORTED;
+  sk_tuning cached;
+  if (gen == GEN_PHILOX) tune = effective_tuning(A, d, dist, prec, tune, cached);
+  const int kernel = gen == GEN_PHILOX ? choose_kernel(A, d, dist, prec, tune)
+                     : tune && tune->kernel == KERNEL_KJI ? KERNEL_KJI
+                                                          : KERNEL_TILE;
+  if (kernel == KERNEL_KJI) {
+    // the Algorithm 3 kernel has FP32 S only, no ablation or counting forms
+    if (gen != GEN_PHILOX || prec != SK_PREC_F32 || (tune && tune->count_rng))
+      return SK_EUNSUPPORTED;
+    return colwise_impl(A, row0, d, dist, seed, Ahat, ld, ws, ws_bytes, (hipStream_t)hip_stream);
+  }
+  if (kernel != KERNEL_TILE) return SK_EINVAL;
   Plan P;
   if (!plan_any(A->m, A->n, A->nnz, d, dist, prec, tune, P)) return SK_EINVAL;
   if ((int64_t)(P.nb_max + 1) * P.nv >= INT32_MAX) return SK_EUNSUPPORTED;
@@ -1081,6 +1237,94 @@ sk_status sketch_impl(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, ui
   return launch_ok();
 }
 
+// ------------------------------------------------------ measured tuner
+// Splits tried for the chosen S-tile shapes, and the most partial-slice
+// memory a candidate may take.
+constexpr int kSplitCands[] = {1, 2, 4, 6, 8, 12, 16, 20, 24, 32, 48, 64};
+constexpr int64_t kTunePartMax = int64_t(4) << 30;
+
+sk_tuning searched(int kernel, int variant, int splits) {
+  sk_tuning t;
+  std::memset(&t, 0, sizeof t);
+  t.kernel = kernel;
+  t.variant = variant;
+  t.splits = splits;
+  return t;
+}
+
+// stage one: the Algorithm 3 kernel (FP32) and each S-tile kernel shape at
+// the model's splits (the matrix-core path has one shape)
+std::vector<sk_tuning> tune_stage_one(const sk_csc* A, int dist, int prec) {
+  std::vector<sk_tuning> c;
+  if (prec == SK_PREC_F32) c.push_back(searched(KERNEL_KJI, 0, 0));
+  if (mfma_format(A->m, A->n, A->nnz, dist, prec, nullptr)) {
+    c.push_back(searched(KERNEL_TILE, 0, 0));
+    return c;
+  }
+  for (int v = 1; v <= kNumVariants; ++v) c.push_back(searched(KERNEL_TILE, v, 0));
+  return c;
+}
+
+// stage two: the splits of one S-tile shape (variant 0: the matrix cores)
+std::vector<sk_tuning> tune_stage_two(const sk_csc* A, int64_t d, int dist, int prec,
+                                      int variant) {
+  std::vector<sk_tuning> c;
+  for (int sp : kSplitCands) {
+    const sk_tuning t = searched(KERNEL_TILE, variant, sp);
+    Plan P;
+    if (!plan_any(A->m, A->n, A->nnz, d, dist, prec, &t, P)) continue;
+    if (P.splits != sp) continue;  // clamped to the block count
+    if ((int64_t)P.splits * d * P.nv * 4 > kTunePartMax) continue;
+    c.push_back(t);
+  }
+  return c;
+}
+
+// every candidate either stage may run (for the workspace bound)
+std::vector<sk_tuning> tune_candidates_all(const sk_csc* A, int64_t d, int dist, int prec) {
+  std::vector<sk_tuning> c = tune_stage_one(A, dist, prec);
+  const size_t first = c.size();
+  for (size_t i = 0; i < first; ++i)
+    if (c[i].kernel == KERNEL_TILE)
+      for (const sk_tuning& t : tune_stage_two(A, d, dist, prec, c[i].variant)) c.push_back(t);
+  return c;
+}
+
+// The time of one sketch with tuning t, in ms: one untimed call, then the
+// fastest of up to three timed ones (one only when it is already slower
+// than `cutoff_ms`), each bracketed by events on the stream.
+sk_status time_call(const sk_csc* A, int64_t d, int dist, uint64_t seed, int prec,
+                    const sk_tuning& t, float* Ahat, int64_t ld, void* ws, size_t ws_bytes,
+                    hipStream_t st, double cutoff_ms, double* ms) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return SK_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return SK_EHIP;
+  }
+  double best = INFINITY;
+  sk_status s = sketch_impl(A, 0, d, dist, seed, prec, &t, Ahat, ld, ws, ws_bytes, st,
+                            GEN_PHILOX, nullptr, 0);
+  for (int r = 0; s == SK_OK && r < 3; ++r) {
+    if (hipEventRecord(e0, st) != hipSuccess) { s = SK_EHIP; break; }
+    s = sketch_impl(A, 0, d, dist, seed, prec, &t, Ahat, ld, ws, ws_bytes, st, GEN_PHILOX,
+                    nullptr, 0);
+    if (s != SK_OK) break;
+    float f = 0.0f;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&f, e0, e1) != hipSuccess) {
+      s = SK_EHIP;
+      break;
+    }
+    best = std::min(best, (double)f);
+    if (best > cutoff_ms) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *ms = best;
+  return s;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1108,6 +1352,19 @@ sk_status sk_sketch_workspace(const sk_csc* A, int64_t d, int32_t dist, int32_t 
   if (s != SK_OK) return s;
   if (d < 1 || dist < 0 || dist > 2 || prec < 0 || prec > 2) return SK_EINVAL;
   if (prec != SK_PREC_F32 && dist != SK_RADEMACHER) return SK_EUNSUPPORTED;
+  sk_tuning cached;
+  const int gen = tune ? tune->rng_mode : GEN_PHILOX;
+  if (gen == GEN_PHILOX) tune = effective_tuning(A, d, dist, prec, tune, cached);
+  const int kernel = gen == GEN_PHILOX ? choose_kernel(A, d, dist, prec, tune)
+                     : tune && tune->kernel == KERNEL_KJI ? KERNEL_KJI
+                                                          : KERNEL_TILE;
+  if (kernel == KERNEL_KJI) {
+    if (gen != GEN_PHILOX || prec != SK_PREC_F32 || (tune && tune->count_rng))
+      return SK_EUNSUPPORTED;
+    *bytes = colwise_bytes();
+    return SK_OK;
+  }
+  if (kernel != KERNEL_TILE) return SK_EINVAL;
   Plan P;
   if (!plan_any(A->m, A->n, A->nnz, d, dist, prec, tune, P)) return SK_EINVAL;
   *bytes = (size_t)layout_for(A->m, A->n, A->nnz, d, P).total;
@@ -1136,7 +1393,7 @@ sk_status sk_sketch_colwise_workspace(const sk_csc* A, size_t* bytes) {
   if (!bytes) return SK_EINVAL;
   sk_status s = check_csc(A);
   if (s != SK_OK) return s;
-  *bytes = (size_t)(align_up((int64_t)sizeof(Header)) + align_up((int64_t)sizeof(Item)));
+  *bytes = colwise_bytes();
   return SK_OK;
 }
 
@@ -1146,41 +1403,7 @@ sk_status sk_sketch_colwise(const sk_csc* A, int64_t row0, int64_t d, int32_t di
   sk_status s = check_csc(A);
   if (s != SK_OK) return s;
   if (d < 1 || row0 < 0 || !Ahat || ld < d || dist < 0 || dist > 2) return SK_EINVAL;
-  size_t need = 0;
-  if ((s = sk_sketch_colwise_workspace(A, &need)) != SK_OK) return s;
-  if (!ws || ws_bytes < need) return SK_EWORKSPACE;
-  hipStream_t st = (hipStream_t)hip_stream;
-  char* w = (char*)ws;
-  Header* hdr = (Header*)w;
-  Item* d_item = (Item*)(w + align_up((int64_t)sizeof(Header)));
-  // validation only: the CSC input is used as given
-  Item I;
-  std::memset(&I, 0, sizeof I);
-  I.m = A->m; I.n = A->n; I.nnz = A->nnz;
-  I.colptr = A->colptr; I.rowidx = A->rowidx; I.vals = A->vals; I.vtype = A->vtype;
-  I.hdr = hdr;
-  hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, (int32_t*)hdr,
-                     (int64_t)(sizeof(Header) / 4), 0);
-  hipLaunchKernelGGL(k_put_item, dim3(1), dim3(64), 0, st, I, d_item);
-  launch_items_cols<&Item::o_valid, OpValidate>(d_item, 1, std::max<int64_t>(A->nnz, A->n + 1),
-                                                st);
-  ColwiseParams P{};
-  P.colptr = A->colptr; P.rowidx = A->rowidx; P.vals = A->vals; P.vtype = A->vtype;
-  P.hdr = hdr; P.n = A->n; P.d = d; P.row0 = row0; P.seed = seed; P.out = Ahat; P.ld = ld;
-  const int dl = dist == SK_RADEMACHER ? 32 : 4;
-  P.tiles = (int32_t)((d + 64 * dl - 1) / (64 * dl));
-  const int64_t grid = A->n * ((P.tiles + CW_WAVES - 1) / CW_WAVES);
-  if (grid >= INT32_MAX) return SK_EUNSUPPORTED;
-  if (dist == SK_RADEMACHER)
-    hipLaunchKernelGGL((k_sketch_colwise<DIST_RADEMACHER, 32>), dim3((unsigned)grid),
-                       dim3(64 * CW_WAVES), 0, st, P);
-  else if (dist == SK_UNIFORM)
-    hipLaunchKernelGGL((k_sketch_colwise<DIST_UNIFORM, 4>), dim3((unsigned)grid),
-                       dim3(64 * CW_WAVES), 0, st, P);
-  else
-    hipLaunchKernelGGL((k_sketch_colwise<DIST_GAUSSIAN, 4>), dim3((unsigned)grid),
-                       dim3(64 * CW_WAVES), 0, st, P);
-  return launch_ok();
+  return colwise_impl(A, row0, d, dist, seed, Ahat, ld, ws, ws_bytes, (hipStream_t)hip_stream);
 }
 
 sk_status sk_rng_throughput(int32_t dist, int32_t gen, int64_t calls, int32_t blocks,
@@ -1448,14 +1671,38 @@ sk_status sk_sketch_batched_status(const void* ws, int32_t count, void* hip_stre
   return worst;
 }
 
+sk_status sk_plan_info(const sk_csc* A, int64_t d, int32_t dist, int32_t prec,
+                       const sk_tuning* tune, double* info, int32_t ninfo) {
+  sk_status s = check_csc(A);
+  if (s != SK_OK) return s;
+  if (d < 1 || dist < 0 || dist > 2 || prec < 0 || prec > 2 || !info || ninfo < 1)
+    return SK_EINVAL;
+  sk_tuning cached;
+  tune = effective_tuning(A, d, dist, prec, tune, cached);
+  Plan P;
+  if (!plan_any(A->m, A->n, A->nnz, d, dist, prec, tune, P)) return SK_EINVAL;
+  const double v[5] = {tile_time_us(P), kji_time_us(A->n, A->nnz, d, dist),
+                       (double)choose_kernel(A, d, dist, prec, tune), P.cost,
+                       (double)(P.variant + 1)};
+  for (int i = 0; i < ninfo && i < 5; ++i) info[i] = v[i];
+  return SK_OK;
+}
+
 sk_status sk_autotune(const sk_csc* A, int64_t d, int32_t dist, sk_tuning* out) {
   if (!out) return SK_EINVAL;
   sk_status s = check_csc(A);
   if (s != SK_OK) return s;
   if (d < 1 || dist < 0 || dist > 2) return SK_EINVAL;
-  Plan P;
-  if (!plan_for(A->m, A->n, A->nnz, d, dist, nullptr, P)) return SK_EINVAL;
+  sk_tuning cached;
+  const sk_tuning* tune = effective_tuning(A, d, dist, SK_PREC_F32, nullptr, cached);
   std::memset(out, 0, sizeof *out);
+  if (choose_kernel(A, d, dist, SK_PREC_F32, tune) == KERNEL_KJI) {
+    out->kernel = KERNEL_KJI;
+    return SK_OK;
+  }
+  Plan P;
+  if (!plan_for(A->m, A->n, A->nnz, d, dist, tune, P)) return SK_EINVAL;
+  out->kernel = KERNEL_TILE;
   out->rows_per_block = P.m_b;
   out->splits = P.splits;
   out->variant = P.variant + 1;
@@ -1463,6 +1710,99 @@ sk_status sk_autotune(const sk_csc* A, int64_t d, int32_t dist, sk_tuning* out) 
   out->tile_rows = P.d_b;
   out->col_split = P.nv != A->n ? 2 : 1;
   return SK_OK;
+}
+
+sk_status sk_autotune_workspace(const sk_csc* A, int64_t d, int32_t dist, int32_t prec,
+                                size_t* bytes) {
+  if (!bytes) return SK_EINVAL;
+  sk_status s = check_csc(A);
+  if (s != SK_OK) return s;
+  if (d < 1 || dist < 0 || dist > 2 || prec < 0 || prec > 2) return SK_EINVAL;
+  if (prec != SK_PREC_F32 && dist != SK_RADEMACHER) return SK_EUNSUPPORTED;
+  size_t most = 0;
+  for (const sk_tuning& t : tune_candidates_all(A, d, dist, prec)) {
+    size_t b = 0;
+    if (sk_sketch_workspace(A, d, dist, prec, &t, &b) == SK_OK) most = std::max(most, b);
+  }
+  *bytes = most;
+  return SK_OK;
+}
+
+sk_status sk_autotune_measure(const sk_csc* A, int64_t d, int32_t dist, uint64_t seed,
+                              int32_t prec, float* Ahat, int64_t ld, void* ws, size_t ws_bytes,
+                              void* hip_stream, sk_tuning* out, double* best_ms) {
+  if (!out) return SK_EINVAL;
+  sk_status s = check_csc(A);
+  if (s != SK_OK) return s;
+  if (d < 1 || !Ahat || ld < d || dist < 0 || dist > 2 || prec < 0 || prec > 2) return SK_EINVAL;
+  size_t need = 0;
+  if ((s = sk_autotune_workspace(A, d, dist, prec, &need)) != SK_OK) return s;
+  if (!ws || ws_bytes < need) return SK_EWORKSPACE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  // stage one: the two kernels, and every S-tile kernel shape at the
+  // model's splits
+  std::vector<std::pair<double, sk_tuning>> timed;
+  double best = INFINITY;
+  for (const sk_tuning& t : tune_stage_one(A, dist, prec)) {
+    double ms = 0.0;
+    s = time_call(A, d, dist, seed, prec, t, Ahat, ld, ws, ws_bytes, st, 1.5 * best, &ms);
+    if (s == SK_EUNSUPPORTED || s == SK_EINVAL) continue;  // not a form this request has
+    if (s != SK_OK) return s;
+    // an invalid A: report it and cache nothing; a plan whose block bound
+    // the matrix exceeds: not a candidate
+    s = sk_sketch_status(ws, st, nullptr, nullptr);
+    if (s == SK_EUNSUPPORTED) continue;
+    if (s != SK_OK) return s;
+    timed.emplace_back(ms, t);
+    best = std::min(best, ms);
+  }
+  if (timed.empty()) return SK_EUNSUPPORTED;
+  // stage two: the splits of the two fastest S-tile shapes
+  std::vector<std::pair<double, sk_tuning>> tiles;
+  for (const auto& e : timed)
+    if (e.second.kernel == KERNEL_TILE) tiles.push_back(e);
+  std::sort(tiles.begin(), tiles.end(),
+            [](const auto& a, const auto& b) { return a.first < b.first; });
+  for (size_t i = 0; i < tiles.size() && i < 2; ++i) {
+    for (const sk_tuning& t : tune_stage_two(A, d, dist, prec, tiles[i].second.variant)) {
+      double ms = 0.0;
+      s = time_call(A, d, dist, seed, prec, t, Ahat, ld, ws, ws_bytes, st, 1.5 * best, &ms);
+      if (s == SK_EUNSUPPORTED || s == SK_EINVAL) continue;
+      if (s != SK_OK) return s;
+      s = sk_sketch_status(ws, st, nullptr, nullptr);
+      if (s == SK_EUNSUPPORTED) continue;
+      if (s != SK_OK) return s;
+      timed.emplace_back(ms, t);
+      best = std::min(best, ms);
+    }
+  }
+  const auto win = std::min_element(timed.begin(), timed.end(), [](const auto& a, const auto& b) {
+    return a.first < b.first;
+  });
+  *out = win->second;
+  if (best_ms) *best_ms = win->first;
+  {
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    g_plans[shape_key(A, d, dist, prec)] = win->second;
+  }
+  // leave the sketch of the chosen tuning in A_hat
+  return sketch_impl(A, 0, d, dist, seed, prec, out, Ahat, ld, ws, ws_bytes, hip_stream,
+                     GEN_PHILOX, nullptr, 0);
+}
+
+int sk_plan_cache_lookup(const sk_csc* A, int64_t d, int32_t dist, int32_t prec,
+                         sk_tuning* out) {
+  if (!A || !out) return SK_EINVAL;
+  std::lock_guard<std::mutex> g(g_plan_mu);
+  const auto it = g_plans.find(shape_key(A, d, dist, prec));
+  if (it == g_plans.end()) return 0;
+  *out = it->second;
+  return 1;
+}
+
+void sk_plan_cache_clear(void) {
+  std::lock_guard<std::mutex> g(g_plan_mu);
+  g_plans.clear();
 }
 
 // ------------------------------------------------------------------ SAP

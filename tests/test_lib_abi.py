@@ -132,3 +132,76 @@ def test_noalloc_oversize_refused_on_host():
                                  None) == -4
     assert lib.sk_sketch_noalloc(ctypes.byref(_csc(m=0)), 0, 64, 1, 1, 0, None, out, 64,
                                  None) == -1
+
+
+def _info(c, d, dist, prec=0, tune=None):
+    info = (ctypes.c_double * 5)()
+    assert binding.lib().sk_plan_info(ctypes.byref(c), d, dist, prec,
+                                      ctypes.byref(tune) if tune else None, info, 5) == 0
+    return list(info)
+
+
+def test_kernel_choice_host_only():
+    lib = binding.lib()
+    lib.sk_plan_cache_clear()
+    # a Table I shape (few nonzeros per row, d = 3n): the Algorithm 3 kernel;
+    # the 2e6 x 2000 uniform case and tiny cases: the S-tile kernel
+    ch7 = _csc(m=105840, n=17640, nnz=423360)
+    info = _info(ch7, 3 * 17640, 1)
+    assert info[2] == 2 and info[1] * 2 < info[0]
+    assert _info(_csc(m=2_000_000, n=2000, nnz=20_000_000), 4000, 1)[2] == 1
+    assert _info(_csc(m=100_000, n=200, nnz=200_000), 400, 0)[2] == 1
+    # sk_autotune reports the kernel; its workspace is the validation record only
+    t = binding.SkTuning()
+    assert lib.sk_autotune(ctypes.byref(ch7), 3 * 17640, 1, ctypes.byref(t)) == 0
+    assert t.kernel == 2 and t.splits == 0
+    out = ctypes.c_size_t()
+    assert lib.sk_sketch_workspace(ctypes.byref(ch7), 3 * 17640, 1, 0, None,
+                                   ctypes.byref(out)) == 0
+    kji = ctypes.c_size_t()
+    assert lib.sk_sketch_colwise_workspace(ctypes.byref(ch7), ctypes.byref(kji)) == 0
+    assert out.value == kji.value
+    # any S-tile field keeps the S-tile kernel; kernel = 1 forces it
+    for field in ("splits", "variant", "col_split"):
+        t = binding.SkTuning()
+        setattr(t, field, 1)
+        assert _info(ch7, 3 * 17640, 1, tune=t)[2] == 1, field
+    t = binding.SkTuning(kernel=1)
+    assert lib.sk_sketch_workspace(ctypes.byref(ch7), 3 * 17640, 1, 0, ctypes.byref(t),
+                                   ctypes.byref(out)) == 0
+    assert out.value > kji.value
+    # the Algorithm 3 kernel has FP32 S only and no ablation / counting forms
+    t = binding.SkTuning(kernel=2)
+    assert lib.sk_sketch_workspace(ctypes.byref(ch7), 1000, 0, 1, ctypes.byref(t),
+                                   ctypes.byref(out)) == -6
+    t = binding.SkTuning(kernel=2, count_rng=1)
+    assert lib.sk_sketch_workspace(ctypes.byref(ch7), 1000, 0, 0, ctypes.byref(t),
+                                   ctypes.byref(out)) == -6
+    t = binding.SkTuning(kernel=3)
+    assert lib.sk_sketch_workspace(ctypes.byref(ch7), 1000, 0, 0, ctypes.byref(t),
+                                   ctypes.byref(out)) == -1
+
+
+def test_measured_tuner_host_side():
+    lib = binding.lib()
+    lib.sk_plan_cache_clear()
+    c = _csc(m=2_000_000, n=2000, nnz=20_000_000)
+    t = binding.SkTuning()
+    assert lib.sk_plan_cache_lookup(ctypes.byref(c), 4000, 1, 0, ctypes.byref(t)) == 0
+    # the tuner's workspace covers every candidate, the default plan among them
+    tw, sw = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.sk_autotune_workspace(ctypes.byref(c), 4000, 1, 0, ctypes.byref(tw)) == 0
+    assert lib.sk_sketch_workspace(ctypes.byref(c), 4000, 1, 0, None, ctypes.byref(sw)) == 0
+    assert tw.value >= sw.value
+    for sp in (1, 8, 32):
+        one = binding.SkTuning(kernel=1, variant=3, splits=sp)
+        assert lib.sk_sketch_workspace(ctypes.byref(c), 4000, 1, 0, ctypes.byref(one),
+                                       ctypes.byref(sw)) == 0
+        assert tw.value >= sw.value
+    # argument errors come back before any device work
+    ms = ctypes.c_double()
+    assert lib.sk_autotune_measure(ctypes.byref(c), 4000, 1, 1, 0, ctypes.c_void_p(8), 4000,
+                                   ctypes.c_void_p(8), 16, None, ctypes.byref(t),
+                                   ctypes.byref(ms)) == -4
+    assert lib.sk_autotune_measure(ctypes.byref(c), 4000, 1, 1, 0, None, 4000, None, 0, None,
+                                   ctypes.byref(t), ctypes.byref(ms)) == -1
