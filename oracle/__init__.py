@@ -16,7 +16,11 @@ something other than itself):
                    E[A_hat^T A_hat] = d sigma^2 A^T A, subspace embedding
   parity        -- error measures only (no part of the method); pinned by a
                    brute-force recomputation on a small case
-  ls_*          -- numpy least squares on dense inputs
+  ls_error / sap_solve_reference -- numpy least squares on dense inputs
+  sap_svd_reference -- the minimum-norm solution of exactly rank-deficient
+                   stand-ins (orthogonality to the known null vectors, numpy's
+                   minimum-norm lstsq), the drop threshold from both sides,
+                   agreement with the QR form on full-rank input
 """
 from __future__ import annotations
 
@@ -187,4 +191,4 @@ def max_threads() -> int:
     return lib().or_max_threads()
 
 
-from .lsq import ls_error, sap_solve_reference  # noqa: E402  (plain numpy LS oracle)
+from .lsq import SVD_DROP, ls_error, sap_solve_reference, sap_svd_reference  # noqa: E402,F401

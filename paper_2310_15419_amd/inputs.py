@@ -304,3 +304,63 @@ def ls_request(seed: int, m: int, n: int, dense_rows: int = 2000, noise: float =
     x = rng.standard_normal(n)
     b = A.to_scipy() @ x + noise * rng.standard_normal(m)
     return A, b, x
+
+
+def ls_request_rank_deficient(seed: int, m: int, n: int, rank: int, dense_rows: int = 300,
+                              near: float = 0.0, noise: float = 1e-6):
+    """A least-squares request whose A has singular values at or near zero (the
+    role of the numerically rank-deficient matrices of Sec. V-E-1): `rank`
+    base columns from the power-law generator with a dense block, values on
+    the grid k/1024 (so sums of them are exact in FP32 and FP64); then n - rank
+    dependent columns, in turn an exact sum of two base columns, a power-of-two
+    multiple of one, and an empty column.  near > 0 adds to the first
+    dependent column one entry of that size in a row where it has none (the
+    column is then independent, with a singular value of about `near`).
+    x_true ~ N(0, I), b = A x_true + noise * N(0, I).
+
+    Returns (A FP64, b, null) with null the list of dependencies: (j, {col:
+    coefficient}) meaning column j = sum coefficient * column, exact (the
+    first one not exact when near > 0)."""
+    if not 2 <= rank < n:
+        raise ValueError("need 2 <= rank < n")
+    base, _ = power_law_columns(m, rank, seed, 0.05, max(dense_rows, rank), np.float64)
+    q = np.round(base.vals * 1024.0)
+    q[q == 0] = 1.0
+    rng = np.random.default_rng(seed + 104729)
+    cols = {}
+    for k in range(rank):
+        sl = slice(base.colptr[k], base.colptr[k + 1])
+        cols[k] = dict(zip(base.rowidx[sl].tolist(), (q[sl] / 1024.0).tolist()))
+    null = []
+    for j in range(rank, n):
+        kind = (j - rank) % 3
+        if kind == 0:
+            a, c = (int(v) for v in rng.choice(rank, size=2, replace=False))
+            col = dict(cols[a])
+            for r_, v in cols[c].items():
+                col[r_] = col.get(r_, 0.0) + v
+            null.append((j, {a: 1.0, c: 1.0}))
+        elif kind == 1:
+            a = int(rng.integers(rank))
+            f = float(2.0 ** int(rng.integers(-3, 4)))
+            col = {r_: f * v for r_, v in cols[a].items()}
+            null.append((j, {a: f}))
+        else:
+            col = {}
+            null.append((j, {}))
+        cols[j] = col
+    if near > 0.0:
+        j0 = rank
+        free = np.setdiff1d(np.arange(m), np.fromiter(cols[j0].keys(), dtype=np.int64))
+        cols[j0][int(rng.choice(free))] = near
+    rows, cidx, vals = [], [], []
+    for j in range(n):
+        items = sorted(cols[j].items())
+        rows.extend(r_ for r_, _ in items)
+        cidx.extend([j] * len(items))
+        vals.extend(v for _, v in items)
+    A = from_coo(m, n, np.array(rows, dtype=np.int64), np.array(cidx, dtype=np.int64),
+                 np.array(vals, dtype=np.float64))
+    x = rng.standard_normal(n)
+    b = A.to_scipy() @ x + noise * rng.standard_normal(m)
+    return A, b, null
