@@ -193,6 +193,15 @@ sk_status sk_sketch_colwise(const sk_csc* A, int64_t row0, int64_t d, int32_t di
                             uint64_t seed, float* Ahat, int64_t ld, void* ws, size_t ws_bytes,
                             void* hip_stream);
 
+/* The same in FP64: A's values in FP64 (FP32 and BF16 widen exactly), the same
+ * S entries (exact in FP64), FP64 sums; A_hat device FP64, column-major, ld >=
+ * d.  For uses that need the sketch beyond FP32 accuracy (the SVD form of
+ * sketch-and-precondition drops singular values only below sigma_max / 1e12).
+ * Workspace and status as sk_sketch_colwise. */
+sk_status sk_sketch_colwise_f64(const sk_csc* A, int64_t row0, int64_t d, int32_t dist,
+                                uint64_t seed, double* Ahat, int64_t ld, void* ws,
+                                size_t ws_bytes, void* hip_stream);
+
 /* Generator throughput, for measuring the cost of one call (the h of Sec.
  * III-A): blocks x 256 threads each make `calls` calls of the generator
  * (gen 0 = Philox4x32-10, 1 = the junk hash of sk_tuning.rng_mode) with the
@@ -335,6 +344,22 @@ sk_status sk_qr_f64(int64_t d, int64_t n, double* A, int64_t lda, double* R, int
 sk_status sk_trinv_f64(int64_t n, const double* R, int64_t ldr, double* Rinv, int64_t ldi,
                        void* hip_stream);
 
+/* One-sided Jacobi SVD in FP64 (the decomposition of the SVD form of
+ * sketch-and-precondition, Sec. V-E-1): G (rows x n, column-major, ld = rows,
+ * rows >= n, 1 <= n <= 8192; device) is orthogonalised in place by plane
+ * rotations of column pairs in the round-robin parallel order until every
+ * pair satisfies |g_p . g_q| <= sqrt(rows) 2^-52 |g_p| |g_q|; the same
+ * rotations accumulate V (n x n, ld = n; device, overwritten).  On return
+ * G = U diag(sigma) (columns orthogonal), V orthogonal, the input equals
+ * G V^T, and sigma[j] = |g_j| (device, n entries, in column order, not
+ * sorted).  *sweeps (host, may be NULL) receives the sweeps run, negated when
+ * the iteration stopped at 40 sweeps without converging.  ws: device
+ * workspace of sk_svd_f64_workspace bytes.  Synchronises hip_stream
+ * (between batches of sweeps). */
+sk_status sk_svd_f64_workspace(int64_t rows, int64_t n, size_t* bytes);
+sk_status sk_svd_f64(int64_t rows, int64_t n, double* G, double* V, double* sigma,
+                     int32_t* sweeps, void* ws, size_t ws_bytes, void* hip_stream);
+
 typedef struct {
   int64_t d;        /* sketch rows, n <= d (the paper uses d = 2n)            */
   int32_t dist;     /* sk_dist of S                                           */
@@ -344,8 +369,23 @@ typedef struct {
   double btol;      /* conlim); conlim <= 0 disables the condition test       */
   double conlim;
   int32_t iter_lim; /* LSQR iteration limit                                   */
-  int32_t pad;
+  int32_t method;   /* SK_SAP_QR or SK_SAP_SVD                                */
 } sk_sap_params;
+
+/* sk_sap_params.method.  SK_SAP_QR: preconditioner R^{-1} from the QR of the
+ * sketch (A must have full column rank).  SK_SAP_SVD (Sec. V-E-1, for A with
+ * singular values near zero): the sketch's singular values sigma_j and right
+ * singular vectors v_j (the QR's R orthogonalised by one-sided Jacobi
+ * rotations in FP64), the singular values below sigma_max / 1e12 dropped;
+ * preconditioner N = sum over the kept j of v_j e_j^T / sigma_j, and x = N y,
+ * so x has no component along the dropped directions (for an exactly
+ * rank-deficient A: the minimum-norm least-squares solution).  The SVD form
+ * sketches in FP64 (sk_sketch_colwise_f64; prec must be SK_PREC_F32, else
+ * SK_EUNSUPPORTED), since an FP32 sketch's rounding leaves singular values
+ * near 1e-7 sigma_max where A has none.  It synchronises hip_stream inside
+ * sk_sap_begin (between Jacobi sweeps, to stop once a sweep rotates nothing;
+ * at most 40 sweeps). */
+enum { SK_SAP_QR = 0, SK_SAP_SVD = 1 };
 
 /* Solver info; the first sizeof(sk_sap_info) bytes of an SAP workspace hold it
  * (device memory) from sk_sap_begin on.  istop follows LSQR's codes: 0 running,
@@ -362,14 +402,20 @@ typedef struct {
   double xnorm;   /* ||y|| estimate                     */
   double bnorm;
   double test1, test2, test3;
+  int32_t rank;   /* columns of the preconditioner kept (n for SK_SAP_QR) */
+  int32_t sweeps; /* Jacobi sweeps (SK_SAP_SVD; 0 for SK_SAP_QR)         */
 } sk_sap_info;
 
 /* Workspace for one solve (device bytes; includes the sketch's workspace, the
- * FP64 QR, R^{-1}, a row-major copy of A and the LSQR vectors). */
+ * FP64 QR, R^{-1} (or, for the SVD form, the Jacobi matrices and N), a
+ * row-major copy of A and the LSQR vectors).  The sketch runs with tune NULL,
+ * so a plan the measured tuner caches for its shape class afterwards can
+ * change the size: query the workspace after tuning. */
 sk_status sk_sap_workspace(const sk_csc* A, const sk_sap_params* p, size_t* bytes);
 
-/* Enqueue on hip_stream: sketch, widen, QR, R^{-1}, the row-major copy of A,
- * and LSQR's start from b (device FP64, m entries). */
+/* Enqueue on hip_stream: sketch, widen, QR, R^{-1} (or the Jacobi SVD and N),
+ * the row-major copy of A, and LSQR's start from b (device FP64, m
+ * entries). */
 sk_status sk_sap_begin(const sk_csc* A, const double* b, const sk_sap_params* p, void* ws,
                        size_t ws_bytes, void* hip_stream);
 
@@ -378,7 +424,7 @@ sk_status sk_sap_begin(const sk_csc* A, const double* b, const sk_sap_params* p,
 sk_status sk_sap_iterate(const sk_csc* A, const sk_sap_params* p, int32_t iters, void* ws,
                          size_t ws_bytes, void* hip_stream);
 
-/* Enqueue x = R^{-1} y (x: device FP64, n entries). */
+/* Enqueue x = R^{-1} y, or x = N y (x: device FP64, n entries). */
 sk_status sk_sap_finish(const sk_csc* A, const sk_sap_params* p, double* x, void* ws,
                         size_t ws_bytes, void* hip_stream);
 

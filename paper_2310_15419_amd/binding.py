@@ -40,7 +40,7 @@ class SapParams(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int64), ("dist", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("atol", ctypes.c_double), ("btol", ctypes.c_double),
                 ("conlim", ctypes.c_double), ("iter_lim", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("method", ctypes.c_int32)]
 
 
 class SapInfo(ctypes.Structure):
@@ -50,7 +50,8 @@ class SapInfo(ctypes.Structure):
                 ("anorm", ctypes.c_double), ("acond", ctypes.c_double),
                 ("xnorm", ctypes.c_double), ("bnorm", ctypes.c_double),
                 ("test1", ctypes.c_double), ("test2", ctypes.c_double),
-                ("test3", ctypes.c_double)]
+                ("test3", ctypes.c_double),
+                ("rank", ctypes.c_int32), ("sweeps", ctypes.c_int32)]
 
 
 class SketchError(RuntimeError):
@@ -87,6 +88,8 @@ def lib():
         L.sk_sketch_colwise_workspace.argtypes = [P(SkCsc), P(ctypes.c_size_t)]
         L.sk_sketch_colwise.argtypes = [P(SkCsc), i64, i64, i32, u64, vp, i64, vp,
                                         ctypes.c_size_t, vp]
+        L.sk_sketch_colwise_f64.argtypes = [P(SkCsc), i64, i64, i32, u64, vp, i64, vp,
+                                            ctypes.c_size_t, vp]
         L.sk_materialize_s.argtypes = [i64, i64, i64, i64, i32, u64, vp, i64, vp]
         L.sk_autotune.argtypes = [P(SkCsc), i64, i32, P(SkTuning)]
         L.sk_plan_info.argtypes = [P(SkCsc), i64, i32, i32, P(SkTuning), P(ctypes.c_double), i32]
@@ -108,6 +111,8 @@ def lib():
         L.sk_qr_f64_workspace.argtypes = [i64, i64, P(ctypes.c_size_t)]
         L.sk_qr_f64.argtypes = [i64, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
         L.sk_trinv_f64.argtypes = [i64, vp, i64, vp, i64, vp]
+        L.sk_svd_f64_workspace.argtypes = [i64, i64, P(ctypes.c_size_t)]
+        L.sk_svd_f64.argtypes = [i64, i64, vp, vp, vp, P(i32), vp, ctypes.c_size_t, vp]
         L.sk_sap_workspace.argtypes = [P(SkCsc), P(SapParams), P(ctypes.c_size_t)]
         L.sk_sap_begin.argtypes = [P(SkCsc), vp, P(SapParams), vp, ctypes.c_size_t, vp]
         L.sk_sap_iterate.argtypes = [P(SkCsc), P(SapParams), i32, vp, ctypes.c_size_t, vp]
@@ -117,12 +122,13 @@ def lib():
         for name in ("sk_sketch_workspace", "sk_sketch", "sk_sketch_noalloc", "sk_sketch_status",
                      "sk_sketch_rng_calls", "sk_sketch_stored", "sk_rng_throughput",
                      "sk_sketch_colwise_workspace", "sk_sketch_colwise",
-                     "sk_materialize_s",
+                     "sk_sketch_colwise_f64", "sk_materialize_s",
                      "sk_autotune", "sk_plan_info", "sk_autotune_workspace",
                      "sk_autotune_measure", "sk_plan_cache_lookup",
                      "sk_sketch_batched_workspace", "sk_sketch_batched",
                      "sk_sketch_batched_plan", "sk_sketch_batched_status", "sk_qr_f64_workspace",
-                     "sk_qr_f64", "sk_trinv_f64", "sk_sap_workspace", "sk_sap_begin",
+                     "sk_qr_f64", "sk_trinv_f64", "sk_svd_f64_workspace", "sk_svd_f64",
+                     "sk_sap_workspace", "sk_sap_begin",
                      "sk_sap_iterate", "sk_sap_finish", "sk_sap_read_info"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -272,6 +278,21 @@ def sketch_colwise_into(A: DeviceCsc, d: int, dist, seed: int, out, ws, row0: in
     _check(lib().sk_sketch_colwise(ctypes.byref(c), row0, d, _dist(dist), seed, out.data_ptr(),
                                    d, ws.data_ptr(), ws.numel(), _stream(stream)),
            "sk_sketch_colwise")
+
+
+def sketch_colwise_f64(A: DeviceCsc, d: int, dist, seed: int, row0: int = 0,
+                       check: bool = True):
+    """sk_sketch_colwise_f64: A_hat in FP64 (the same S), torch FP64 (d, n)."""
+    import torch
+    ws = alloc_workspace(colwise_workspace_bytes(A), A.colptr.device)
+    out = torch.empty((A.n, d), dtype=torch.float64, device=A.colptr.device)
+    c = A.c_struct()
+    _check(lib().sk_sketch_colwise_f64(ctypes.byref(c), row0, d, _dist(dist), seed,
+                                       out.data_ptr(), d, ws.data_ptr(), ws.numel(),
+                                       _stream(None)), "sk_sketch_colwise_f64")
+    if check:
+        _check(sketch_status(ws)["status"], "sk_sketch_colwise_f64 (device validation)")
+    return out.t()
 
 
 def sketch_colwise(A: DeviceCsc, d: int, dist, seed: int, row0: int = 0, check: bool = True):
@@ -462,10 +483,33 @@ def trinv_f64(R, stream=None):
     return out.t()
 
 
+def svd_f64(M, stream=None):
+    """One-sided Jacobi SVD of a tall FP64 matrix given as a torch (rows, n)
+    tensor: returns (U diag(sigma) as (rows, n), V (n, n), sigma (n,), sweeps)
+    with M = (U diag(sigma)) V^T; sigma in column order."""
+    import torch
+    rows, n = M.shape
+    G = M.t().contiguous()  # column-major storage of M
+    V = torch.empty((n, n), dtype=torch.float64, device=M.device)
+    sig = torch.empty(n, dtype=torch.float64, device=M.device)
+    need = ctypes.c_size_t()
+    _check(lib().sk_svd_f64_workspace(rows, n, ctypes.byref(need)), "sk_svd_f64_workspace")
+    ws = alloc_workspace(int(need.value), M.device)
+    sweeps = ctypes.c_int32()
+    _check(lib().sk_svd_f64(rows, n, G.data_ptr(), V.data_ptr(), sig.data_ptr(),
+                            ctypes.byref(sweeps), ws.data_ptr(), ws.numel(), _stream(stream)),
+           "sk_svd_f64")
+    return G.t(), V.t(), sig, int(sweeps.value)
+
+
+SAP_QR, SAP_SVD = 0, 1
+
+
 def sap_params(d: int, dist, seed: int, atol: float = 1e-10, btol: float = 1e-10,
-               conlim: float = 1e8, iter_lim: int = 1000, prec: int = PREC_F32) -> SapParams:
+               conlim: float = 1e8, iter_lim: int = 1000, prec: int = PREC_F32,
+               method: int = SAP_QR) -> SapParams:
     return SapParams(int(d), _dist(dist), int(prec), int(seed), float(atol), float(btol),
-                     float(conlim), int(iter_lim), 0)
+                     float(conlim), int(iter_lim), int(method))
 
 
 class SapSolve:
@@ -548,4 +592,5 @@ EXPORTED = ["sk_status_string", "sk_variant_count", "sk_sketch_workspace", "sk_s
             "sk_sketch_batched_status", "sk_qr_f64_workspace", "sk_qr_f64", "sk_trinv_f64",
             "sk_sap_workspace", "sk_sap_begin", "sk_sap_iterate", "sk_sap_finish",
             "sk_sap_read_info", "sk_plan_info", "sk_autotune_workspace", "sk_autotune_measure",
-            "sk_plan_cache_lookup", "sk_plan_cache_clear"]
+            "sk_plan_cache_lookup", "sk_plan_cache_clear", "sk_svd_f64_workspace",
+            "sk_svd_f64", "sk_sketch_colwise_f64"]

@@ -32,10 +32,16 @@ struct ColwiseParams {
   const Header* hdr;  // validation status of A (set by the validation pass)
   int64_t n, d, row0;
   uint64_t seed;
-  float* out;
+  void* out;          // float (FP32 form) or double (FP64 form)
   int64_t ld;
   int32_t tiles;      // S-row tiles of 64 * DL rows
 };
+
+// a_jk in FP64 (FP32 and BF16 values widen exactly)
+__device__ __forceinline__ double load_value_f64(const void* vals, int vtype, int64_t p) {
+  if (vtype == 0) return in_global((const double*)vals)[p];
+  return (double)load_value(vals, vtype, p);
+}
 
 constexpr int CW_WAVES = 4;  // waves (tiles of one column) per workgroup
 
@@ -77,7 +83,11 @@ __device__ __forceinline__ void colwise_values(uint64_t seed, uint64_t gi, uint6
   }
 }
 
-template <int DIST, int DL>
+// ACC = float: the product form (A's values rounded to FP32, FP32 sums).
+// ACC = double: the FP64 form for the SVD form of sketch-and-precondition,
+// where singular values down to 1e-12 sigma_max must survive the sketch: the
+// same S entries (exact in FP64), A's values in FP64, FP64 sums.
+template <int DIST, int DL, typename ACC = float>
 __global__ __launch_bounds__(64 * CW_WAVES) void k_sketch_colwise(ColwiseParams P) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -86,26 +96,33 @@ __global__ __launch_bounds__(64 * CW_WAVES) void k_sketch_colwise(ColwiseParams 
   const int64_t tile = (blockIdx.x - k * tgroups) * CW_WAVES + wave;
   if (tile >= P.tiles) return;
   const int64_t i0 = tile * (64 * DL) + (int64_t)lane * DL;  // the lane's first row
-  float acc[DL];
+  ACC acc[DL];
 #pragma unroll
-  for (int t = 0; t < DL; ++t) acc[t] = 0.0f;
+  for (int t = 0; t < DL; ++t) acc[t] = (ACC)0;
   const int status = P.hdr->status;
   if (status == 0 && i0 < P.d) {
     const uint64_t gi = (uint64_t)(P.row0 + i0);
     const int64_t p0 = P.colptr[k], p1 = P.colptr[k + 1];
     for (int64_t p = p0; p < p1; ++p) {
       const uint64_t j = (uint64_t)(uint32_t)P.rowidx[p];
-      const float a = load_value(P.vals, P.vtype, p);
       float s[DL];
       colwise_values<DIST, DL>(P.seed, gi, j, s);
+      if constexpr (sizeof(ACC) == 4) {
+        const float a = load_value(P.vals, P.vtype, p);
 #pragma unroll
-      for (int t = 0; t < DL; ++t) acc[t] = __builtin_fmaf(a, s[t], acc[t]);
+        for (int t = 0; t < DL; ++t) acc[t] = __builtin_fmaf(a, s[t], acc[t]);
+      } else {
+        const double a = load_value_f64(P.vals, P.vtype, p);
+#pragma unroll
+        for (int t = 0; t < DL; ++t) acc[t] = __builtin_fma(a, (double)s[t], acc[t]);
+      }
     }
   }
-  const float nan = __uint_as_float(0x7FC00000u);
+  ACC* out = (ACC*)P.out;
+  const ACC nan = (ACC)__builtin_nan("");
 #pragma unroll
   for (int t = 0; t < DL; ++t)
-    if (i0 + t < P.d) P.out[i0 + t + k * P.ld] = status ? nan : acc[t];
+    if (i0 + t < P.d) out[i0 + t + k * P.ld] = status ? nan : acc[t];
 }
 
 }  // namespace sk

@@ -23,6 +23,7 @@
 #include "sk_rng.hpp"
 #include "sk_sap.hpp"
 #include "sk_sketch.hpp"
+#include "sk_svd.hpp"
 #include "sketch.h"
 
 using namespace sk;
@@ -876,13 +877,17 @@ sk_status batch_plan(int32_t count, const sk_csc* A, const int64_t* d, const int
 static_assert(offsetof(LsqrState, rnorm) == offsetof(sk_sap_info, rnorm) &&
                   offsetof(LsqrState, test3) == offsetof(sk_sap_info, test3) &&
                   offsetof(LsqrState, itn) == offsetof(sk_sap_info, iterations) &&
-                  offsetof(LsqrState, done) == offsetof(sk_sap_info, done),
+                  offsetof(LsqrState, done) == offsetof(sk_sap_info, done) &&
+                  offsetof(LsqrState, rank) == offsetof(sk_sap_info, rank) &&
+                  offsetof(LsqrState, sweeps) == offsetof(sk_sap_info, sweeps) &&
+                  sizeof(sk_sap_info) <= offsetof(LsqrState, alpha),
               "solver info prefix");
 
 struct SapLayout {
-  int64_t state, sk_ws, sk_bytes, ahat, q, tau, tq, r, rinv, rinvt, v64, rcnt, rowptr, cursor,
-      ccol, cval, lidx, lrows, sums, cbase, cpart, u, partial, partial2, v, w, y, tn, sn, t2,
-      total;
+  int64_t state, sk_ws, sk_bytes, ahat, q, tau, tq, r, rinv, rinvt, vsv, sig, smax, jctl, v64,
+      rcnt, rowptr, cursor, ccol, cval, lidx, lrows, sums, cbase, cpart, u, partial, partial2, v,
+      w, y, tn, sn, t2, total;
+  bool svd;
   int64_t nchunk_max, nblk_m, nlong_max, nblk_long;
 };
 
@@ -891,14 +896,23 @@ sk_status sap_layout(const sk_csc* A, const sk_sap_params* p, SapLayout& L) {
   if (s != SK_OK) return s;
   if (!p) return SK_EINVAL;
   const int64_t m = A->m, n = A->n, nnz = A->nnz, d = p->d;
-  if (n > m || d < n || n > SAP_MAX_N || p->dist < 0 || p->dist > 2 || p->iter_lim < 1)
+  if (n > m || d < n || n > SAP_MAX_N || p->dist < 0 || p->dist > 2 || p->iter_lim < 1 ||
+      (p->method != SK_SAP_QR && p->method != SK_SAP_SVD))
     return SK_EINVAL;
-  Plan P;
-  if (!plan_for(m, n, nnz, d, p->dist, nullptr, P)) return SK_EINVAL;
-  const Layout SL = layout_for(m, n, nnz, d, P);
+  L.svd = p->method == SK_SAP_SVD;
+  // the sketch's own workspace: the FP32 sketch's plan (the kernel choice and
+  // any cached tuning of the shape class), or the FP64 Algorithm 3 kernel's
+  // validation record for the SVD form
+  size_t sk_bytes = 0;
+  if (L.svd) {
+    if (p->prec != SK_PREC_F32) return SK_EUNSUPPORTED;
+    sk_bytes = colwise_bytes();
+  } else if ((s = sk_sketch_workspace(A, d, p->dist, p->prec, nullptr, &sk_bytes)) != SK_OK) {
+    return s;
+  }
   int64_t off = 0;
   L.state = off;   off = align_up(off + (int64_t)sizeof(LsqrState));
-  L.sk_ws = off;   L.sk_bytes = SL.total; off = align_up(off + SL.total);
+  L.sk_ws = off;   L.sk_bytes = (int64_t)sk_bytes; off = align_up(off + L.sk_bytes);
   L.ahat = off;    off = align_up(off + 4 * d * n);
   L.q = off;       off = align_up(off + 8 * d * n);
   L.tau = off;     off = align_up(off + 8 * n);
@@ -906,6 +920,11 @@ sk_status sap_layout(const sk_csc* A, const sk_sap_params* p, SapLayout& L) {
   L.r = off;       off = align_up(off + 8 * n * n);
   L.rinv = off;    off = align_up(off + 8 * n * n);
   L.rinvt = off;   off = align_up(off + 8 * n * n);
+  const int64_t nsv = L.svd ? n : 0;  // the Jacobi SVD's arrays
+  L.vsv = off;     off = align_up(off + 8 * nsv * nsv);
+  L.sig = off;     off = align_up(off + 8 * nsv);
+  L.smax = off;    off = align_up(off + 8);
+  L.jctl = off;    off = align_up(off + (int64_t)sizeof(JacobiCtl));
   L.v64 = off;     off = align_up(off + 8 * std::max<int64_t>(nnz, 1));
   L.rcnt = off;    off = align_up(off + 4 * m);
   L.rowptr = off;  off = align_up(off + 4 * (m + 2));
@@ -969,6 +988,37 @@ sk_status trinv_launch(int64_t n, const double* R, int64_t ldr, double* Ri, int6
 }
 
 // one LSQR iteration's launches (every kernel returns at once after the stop)
+// One-sided Jacobi on G (rows x n, in place) with V = I accumulated: sweeps
+// of the round-robin order, enqueued in batches; between batches the host
+// reads the converged flag (a sweep without rotations) and stops.  Relative
+// orthogonality tolerance sqrt(rows) * 2^-52.
+constexpr int kJacobiMaxSweeps = 40;
+constexpr int kJacobiBatch = 4;
+
+sk_status jacobi_svd(int64_t rows, int64_t n, double* G, double* V, JacobiCtl* ctl,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_eye, dim3(blocks_for(n * n, 256)), dim3(256), 0, st, V, n);
+  hipLaunchKernelGGL(k_jacobi_reset, dim3(1), dim3(64), 0, st, ctl);
+  const int64_t npad = n + (n & 1);
+  const double tol = std::sqrt((double)rows) * 0x1.0p-52;
+  for (int sweep = 0; sweep < kJacobiMaxSweeps;) {
+    for (int b = 0; b < kJacobiBatch && sweep < kJacobiMaxSweeps; ++b, ++sweep) {
+      for (int64_t step = 0; step < npad - 1; ++step)
+        hipLaunchKernelGGL(k_jacobi_step, dim3((unsigned)(npad / 2)), dim3(SVD_THREADS), 0, st,
+                           G, rows, V, n, npad, step, tol, ctl);
+      hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, ctl);
+    }
+    sk_status s = launch_ok();
+    if (s != SK_OK) return s;
+    JacobiCtl h;
+    if (hipMemcpyAsync(&h, ctl, sizeof h, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return SK_EHIP;
+    if (h.converged) break;
+  }
+  return SK_OK;
+}
+
 void lsqr_iteration(const sk_csc* A, const SapLayout& L, char* w, hipStream_t st) {
   const int64_t m = A->m, n = A->n;
   LsqrState* state = (LsqrState*)(w + L.state);
@@ -978,7 +1028,8 @@ void lsqr_iteration(const sk_csc* A, const SapLayout& L, char* w, hipStream_t st
   double* u = (double*)(w + L.u);
   double* partial = (double*)(w + L.partial);
   double* partial2 = (double*)(w + L.partial2);
-  hipLaunchKernelGGL(k_gemv_upper, dim3(blocks_for(n * 64, 256)), dim3(256), 0, st,
+  hipLaunchKernelGGL(L.svd ? k_gemv_upper<false> : k_gemv_upper<true>,
+                     dim3(blocks_for(n * 64, 256)), dim3(256), 0, st,
                      (const double*)(w + L.rinvt), n, v, tn, state);
   hipLaunchKernelGGL(k_lsqr_av<false>, dim3((unsigned)L.nblk_m), dim3(SAP_THREADS), 0, st,
                      (const int32_t*)(w + L.rowptr), (const int32_t*)(w + L.ccol),
@@ -997,7 +1048,8 @@ void lsqr_iteration(const sk_csc* A, const SapLayout& L, char* w, hipStream_t st
   hipLaunchKernelGGL(k_lsqr_colsum, dim3(blocks_for(n, 256)), dim3(256), 0, st,
                      (const int32_t*)(w + L.cbase), n, (const double*)(w + L.cpart),
                      (double*)(w + L.sn), state);
-  hipLaunchKernelGGL(k_gemv_upper_t, dim3(blocks_for(n * 64, 256)), dim3(256), 0, st, Ri, n, n,
+  hipLaunchKernelGGL(L.svd ? k_gemv_upper_t<false> : k_gemv_upper_t<true>,
+                     dim3(blocks_for(n * 64, 256)), dim3(256), 0, st, Ri, n, n,
                      (const double*)(w + L.sn), (double*)(w + L.t2), state);
   hipLaunchKernelGGL(k_lsqr_update<false>, dim3(1), dim3(1024), 0, st, n,
                      (const double*)(w + L.t2), v, (double*)(w + L.w), (double*)(w + L.y), state);
@@ -1034,9 +1086,10 @@ sk_status scratch_for_current_device(void** out) {
 
 namespace {
 // The Algorithm 3 (kji) kernel after the validation pass (arguments checked
-// by the caller).
+// by the caller); ACC = double: the FP64 form.
+template <typename ACC = float>
 sk_status colwise_impl(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint64_t seed,
-                       float* Ahat, int64_t ld, void* ws, size_t ws_bytes, hipStream_t st) {
+                       ACC* Ahat, int64_t ld, void* ws, size_t ws_bytes, hipStream_t st) {
   if (!ws || ws_bytes < colwise_bytes()) return SK_EWORKSPACE;
   const int dl = dist == SK_RADEMACHER ? 32 : 4;
   const int64_t tiles = (d + 64 * dl - 1) / (64 * dl);
@@ -1061,13 +1114,13 @@ sk_status colwise_impl(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, u
   P.hdr = hdr; P.n = A->n; P.d = d; P.row0 = row0; P.seed = seed; P.out = Ahat; P.ld = ld;
   P.tiles = (int32_t)tiles;
   if (dist == SK_RADEMACHER)
-    hipLaunchKernelGGL((k_sketch_colwise<DIST_RADEMACHER, 32>), dim3((unsigned)grid),
+    hipLaunchKernelGGL((k_sketch_colwise<DIST_RADEMACHER, 32, ACC>), dim3((unsigned)grid),
                        dim3(64 * CW_WAVES), 0, st, P);
   else if (dist == SK_UNIFORM)
-    hipLaunchKernelGGL((k_sketch_colwise<DIST_UNIFORM, 4>), dim3((unsigned)grid),
+    hipLaunchKernelGGL((k_sketch_colwise<DIST_UNIFORM, 4, ACC>), dim3((unsigned)grid),
                        dim3(64 * CW_WAVES), 0, st, P);
   else
-    hipLaunchKernelGGL((k_sketch_colwise<DIST_GAUSSIAN, 4>), dim3((unsigned)grid),
+    hipLaunchKernelGGL((k_sketch_colwise<DIST_GAUSSIAN, 4, ACC>), dim3((unsigned)grid),
                        dim3(64 * CW_WAVES), 0, st, P);
   return launch_ok();
 }
@@ -1404,6 +1457,16 @@ sk_status sk_sketch_colwise(const sk_csc* A, int64_t row0, int64_t d, int32_t di
   if (s != SK_OK) return s;
   if (d < 1 || row0 < 0 || !Ahat || ld < d || dist < 0 || dist > 2) return SK_EINVAL;
   return colwise_impl(A, row0, d, dist, seed, Ahat, ld, ws, ws_bytes, (hipStream_t)hip_stream);
+}
+
+sk_status sk_sketch_colwise_f64(const sk_csc* A, int64_t row0, int64_t d, int32_t dist,
+                                uint64_t seed, double* Ahat, int64_t ld, void* ws,
+                                size_t ws_bytes, void* hip_stream) {
+  sk_status s = check_csc(A);
+  if (s != SK_OK) return s;
+  if (d < 1 || row0 < 0 || !Ahat || ld < d || dist < 0 || dist > 2) return SK_EINVAL;
+  return colwise_impl<double>(A, row0, d, dist, seed, Ahat, ld, ws, ws_bytes,
+                              (hipStream_t)hip_stream);
 }
 
 sk_status sk_rng_throughput(int32_t dist, int32_t gen, int64_t calls, int32_t blocks,
@@ -1829,6 +1892,35 @@ sk_status sk_trinv_f64(int64_t n, const double* R, int64_t ldr, double* Rinv, in
   return trinv_launch(n, R, ldr, Rinv, ldi, (hipStream_t)hip_stream);
 }
 
+sk_status sk_svd_f64_workspace(int64_t rows, int64_t n, size_t* bytes) {
+  if (!bytes || n < 1 || rows < n || n > SAP_MAX_N || n >= INT32_MAX / 2) return SK_EINVAL;
+  *bytes = (size_t)align_up((int64_t)sizeof(JacobiCtl));
+  return SK_OK;
+}
+
+sk_status sk_svd_f64(int64_t rows, int64_t n, double* G, double* V, double* sigma,
+                     int32_t* sweeps, void* ws, size_t ws_bytes, void* hip_stream) {
+  size_t need = 0;
+  sk_status s = sk_svd_f64_workspace(rows, n, &need);
+  if (s != SK_OK) return s;
+  if (!G || !V || !sigma) return SK_EINVAL;
+  if (!ws || ws_bytes < need) return SK_EWORKSPACE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  JacobiCtl* ctl = (JacobiCtl*)ws;
+  if ((s = jacobi_svd(rows, n, G, V, ctl, st)) != SK_OK) return s;
+  hipLaunchKernelGGL(k_col_norms, dim3((unsigned)n), dim3(SVD_THREADS), 0, st, (const double*)G,
+                     rows, sigma);
+  if ((s = launch_ok()) != SK_OK) return s;
+  if (sweeps) {
+    JacobiCtl h;
+    if (hipMemcpyAsync(&h, ctl, sizeof h, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return SK_EHIP;
+    *sweeps = h.converged ? h.sweeps : -h.sweeps;
+  }
+  return SK_OK;
+}
+
 sk_status sk_sap_workspace(const sk_csc* A, const sk_sap_params* p, size_t* bytes) {
   if (!bytes) return SK_EINVAL;
   SapLayout L;
@@ -1851,20 +1943,43 @@ sk_status sk_sap_begin(const sk_csc* A, const double* b, const sk_sap_params* p,
   LsqrState* state = (LsqrState*)(w + L.state);
   const double ctol = p->conlim > 0.0 ? 1.0 / p->conlim : 0.0;
   hipLaunchKernelGGL(k_lsqr_set, dim3(1), dim3(64), 0, st, state, p->atol, p->btol, ctol,
-                     p->iter_lim);
-  // the sketch (FP32), widened to FP64
-  float* ahat = (float*)(w + L.ahat);
-  if ((s = sk_sketch(A, 0, d, p->dist, p->seed, p->prec, nullptr, ahat, d, w + L.sk_ws,
-                     (size_t)L.sk_bytes, hip_stream)) != SK_OK)
-    return s;
+                     p->iter_lim, (int32_t)n);
+  // the sketch: FP32 and widened to FP64 for the QR form; FP64 throughout
+  // for the SVD form (an FP32 sketch's rounding would leave singular values
+  // near 1e-7 sigma_max where A has none, far above the drop threshold)
   double* q = (double*)(w + L.q);
-  hipLaunchKernelGGL(k_widen, dim3(blocks_for(d * n, 256)), dim3(256), 0, st, ahat, d, d, n, q, d);
+  if (L.svd) {
+    if ((s = colwise_impl<double>(A, 0, d, p->dist, p->seed, q, d, w + L.sk_ws,
+                                  (size_t)L.sk_bytes, st)) != SK_OK)
+      return s;
+  } else {
+    float* ahat = (float*)(w + L.ahat);
+    if ((s = sk_sketch(A, 0, d, p->dist, p->seed, p->prec, nullptr, ahat, d, w + L.sk_ws,
+                       (size_t)L.sk_bytes, hip_stream)) != SK_OK)
+      return s;
+    hipLaunchKernelGGL(k_widen, dim3(blocks_for(d * n, 256)), dim3(256), 0, st, ahat, d, d, n, q,
+                       d);
+  }
   // R and R^{-1}
   double* R = (double*)(w + L.r);
   double* Ri = (double*)(w + L.rinv);
   if ((s = qr_launch(d, n, q, d, R, n, (double*)(w + L.tau), (double*)(w + L.tq), st)) != SK_OK)
     return s;
-  if ((s = trinv_launch(n, R, n, Ri, n, st)) != SK_OK) return s;
+  if (L.svd) {
+    // Sec. V-E-1: N = V_r diag(1 / sigma_r) from the SVD of R (that of the sketch)
+    if ((s = jacobi_svd(n, n, R, (double*)(w + L.vsv), (JacobiCtl*)(w + L.jctl), st)) != SK_OK)
+      return s;
+    double* sig = (double*)(w + L.sig);
+    hipLaunchKernelGGL(k_col_norms, dim3((unsigned)n), dim3(SVD_THREADS), 0, st,
+                       (const double*)R, n, sig);
+    hipLaunchKernelGGL(k_svd_rank, dim3(1), dim3(SVD_THREADS), 0, st, (const double*)sig, n,
+                       (const JacobiCtl*)(w + L.jctl), (double*)(w + L.smax), state);
+    hipLaunchKernelGGL(k_svd_precond, dim3(blocks_for(n * n, 256)), dim3(256), 0, st,
+                       (const double*)(w + L.vsv), (const double*)sig,
+                       (const double*)(w + L.smax), n, Ri);
+  } else if ((s = trinv_launch(n, R, n, Ri, n, st)) != SK_OK) {
+    return s;
+  }
   hipLaunchKernelGGL(k_transpose, dim3(blocks_for(n * n, 256)), dim3(256), 0, st, (const double*)Ri,
                      n, (double*)(w + L.rinvt));
   // FP64 values, row counts, row-major copy (only of input the sketch's
@@ -1917,7 +2032,8 @@ sk_status sk_sap_begin(const sk_csc* A, const double* b, const sk_sap_params* p,
   hipLaunchKernelGGL(k_lsqr_colsum, dim3(blocks_for(n, 256)), dim3(256), 0, st,
                      (const int32_t*)cbase, n, (const double*)(w + L.cpart), (double*)(w + L.sn),
                      state);
-  hipLaunchKernelGGL(k_gemv_upper_t, dim3(blocks_for(n * 64, 256)), dim3(256), 0, st,
+  hipLaunchKernelGGL(L.svd ? k_gemv_upper_t<false> : k_gemv_upper_t<true>,
+                     dim3(blocks_for(n * 64, 256)), dim3(256), 0, st,
                      (const double*)Ri, n, n, (const double*)(w + L.sn), (double*)(w + L.t2),
                      state);
   hipLaunchKernelGGL(k_lsqr_update<true>, dim3(1), dim3(1024), 0, st, n,
@@ -1947,7 +2063,8 @@ sk_status sk_sap_finish(const sk_csc* A, const sk_sap_params* p, double* x, void
   if (!ws || ws_bytes < (size_t)L.total) return SK_EWORKSPACE;
   char* w = (char*)ws;
   const int64_t n = A->n;
-  hipLaunchKernelGGL(k_gemv_upper_final, dim3(blocks_for(n, 256)), dim3(256), 0,
+  hipLaunchKernelGGL(L.svd ? k_gemv_upper_final<false> : k_gemv_upper_final<true>,
+                     dim3(blocks_for(n, 256)), dim3(256), 0,
                      (hipStream_t)hip_stream, (const double*)(w + L.rinv), n, n,
                      (const double*)(w + L.y), x);
   return launch_ok();

@@ -643,6 +643,7 @@ __global__ void k_col_chunks(const int64_t* __restrict__ colptr, int64_t n,
 struct LsqrState {
   int32_t itn, istop, done, iter_lim;
   double rnorm, arnorm, anorm, acond, xnorm, bnorm, test1, test2, test3;
+  int32_t rank, sweeps;  // preconditioner rank; Jacobi sweeps of the SVD form
   // private
   double alpha, beta, rhobar, phibar;
   double ddnorm, res2, xxnorm, z, cs2, sn2;
@@ -658,8 +659,11 @@ __global__ void k_transpose(const double* __restrict__ R, int64_t n, double* __r
   Rt[j + i * n] = R[i + j * n];
 }
 
-// t = Rinv v from the transposed copy Rit = Rinv^T (row i of Rinv is column i
-// of Rit, contiguous): one wave per row
+// The preconditioner products of LSQR.  M is R^{-1} (upper triangular: the
+// QR form, UPPER) or N = V_r diag(1 / sigma_r) (dense: the SVD form).
+// t = M v from the transposed copy Mt = M^T (row i of M is column i of Mt,
+// contiguous): one wave per row
+template <bool UPPER>
 __global__ void k_gemv_upper(const double* __restrict__ Rit, int64_t n,
                              const double* __restrict__ v, double* __restrict__ t,
                              const LsqrState* __restrict__ st) {
@@ -670,12 +674,14 @@ __global__ void k_gemv_upper(const double* __restrict__ Rit, int64_t n,
   const double* row = Rit + i * n;
   double acc = 0.0;
 #pragma unroll 4
-  for (int64_t j = i + lane; j < n; j += 64) acc += row[j] * v[j];
+  for (int64_t j = (UPPER ? i : 0) + lane; j < n; j += 64) acc += row[j] * v[j];
   acc = wave_sum(acc);
   if (lane == 0) t[i] = acc;
 }
 
-// t = Rinv^T s: one wave per column j (t[j] = sum_{i <= j} Ri[i, j] s[i])
+// t = M^T s: one wave per column j (t[j] = sum_i M[i, j] s[i], i <= j when
+// M is upper triangular)
+template <bool UPPER>
 __global__ void k_gemv_upper_t(const double* __restrict__ Ri, int64_t ldi, int64_t n,
                                const double* __restrict__ s, double* __restrict__ t,
                                const LsqrState* __restrict__ st) {
@@ -684,8 +690,9 @@ __global__ void k_gemv_upper_t(const double* __restrict__ Ri, int64_t ldi, int64
   const int lane = threadIdx.x & 63;
   if (j >= n) return;
   double acc = 0.0;
+  const int64_t i_end = UPPER ? j + 1 : n;
 #pragma unroll 4
-  for (int64_t i = lane; i <= j; i += 64) acc += Ri[i + j * ldi] * s[i];
+  for (int64_t i = lane; i < i_end; i += 64) acc += Ri[i + j * ldi] * s[i];
   acc = wave_sum(acc);
   if (lane == 0) t[j] = acc;
 }
@@ -909,13 +916,14 @@ __global__ __launch_bounds__(1024) void k_lsqr_update(int64_t n, const double* _
   }
 }
 
-// x = Rinv y (after the solve); not gated by the stop flag
+// x = M y (after the solve); not gated by the stop flag
+template <bool UPPER>
 __global__ void k_gemv_upper_final(const double* __restrict__ Ri, int64_t ldi, int64_t n,
                                    const double* __restrict__ y, double* __restrict__ x) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
-  for (int64_t j = i; j < n; ++j) s += Ri[i + j * ldi] * y[j];
+  for (int64_t j = UPPER ? i : 0; j < n; ++j) s += Ri[i + j * ldi] * y[j];
   x[i] = s;
 }
 
@@ -932,10 +940,10 @@ __global__ void k_lsqr_input_check(LsqrState* __restrict__ st, const Header* __r
 }
 
 __global__ void k_lsqr_set(LsqrState* __restrict__ st, double atol, double btol, double ctol,
-                           int32_t iter_lim) {
+                           int32_t iter_lim, int32_t rank) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     LsqrState s{};
-    s.atol = atol; s.btol = btol; s.ctol = ctol; s.iter_lim = iter_lim;
+    s.atol = atol; s.btol = btol; s.ctol = ctol; s.iter_lim = iter_lim; s.rank = rank;
     *st = s;
   }
 }

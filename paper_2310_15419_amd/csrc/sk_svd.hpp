@@ -1,0 +1,177 @@
+// sk_svd.hpp -- the SVD form of sketch-and-precondition (Sec. V-E-1): the
+// singular values and right singular vectors of the sketch A_hat = S A, with
+// the singular values below sigma_max / 1e12 dropped, give the
+// preconditioner N = V_r diag(1 / sigma_r) in place of R^{-1}.
+//
+// A_hat is first reduced by the Householder QR the QR form already runs
+// (A_hat = Q R, same singular values and right singular vectors), then R is
+// orthogonalised by one-sided (Hestenes) Jacobi rotations: columns p and q of
+// G (initially R) are rotated until G^T G is diagonal to a relative tolerance;
+// the same rotations applied to V (initially I) give G = U diag(sigma) with
+// G = R V.  One-sided Jacobi works on G itself, never on G^T G, so singular
+// values down to rounding level of sigma_max come out with small relative
+// error -- the property that matters for choosing what to drop.
+//
+// Parallel order: the round-robin (circle) tournament on the n columns
+// (padded to even): n_pad - 1 steps per sweep, each with n_pad / 2 disjoint
+// pairs, one workgroup per pair.  A sweep with no rotation ends the
+// iteration: a device flag that every later step reads first, so sweeps
+// enqueued past convergence cost only their launches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sk_sap.hpp"
+
+namespace sk {
+
+constexpr int SVD_THREADS = 256;
+constexpr double SVD_DROP = 1e-12;  // Sec. V-E-1: drop sigma < sigma_max * 1e-12
+
+// Jacobi control block (int32): [0] rotations in the current sweep, [1] the
+// converged flag, [2] sweeps done
+struct JacobiCtl {
+  int32_t rotations, converged, sweeps, pad;
+};
+
+__global__ void k_eye(double* __restrict__ V, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n) return;
+  const int64_t j = t / n, i = t - j * n;
+  V[t] = i == j ? 1.0 : 0.0;
+}
+
+__global__ void k_jacobi_reset(JacobiCtl* __restrict__ c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c = JacobiCtl{0, 0, 0, 0};
+}
+
+// One step of a sweep: workgroup b rotates its pair (p, q) of the circle
+// order in G (rows x n, column-major, rows >= n) and V (n x n), unless G's
+// columns p and q are already orthogonal to the tolerance:
+// |g_p . g_q| <= tol |g_p| |g_q|.
+__global__ __launch_bounds__(SVD_THREADS) void k_jacobi_step(double* __restrict__ G,
+                                                             int64_t rows,
+                                                             double* __restrict__ V, int64_t n,
+                                                             int64_t npad, int64_t step,
+                                                             double tol,
+                                                             JacobiCtl* __restrict__ ctl) {
+  if (ctl->converged) return;
+  const int64_t L = npad - 1;
+  const int64_t b = blockIdx.x;
+  int64_t p, q;
+  if (b == 0) {
+    p = step;
+    q = L;
+  } else {
+    p = (step + b) % L;
+    q = (step - b + L) % L;
+  }
+  if (p > q) { const int64_t t = p; p = q; q = t; }
+  if (q >= n) return;  // the padding column (odd n)
+  __shared__ double sh[3][16];
+  double* gp = G + p * rows;
+  double* gq = G + q * rows;
+  double a = 0.0, c = 0.0, g = 0.0;
+  for (int64_t i = threadIdx.x; i < rows; i += SVD_THREADS) {
+    const double x = gp[i], y = gq[i];
+    a = __builtin_fma(x, x, a);
+    c = __builtin_fma(y, y, c);
+    g = __builtin_fma(x, y, g);
+  }
+  const double alpha = block_sum(a, sh[0]);
+  const double beta = block_sum(c, sh[1]);
+  const double gamma = block_sum(g, sh[2]);
+  // also false for a zero column (gamma = 0) and for NaN input
+  if (!(fabs(gamma) > tol * sqrt(alpha) * sqrt(beta))) return;
+  // the rotation that zeroes the (p, q) entry of G^T G: t = tan(theta) is the
+  // smaller root of t^2 + 2 zeta t - 1 = 0, zeta = (beta - alpha) / (2 gamma)
+  const double zeta = (beta - alpha) / (2.0 * gamma);
+  const double t = fabs(zeta) > 1e150 ? 0.5 / zeta
+                                      : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + t * t);
+  const double sn = cs * t;
+  for (int64_t i = threadIdx.x; i < rows; i += SVD_THREADS) {
+    const double x = gp[i], y = gq[i];
+    gp[i] = cs * x - sn * y;
+    gq[i] = sn * x + cs * y;
+  }
+  double* vp = V + p * n;
+  double* vq = V + q * n;
+  for (int64_t i = threadIdx.x; i < n; i += SVD_THREADS) {
+    const double x = vp[i], y = vq[i];
+    vp[i] = cs * x - sn * y;
+    vq[i] = sn * x + cs * y;
+  }
+  if (threadIdx.x == 0) atomicAdd(&ctl->rotations, 1);
+}
+
+// end of a sweep: converged when it rotated nothing
+__global__ void k_jacobi_sweep_end(JacobiCtl* __restrict__ ctl) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || ctl->converged) return;
+  ctl->sweeps += 1;
+  if (ctl->rotations == 0) ctl->converged = 1;
+  ctl->rotations = 0;
+}
+
+// sigma_j = |g_j| (one workgroup per column; fixed summation order)
+__global__ __launch_bounds__(SVD_THREADS) void k_col_norms(const double* __restrict__ G,
+                                                           int64_t rows,
+                                                           double* __restrict__ sigma) {
+  __shared__ double sh[16];
+  const int64_t j = blockIdx.x;
+  const double* g = G + j * rows;
+  double a = 0.0;
+  for (int64_t i = threadIdx.x; i < rows; i += SVD_THREADS) a = __builtin_fma(g[i], g[i], a);
+  const double s = block_sum(a, sh);
+  if (threadIdx.x == 0) sigma[j] = sqrt(s);
+}
+
+// sigma_max, the kept count r and the sweep count into the solver state
+// (one workgroup; the maximum is order-independent, the count exact)
+__global__ __launch_bounds__(SVD_THREADS) void k_svd_rank(const double* __restrict__ sigma,
+                                                          int64_t n, const JacobiCtl* __restrict__ ctl,
+                                                          double* __restrict__ smax_out,
+                                                          LsqrState* __restrict__ st) {
+  __shared__ double shm[SVD_THREADS];
+  __shared__ int shc[SVD_THREADS];
+  double mx = 0.0;
+  for (int64_t j = threadIdx.x; j < n; j += SVD_THREADS) mx = fmax(mx, sigma[j]);
+  shm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = SVD_THREADS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) shm[threadIdx.x] = fmax(shm[threadIdx.x], shm[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double smax = shm[0];
+  const double cut = smax * SVD_DROP;
+  int cnt = 0;
+  for (int64_t j = threadIdx.x; j < n; j += SVD_THREADS)
+    cnt += (smax > 0.0 && sigma[j] >= cut) ? 1 : 0;
+  shc[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int s = SVD_THREADS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) shc[threadIdx.x] += shc[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *smax_out = smax;
+    st->rank = shc[0];
+    st->sweeps = ctl->sweeps;
+  }
+}
+
+// N = V diag(1 / sigma_j) over the kept columns, zero columns for the dropped
+// ones (their LSQR coordinates then stay zero: x lies in the span of the kept
+// right singular vectors, the row space of A up to the dropped part)
+__global__ void k_svd_precond(const double* __restrict__ V, const double* __restrict__ sigma,
+                              const double* __restrict__ smax, int64_t n,
+                              double* __restrict__ N) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n) return;
+  const int64_t j = t / n;
+  const double s = sigma[j], mx = *smax;
+  N[t] = (mx > 0.0 && s >= mx * SVD_DROP) ? V[t] / s : 0.0;
+}
+
+}  // namespace sk

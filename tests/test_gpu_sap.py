@@ -84,3 +84,123 @@ def test_sap_rejects_bad_shapes(B):
     dA, db = device_request(B, A, b)
     with pytest.raises(B.SketchError):
         B.SapSolve(dA, db, B.sap_params(30, "rademacher", 1))  # d < n
+
+
+# ------------------------------------------------------------- SVD form
+@pytest.mark.parametrize("rows,n,deficient", [(300, 77, 0), (64, 64, 0), (40, 1, 0), (41, 2, 0),
+                                              (257, 33, 5), (1200, 301, 40), (2000, 1000, 0)])
+def test_svd_against_numpy(B, rows, n, deficient):
+    import torch
+    rng = np.random.default_rng(rows * 7 + n)
+    M = rng.standard_normal((rows, n)) * np.exp(rng.uniform(-4, 4, n))  # column scales
+    if deficient:  # exact copies scaled by powers of two
+        M[:, -deficient:] = M[:, :deficient] * 2.0 ** rng.integers(-3, 4, deficient)
+    print(f"svd rows={rows} n={n} deficient={deficient}", flush=True)
+    G, V, sig, sweeps = B.svd_f64(torch.from_numpy(M).cuda())
+    G, V, sig = G.cpu().numpy(), V.cpu().numpy(), sig.cpu().numpy()
+    assert 0 < sweeps <= 40, sweeps
+    nrm = np.linalg.norm(M, 2)
+    eps = 2.0 ** -52
+    # M = G V^T with V orthogonal; G's columns orthogonal to the tolerance.
+    # Each entry goes through about n * sweeps rotations, each rounding once:
+    # backward errors of O(n eps) (Jacobi's standard bound)
+    print(f"sweeps {sweeps}", flush=True)
+    assert np.linalg.norm(V.T @ V - np.eye(n)) <= 50 * n * eps
+    assert np.linalg.norm(G @ V.T - M) <= 50 * n * eps * np.linalg.norm(M)
+    GtG = G.T @ G
+    d = np.sqrt(np.diag(GtG))
+    off = np.abs(GtG - np.diag(np.diag(GtG)))
+    big = d > 1e-13 * nrm
+    assert np.all(off[np.ix_(big, big)] <= 10 * np.sqrt(rows) * eps * np.outer(d[big], d[big]))
+    # singular values: numpy's, each within the backward error above (Weyl)
+    s_np = np.linalg.svd(M, compute_uv=False)
+    dev = np.abs(np.sort(sig)[::-1] - s_np).max()
+    print(f"max |sigma - numpy| = {dev:.3e} (sigma_max {nrm:.3e})", flush=True)
+    assert dev <= 50 * n * eps * np.linalg.norm(M)
+    if deficient:
+        assert np.sum(sig < 1e-12 * sig.max()) == deficient
+
+
+def test_colwise_f64_against_oracle(B, oracle_lib):
+    # the FP64 form against the oracle's FP64 sketch: each entry within a few
+    # FP64 roundings of its terms' size, sum_j |a_jk| max|S|
+    A = inputs.uniform_positions(7001, 45, 9000, 3, "normal", np.float64)
+    col = np.abs(A.to_dense()).sum(axis=0)[None, :]
+    for dist in ("rademacher", "uniform", "gaussian"):
+        got = B.sketch_colwise_f64(B.DeviceCsc.from_host(A), 300, dist, 8, row0=5).cpu().numpy()
+        ref = oracle_lib.sketch(A.m, A.n, A.colptr, A.rowidx, A.vals, 300, dist, 8, row0=5)
+        smax = oracle_lib.S_MAX[oracle_lib.DIST_NAMES[dist]]
+        err = np.abs(got - ref)
+        assert np.all(err <= 1e-13 * col * smax), (dist, float((err / (col * smax)).max()))
+
+
+def _null_ok(x, null, tol):
+    for j, comb in null:
+        v = x[j] - sum(c * x[k] for k, c in comb.items())
+        assert abs(v) <= tol * np.linalg.norm(x) * np.sqrt(1 + sum(c * c for c in comb.values()))
+
+
+@pytest.mark.parametrize("dist", ["rademacher", "uniform", "gaussian"])
+@pytest.mark.parametrize("m,n,rank", [(20_000, 60, 45), (40_000, 151, 120)])
+def test_sap_svd_rank_deficient(B, oracle_lib, dist, m, n, rank):
+    A, b, null = inputs.ls_request_rank_deficient(n + rank, m, n, rank, dense_rows=200)
+    dA, db = device_request(B, A, b)
+    p = B.sap_params(2 * n, dist, 99, atol=1e-12, btol=1e-12, method=B.SAP_SVD)
+    print(f"sap-svd m={m} n={n} rank={rank} {dist}", flush=True)
+    x, info = B.SapSolve(dA, db, p).solve(chunk=8)
+    x = x.cpu().numpy()
+    assert info["status"] == 0 and info["done"] == 1 and info["istop"] in (1, 2), info
+    assert info["rank"] == rank and 0 < info["sweeps"] <= 40, info
+    # the minimum-norm least-squares solution
+    xs = np.linalg.lstsq(A.to_dense(), b, rcond=1e-10)[0]
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs), np.linalg.norm(x - xs)
+    _null_ok(x, null, 1e-9)
+    assert oracle_lib.ls_error(A.to_scipy(), x, b) <= 1e-9
+    # the oracle's SAP-SVD with its own FP64 sketch of the same S: same rank,
+    # about as many iterations
+    Ahat = oracle_lib.sketch(A.m, A.n, A.colptr, A.rowidx, A.vals, 2 * n, dist, 99)
+    xo, itn, _, r = oracle_lib.sap_svd_reference(A.to_scipy(), b, Ahat, tol=1e-12)
+    assert r == rank
+    assert abs(info["iterations"] - itn) <= max(3, itn // 10), (info["iterations"], itn)
+    assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+
+
+def test_sap_svd_full_rank_equals_qr(B):
+    A, b, _ = inputs.ls_request(31, 30_000, 90, dense_rows=300)
+    dA, db = device_request(B, A, b)
+    out = {}
+    for method in (B.SAP_QR, B.SAP_SVD):
+        p = B.sap_params(180, "uniform", 5, atol=1e-12, btol=1e-12, method=method)
+        x, info = B.SapSolve(dA, db, p).solve(chunk=8)
+        assert info["status"] == 0 and info["istop"] in (1, 2), info
+        assert info["rank"] == 90
+        out[method] = (x.cpu().numpy(), info)
+    (xq, iq), (xv, iv) = out[B.SAP_QR], out[B.SAP_SVD]
+    assert iq["sweeps"] == 0 and iv["sweeps"] > 0
+    assert np.linalg.norm(xv - xq) <= 1e-9 * np.linalg.norm(xq)
+    assert abs(iq["iterations"] - iv["iterations"]) <= 3
+
+
+def test_sap_svd_near_singular_value_kept(B, oracle_lib):
+    m, n, rank = 20_000, 50, 40
+    A, b, null = inputs.ls_request_rank_deficient(9, m, n, rank, dense_rows=200,
+                                                  near=2.0 ** -20, noise=0.0)
+    dA, db = device_request(B, A, b)
+    p = B.sap_params(2 * n, "gaussian", 3, atol=1e-12, btol=1e-12, method=B.SAP_SVD)
+    x, info = B.SapSolve(dA, db, p).solve(chunk=8)
+    x = x.cpu().numpy()
+    assert info["status"] == 0 and info["rank"] == rank + 1, info
+    Ahat = oracle_lib.sketch(A.m, A.n, A.colptr, A.rowidx, A.vals, 2 * n, "gaussian", 3)
+    xo, _, sig, r = oracle_lib.sap_svd_reference(A.to_scipy(), b, Ahat, tol=1e-12)
+    assert r == rank + 1
+    kappa = sig[0] / sig[r - 1]
+    assert np.linalg.norm(x - xo) <= 20 * kappa * 1e-12 * np.linalg.norm(xo)
+    _null_ok(x, null[1:], 1e-8)
+
+
+def test_sap_svd_refuses_reduced_precision(B):
+    A, b, _ = inputs.ls_request(1, 5000, 40, dense_rows=100)
+    dA, db = device_request(B, A, b)
+    with pytest.raises(B.SketchError):
+        B.SapSolve(dA, db, B.sap_params(80, "rademacher", 1, prec=B.PREC_BF16,
+                                        method=B.SAP_SVD))
