@@ -483,6 +483,76 @@ def bench_serving(B, pool: int, count: int, rates, slots: int, m_hi: float, n_hi
             "capacity_per_s": capacity, "points": points}
 
 
+# ------------------------------------------------ SAP: QR and SVD forms
+def ls_error_host(As, x, b) -> float:
+    """Error(x) = ||A^T (A x - b)|| / (||A||_F ||A x - b||) of Sec. V-E-2 (scipy, FP64)."""
+    r = As @ x - b
+    fro = float(np.sqrt(As.multiply(As).sum()))
+    return float(np.linalg.norm(As.T @ r) / (fro * np.linalg.norm(r)))
+
+
+def bench_sap(B, reps: int) -> dict:
+    """Single sketch-and-precondition solves at the largest serving size: the QR
+    form and the SVD form (Sec. V-E-1: singular values below sigma_max / 1e12
+    dropped) on a full-rank request (m = 4e6, n = 1000, d = 2n), and both on a
+    rank-deficient stand-in (m = 1e6, n = 500, rank 400), where R is singular.
+    Setup (sketch + factorisation + preconditioner) and LSQR times (wall clock
+    around synchronised calls, best of `reps`), iterations, kept rank, Jacobi
+    sweeps and Error(x)."""
+    import torch
+    from paper_2310_15419_amd import inputs
+    cases = []
+    t0 = time.perf_counter()
+    A, b, _ = inputs.ls_request(77, 4_000_000, 1000, dense_rows=2000)
+    cases.append(("full rank", A, b, 1000))
+    A2, b2, _ = inputs.ls_request_rank_deficient(78, 1_000_000, 500, 400, dense_rows=2000)
+    cases.append(("rank deficient (rank 400)", A2, b2, 400))
+    log(f"SAP requests in {time.perf_counter() - t0:.1f} s")
+    rows = []
+    for name, A, b, rank in cases:
+        dA = B.DeviceCsc.from_host(A)
+        db = torch.from_numpy(b).cuda()
+        As = A.to_scipy()
+        for method, mname in ((B.SAP_QR, "qr"), (B.SAP_SVD, "svd")):
+            p = B.sap_params(2 * A.n, "rademacher", 91, atol=1e-10, btol=1e-10, method=method)
+            best = None
+            for _ in range(reps):
+                sv = B.SapSolve(dA, db, p)
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                sv.begin()
+                torch.cuda.synchronize()
+                tb = time.perf_counter()
+                while True:
+                    sv.iterate(16)
+                    inf = sv.info()
+                    if inf["done"]:
+                        break
+                x = sv.finish()
+                torch.cuda.synchronize()
+                tc = time.perf_counter()
+                t = ((tb - ta) * 1e3, (tc - tb) * 1e3)
+                if best is None or sum(t) < sum(best[0]):
+                    best = (t, inf, x)
+                del sv
+            (setup_ms, lsqr_ms), inf, x = best
+            xh = x.cpu().numpy()
+            finite = bool(np.all(np.isfinite(xh)))
+            row = {"case": name, "m": A.m, "n": A.n, "nnz": A.nnz, "true_rank": rank,
+                   "method": mname, "setup_ms": setup_ms, "lsqr_ms": lsqr_ms,
+                   "total_ms": setup_ms + lsqr_ms, "iterations": int(inf["iterations"]),
+                   "istop": int(inf["istop"]), "kept_rank": int(inf["rank"]),
+                   "sweeps": int(inf["sweeps"]), "x_finite": finite,
+                   "error": ls_error_host(As, xh, b) if finite else None}
+            log(f"SAP {name} {mname}: setup {setup_ms:.1f} ms, LSQR {lsqr_ms:.1f} ms, "
+                f"{row['iterations']} it, rank {row['kept_rank']}, sweeps {row['sweeps']}, "
+                f"Error {row['error']}")
+            rows.append(row)
+        del dA, db
+    return {"workload": "SAP single solves: power-law columns + dense 2000-row block, b = A x + "
+                        "1e-6 noise, d = 2n, S +-1 seed 91, LSQR to 1e-10", "solves": rows}
+
+
 # ------------------------------------------- the paper's SpMM workloads
 def bench_spmm_shapes(B, which: str, steps: int) -> dict:
     """Stand-ins for the paper's SpMM test matrices (Table I shapes, or the
@@ -609,7 +679,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plain_scale",
                     help="plain_scale (default), plain_small, skewed, batched, serving, "
-                         "table1, abnormal, tuner")
+                         "table1, abnormal, tuner, sap")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
@@ -666,6 +736,17 @@ def main():
             "steps": args.serve_requests, "warmup": 2, "ms_per_step": head["batched"]["mean_ms"],
             "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64 (sketch f32)", "data": "synthetic", "config": sv}), flush=True)
+        return
+    if args.workload == "sap":
+        sp = bench_sap(B, max(1, args.steps))
+        svd = [r for r in sp["solves"] if r["method"] == "svd"]
+        print(json.dumps({
+            "metric": "sketch-and-precondition solve time, QR and SVD forms",
+            "value": svd[0]["total_ms"], "unit": "ms (SVD form, full-rank m=4e6 n=1000)",
+            "n_gpus": 1, "steps": max(1, args.steps), "warmup": 0,
+            "ms_per_step": svd[0]["total_ms"], "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64 (sketch f32 for QR, f64 for SVD)",
+            "data": "synthetic", "config": sp}), flush=True)
         return
     if args.workload == "tuner":
         tr = bench_tuner(B, ["plain_scale", "skewed"], args.steps)

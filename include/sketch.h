@@ -348,8 +348,10 @@ sk_status sk_trinv_f64(int64_t n, const double* R, int64_t ldr, double* Rinv, in
  * sketch-and-precondition, Sec. V-E-1): G (rows x n, column-major, ld = rows,
  * rows >= n, 1 <= n <= 8192; device) is orthogonalised in place by plane
  * rotations of column pairs in the round-robin parallel order until every
- * pair satisfies |g_p . g_q| <= sqrt(rows) 2^-52 |g_p| |g_q|; the same
- * rotations accumulate V (n x n, ld = n; device, overwritten).  On return
+ * pair satisfies |g_p . g_q| <= sqrt(rows) 2^-52 |g_p| |g_q| or holds a
+ * column at the rounding floor, |g| <= 2^-52 |G|_F (such a column is noise
+ * and its singular value far below any drop threshold); the same rotations
+ * accumulate V (n x n, ld = n; device, overwritten).  On return
  * G = U diag(sigma) (columns orthogonal), V orthogonal, the input equals
  * G V^T, and sigma[j] = |g_j| (device, n entries, in column order, not
  * sorted).  *sweeps (host, may be NULL) receives the sweeps run, negated when

@@ -998,14 +998,17 @@ constexpr int kJacobiBatch = 4;
 sk_status jacobi_svd(int64_t rows, int64_t n, double* G, double* V, JacobiCtl* ctl,
                      hipStream_t st) {
   hipLaunchKernelGGL(k_eye, dim3(blocks_for(n * n, 256)), dim3(256), 0, st, V, n);
-  hipLaunchKernelGGL(k_jacobi_reset, dim3(1), dim3(64), 0, st, ctl);
+  hipLaunchKernelGGL(k_jacobi_reset, dim3(1), dim3(SVD_THREADS), 0, st, (const double*)G,
+                     rows * n, ctl);
   const int64_t npad = n + (n & 1);
   const double tol = std::sqrt((double)rows) * 0x1.0p-52;
+  const bool reg = rows <= (int64_t)SVD_THREADS * SVD_RPT;  // n <= rows
   for (int sweep = 0; sweep < kJacobiMaxSweeps;) {
     for (int b = 0; b < kJacobiBatch && sweep < kJacobiMaxSweeps; ++b, ++sweep) {
       for (int64_t step = 0; step < npad - 1; ++step)
-        hipLaunchKernelGGL(k_jacobi_step, dim3((unsigned)(npad / 2)), dim3(SVD_THREADS), 0, st,
-                           G, rows, V, n, npad, step, tol, ctl);
+        hipLaunchKernelGGL(reg ? k_jacobi_step<true> : k_jacobi_step<false>,
+                           dim3((unsigned)(npad / 2)), dim3(SVD_THREADS), 0, st, G, rows, V, n,
+                           npad, step, tol, ctl);
       hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, ctl);
     }
     sk_status s = launch_ok();

@@ -29,11 +29,16 @@ namespace sk {
 constexpr int SVD_THREADS = 256;
 constexpr double SVD_DROP = 1e-12;  // Sec. V-E-1: drop sigma < sigma_max * 1e-12
 
-// Jacobi control block (int32): [0] rotations in the current sweep, [1] the
-// converged flag, [2] sweeps done
+// Jacobi control block: rotations in the current sweep, the converged flag,
+// sweeps done, and the squared rounding floor of G's column norms
 struct JacobiCtl {
   int32_t rotations, converged, sweeps, pad;
+  double floor2;
 };
+
+// Rows per thread held in registers by a step (rows <= SVD_THREADS * this;
+// taller G runs the looping form)
+constexpr int SVD_RPT = 8;
 
 __global__ void k_eye(double* __restrict__ V, int64_t n) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -42,24 +47,70 @@ __global__ void k_eye(double* __restrict__ V, int64_t n) {
   V[t] = i == j ? 1.0 : 0.0;
 }
 
-__global__ void k_jacobi_reset(JacobiCtl* __restrict__ c) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *c = JacobiCtl{0, 0, 0, 0};
+// Reset the control block; floor2 = (2^-52 |G|_F)^2.  A column whose norm is
+// at that floor holds only rounding noise: its singular value is below
+// 2^-52 |G|_F <= 2^-52 sqrt(n) sigma_max, far under the drop threshold, and
+// rotating it against the others would only stir that noise (the pair test
+// is relative, and noise never passes it), so steps leave such pairs alone.
+// A rotation against a column of norm f turns the other column by an angle
+// of at most f / (its norm), so what is left undone is rounding-sized.
+__global__ __launch_bounds__(SVD_THREADS) void k_jacobi_reset(const double* __restrict__ G,
+                                                              int64_t count,
+                                                              JacobiCtl* __restrict__ c) {
+  __shared__ double sh[16];
+  double a = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += SVD_THREADS) a = __builtin_fma(G[i], G[i], a);
+  const double f = block_sum(a, sh);
+  if (threadIdx.x == 0) {
+    JacobiCtl z{};
+    z.floor2 = f * 0x1.0p-104;
+    *c = z;
+  }
 }
 
-// One step of a sweep: workgroup b rotates its pair (p, q) of the circle
-// order in G (rows x n, column-major, rows >= n) and V (n x n), unless G's
-// columns p and q are already orthogonal to the tolerance:
-// |g_p . g_q| <= tol |g_p| |g_q|.
-__global__ __launch_bounds__(SVD_THREADS) void k_jacobi_step(double* __restrict__ G,
-                                                             int64_t rows,
-                                                             double* __restrict__ V, int64_t n,
-                                                             int64_t npad, int64_t step,
-                                                             double tol,
-                                                             JacobiCtl* __restrict__ ctl) {
-  if (ctl->converged) return;
+// Sums of three values over the workgroup (fixed order), every thread gets them
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int nw = SVD_THREADS / 64;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  if (lane == 0) {
+    sh[wave] = a;
+    sh[nw + wave] = b;
+    sh[2 * nw + wave] = c;
+  }
+  __syncthreads();
+  a = b = c = 0.0;
+  for (int w = 0; w < nw; ++w) {
+    a += sh[w];
+    b += sh[nw + w];
+    c += sh[2 * nw + w];
+  }
+}
+
+// the rotation (cs, sn) that zeroes the (p, q) entry of G^T G, or false when
+// the pair is orthogonal to the tolerance or at the rounding floor:
+// t = tan(theta) is the smaller root of t^2 + 2 zeta t - 1 = 0 with
+// zeta = (beta - alpha) / (2 gamma)
+__device__ __forceinline__ bool jacobi_rotation(double alpha, double beta, double gamma,
+                                                double tol, double floor2, double& cs,
+                                                double& sn) {
+  // also false for a zero column (gamma = 0) and for NaN input
+  if (!(fabs(gamma) > tol * sqrt(alpha) * sqrt(beta))) return false;
+  if (!(fmin(alpha, beta) > floor2)) return false;
+  const double zeta = (beta - alpha) / (2.0 * gamma);
+  const double t = fabs(zeta) > 1e150 ? 0.5 / zeta
+                                      : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  cs = 1.0 / sqrt(1.0 + t * t);
+  sn = cs * t;
+  return true;
+}
+
+// the pair (p, q) of workgroup b in step `step` of the circle order
+__device__ __forceinline__ void jacobi_pair(int64_t npad, int64_t step, int64_t b, int64_t& p,
+                                            int64_t& q) {
   const int64_t L = npad - 1;
-  const int64_t b = blockIdx.x;
-  int64_t p, q;
   if (b == 0) {
     p = step;
     q = L;
@@ -68,42 +119,83 @@ __global__ __launch_bounds__(SVD_THREADS) void k_jacobi_step(double* __restrict_
     q = (step - b + L) % L;
   }
   if (p > q) { const int64_t t = p; p = q; q = t; }
+}
+
+// One step of a sweep: workgroup b rotates its pair (p, q) of the circle
+// order in G (rows x n, column-major, rows >= n) and V (n x n), unless G's
+// columns p and q are already orthogonal to the tolerance,
+// |g_p . g_q| <= tol |g_p| |g_q|, or one of them is at the rounding floor.
+// REG: the two columns of G and of V stay in registers between the sums and
+// the update (rows, n <= SVD_THREADS * SVD_RPT), V's loads issued with G's.
+template <bool REG>
+__global__ __launch_bounds__(SVD_THREADS) void k_jacobi_step(double* __restrict__ G,
+                                                             int64_t rows,
+                                                             double* __restrict__ V, int64_t n,
+                                                             int64_t npad, int64_t step,
+                                                             double tol,
+                                                             JacobiCtl* __restrict__ ctl) {
+  if (ctl->converged) return;
+  int64_t p, q;
+  jacobi_pair(npad, step, blockIdx.x, p, q);
   if (q >= n) return;  // the padding column (odd n)
-  __shared__ double sh[3][16];
+  __shared__ double sh[3 * SVD_THREADS / 64];
   double* gp = G + p * rows;
   double* gq = G + q * rows;
-  double a = 0.0, c = 0.0, g = 0.0;
-  for (int64_t i = threadIdx.x; i < rows; i += SVD_THREADS) {
-    const double x = gp[i], y = gq[i];
-    a = __builtin_fma(x, x, a);
-    c = __builtin_fma(y, y, c);
-    g = __builtin_fma(x, y, g);
-  }
-  const double alpha = block_sum(a, sh[0]);
-  const double beta = block_sum(c, sh[1]);
-  const double gamma = block_sum(g, sh[2]);
-  // also false for a zero column (gamma = 0) and for NaN input
-  if (!(fabs(gamma) > tol * sqrt(alpha) * sqrt(beta))) return;
-  // the rotation that zeroes the (p, q) entry of G^T G: t = tan(theta) is the
-  // smaller root of t^2 + 2 zeta t - 1 = 0, zeta = (beta - alpha) / (2 gamma)
-  const double zeta = (beta - alpha) / (2.0 * gamma);
-  const double t = fabs(zeta) > 1e150 ? 0.5 / zeta
-                                      : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double cs = 1.0 / sqrt(1.0 + t * t);
-  const double sn = cs * t;
-  for (int64_t i = threadIdx.x; i < rows; i += SVD_THREADS) {
-    const double x = gp[i], y = gq[i];
-    gp[i] = cs * x - sn * y;
-    gq[i] = sn * x + cs * y;
-  }
   double* vp = V + p * n;
   double* vq = V + q * n;
-  for (int64_t i = threadIdx.x; i < n; i += SVD_THREADS) {
-    const double x = vp[i], y = vq[i];
-    vp[i] = cs * x - sn * y;
-    vq[i] = sn * x + cs * y;
+  const int tid = threadIdx.x;
+  double a = 0.0, c = 0.0, g = 0.0, cs, sn;
+  if constexpr (REG) {
+    double x[SVD_RPT], y[SVD_RPT], u[SVD_RPT], w[SVD_RPT];
+#pragma unroll
+    for (int k = 0; k < SVD_RPT; ++k) {
+      const int64_t i = tid + (int64_t)k * SVD_THREADS;
+      x[k] = i < rows ? gp[i] : 0.0;
+      y[k] = i < rows ? gq[i] : 0.0;
+      u[k] = i < n ? vp[i] : 0.0;
+      w[k] = i < n ? vq[i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < SVD_RPT; ++k) {
+      a = __builtin_fma(x[k], x[k], a);
+      c = __builtin_fma(y[k], y[k], c);
+      g = __builtin_fma(x[k], y[k], g);
+    }
+    block_sum3(a, c, g, sh);
+    if (!jacobi_rotation(a, c, g, tol, ctl->floor2, cs, sn)) return;
+#pragma unroll
+    for (int k = 0; k < SVD_RPT; ++k) {
+      const int64_t i = tid + (int64_t)k * SVD_THREADS;
+      if (i < rows) {
+        gp[i] = cs * x[k] - sn * y[k];
+        gq[i] = sn * x[k] + cs * y[k];
+      }
+      if (i < n) {
+        vp[i] = cs * u[k] - sn * w[k];
+        vq[i] = sn * u[k] + cs * w[k];
+      }
+    }
+  } else {
+    for (int64_t i = tid; i < rows; i += SVD_THREADS) {
+      const double x = gp[i], y = gq[i];
+      a = __builtin_fma(x, x, a);
+      c = __builtin_fma(y, y, c);
+      g = __builtin_fma(x, y, g);
+    }
+    block_sum3(a, c, g, sh);
+    if (!jacobi_rotation(a, c, g, tol, ctl->floor2, cs, sn)) return;
+    for (int64_t i = tid; i < rows; i += SVD_THREADS) {
+      const double x = gp[i], y = gq[i];
+      gp[i] = cs * x - sn * y;
+      gq[i] = sn * x + cs * y;
+    }
+    for (int64_t i = tid; i < n; i += SVD_THREADS) {
+      const double x = vp[i], y = vq[i];
+      vp[i] = cs * x - sn * y;
+      vq[i] = sn * x + cs * y;
+    }
   }
-  if (threadIdx.x == 0) atomicAdd(&ctl->rotations, 1);
+  if (tid == 0) atomicAdd(&ctl->rotations, 1);
 }
 
 // end of a sweep: converged when it rotated nothing

@@ -204,3 +204,24 @@ def test_sap_svd_refuses_reduced_precision(B):
     with pytest.raises(B.SketchError):
         B.SapSolve(dA, db, B.sap_params(80, "rademacher", 1, prec=B.PREC_BF16,
                                         method=B.SAP_SVD))
+
+
+def test_sap_largest_serving_size_by_properties(B, oracle_lib):
+    # m = 4e6, n = 1000, d = 2n (the largest serving request): too large for a
+    # dense reference, so checked by what holds at any size -- Error(x), the
+    # normal equations' relative residual (Sec. V-E-2), the iteration count of
+    # a d = 2n embedding, and the QR and SVD forms agreeing
+    A, b, _ = inputs.ls_request(77, 4_000_000, 1000, dense_rows=2000)
+    dA, db = device_request(B, A, b)
+    As = A.to_scipy()
+    xs = {}
+    for method in (B.SAP_QR, B.SAP_SVD):
+        p = B.sap_params(2000, "rademacher", 91, atol=1e-10, btol=1e-10, method=method)
+        print(f"sap m=4e6 n=1000 method {method}", flush=True)
+        x, info = B.SapSolve(dA, db, p).solve(chunk=16)
+        x = x.cpu().numpy()
+        assert info["status"] == 0 and info["istop"] in (1, 2), info
+        assert 30 <= info["iterations"] <= 120 and info["rank"] == 1000, info
+        assert oracle_lib.ls_error(As, x, b) <= 1e-9
+        xs[method] = x
+    assert np.linalg.norm(xs[0] - xs[1]) <= 1e-8 * np.linalg.norm(xs[0])
