@@ -579,7 +579,7 @@ def bench_spmm_shapes(B, which: str, steps: int) -> dict:
         out_c = torch.empty_like(out_t)
         tile = {"kernel": B.KERNEL_TILE}
         ws = B.alloc_workspace(B.workspace_bytes(dA, d, "uniform", tune=tile))
-        wc = B.alloc_workspace(B.colwise_workspace_bytes(dA))
+        wc = B.alloc_workspace(B.colwise_workspace_bytes(dA, d))
         t_ms = timed_ms(lambda: B.sketch_into(dA, d, "uniform", 5, out_t, ws, tune=tile), steps,
                         stream)
         R = B.sketch_status(ws)["nonempty_rows"]

@@ -185,10 +185,15 @@ sk_status sk_sketch_stored(const sk_csc* A, int64_t d, const float* S, int64_t l
  * given CSC (validated on the device, no inspector).  Same S, so the same
  * A_hat as sk_sketch up to FP32 summation order (each entry here sums the
  * column's nonzeros in row order).  Generator calls: nnz x (groups of 4, or
- * of 128 for +-1, that the rows touch per 256 / 2048 rows).  Workspace:
- * sk_sketch_colwise_workspace bytes (the validation status, read with
- * sk_sketch_status).  Asynchronous on hip_stream. */
-sk_status sk_sketch_colwise_workspace(const sk_csc* A, size_t* bytes);
+ * of 128 for +-1, that the rows touch per 256 / 2048 rows).  A column with
+ * more than C nonzeros (C a power of two >= 512 chosen from nnz and d so that
+ * the partials stay within 256 MiB) is split into chunks of C nonzeros
+ * walked in parallel, whose partial sums are then added in chunk order (each
+ * entry of such a column is a sum of per-chunk sums).  Workspace:
+ * sk_sketch_colwise_workspace bytes for this A and d (the validation status,
+ * read with sk_sketch_status; the chunk bookkeeping and the partials).
+ * Asynchronous on hip_stream. */
+sk_status sk_sketch_colwise_workspace(const sk_csc* A, int64_t d, size_t* bytes);
 sk_status sk_sketch_colwise(const sk_csc* A, int64_t row0, int64_t d, int32_t dist,
                             uint64_t seed, float* Ahat, int64_t ld, void* ws, size_t ws_bytes,
                             void* hip_stream);

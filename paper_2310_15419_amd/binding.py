@@ -85,7 +85,7 @@ def lib():
         L.sk_sketch_stored.argtypes = [P(SkCsc), i64, vp, i64, P(SkTuning), vp, i64, vp,
                                        ctypes.c_size_t, vp]
         L.sk_rng_throughput.argtypes = [i32, i32, i64, i32, u64, vp, vp]
-        L.sk_sketch_colwise_workspace.argtypes = [P(SkCsc), P(ctypes.c_size_t)]
+        L.sk_sketch_colwise_workspace.argtypes = [P(SkCsc), i64, P(ctypes.c_size_t)]
         L.sk_sketch_colwise.argtypes = [P(SkCsc), i64, i64, i32, u64, vp, i64, vp,
                                         ctypes.c_size_t, vp]
         L.sk_sketch_colwise_f64.argtypes = [P(SkCsc), i64, i64, i32, u64, vp, i64, vp,
@@ -263,10 +263,10 @@ def sketch_stored_into(A: DeviceCsc, S, out, ws, tune=None, stream=None) -> None
            "sk_sketch_stored")
 
 
-def colwise_workspace_bytes(A: DeviceCsc) -> int:
+def colwise_workspace_bytes(A: DeviceCsc, d: int) -> int:
     out = ctypes.c_size_t()
     c = A.c_struct()
-    _check(lib().sk_sketch_colwise_workspace(ctypes.byref(c), ctypes.byref(out)),
+    _check(lib().sk_sketch_colwise_workspace(ctypes.byref(c), d, ctypes.byref(out)),
            "sk_sketch_colwise_workspace")
     return int(out.value)
 
@@ -284,7 +284,7 @@ def sketch_colwise_f64(A: DeviceCsc, d: int, dist, seed: int, row0: int = 0,
                        check: bool = True):
     """sk_sketch_colwise_f64: A_hat in FP64 (the same S), torch FP64 (d, n)."""
     import torch
-    ws = alloc_workspace(colwise_workspace_bytes(A), A.colptr.device)
+    ws = alloc_workspace(colwise_workspace_bytes(A, d), A.colptr.device)
     out = torch.empty((A.n, d), dtype=torch.float64, device=A.colptr.device)
     c = A.c_struct()
     _check(lib().sk_sketch_colwise_f64(ctypes.byref(c), row0, d, _dist(dist), seed,
@@ -298,7 +298,7 @@ def sketch_colwise_f64(A: DeviceCsc, d: int, dist, seed: int, row0: int = 0,
 def sketch_colwise(A: DeviceCsc, d: int, dist, seed: int, row0: int = 0, check: bool = True):
     """A_hat in the Algorithm 3 loop order, as a torch FP32 tensor of shape (d, n)."""
     import torch
-    ws = alloc_workspace(colwise_workspace_bytes(A), A.colptr.device)
+    ws = alloc_workspace(colwise_workspace_bytes(A, d), A.colptr.device)
     out = torch.empty((A.n, d), dtype=torch.float32, device=A.colptr.device)
     sketch_colwise_into(A, d, dist, seed, out, ws, row0)
     if check:

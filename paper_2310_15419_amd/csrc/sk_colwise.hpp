@@ -12,8 +12,15 @@
 // each (DL = 4: one generator call per lane per nonzero for (-1,1) and the
 // Gaussian; DL = 32: one word of a call per lane for +-1).  The nonzeros of
 // column k are the same for the whole wave, so their row indices and values
-// are scalar loads.  Every A_hat entry is one lane's FP32 sum in row order of
-// the column: no atomics, a fixed summation order.
+// are scalar loads.  Every A_hat entry is one lane's sum in row order of the
+// column: no atomics, a fixed summation order.
+//
+// Heavy columns: a column with more than C nonzeros is cut into chunks of C
+// consecutive nonzeros, each walked by its own waves into a partial sum; a
+// second kernel adds a column's partials in chunk order.  Work items are
+// chunks (a light column is one chunk and writes A_hat directly), located
+// by a search over the scanned chunk counts.  C is a power of two chosen
+// from the shape so that the partials fit a fixed budget.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,7 +42,54 @@ struct ColwiseParams {
   void* out;          // float (FP32 form) or double (FP64 form)
   int64_t ld;
   int32_t tiles;      // S-row tiles of 64 * DL rows
+  int32_t chunk;      // C: nonzeros per chunk of a heavy column
+  const int32_t* cbase;  // [n + 1]: first chunk of each column (scanned)
+  const int32_t* hbase;  // [n + 1]: first partial slot of each column (heavy only)
+  void* part;         // partial sums of heavy columns' chunks, d per slot
 };
+
+// chunks of column k: one for a light column (at most C nonzeros, or any
+// column of a matrix that failed validation), ceil(len / C) for a heavy one
+__device__ __forceinline__ int32_t colwise_chunks(const int64_t* colptr, int64_t k, int32_t C,
+                                                  int status) {
+  if (status) return 1;
+  const int64_t len = colptr[k + 1] - colptr[k];
+  return len > C ? (int32_t)((len + C - 1) / C) : 1;
+}
+
+// per column: chunks, heavy chunks (partial slots) and the heavy flag, for
+// three scans
+__global__ void k_colwise_counts(const int64_t* __restrict__ colptr, int64_t n, int32_t C,
+                                 const Header* __restrict__ hdr, int32_t* __restrict__ cb,
+                                 int32_t* __restrict__ hb, int32_t* __restrict__ hk) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int32_t c = colwise_chunks(colptr, k, C, hdr->status);
+  cb[k] = c;
+  hb[k] = c > 1 ? c : 0;
+  hk[k] = c > 1 ? 1 : 0;
+}
+
+// the heavy columns in order (hk scanned: column k is heavy when its rank
+// moves)
+__global__ void k_colwise_heavy_list(const int32_t* __restrict__ hk, int64_t n,
+                                     int32_t* __restrict__ hcol) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  if (hk[k + 1] > hk[k]) hcol[hk[k]] = (int32_t)k;
+}
+
+// the column holding chunk c: the k with cbase[k] <= c < cbase[k + 1]
+// (every column has at least one chunk, so the bounds increase strictly)
+__device__ __forceinline__ int64_t colwise_column(const int32_t* cbase, int64_t n, int64_t c) {
+  int64_t lo = 0, hi = n;  // cbase[lo] <= c < cbase[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (cbase[mid] <= c) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
 
 // a_jk in FP64 (FP32 and BF16 values widen exactly)
 __device__ __forceinline__ double load_value_f64(const void* vals, int vtype, int64_t p) {
@@ -92,9 +146,12 @@ __global__ __launch_bounds__(64 * CW_WAVES) void k_sketch_colwise(ColwiseParams 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t tgroups = (P.tiles + CW_WAVES - 1) / CW_WAVES;
-  const int64_t k = blockIdx.x / tgroups;
-  const int64_t tile = (blockIdx.x - k * tgroups) * CW_WAVES + wave;
-  if (tile >= P.tiles) return;
+  const int64_t c = blockIdx.x / tgroups;  // the chunk
+  const int64_t tile = (blockIdx.x - c * tgroups) * CW_WAVES + wave;
+  if (tile >= P.tiles || c >= P.cbase[P.n]) return;
+  const int64_t k = colwise_column(P.cbase, P.n, c);
+  const int64_t r = c - P.cbase[k];                 // chunk within the column
+  const bool heavy = P.cbase[k + 1] - P.cbase[k] > 1;
   const int64_t i0 = tile * (64 * DL) + (int64_t)lane * DL;  // the lane's first row
   ACC acc[DL];
 #pragma unroll
@@ -102,7 +159,9 @@ __global__ __launch_bounds__(64 * CW_WAVES) void k_sketch_colwise(ColwiseParams 
   const int status = P.hdr->status;
   if (status == 0 && i0 < P.d) {
     const uint64_t gi = (uint64_t)(P.row0 + i0);
-    const int64_t p0 = P.colptr[k], p1 = P.colptr[k + 1];
+    const int64_t p0 = P.colptr[k] + (heavy ? r * P.chunk : 0);
+    const int64_t pe = P.colptr[k + 1];
+    const int64_t p1 = heavy && p0 + P.chunk < pe ? p0 + P.chunk : pe;
     for (int64_t p = p0; p < p1; ++p) {
       const uint64_t j = (uint64_t)(uint32_t)P.rowidx[p];
       float s[DL];
@@ -118,11 +177,37 @@ __global__ __launch_bounds__(64 * CW_WAVES) void k_sketch_colwise(ColwiseParams 
       }
     }
   }
+  if (heavy) {  // the chunk's partial sum (a matrix that failed validation has no heavy column)
+    ACC* part = (ACC*)P.part + (P.hbase[k] + r) * P.d;
+#pragma unroll
+    for (int t = 0; t < DL; ++t)
+      if (i0 + t < P.d) part[i0 + t] = acc[t];
+    return;
+  }
   ACC* out = (ACC*)P.out;
   const ACC nan = (ACC)__builtin_nan("");
 #pragma unroll
   for (int t = 0; t < DL; ++t)
     if (i0 + t < P.d) out[i0 + t + k * P.ld] = status ? nan : acc[t];
+}
+
+// A_hat[:, k] of each heavy column k: its chunks' partials added in chunk
+// order.  Grid: heavy-column capacity x row blocks of 256.
+template <typename ACC>
+__global__ void k_colwise_reduce(const int32_t* __restrict__ hk, const int32_t* __restrict__ hcol,
+                                 const int32_t* __restrict__ cbase,
+                                 const int32_t* __restrict__ hbase, int64_t n, int64_t d,
+                                 const ACC* __restrict__ part, ACC* __restrict__ out, int64_t ld) {
+  const int64_t rblocks = (d + 255) / 256;
+  const int64_t h = blockIdx.x / rblocks;
+  const int64_t i = (blockIdx.x - h * rblocks) * 256 + threadIdx.x;
+  if (h >= hk[n] || i >= d) return;
+  const int64_t k = hcol[h];
+  const int64_t nch = cbase[k + 1] - cbase[k];
+  const ACC* src = part + (int64_t)hbase[k] * d + i;
+  ACC s = (ACC)0;
+  for (int64_t r = 0; r < nch; ++r) s += src[r * d];
+  out[i + k * ld] = s;
 }
 
 }  // namespace sk

@@ -545,8 +545,41 @@ const sk_tuning* effective_tuning(const sk_csc* A, int64_t d, int dist, int prec
   return &buf;
 }
 
-size_t colwise_bytes() {
-  return (size_t)(align_up((int64_t)sizeof(Header)) + align_up((int64_t)sizeof(Item)));
+// Workspace of the Algorithm 3 kernel: the validation record, the chunk
+// bookkeeping of heavy columns and their partial sums (8 bytes each, so one
+// layout serves the FP32 and the FP64 form).  C, the chunk length, is the
+// smallest power of two from 512 on that keeps the partials (at most
+// 2 nnz / C chunks of d values) within kColwisePartBytes.
+constexpr int64_t kColwisePartBytes = int64_t(256) << 20;
+
+struct ColwiseLayout {
+  int64_t hdr, item, cb, hb, hk, hcol, sums, part, total;
+  int64_t chunk, chunks_max, heavy_max, slots_max;
+};
+
+ColwiseLayout colwise_layout(int64_t n, int64_t nnz, int64_t d) {
+  ColwiseLayout L{};
+  int64_t C = 512;
+  while (2 * ((nnz + C - 1) / C) * d * 8 > kColwisePartBytes && C < (int64_t(1) << 30)) C *= 2;
+  L.chunk = C;
+  L.chunks_max = n + (nnz + C - 1) / C;  // every column one chunk, heavy ones ceil(len / C)
+  L.heavy_max = nnz / C + 1;             // a heavy column has more than C nonzeros
+  L.slots_max = 2 * ((nnz + C - 1) / C) + 1;
+  int64_t off = 0;
+  L.hdr = off;   off = align_up(off + (int64_t)sizeof(Header));
+  L.item = off;  off = align_up(off + (int64_t)sizeof(Item));
+  L.cb = off;    off = align_up(off + 4 * (n + 2));
+  L.hb = off;    off = align_up(off + 4 * (n + 2));
+  L.hk = off;    off = align_up(off + 4 * (n + 2));
+  L.hcol = off;  off = align_up(off + 4 * (L.heavy_max + 1));
+  L.sums = off;  off = align_up(off + 4 * scan_sums_len(n + 1));
+  L.part = off;  off = align_up(off + 8 * L.slots_max * d);
+  L.total = off;
+  return L;
+}
+
+size_t colwise_bytes(const sk_csc* A, int64_t d) {
+  return (size_t)colwise_layout(A->n, A->nnz, d).total;
 }
 
 int blocks_for(int64_t count, int threads) {
@@ -906,7 +939,7 @@ sk_status sap_layout(const sk_csc* A, const sk_sap_params* p, SapLayout& L) {
   size_t sk_bytes = 0;
   if (L.svd) {
     if (p->prec != SK_PREC_F32) return SK_EUNSUPPORTED;
-    sk_bytes = colwise_bytes();
+    sk_bytes = colwise_bytes(A, d);
   } else if ((s = sk_sketch_workspace(A, d, p->dist, p->prec, nullptr, &sk_bytes)) != SK_OK) {
     return s;
   }
@@ -1093,14 +1126,23 @@ namespace {
 template <typename ACC = float>
 sk_status colwise_impl(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint64_t seed,
                        ACC* Ahat, int64_t ld, void* ws, size_t ws_bytes, hipStream_t st) {
-  if (!ws || ws_bytes < colwise_bytes()) return SK_EWORKSPACE;
+  const ColwiseLayout CL = colwise_layout(A->n, A->nnz, d);
+  if (!ws || ws_bytes < (size_t)CL.total) return SK_EWORKSPACE;
   const int dl = dist == SK_RADEMACHER ? 32 : 4;
   const int64_t tiles = (d + 64 * dl - 1) / (64 * dl);
-  const int64_t grid = A->n * ((tiles + CW_WAVES - 1) / CW_WAVES);
-  if (grid >= INT32_MAX) return SK_EUNSUPPORTED;
+  const int64_t tgroups = (tiles + CW_WAVES - 1) / CW_WAVES;
+  const int64_t grid = CL.chunks_max * tgroups;
+  const int64_t rgrid = CL.heavy_max * ((d + 255) / 256);
+  if (grid >= INT32_MAX || rgrid >= INT32_MAX || CL.chunks_max >= INT32_MAX / 2)
+    return SK_EUNSUPPORTED;
   char* w = (char*)ws;
-  Header* hdr = (Header*)w;
-  Item* d_item = (Item*)(w + align_up((int64_t)sizeof(Header)));
+  Header* hdr = (Header*)(w + CL.hdr);
+  Item* d_item = (Item*)(w + CL.item);
+  int32_t* cb = (int32_t*)(w + CL.cb);
+  int32_t* hb = (int32_t*)(w + CL.hb);
+  int32_t* hk = (int32_t*)(w + CL.hk);
+  int32_t* hcol = (int32_t*)(w + CL.hcol);
+  int32_t* sums = (int32_t*)(w + CL.sums);
   // validation only: the CSC input is used as given
   Item I;
   std::memset(&I, 0, sizeof I);
@@ -1112,10 +1154,24 @@ sk_status colwise_impl(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, u
   hipLaunchKernelGGL(k_put_item, dim3(1), dim3(64), 0, st, I, d_item);
   launch_items_cols<&Item::o_valid, OpValidate>(d_item, 1, std::max<int64_t>(A->nnz, A->n + 1),
                                                 st);
+  // chunks of the heavy columns
+  const int64_t n = A->n;
+  hipLaunchKernelGGL(k_colwise_counts, dim3(blocks_for(n, 256)), dim3(256), 0, st, A->colptr, n,
+                     (int32_t)CL.chunk, (const Header*)hdr, cb, hb, hk);
+  sk_status s;
+  if ((s = scan_i32(cb, n, sums, st)) != SK_OK) return s;
+  if ((s = scan_i32(hb, n, sums, st)) != SK_OK) return s;
+  if ((s = scan_i32(hk, n, sums, st)) != SK_OK) return s;
+  hipLaunchKernelGGL(k_colwise_heavy_list, dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                     (const int32_t*)hk, n, hcol);
   ColwiseParams P{};
   P.colptr = A->colptr; P.rowidx = A->rowidx; P.vals = A->vals; P.vtype = A->vtype;
-  P.hdr = hdr; P.n = A->n; P.d = d; P.row0 = row0; P.seed = seed; P.out = Ahat; P.ld = ld;
+  P.hdr = hdr; P.n = n; P.d = d; P.row0 = row0; P.seed = seed; P.out = Ahat; P.ld = ld;
   P.tiles = (int32_t)tiles;
+  P.chunk = (int32_t)CL.chunk;
+  P.cbase = cb;
+  P.hbase = hb;
+  P.part = w + CL.part;
   if (dist == SK_RADEMACHER)
     hipLaunchKernelGGL((k_sketch_colwise<DIST_RADEMACHER, 32, ACC>), dim3((unsigned)grid),
                        dim3(64 * CW_WAVES), 0, st, P);
@@ -1125,6 +1181,9 @@ sk_status colwise_impl(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, u
   else
     hipLaunchKernelGGL((k_sketch_colwise<DIST_GAUSSIAN, 4, ACC>), dim3((unsigned)grid),
                        dim3(64 * CW_WAVES), 0, st, P);
+  hipLaunchKernelGGL(k_colwise_reduce<ACC>, dim3((unsigned)rgrid), dim3(256), 0, st,
+                     (const int32_t*)hk, (const int32_t*)hcol, (const int32_t*)cb,
+                     (const int32_t*)hb, n, d, (const ACC*)(w + CL.part), Ahat, ld);
   return launch_ok();
 }
 
@@ -1417,7 +1476,7 @@ sk_status sk_sketch_workspace(const sk_csc* A, int64_t d, int32_t dist, int32_t 
   if (kernel == KERNEL_KJI) {
     if (gen != GEN_PHILOX || prec != SK_PREC_F32 || (tune && tune->count_rng))
       return SK_EUNSUPPORTED;
-    *bytes = colwise_bytes();
+    *bytes = colwise_bytes(A, d);
     return SK_OK;
   }
   if (kernel != KERNEL_TILE) return SK_EINVAL;
@@ -1445,11 +1504,12 @@ sk_status sk_sketch_stored(const sk_csc* A, int64_t d, const float* S, int64_t l
 }
 
 // ------------------------------------------- Algorithm 3 (kji) order
-sk_status sk_sketch_colwise_workspace(const sk_csc* A, size_t* bytes) {
+sk_status sk_sketch_colwise_workspace(const sk_csc* A, int64_t d, size_t* bytes) {
   if (!bytes) return SK_EINVAL;
   sk_status s = check_csc(A);
   if (s != SK_OK) return s;
-  *bytes = colwise_bytes();
+  if (d < 1) return SK_EINVAL;
+  *bytes = colwise_bytes(A, d);
   return SK_OK;
 }
 

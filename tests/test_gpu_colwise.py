@@ -84,3 +84,29 @@ def test_abnormal_patterns_both_kernels(B, oracle_lib, kind):
     check(oracle_lib, tile, A, d, "uniform", 9, 0, f"abnormal {kind} S-tile kernel")
     col = B.sketch_colwise(dA, d, "uniform", 9).cpu().numpy()
     check(oracle_lib, col, A, d, "uniform", 9, 0, f"abnormal {kind} kji kernel")
+
+
+@pytest.mark.parametrize("dist", DISTS)
+def test_colwise_heavy_columns_in_chunks(B, oracle_lib, dist):
+    # columns of 512 (one chunk), 513 (two, the second of one entry), 1024
+    # (two full chunks), 5000 (ten) nonzeros, an empty one and a short one;
+    # d over several tiles with a ragged tail
+    m = 20_000
+    rng = np.random.default_rng(17)
+    lens = [512, 0, 513, 3, 1024, 5000]
+    rows, cols = [], []
+    for k, ln in enumerate(lens):
+        rows.append(np.sort(rng.choice(m, size=ln, replace=False)))
+        cols.append(np.full(ln, k))
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    A = inputs.from_coo(m, len(lens), rows, cols, rng.standard_normal(rows.size))
+    dA = B.DeviceCsc.from_host(A)
+    for d, row0 in ((700, 0), (2100, 37)):
+        print(f"heavy columns {dist} d={d}", flush=True)
+        got = B.sketch_colwise(dA, d, dist, 9, row0=row0).cpu().numpy()
+        check(oracle_lib, got, A, d, dist, 9, row0, f"heavy {dist} d={d}")
+        got64 = B.sketch_colwise_f64(dA, d, dist, 9, row0=row0).cpu().numpy()
+        ref = oracle_lib.sketch(A.m, A.n, A.colptr, A.rowidx, A.vals, d, dist, 9, row0=row0)
+        col = np.abs(A.to_dense()).sum(axis=0)[None, :]
+        smax = oracle_lib.S_MAX[oracle_lib.DIST_NAMES[dist]]
+        assert np.all(np.abs(got64 - ref) <= 1e-13 * col * smax)

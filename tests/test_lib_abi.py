@@ -159,7 +159,7 @@ def test_kernel_choice_host_only():
     assert lib.sk_sketch_workspace(ctypes.byref(ch7), 3 * 17640, 1, 0, None,
                                    ctypes.byref(out)) == 0
     kji = ctypes.c_size_t()
-    assert lib.sk_sketch_colwise_workspace(ctypes.byref(ch7), ctypes.byref(kji)) == 0
+    assert lib.sk_sketch_colwise_workspace(ctypes.byref(ch7), 3 * 17640, ctypes.byref(kji)) == 0
     assert out.value == kji.value
     # any S-tile field keeps the S-tile kernel; kernel = 1 forces it
     for field in ("splits", "variant", "col_split"):
