@@ -770,7 +770,7 @@ def main():
         return
     if args.workload == "batched":
         bt = bench_batched(B, args.batch_count, args.steps, args.dense_min_pct, args.workers,
-                           oracle_all=False)
+                           oracle_all=True)
         print(json.dumps({
             "metric": f"batched vs plain at fixed error ({args.batch_count} sketches)",
             "value": bt["modes"]["batched_bf16"]["nnz_d_per_s"], "unit": "nnz*d/s",

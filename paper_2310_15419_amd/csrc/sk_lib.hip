@@ -1414,7 +1414,7 @@ sk_status time_call(const sk_csc* A, int64_t d, int dist, uint64_t seed, int pre
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return SK_EHIP;
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return SK_EHIP;
   }
   double best = INFINITY;
@@ -1434,8 +1434,8 @@ sk_status time_call(const sk_csc* A, int64_t d, int dist, uint64_t seed, int pre
     best = std::min(best, (double)f);
     if (best > cutoff_ms) break;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   *ms = best;
   return s;
 }
