@@ -7,8 +7,9 @@ this module only marshals arguments and builds the shared object.
 
 Pinned functions (each is checked in ``tests/test_oracle_*.py`` against
 something other than itself):
-  philox        -- against an independent Philox4x32-10 (PyTorch's header
-                   engine, compiled into a test harness)
+  philox        -- against two independent Philox4x32-10 engines (PyTorch's
+                   header engine, compiled into a test harness; rocRAND's
+                   host generator through its C API)
   s_entry / materialize_s -- against the generator words (independent Philox)
                    for +-1 and (-1,1) exactly; Gaussian against FP64 libm
                    Box-Muller

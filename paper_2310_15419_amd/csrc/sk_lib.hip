@@ -953,7 +953,7 @@ sk_status sap_layout(const sk_csc* A, const sk_sap_params* p, SapLayout& L) {
   L.r = off;       off = align_up(off + 8 * n * n);
   L.rinv = off;    off = align_up(off + 8 * n * n);
   L.rinvt = off;   off = align_up(off + 8 * n * n);
-  const int64_t nsv = L.svd ? n : 0;  // the Jacobi SVD's arrays
+  const int64_t nsv = L.svd ? n : 0;  // the Jacobi SVD's arrays (R^T orthogonalised)
   L.vsv = off;     off = align_up(off + 8 * nsv * nsv);
   L.sig = off;     off = align_up(off + 8 * nsv);
   L.smax = off;    off = align_up(off + 8);
@@ -1030,7 +1030,8 @@ constexpr int kJacobiBatch = 4;
 
 sk_status jacobi_svd(int64_t rows, int64_t n, double* G, double* V, JacobiCtl* ctl,
                      hipStream_t st) {
-  hipLaunchKernelGGL(k_eye, dim3(blocks_for(n * n, 256)), dim3(256), 0, st, V, n);
+  const bool withv = V != nullptr;  // else no V is accumulated
+  if (withv) hipLaunchKernelGGL(k_eye, dim3(blocks_for(n * n, 256)), dim3(256), 0, st, V, n);
   hipLaunchKernelGGL(k_jacobi_reset, dim3(1), dim3(SVD_THREADS), 0, st, (const double*)G,
                      rows * n, ctl);
   const int64_t npad = n + (n & 1);
@@ -1039,7 +1040,8 @@ sk_status jacobi_svd(int64_t rows, int64_t n, double* G, double* V, JacobiCtl* c
   for (int sweep = 0; sweep < kJacobiMaxSweeps;) {
     for (int b = 0; b < kJacobiBatch && sweep < kJacobiMaxSweeps; ++b, ++sweep) {
       for (int64_t step = 0; step < npad - 1; ++step)
-        hipLaunchKernelGGL(reg ? k_jacobi_step<true> : k_jacobi_step<false>,
+        hipLaunchKernelGGL(withv ? (reg ? k_jacobi_step<true, true> : k_jacobi_step<false, true>)
+                                 : (reg ? k_jacobi_step<true, false> : k_jacobi_step<false, false>),
                            dim3((unsigned)(npad / 2)), dim3(SVD_THREADS), 0, st, G, rows, V, n,
                            npad, step, tol, ctl);
       hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, ctl);
@@ -2029,17 +2031,20 @@ sk_status sk_sap_begin(const sk_csc* A, const double* b, const sk_sap_params* p,
   if ((s = qr_launch(d, n, q, d, R, n, (double*)(w + L.tau), (double*)(w + L.tq), st)) != SK_OK)
     return s;
   if (L.svd) {
-    // Sec. V-E-1: N = V_r diag(1 / sigma_r) from the SVD of R (that of the sketch)
-    if ((s = jacobi_svd(n, n, R, (double*)(w + L.vsv), (JacobiCtl*)(w + L.jctl), st)) != SK_OK)
-      return s;
+    // Sec. V-E-1: N = V_r diag(1 / sigma_r) from the SVD of R (that of the
+    // sketch), through one-sided Jacobi on R^T (no V to carry)
+    double* Gt = (double*)(w + L.vsv);
+    hipLaunchKernelGGL(k_transpose, dim3(blocks_for(n * n, 256)), dim3(256), 0, st,
+                       (const double*)R, n, Gt);
+    if ((s = jacobi_svd(n, n, Gt, nullptr, (JacobiCtl*)(w + L.jctl), st)) != SK_OK) return s;
     double* sig = (double*)(w + L.sig);
     hipLaunchKernelGGL(k_col_norms, dim3((unsigned)n), dim3(SVD_THREADS), 0, st,
-                       (const double*)R, n, sig);
+                       (const double*)Gt, n, sig);
     hipLaunchKernelGGL(k_svd_rank, dim3(1), dim3(SVD_THREADS), 0, st, (const double*)sig, n,
                        (const JacobiCtl*)(w + L.jctl), (double*)(w + L.smax), state);
     hipLaunchKernelGGL(k_svd_precond, dim3(blocks_for(n * n, 256)), dim3(256), 0, st,
-                       (const double*)(w + L.vsv), (const double*)sig,
-                       (const double*)(w + L.smax), n, Ri);
+                       (const double*)Gt, (const double*)sig, (const double*)(w + L.smax), n,
+                       Ri);
   } else if ((s = trinv_launch(n, R, n, Ri, n, st)) != SK_OK) {
     return s;
   }

@@ -4,11 +4,12 @@
 // preconditioner N = V_r diag(1 / sigma_r) in place of R^{-1}.
 //
 // A_hat is first reduced by the Householder QR the QR form already runs
-// (A_hat = Q R, same singular values and right singular vectors), then R is
-// orthogonalised by one-sided (Hestenes) Jacobi rotations: columns p and q of
-// G (initially R) are rotated until G^T G is diagonal to a relative tolerance;
+// (A_hat = Q R, same singular values and right singular vectors), then a
+// matrix is orthogonalised by one-sided (Hestenes) Jacobi rotations: columns
+// p and q of G are rotated until G^T G is diagonal to a relative tolerance;
 // the same rotations applied to V (initially I) give G = U diag(sigma) with
-// G = R V.  One-sided Jacobi works on G itself, never on G^T G, so singular
+// G = G0 V.  The least-squares path orthogonalises G0 = R^T and needs no V
+// (see k_svd_precond); the general entry point accumulates V.  One-sided Jacobi works on G itself, never on G^T G, so singular
 // values down to rounding level of sigma_max come out with small relative
 // error -- the property that matters for choosing what to drop.
 //
@@ -127,7 +128,8 @@ __device__ __forceinline__ void jacobi_pair(int64_t npad, int64_t step, int64_t 
 // |g_p . g_q| <= tol |g_p| |g_q|, or one of them is at the rounding floor.
 // REG: the two columns of G and of V stay in registers between the sums and
 // the update (rows, n <= SVD_THREADS * SVD_RPT), V's loads issued with G's.
-template <bool REG>
+// WITHV = false: no V is accumulated (V unused).
+template <bool REG, bool WITHV = true>
 __global__ __launch_bounds__(SVD_THREADS) void k_jacobi_step(double* __restrict__ G,
                                                              int64_t rows,
                                                              double* __restrict__ V, int64_t n,
@@ -141,8 +143,8 @@ __global__ __launch_bounds__(SVD_THREADS) void k_jacobi_step(double* __restrict_
   __shared__ double sh[3 * SVD_THREADS / 64];
   double* gp = G + p * rows;
   double* gq = G + q * rows;
-  double* vp = V + p * n;
-  double* vq = V + q * n;
+  double* vp = WITHV ? V + p * n : nullptr;
+  double* vq = WITHV ? V + q * n : nullptr;
   const int tid = threadIdx.x;
   double a = 0.0, c = 0.0, g = 0.0, cs, sn;
   if constexpr (REG) {
@@ -152,8 +154,8 @@ __global__ __launch_bounds__(SVD_THREADS) void k_jacobi_step(double* __restrict_
       const int64_t i = tid + (int64_t)k * SVD_THREADS;
       x[k] = i < rows ? gp[i] : 0.0;
       y[k] = i < rows ? gq[i] : 0.0;
-      u[k] = i < n ? vp[i] : 0.0;
-      w[k] = i < n ? vq[i] : 0.0;
+      u[k] = WITHV && i < n ? vp[i] : 0.0;
+      w[k] = WITHV && i < n ? vq[i] : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < SVD_RPT; ++k) {
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(SVD_THREADS) void k_jacobi_step(double* __restrict_
         gp[i] = cs * x[k] - sn * y[k];
         gq[i] = sn * x[k] + cs * y[k];
       }
-      if (i < n) {
+      if (WITHV && i < n) {
         vp[i] = cs * u[k] - sn * w[k];
         vq[i] = sn * u[k] + cs * w[k];
       }
@@ -189,10 +191,12 @@ __global__ __launch_bounds__(SVD_THREADS) void k_jacobi_step(double* __restrict_
       gp[i] = cs * x - sn * y;
       gq[i] = sn * x + cs * y;
     }
-    for (int64_t i = tid; i < n; i += SVD_THREADS) {
-      const double x = vp[i], y = vq[i];
-      vp[i] = cs * x - sn * y;
-      vq[i] = sn * x + cs * y;
+    if (WITHV) {
+      for (int64_t i = tid; i < n; i += SVD_THREADS) {
+        const double x = vp[i], y = vq[i];
+        vp[i] = cs * x - sn * y;
+        vq[i] = sn * x + cs * y;
+      }
     }
   }
   if (tid == 0) atomicAdd(&ctl->rotations, 1);
@@ -253,17 +257,20 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_rank(const double* __restri
   }
 }
 
-// N = V diag(1 / sigma_j) over the kept columns, zero columns for the dropped
+// N = sum over the kept j of v_j e_j^T / sigma_j, zero columns for the dropped
 // ones (their LSQR coordinates then stay zero: x lies in the span of the kept
-// right singular vectors, the row space of A up to the dropped part)
-__global__ void k_svd_precond(const double* __restrict__ V, const double* __restrict__ sigma,
+// right singular vectors, the row space of A up to the dropped part).  The
+// sketch-and-precondition path orthogonalises G = R^T (no V accumulated):
+// then R^T V' = G = U' diag(sigma), so R = V' diag(sigma) U'^T and R's right
+// singular vectors are v_j = g_j / sigma_j, giving N's column j = g_j / sigma_j^2.
+__global__ void k_svd_precond(const double* __restrict__ G, const double* __restrict__ sigma,
                               const double* __restrict__ smax, int64_t n,
                               double* __restrict__ N) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * n) return;
   const int64_t j = t / n;
   const double s = sigma[j], mx = *smax;
-  N[t] = (mx > 0.0 && s >= mx * SVD_DROP) ? V[t] / s : 0.0;
+  N[t] = (mx > 0.0 && s >= mx * SVD_DROP) ? (G[t] / s) / s : 0.0;
 }
 
 }  // namespace sk

@@ -162,3 +162,36 @@ def test_s_entry_against_independent_words(oracle_lib, seed):
         z = (z0 if i % 2 == 0 else z1)[0]
         got = oracle_lib.s_entry("gaussian", seed, i, j)
         assert abs(got - z) <= 2.0**-20 * max(r[0], 1.0), (i, j, got, z)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("seed", [0, 1, 0x0123456789ABCDEF, 0xFFFFFFFFFFFFFFFF])
+@pytest.mark.parametrize("offset_calls", [0, 12345, (1 << 32) - 3])
+def test_philox_against_rocrand(oracle_lib, seed, offset_calls):
+    """A second independent Philox4x32-10: rocRAND's host generator (it needs
+    the HIP runtime, hence a device).  Its output 4k + w is word w of the
+    block function at counter (k_lo, k_hi, 0, 0) with key (seed_lo, seed_hi);
+    an offset of 4 (2^32 - 3) calls crosses the carry into the second counter
+    word."""
+    import ctypes
+    import torch
+    assert torch.cuda.is_available(), "the HIP runtime needs a device"
+    try:
+        L = ctypes.CDLL("/opt/rocm/lib/librocrand.so")
+    except OSError:
+        pytest.skip("rocRAND is not installed")
+    gen = ctypes.c_void_p()
+    assert L.rocrand_create_generator_host_blocking(ctypes.byref(gen), 404) == 0  # PHILOX4_32_10
+    try:
+        assert L.rocrand_set_seed(gen, ctypes.c_ulonglong(seed)) == 0
+        assert L.rocrand_set_offset(gen, ctypes.c_ulonglong(4 * offset_calls)) == 0
+        n = 4 * 1024
+        out = np.zeros(n, dtype=np.uint32)
+        assert L.rocrand_generate(gen, out.ctypes.data_as(ctypes.c_void_p), ctypes.c_size_t(n)) == 0
+    finally:
+        L.rocrand_destroy_generator(gen)
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    for k in range(1024):
+        c = offset_calls + k
+        want = oracle_lib.philox((c & 0xFFFFFFFF, c >> 32, 0, 0), key)
+        assert [int(x) for x in out[4 * k:4 * k + 4]] == [int(x) for x in want], k
