@@ -66,9 +66,15 @@ def kernel_sources_sha() -> str:
     return h.hexdigest()
 
 
-def counter_traffic(workload: str):
+def plan_string(plan: dict) -> str:
+    return " ".join(f"{k}={plan[k]}" for k in ("variant", "splits", "tile_rows",
+                                              "rows_per_block", "col_split"))
+
+
+def counter_traffic(workload: str, plan: dict):
     """HBM bytes per launch of the sketch kernel from the committed counter
-    summary, or None when it does not apply (other workload, changed kernel)."""
+    summary, or None when it does not apply (other workload, changed kernel
+    sources, or another plan)."""
     if workload != "plain_scale" or not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -78,6 +84,8 @@ def counter_traffic(workload: str):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_sources_sha256") != kernel_sources_sha():
+        return None
+    if vals.get("plan") != plan_string(plan):
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -304,7 +312,9 @@ def bench_plain(args, B):
                    "input_sha256": A.sha256()},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "TOP/s (full-rate VALU lane-ops)", "frac": achieved / VALU_PEAK,
-                     "traffic": counter_traffic(args.workload), "kernel": "k_sketch",
+                     "traffic": (counter_traffic(args.workload, B.autotune(dA, d, dist))
+                                 if not any(tune.values()) else None),
+                     "kernel": "k_sketch",
                      "kernel_ms": kms,
                      "work": {"generator_calls": calls, "s_values": entries, "fma": fmas,
                               "lane_ops": work},

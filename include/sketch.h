@@ -252,7 +252,7 @@ sk_status sk_plan_info(const sk_csc* A, int64_t d, int32_t dist, int32_t prec,
 /* Autotuner, measured form: runs the candidates on the device and keeps the
  * fastest.  Stage one times the Algorithm 3 kernel (FP32 only) and every
  * S-tile kernel shape at the model's splits (the matrix-core path: its one
- * shape); stage two times splits 1..64 for the two fastest S-tile shapes.
+ * shape); stage two times splits 1..64 for the three fastest S-tile shapes.
  * Each candidate: one untimed call, then the best of up to three calls timed
  * with events on hip_stream (one when already 1.5x slower than the best).
  * The winner (fields kernel, variant, splits; the rest 0) is written to *out,

@@ -270,15 +270,29 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
   } else if (unit_cycles > 0) {
     splits = (int64_t)std::ceil(best / ((double)P.tiles * P.ncr * unit_cycles));
   } else {
-    // about eight workgroups per CU, rounded to the nearest multiple of four
-    // from eight splits on (the splits then sit on fixed pairs of XCDs).
-    // Fewer splits write and reduce fewer partial slices; more balance
-    // uneven blocks (measured: uniform rows favour 12-16 splits at d = 4000,
-    // power-law columns 24 at d = 3000)
+    // Few splits, in whole rounds of workgroups: every split writes a full
+    // partial slice (d x columns FP32) that the reduction reads back, so
+    // more splits cost traffic that grows with d n, not with the work
+    // (measured on MI355X: 2-6 splits beat 16-24 on the 2e6 x 2000 uniform
+    // and the 4e6 x 1000 power-law workloads; on a Table I shape with
+    // d = 3n the 16 partial slices took most of the time).  The splits are
+    // cost-balanced, so the workgroups run about equally long and a launch
+    // of x rounds of resident workgroups (one of 1024 threads or two of 512
+    // per CU) keeps x / ceil(x) of the chip busy: 375 workgroups on 256 CUs
+    // measured 24 ms where 250 took 18.  Take the fewest splits (up to 16)
+    // with that fraction >= 0.9, else the best one.  (MI355X's 256 CUs as a
+    // constant: the plan, and so the summation order, follows from the
+    // shape alone.)
     const int64_t wgs_now = (int64_t)P.tiles * ncr;
-    splits = std::max<int64_t>(1, (2048 + wgs_now / 2) / wgs_now);
-    if (splits >= 8) splits = (splits + 2) / 4 * 4;
-    splits = std::min<int64_t>(splits, 64);
+    const double resident = 256.0 * (V.wgs >= 1024 ? 1 : 2);
+    splits = 1;
+    double best_util = -1.0;
+    for (int64_t sp = 1; sp <= 16; ++sp) {
+      const double x = (double)(wgs_now * sp) / resident;
+      const double util = x / std::ceil(x);
+      if (util >= 0.9) { splits = sp; break; }
+      if (util > best_util + 1e-9) { best_util = util; splits = sp; }
+    }
   }
   splits = std::max<int64_t>(1, std::min<int64_t>(splits, P.nb_max));
   P.splits = (int32_t)splits;
@@ -1885,13 +1899,13 @@ sk_status sk_autotune_measure(const sk_csc* A, int64_t d, int32_t dist, uint64_t
     best = std::min(best, ms);
   }
   if (timed.empty()) return SK_EUNSUPPORTED;
-  // stage two: the splits of the two fastest S-tile shapes
+  // stage two: the splits of the three fastest S-tile shapes
   std::vector<std::pair<double, sk_tuning>> tiles;
   for (const auto& e : timed)
     if (e.second.kernel == KERNEL_TILE) tiles.push_back(e);
   std::sort(tiles.begin(), tiles.end(),
             [](const auto& a, const auto& b) { return a.first < b.first; });
-  for (size_t i = 0; i < tiles.size() && i < 2; ++i) {
+  for (size_t i = 0; i < tiles.size() && i < 3; ++i) {
     for (const sk_tuning& t : tune_stage_two(A, d, dist, prec, tiles[i].second.variant)) {
       double ms = 0.0;
       s = time_call(A, d, dist, seed, prec, t, Ahat, ld, ws, ws_bytes, st, 1.5 * best, &ms);
