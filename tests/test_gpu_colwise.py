@@ -110,3 +110,23 @@ def test_colwise_heavy_columns_in_chunks(B, oracle_lib, dist):
         col = np.abs(A.to_dense()).sum(axis=0)[None, :]
         smax = oracle_lib.S_MAX[oracle_lib.DIST_NAMES[dist]]
         assert np.all(np.abs(got64 - ref) <= 1e-13 * col * smax)
+
+
+def test_colwise_longer_chunks_at_large_d(B, oracle_lib):
+    # nnz * d large enough that the chunk length doubles (the partials of
+    # 512-entry chunks would pass 256 MiB): four columns of 10000 nonzeros,
+    # d = 300000; checked on the first and last 3000 rows (the oracle
+    # sketches any row range through row0)
+    m, n, d = 50_000, 4, 300_000
+    rng = np.random.default_rng(23)
+    rows = np.concatenate([np.sort(rng.choice(m, size=10_000, replace=False)) for _ in range(n)])
+    cols = np.repeat(np.arange(n), 10_000)
+    A = inputs.from_coo(m, n, rows, cols, rng.uniform(-1, 1, rows.size))
+    got = B.sketch_colwise(B.DeviceCsc.from_host(A), d, "uniform", 4).cpu().numpy()
+    for r0 in (0, d - 3000):
+        ref = oracle_lib.sketch(A.m, A.n, A.colptr, A.rowidx, A.vals, 3000, "uniform", 4,
+                                row0=r0)
+        p = oracle_lib.parity(got[r0:r0 + 3000].astype(np.float64), ref, A.colptr, A.vals,
+                              "uniform")
+        print(f"rows {r0}..: {p}", flush=True)
+        assert p["nonfinite"] == 0 and p["max_elem_scaled"] <= oracle_lib.ELEM_TOL, p
