@@ -202,6 +202,94 @@ __global__ __launch_bounds__(SVD_THREADS) void k_jacobi_step(double* __restrict_
   if (tid == 0) atomicAdd(&ctl->rotations, 1);
 }
 
+// Block form (no V): the columns are grouped into blocks of W; one step of
+// the round-robin order over blocks gives each workgroup a pair of blocks,
+// whose 2W columns it copies into LDS (2W x rows doubles), orthogonalises
+// among themselves by one inner round-robin sweep (2W - 1 inner steps of W
+// disjoint column pairs, 1024 / W threads per pair), and writes back.  A
+// sweep over the block pairs checks every column pair at least once, so a
+// sweep with no rotation anywhere is converged as in the pairwise form; it
+// needs nblocks - 1 launches instead of n - 1.  The same test and rotation
+// as the pairwise step.
+template <int W>
+__global__ __launch_bounds__(1024) void k_jacobi_block(double* __restrict__ G, int64_t rows,
+                                                       int64_t n, int64_t nblk, int64_t nbpad,
+                                                       int64_t step, double tol,
+                                                       JacobiCtl* __restrict__ ctl) {
+  if (ctl->converged) return;
+  constexpr int TPP = 1024 / W;  // threads per column pair
+  constexpr int WPP = TPP / 64;  // waves per column pair
+  extern __shared__ __align__(16) double colbuf[];  // 2W columns of `rows`
+  __shared__ double red[W][WPP][3];
+  __shared__ int rot_count;
+  int64_t bp, bq;
+  jacobi_pair(nbpad, step, blockIdx.x, bp, bq);
+  if (bq >= nblk) return;  // the padding block
+  const int tid = threadIdx.x;
+  if (tid == 0) rot_count = 0;
+  auto gcol = [&](int c) -> int64_t { return c < W ? bp * W + c : bq * W + (c - W); };
+  for (int64_t x = tid; x < (int64_t)2 * W * rows; x += 1024) {
+    const int c = (int)(x / rows);
+    const int64_t i = x - (int64_t)c * rows;
+    const int64_t gc = gcol(c);
+    colbuf[x] = gc < n ? G[gc * rows + i] : 0.0;
+  }
+  __syncthreads();
+  const int pr = tid / TPP;  // this thread's pair in an inner step
+  const int lt = tid - pr * TPP;
+  const int wv = lt >> 6;
+  const double floor2 = ctl->floor2;
+  int rotated = 0;
+  for (int s = 0; s < 2 * W - 1; ++s) {
+    int64_t p, q;
+    jacobi_pair(2 * W, s, pr, p, q);
+    double* x = colbuf + p * rows;
+    double* y = colbuf + q * rows;
+    double a = 0.0, c = 0.0, g = 0.0;
+    for (int64_t i = lt; i < rows; i += TPP) {
+      const double u = x[i], v = y[i];
+      a = __builtin_fma(u, u, a);
+      c = __builtin_fma(v, v, c);
+      g = __builtin_fma(u, v, g);
+    }
+    a = wave_sum(a);
+    c = wave_sum(c);
+    g = wave_sum(g);
+    if ((lt & 63) == 0) {
+      red[pr][wv][0] = a;
+      red[pr][wv][1] = c;
+      red[pr][wv][2] = g;
+    }
+    __syncthreads();
+    a = c = g = 0.0;
+    for (int k = 0; k < WPP; ++k) {  // fixed order
+      a += red[pr][k][0];
+      c += red[pr][k][1];
+      g += red[pr][k][2];
+    }
+    double cs, sn;
+    if (jacobi_rotation(a, c, g, tol, floor2, cs, sn)) {
+      for (int64_t i = lt; i < rows; i += TPP) {
+        const double u = x[i], v = y[i];
+        x[i] = cs * u - sn * v;
+        y[i] = sn * u + cs * v;
+      }
+      rotated += lt == 0;
+    }
+    __syncthreads();  // the next inner step reads other threads' rows
+  }
+  if (rotated) atomicAdd(&rot_count, rotated);
+  __syncthreads();
+  if (rot_count == 0) return;  // nothing moved: G is unchanged
+  for (int64_t x = tid; x < (int64_t)2 * W * rows; x += 1024) {
+    const int c = (int)(x / rows);
+    const int64_t i = x - (int64_t)c * rows;
+    const int64_t gc = gcol(c);
+    if (gc < n) G[gc * rows + i] = colbuf[x];
+  }
+  if (tid == 0) atomicAdd(&ctl->rotations, rot_count);
+}
+
 // end of a sweep: converged when it rotated nothing
 __global__ void k_jacobi_sweep_end(JacobiCtl* __restrict__ ctl) {
   if (threadIdx.x != 0 || blockIdx.x != 0 || ctl->converged) return;

@@ -225,3 +225,20 @@ def test_sap_largest_serving_size_by_properties(B, oracle_lib):
         assert oracle_lib.ls_error(As, x, b) <= 1e-9
         xs[method] = x
     assert np.linalg.norm(xs[0] - xs[1]) <= 1e-8 * np.linalg.norm(xs[0])
+
+
+def test_sap_svd_block_form_rank_deficient(B, oracle_lib):
+    # n >= 768 runs the block form of the Jacobi sweep (column blocks rotated
+    # in LDS); exactly rank-deficient, so x is the minimum-norm solution
+    m, n, rank = 30_000, 800, 700
+    A, b, null = inputs.ls_request_rank_deficient(4, m, n, rank, dense_rows=900)
+    dA, db = device_request(B, A, b)
+    p = B.sap_params(2 * n, "rademacher", 17, atol=1e-12, btol=1e-12, method=B.SAP_SVD)
+    print(f"sap-svd block form m={m} n={n} rank={rank}", flush=True)
+    x, info = B.SapSolve(dA, db, p).solve(chunk=16)
+    x = x.cpu().numpy()
+    assert info["status"] == 0 and info["istop"] in (1, 2), info
+    assert info["rank"] == rank and 0 < info["sweeps"] <= 40, info
+    xs = np.linalg.lstsq(A.to_dense(), b, rcond=1e-10)[0]
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs), np.linalg.norm(x - xs)
+    _null_ok(x, null, 1e-9)
