@@ -246,11 +246,28 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double* __restrict__ G, i
     double* x = colbuf + p * rows;
     double* y = colbuf + q * rows;
     double a = 0.0, c = 0.0, g = 0.0;
-    for (int64_t i = lt; i < rows; i += TPP) {
-      const double u = x[i], v = y[i];
-      a = __builtin_fma(u, u, a);
-      c = __builtin_fma(v, v, c);
-      g = __builtin_fma(u, v, g);
+    // the thread's rows of both columns stay in registers for the update
+    // when rows <= TPP * RPT (else they are read again)
+    constexpr int RPT = 8;
+    double ur[RPT], vr[RPT];
+    const bool regs = rows <= (int64_t)TPP * RPT;
+    if (regs) {
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int64_t i = lt + (int64_t)k * TPP;
+        ur[k] = i < rows ? x[i] : 0.0;
+        vr[k] = i < rows ? y[i] : 0.0;
+        a = __builtin_fma(ur[k], ur[k], a);
+        c = __builtin_fma(vr[k], vr[k], c);
+        g = __builtin_fma(ur[k], vr[k], g);
+      }
+    } else {
+      for (int64_t i = lt; i < rows; i += TPP) {
+        const double u = x[i], v = y[i];
+        a = __builtin_fma(u, u, a);
+        c = __builtin_fma(v, v, c);
+        g = __builtin_fma(u, v, g);
+      }
     }
     a = wave_sum(a);
     c = wave_sum(c);
@@ -269,10 +286,21 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double* __restrict__ G, i
     }
     double cs, sn;
     if (jacobi_rotation(a, c, g, tol, floor2, cs, sn)) {
-      for (int64_t i = lt; i < rows; i += TPP) {
-        const double u = x[i], v = y[i];
-        x[i] = cs * u - sn * v;
-        y[i] = sn * u + cs * v;
+      if (regs) {
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          const int64_t i = lt + (int64_t)k * TPP;
+          if (i < rows) {
+            x[i] = cs * ur[k] - sn * vr[k];
+            y[i] = sn * ur[k] + cs * vr[k];
+          }
+        }
+      } else {
+        for (int64_t i = lt; i < rows; i += TPP) {
+          const double u = x[i], v = y[i];
+          x[i] = cs * u - sn * v;
+          y[i] = sn * u + cs * v;
+        }
       }
       rotated += lt == 0;
     }
