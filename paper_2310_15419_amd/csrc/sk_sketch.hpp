@@ -324,11 +324,12 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
             const int32_t pc0 = seg_lds[cl + c], pc1 = seg_lds[cl + c + 1];
             const int32_t lo = pc0 > sp ? pc0 : sp;
             const int32_t hi = pc1 < s1 ? pc1 : s1;
-            int32_t p = lo - s0a;
-            const int32_t pe = hi - s0a;
-            for (; p + 1 < pe; p += 2) {
-              const uint2 e0 = E_lds[p];
-              const uint2 e1 = E_lds[p + 1];
+            // walk by LDS pointer: one add and one compare per two entries
+            const uint2* ep = E_lds + (lo - s0a);
+            const uint2* const ep_last = E_lds + (hi - s0a) - 1;
+            for (; ep < ep_last; ep += 2) {
+              const uint2 e0 = ep[0];
+              const uint2 e1 = ep[1];
               float x0[DL], x1[DL];
               load_rows<DL>(reinterpret_cast<const float*>(Sl + e0.x), x0);
               load_rows<DL>(reinterpret_cast<const float*>(Sl + e1.x), x1);
@@ -339,8 +340,8 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
 #pragma unroll
               for (int t = 0; t < DL; ++t) acc[c][t] = __builtin_fmaf(a1, x1[t], acc[c][t]);
             }
-            if (p < pe) {
-              const uint2 e0 = E_lds[p];
+            if (ep == ep_last) {
+              const uint2 e0 = *ep;
               float x0[DL];
               load_rows<DL>(reinterpret_cast<const float*>(Sl + e0.x), x0);
               const float a0 = __uint_as_float(e0.y);
