@@ -412,13 +412,14 @@ double kji_time_us(int64_t n, int64_t nnz, int64_t d, int dist) {
 
 // Predicted time of the S-tile kernel's plan: its cost model (CU-cycles on
 // 256 CUs at 2.4 GHz) times a factor fitted to measured runs, plus the fixed
-// cost of the inspector and reduction launches.  The model counts issue
-// slots; the column walk's LDS bank conflicts and the lockstep padding it
-// leaves out make the measured time 1.7-2.1x the count on matrices with
-// uniform nonzero positions (the Table I stand-ins, Table VI's B and the
-// 2e6 x 2000 uniform case), hence the factor 2.
+// cost of the validation, inspector and reduction launches (measured
+// 0.11-0.15 ms on small inputs).  The model counts issue slots; the column
+// walk's LDS bank conflicts and the lockstep padding it leaves out make the
+// measured time 1.7-2.1x the count on matrices with uniform nonzero
+// positions (the Table I stand-ins, Table VI's B and the 2e6 x 2000
+// uniform case), hence the factor 2.
 constexpr double kTileCostFactor = 2.0;
-constexpr double kTileFixedUs = 40.0;
+constexpr double kTileFixedUs = 150.0;
 double tile_time_us(const Plan& P) {
   return kTileCostFactor * P.cost / (256.0 * 2400.0) + kTileFixedUs;
 }
