@@ -1043,12 +1043,15 @@ sk_status trinv_launch(int64_t n, const double* R, int64_t ldr, double* Ri, int6
 constexpr int kJacobiMaxSweeps = 40;
 constexpr int kJacobiBatch = 4;
 
-sk_status jacobi_svd(int64_t rows, int64_t n, double* G, double* V, JacobiCtl* ctl,
+// tmp: n doubles of scratch (the column norms for the rounding floor)
+sk_status jacobi_svd(int64_t rows, int64_t n, double* G, double* V, JacobiCtl* ctl, double* tmp,
                      hipStream_t st) {
   const bool withv = V != nullptr;  // else no V is accumulated
   if (withv) hipLaunchKernelGGL(k_eye, dim3(blocks_for(n * n, 256)), dim3(256), 0, st, V, n);
-  hipLaunchKernelGGL(k_jacobi_reset, dim3(1), dim3(SVD_THREADS), 0, st, (const double*)G,
-                     rows * n, ctl);
+  hipLaunchKernelGGL(k_col_norms, dim3((unsigned)n), dim3(SVD_THREADS), 0, st, (const double*)G,
+                     rows, tmp);
+  hipLaunchKernelGGL(k_jacobi_reset, dim3(1), dim3(SVD_THREADS), 0, st, (const double*)tmp, n,
+                     ctl);
   const int64_t npad = n + (n & 1);
   const double tol = std::sqrt((double)rows) * 0x1.0p-52;
   const bool reg = rows <= (int64_t)SVD_THREADS * SVD_RPT;  // n <= rows
@@ -2014,7 +2017,7 @@ sk_status sk_svd_f64(int64_t rows, int64_t n, double* G, double* V, double* sigm
   if (!ws || ws_bytes < need) return SK_EWORKSPACE;
   hipStream_t st = (hipStream_t)hip_stream;
   JacobiCtl* ctl = (JacobiCtl*)ws;
-  if ((s = jacobi_svd(rows, n, G, V, ctl, st)) != SK_OK) return s;
+  if ((s = jacobi_svd(rows, n, G, V, ctl, sigma, st)) != SK_OK) return s;
   hipLaunchKernelGGL(k_col_norms, dim3((unsigned)n), dim3(SVD_THREADS), 0, st, (const double*)G,
                      rows, sigma);
   if ((s = launch_ok()) != SK_OK) return s;
@@ -2078,8 +2081,8 @@ sk_status sk_sap_begin(const sk_csc* A, const double* b, const sk_sap_params* p,
     double* Gt = (double*)(w + L.vsv);
     hipLaunchKernelGGL(k_transpose, dim3(blocks_for(n * n, 256)), dim3(256), 0, st,
                        (const double*)R, n, Gt);
-    if ((s = jacobi_svd(n, n, Gt, nullptr, (JacobiCtl*)(w + L.jctl), st)) != SK_OK) return s;
     double* sig = (double*)(w + L.sig);
+    if ((s = jacobi_svd(n, n, Gt, nullptr, (JacobiCtl*)(w + L.jctl), sig, st)) != SK_OK) return s;
     hipLaunchKernelGGL(k_col_norms, dim3((unsigned)n), dim3(SVD_THREADS), 0, st,
                        (const double*)Gt, n, sig);
     hipLaunchKernelGGL(k_svd_rank, dim3(1), dim3(SVD_THREADS), 0, st, (const double*)sig, n,

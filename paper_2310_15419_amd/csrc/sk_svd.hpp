@@ -48,19 +48,20 @@ __global__ void k_eye(double* __restrict__ V, int64_t n) {
   V[t] = i == j ? 1.0 : 0.0;
 }
 
-// Reset the control block; floor2 = (2^-52 |G|_F)^2.  A column whose norm is
-// at that floor holds only rounding noise: its singular value is below
+// Reset the control block; floor2 = (2^-52 |G|_F)^2 from the column norms
+// (|G|_F^2 = sum of the squared column norms).  A column whose norm is at
+// that floor holds only rounding noise: its singular value is below
 // 2^-52 |G|_F <= 2^-52 sqrt(n) sigma_max, far under the drop threshold, and
 // rotating it against the others would only stir that noise (the pair test
 // is relative, and noise never passes it), so steps leave such pairs alone.
 // A rotation against a column of norm f turns the other column by an angle
 // of at most f / (its norm), so what is left undone is rounding-sized.
-__global__ __launch_bounds__(SVD_THREADS) void k_jacobi_reset(const double* __restrict__ G,
-                                                              int64_t count,
+__global__ __launch_bounds__(SVD_THREADS) void k_jacobi_reset(const double* __restrict__ cnorm,
+                                                              int64_t n,
                                                               JacobiCtl* __restrict__ c) {
   __shared__ double sh[16];
   double a = 0.0;
-  for (int64_t i = threadIdx.x; i < count; i += SVD_THREADS) a = __builtin_fma(G[i], G[i], a);
+  for (int64_t j = threadIdx.x; j < n; j += SVD_THREADS) a = __builtin_fma(cnorm[j], cnorm[j], a);
   const double f = block_sum(a, sh);
   if (threadIdx.x == 0) {
     JacobiCtl z{};
