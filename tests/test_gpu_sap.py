@@ -242,3 +242,28 @@ def test_sap_svd_block_form_rank_deficient(B, oracle_lib):
     xs = np.linalg.lstsq(A.to_dense(), b, rcond=1e-10)[0]
     assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs), np.linalg.norm(x - xs)
     _null_ok(x, null, 1e-9)
+
+
+def test_sap_svd_degenerate_ranks(B):
+    import torch
+    m, n = 3000, 12
+    # A = 0: every singular value is zero, nothing is kept, x = 0 (the
+    # minimum-norm solution) and LSQR stops at once
+    Z = inputs.from_coo(m, n, np.array([], dtype=np.int64), np.array([], dtype=np.int64),
+                        np.array([], dtype=np.float64))
+    b = np.random.default_rng(1).standard_normal(m)
+    dZ, db = device_request(B, Z, b)
+    x, info = B.SapSolve(dZ, db, B.sap_params(24, "gaussian", 3, method=B.SAP_SVD)).solve()
+    assert info["status"] == 0 and info["rank"] == 0 and info["done"] == 1, info
+    assert np.array_equal(x.cpu().numpy(), np.zeros(n))
+    # rank 1: one nonzero column among empty ones
+    rows = np.arange(0, m, 7)
+    A1 = inputs.from_coo(m, n, rows, np.full(rows.size, 5), np.linspace(-1.0, 2.0, rows.size))
+    dA, db = device_request(B, A1, b)
+    x, info = B.SapSolve(dA, db, B.sap_params(24, "rademacher", 3, method=B.SAP_SVD,
+                                              atol=1e-12, btol=1e-12)).solve()
+    x = x.cpu().numpy()
+    assert info["status"] == 0 and info["rank"] == 1 and info["istop"] in (1, 2), info
+    xs = np.linalg.lstsq(A1.to_dense(), b, rcond=1e-10)[0]
+    assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
+    assert np.count_nonzero(x) == 1 and x[5] != 0.0
