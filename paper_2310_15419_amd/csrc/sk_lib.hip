@@ -176,9 +176,18 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
   if (forced_variant >= 0 && tune && tune->variant > 0 && tune->variant - 1 != forced_variant)
     return false;
   if (v < 0) {
-    // auto: enough columns per workgroup, then the most S rows per lane
+    // auto: enough columns per workgroup, then the most S rows per lane.
+    // Between 512 and 2048 columns: four lanes per column group (shape 3)
+    // when rows hold several nonzeros; pairs of lanes with half the columns
+    // per group (shape 4) when they hold about one (nnz / nonempty rows < 2
+    // for uniform positions): a block's column segments then hold zero or
+    // one entry and a lane's per-column setup, not its multiply-adds, is the
+    // cost, which shape 4 halves (measured on MI355X: the 4e6 x 1000
+    // power-law matrix 4.4 against 5.3 ms, the 2e6 x 2000 one with ten
+    // nonzeros per row 21.6 against 18.1 ms)
+    const double r_uni = std::max(1.0, (double)m * -std::expm1(-(double)nnz / (double)m));
     if (n <= 512) v = 5;
-    else if (n <= 2048) v = 2;  // eight S rows per lane: measured fastest at n ~ 1e3
+    else if (n <= 2048) v = (double)nnz / r_uni < 2.0 ? 3 : 2;
     else v = 1;
   }
   const Variant& V = kVariants[v];
