@@ -68,7 +68,7 @@ def kernel_sources_sha() -> str:
 
 def plan_string(plan: dict) -> str:
     return " ".join(f"{k}={plan[k]}" for k in ("variant", "splits", "tile_rows",
-                                              "rows_per_block", "col_split"))
+                                              "rows_per_block", "col_split", "balance"))
 
 
 def counter_traffic(workload: str, plan: dict):
@@ -257,7 +257,8 @@ def bench_plain(args, B):
     dA = B.DeviceCsc.from_host(A, dtype=np.float32 if A.vals.dtype != np.float64 else None)
     tune = {"variant": args.variant, "rows_per_block": args.rows_per_block,
             "splits": args.splits, "dense_min_pct": args.dense_min_pct,
-            "col_split": args.col_split, "row_pad": args.row_pad, "tile_rows": args.tile_rows}
+            "col_split": args.col_split, "row_pad": args.row_pad, "tile_rows": args.tile_rows,
+            "balance": args.balance}
     ws = B.alloc_workspace(B.workspace_bytes(dA, d, dist, tune=tune))
     out = torch.empty((A.n, d), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
@@ -701,6 +702,8 @@ def main():
     ap.add_argument("--dense-min-pct", type=int, default=0)
     ap.add_argument("--col-split", type=int, default=0, help="0 auto, 1 off, 2 on")
     ap.add_argument("--row-pad", type=int, default=0)
+    ap.add_argument("--balance", type=int, default=0,
+                    help="row blocks: 0 auto, 1 rows in order, 2 balanced")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--workers", type=int, default=0,

@@ -122,6 +122,18 @@ typedef struct {
                              kernel only for FP32 requests that set no other
                              field, when its predicted time (from the shape
                              alone) is under half the S-tile kernel's.     */
+  int32_t balance;        /* row blocks of the S-tile kernel (single sketches):
+                             0 = auto, 1 = nonempty rows in order, 2 =
+                             balanced: inside super-blocks of up to 16 blocks
+                             the rows are dealt to blocks so that each
+                             column's entry count per block is about even
+                             (the lockstep of the column walk then wastes
+                             less; A_hat is the same up to rounding, S being
+                             a function of the row index).  Needs n <= 2048
+                             (else rows in order).  Auto: on for 512 <= n <=
+                             2048 when a block holds about 1 to 16 entries per
+                             column and the matrix has at least four
+                             super-blocks of nonempty rows.                  */
 } sk_tuning;
 
 /* Human-readable name of a status code (static storage). */
@@ -243,8 +255,9 @@ sk_status sk_autotune(const sk_csc* A, int64_t d, int32_t dist, sk_tuning* out);
 /* The cost model's view of a request, for inspection (host-only): info[0] =
  * predicted S-tile kernel time (us), info[1] = predicted Algorithm 3 kernel
  * time (us), info[2] = the kernel auto picks (1 or 2), info[3] = the S-tile
- * plan's cost (CU-cycles), info[4] = its kernel shape (1-based); the first
- * ninfo of these are written.  tune as for sk_sketch (NULL: the cached
+ * plan's cost (CU-cycles), info[4] = its kernel shape (1-based), info[5] =
+ * its blocks per balanced super-block (0: rows in order, see
+ * sk_tuning.balance); the first ninfo of these are written.  tune as for sk_sketch (NULL: the cached
  * plan, else the model). */
 sk_status sk_plan_info(const sk_csc* A, int64_t d, int32_t dist, int32_t prec,
                        const sk_tuning* tune, double* info, int32_t ninfo);

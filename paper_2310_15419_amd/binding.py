@@ -33,7 +33,7 @@ class SkTuning(ctypes.Structure):
                 ("phases", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("col_split", ctypes.c_int32), ("row_pad", ctypes.c_int32),
                 ("count_rng", ctypes.c_int32), ("rng_mode", ctypes.c_int32),
-                ("kernel", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("balance", ctypes.c_int32)]
 
 
 class SapParams(ctypes.Structure):
@@ -364,12 +364,12 @@ KERNEL_AUTO, KERNEL_TILE, KERNEL_KJI = 0, 1, 2
 
 def plan_info(A: DeviceCsc, d: int, dist, prec: int = PREC_F32, tune=None) -> dict:
     """The cost model's view of a request (sk_plan_info)."""
-    info = (ctypes.c_double * 5)()
+    info = (ctypes.c_double * 6)()
     c = A.c_struct()
-    _check(lib().sk_plan_info(ctypes.byref(c), d, _dist(dist), prec, _tuning(tune), info, 5),
+    _check(lib().sk_plan_info(ctypes.byref(c), d, _dist(dist), prec, _tuning(tune), info, 6),
            "sk_plan_info")
     return {"tile_us": info[0], "kji_us": info[1], "kernel": int(info[2]),
-            "tile_cost": info[3], "variant": int(info[4])}
+            "tile_cost": info[3], "variant": int(info[4]), "balance_sb": int(info[5])}
 
 
 def autotune_measure(A: DeviceCsc, d: int, dist, seed: int, out, prec: int = PREC_F32,

@@ -15,6 +15,7 @@
 #include <mutex>
 #include <tuple>
 
+#include "sk_balance.hpp"
 #include "sk_batch.hpp"
 #include "sk_colwise.hpp"
 #include "sk_dense.hpp"
@@ -131,6 +132,7 @@ struct Plan {
   double cost;        // autotuner's cost estimate (CU-cycles)
   int32_t row_bytes;  // row offset unit of the entries (S-tile row bytes; 1 on MFMA)
   int32_t mfma;       // 0: sparse FP32 kernel; MF_BF16 / MF_FP8: matrix-core kernel
+  int32_t bal_sb;     // balanced row blocks: blocks per super-block (0: rows in order)
 };
 
 constexpr int kDenseAutoPct = 40;                 // FP32 operands
@@ -323,6 +325,20 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
   P.cost = best;
   P.row_bytes = P.ldS * 4;
   P.mfma = 0;
+  // balanced row blocks (single sketches): where a block holds a few entries
+  // per column, so that the lockstep of the column walk costs most (measured
+  // on MI355X, the 2e6 x 2000 workload with ten nonzeros per row and 3.7
+  // entries per (block, column): kernel 17.6 -> 15.2-15.5 ms with 16-32
+  // blocks per super-block)
+  P.bal_sb = 0;
+  const int bal_mode = tune ? tune->balance : 0;
+  if (unit_cycles <= 0 && bal_mode != 1 && n <= BAL_N_MAX && P.m_b >= 1) {
+    const int sb = (int)std::min<int64_t>(BAL_SB_MAX, BAL_SBM_MAX / P.m_b);
+    const double lam = (double)P.m_b * per_row / (double)n;  // entries per (block, column)
+    const bool auto_on = n >= 512 && sb >= 8 && r_est >= 4.0 * sb * P.m_b && per_row >= 4.0 &&
+                         lam >= 1.0 && lam <= 16.0;
+    if (sb >= 2 && (bal_mode == 2 || (bal_mode == 0 && auto_on))) P.bal_sb = sb;
+  }
   return true;
 }
 
@@ -455,6 +471,7 @@ struct Layout {
   int64_t hdr, item, ridx, rcnt, rowlist, rowcnt, bfl, bstart, vbase, pos, seg, ent, bcost, sums,
       rowinfo;
   int64_t dflag, dlist, doff, dhdr, drows, dense, part, total;
+  int64_t bal_rowoff, bal_ccol, bal_newidx, bal_orig, bal_rowidx, bal_vals;
 };
 
 int64_t scan_sums_len(int64_t longest) { return longest / SCAN_CHUNK + 2; }
@@ -487,6 +504,14 @@ Layout layout_for(int64_t m, int64_t n, int64_t nnz, int64_t d, const Plan& P) {
   L.dhdr = off;    off = align_up(off + (int64_t)sizeof(DenseHeader));
   L.drows = off;   off = align_up(off + 4 * std::max<int64_t>(P.kd_max, 1));
   L.dense = off;   off = align_up(off + 4 * P.kd_max * n);
+  if (P.bal_sb) {  // balanced row blocks: the row pattern, the renumbering and A'
+    L.bal_rowoff = off; off = align_up(off + 4 * (P.r_max + 2));
+    L.bal_ccol = off;   off = align_up(off + 2 * std::max<int64_t>(nnz, 1));
+    L.bal_newidx = off; off = align_up(off + 4 * m);
+    L.bal_orig = off;   off = align_up(off + 4 * P.r_max);
+    L.bal_rowidx = off; off = align_up(off + 4 * std::max<int64_t>(nnz, 1));
+    L.bal_vals = off;   off = align_up(off + 4 * std::max<int64_t>(nnz, 1));
+  }
   L.part = off;
   if (P.slices > 1 || P.nv != n)
     off = align_up(off + 4 * ((int64_t)P.splits * d * P.nv + (P.dense_pct ? d * n : 0)));
@@ -517,7 +542,8 @@ constexpr double kKjiMargin = 2.0;
 // any field that only the S-tile kernel has
 bool tile_fields_set(const sk_tuning* t) {
   return t && (t->rows_per_block || t->splits || t->variant || t->dense_min_pct || t->phases ||
-               t->tile_rows || t->col_split || t->row_pad || t->count_rng || t->rng_mode);
+               t->tile_rows || t->col_split || t->row_pad || t->count_rng || t->rng_mode ||
+               t->balance);
 }
 
 // KERNEL_TILE or KERNEL_KJI for a request (FP32 only for the latter); an
@@ -702,20 +728,29 @@ sk_status scan_regions(int32_t* all, int64_t total, Item* it, int count, int32_t
 // a1 + a2 for every item: validation, nonempty rows, entry-balanced row
 // blocks, heavy-column splitting, segments and the entry scatter.  The
 // items' headers must be zero.
-sk_status run_inspector(Item* it, int count, const InspectSizes& Z, const InspectArrays& W,
-                        hipStream_t st) {
-  sk_status s;
+// (a1 and the nonempty rows; `validate` = false: the input was validated
+// before, e.g. A' of the balanced blocks)
+sk_status inspect_rows(Item* it, int count, const InspectSizes& Z, const InspectArrays& W,
+                       hipStream_t st, bool validate) {
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(Z.ridx + 1, 256 * 8)), dim3(256), 0, st,
                      W.ridx, Z.ridx + 1, 0);
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(Z.bfl + 1, 256 * 8)), dim3(256), 0, st,
                      W.bfl, Z.bfl + 1, 0);
-  launch_items_cols<&Item::o_valid, OpValidate>(it, count, Z.valid, st);
+  if (validate) launch_items_cols<&Item::o_valid, OpValidate>(it, count, Z.valid, st);
   if (Z.rt > 0)
     hipLaunchKernelGGL(k_row_counts, dim3((unsigned)Z.rt), dim3(1024), 0, st, it, count, Z.rt);
   if (Z.slabs) launch_items<&Item::o_m, OpRowReduce>(it, count, Z.m, st);
+  sk_status s;
   if ((s = scan_regions<SCAN_RIDX, &Item::o_ridx>(W.ridx, Z.ridx, it, count, W.sums, st)) != SK_OK)
     return s;
   launch_items<&Item::o_m, OpRowlist>(it, count, Z.m, st);
+  return launch_ok();
+}
+
+// the row blocks, segments and entry scatter after inspect_rows
+sk_status inspect_blocks(Item* it, int count, const InspectSizes& Z, const InspectArrays& W,
+                         hipStream_t st) {
+  sk_status s;
   hipLaunchKernelGGL(k_partition, dim3(blocks_for(Z.grp * 64, 256)), dim3(256), 0, st, it, count,
                      Z.grp);
   if ((s = scan_regions<SCAN_BFL, &Item::o_bfl>(W.bfl, Z.bfl, it, count, W.sums, st)) != SK_OK)
@@ -735,6 +770,12 @@ sk_status run_inspector(Item* it, int count, const InspectSizes& Z, const Inspec
   launch_items<&Item::o_m, OpRowInfo>(it, count, Z.m, st);
   launch_items_cols<&Item::o_nnz, OpScatter>(it, count, Z.nnz, st);
   return launch_ok();
+}
+
+sk_status run_inspector(Item* it, int count, const InspectSizes& Z, const InspectArrays& W,
+                        hipStream_t st) {
+  sk_status s = inspect_rows(it, count, Z, W, st, true);
+  return s != SK_OK ? s : inspect_blocks(it, count, Z, W, st);
 }
 
 // block costs and their prefix (after the dense selection, if any)
@@ -1246,6 +1287,55 @@ sk_status colwise_impl(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, u
 // The sketch with generator mode `gen` (GEN_PHILOX for the product; the
 // others are the distribution-cost ablation's, on the shapes that have them,
 // without the dense path or the folded virtual columns).
+// a2 with balanced row blocks: the nonempty rows of A, their renumbering
+// (sk_balance.hpp), the full inspector on A' and the row list mapped back to
+// the rows of A (the generator's counters)
+sk_status balanced_inspector(const sk_csc* A, const Plan& P, const Item& I, const Layout& L,
+                             char* w, Item* d_item, const InspectSizes& Z, const InspectArrays& W,
+                             hipStream_t st) {
+  sk_status s;
+  if ((s = inspect_rows(d_item, 1, Z, W, st, true)) != SK_OK) return s;
+  BalParams B{};
+  B.hdr = I.hdr;
+  B.m = A->m; B.n = A->n; B.nnz = A->nnz; B.r_max = P.r_max;
+  B.colptr = A->colptr; B.rowidx = A->rowidx; B.vals = A->vals; B.vtype = A->vtype;
+  B.m_b = P.m_b; B.sb = P.bal_sb; B.sbm = P.bal_sb * P.m_b;
+  B.ridx = I.ridx; B.rowlist = I.rowlist; B.rowcnt = I.rowcnt;
+  B.rowoff = (int32_t*)(w + L.bal_rowoff);
+  B.ccol = (uint16_t*)(w + L.bal_ccol);
+  B.newidx = (int32_t*)(w + L.bal_newidx);
+  B.orig = (int32_t*)(w + L.bal_orig);
+  B.rowidx2 = (int32_t*)(w + L.bal_rowidx);
+  B.vals2 = (float*)(w + L.bal_vals);
+  hipLaunchKernelGGL(k_bal_prep, dim3(blocks_for(P.r_max, 256)), dim3(256), 0, st, B);
+  if ((s = scan_i32(B.rowoff, P.r_max, W.sums, st)) != SK_OK) return s;
+  if (I.rpart)
+    hipLaunchKernelGGL(k_bal_slab_prefix, dim3(blocks_for(A->m, 256)), dim3(256), 0, st, B,
+                       I.rpart);
+  if (A->nnz > 0 && Z.rt > 0)
+    hipLaunchKernelGGL(k_bal_csr, dim3((unsigned)Z.rt), dim3(1024), 0, st, B,
+                       (const int32_t*)I.rpart);
+  const size_t lds = bal_assign_lds(A->n, B.sb, B.sbm);
+  if (hipFuncSetAttribute((const void*)k_bal_assign, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds) != hipSuccess)
+    return SK_EHIP;
+  const int64_t nsb = (P.r_max + B.sbm - 1) / B.sbm;
+  hipLaunchKernelGGL(k_bal_assign, dim3((unsigned)nsb), dim3(BAL_THREADS), lds, st, B);
+  const int64_t ngrp = (nsb + BAL_BUILD_G - 1) / BAL_BUILD_G;
+  hipLaunchKernelGGL(k_bal_build, dim3(blocks_for(ngrp * A->n * 64, 256)), dim3(256), 0, st, B);
+  if ((s = launch_ok()) != SK_OK) return s;
+  Item I2 = I;  // A' (validated through A)
+  I2.rowidx = B.rowidx2;
+  I2.vals = B.vals2;
+  I2.vtype = SK_F32;
+  hipLaunchKernelGGL(k_put_item, dim3(1), dim3(64), 0, st, I2, d_item);
+  if ((s = inspect_rows(d_item, 1, Z, W, st, false)) != SK_OK) return s;
+  if ((s = inspect_blocks(d_item, 1, Z, W, st)) != SK_OK) return s;
+  hipLaunchKernelGGL(k_bal_remap, dim3(blocks_for(P.r_max, 256)), dim3(256), 0, st, I.hdr,
+                     B.orig, P.r_max, I.rowlist);
+  return launch_ok();
+}
+
 sk_status sketch_impl(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, uint64_t seed,
                       int32_t prec, const sk_tuning* tune, float* Ahat, int64_t ld, void* ws,
                       size_t ws_bytes, void* hip_stream, int gen, const float* s_pre,
@@ -1320,7 +1410,11 @@ sk_status sketch_impl(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, ui
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(256), 0, st, I.rowlist + P.r_max,
                        (int64_t)P.m_b + 1, 0);
     const InspectArrays W{I.ridx, I.rcnt, I.bfl, I.vbase, I.seg, I.bcost, (int32_t*)(w + L.sums)};
-    if ((s = run_inspector(d_item, 1, Z, W, st)) != SK_OK) return s;
+    if (P.bal_sb) {
+      if ((s = balanced_inspector(A, P, I, L, w, d_item, Z, W, st)) != SK_OK) return s;
+    } else if ((s = run_inspector(d_item, 1, Z, W, st)) != SK_OK) {
+      return s;
+    }
     // a5 (selection): dense row blocks, their rows concatenated and densified
     if (P.dense_pct) {
       hipLaunchKernelGGL(k_dense_select, dim3(1), dim3(256), 0, st, I.seg, nv, n, I.bstart,
@@ -1828,6 +1922,7 @@ sk_status sk_sketch_batched_plan(int32_t count, const sk_csc* A, const int64_t* 
                : 101;
     chosen[i].tile_rows = P.mfma ? 0 : P.d_b;
     chosen[i].col_split = 1;
+    chosen[i].balance = 1;  // (a batch keeps every item's rows in order)
   }
   return SK_OK;
 }
@@ -1863,10 +1958,10 @@ sk_status sk_plan_info(const sk_csc* A, int64_t d, int32_t dist, int32_t prec,
   tune = effective_tuning(A, d, dist, prec, tune, cached);
   Plan P;
   if (!plan_any(A->m, A->n, A->nnz, d, dist, prec, tune, P)) return SK_EINVAL;
-  const double v[5] = {tile_time_us(P), kji_time_us(A->n, A->nnz, d, dist),
+  const double v[6] = {tile_time_us(P), kji_time_us(A->n, A->nnz, d, dist),
                        (double)choose_kernel(A, d, dist, prec, tune), P.cost,
-                       (double)(P.variant + 1)};
-  for (int i = 0; i < ninfo && i < 5; ++i) info[i] = v[i];
+                       (double)(P.variant + 1), (double)(P.mfma ? 0 : P.bal_sb)};
+  for (int i = 0; i < ninfo && i < 6; ++i) info[i] = v[i];
   return SK_OK;
 }
 
@@ -1891,6 +1986,7 @@ sk_status sk_autotune(const sk_csc* A, int64_t d, int32_t dist, sk_tuning* out) 
   out->dense_min_pct = P.dense_pct ? P.dense_pct : 101;
   out->tile_rows = P.d_b;
   out->col_split = P.nv != A->n ? 2 : 1;
+  out->balance = P.bal_sb ? 2 : 1;
   return SK_OK;
 }
 

@@ -205,3 +205,34 @@ def test_measured_tuner_host_side():
                                    ctypes.byref(ms)) == -4
     assert lib.sk_autotune_measure(ctypes.byref(c), 4000, 1, 1, 0, None, 4000, None, 0, None,
                                    ctypes.byref(t), ctypes.byref(ms)) == -1
+
+
+def test_balanced_blocks_rule_host_only():
+    """Balanced row blocks: on by the model for the 2e6 x 2000 uniform shape
+    (about 3.7 entries per (block, column)), off below 512 columns, off above
+    2048 (the count table's limit) even when asked, off when asked; the
+    workspace grows by the renumbered copy of A."""
+    lib = binding.lib()
+    lib.sk_plan_cache_clear()
+
+    def bal(c, d, tune=None):
+        info = (ctypes.c_double * 6)()
+        assert lib.sk_plan_info(ctypes.byref(c), d, 1, 0, ctypes.byref(tune) if tune else None,
+                                info, 6) == 0
+        return int(info[5])
+
+    big = _csc(m=2_000_000, n=2000, nnz=20_000_000)
+    assert bal(big, 4000) == 16
+    assert bal(big, 4000, binding.SkTuning(balance=1)) == 0
+    assert bal(_csc(m=100_000, n=200, nnz=200_000), 400) == 0
+    assert bal(_csc(m=100_000, n=200, nnz=200_000), 400, binding.SkTuning(balance=2)) > 0
+    assert bal(_csc(m=2_000_000, n=3000, nnz=20_000_000), 4000, binding.SkTuning(balance=2)) == 0
+    on, off = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.sk_sketch_workspace(ctypes.byref(big), 4000, 1, 0, None, ctypes.byref(on)) == 0
+    assert lib.sk_sketch_workspace(ctypes.byref(big), 4000, 1, 0,
+                                   ctypes.byref(binding.SkTuning(balance=1)),
+                                   ctypes.byref(off)) == 0
+    assert on.value >= off.value + 10 * 20_000_000
+    t = binding.SkTuning()
+    assert lib.sk_autotune(ctypes.byref(big), 4000, 1, ctypes.byref(t)) == 0
+    assert t.balance == 2
