@@ -59,6 +59,7 @@ struct BalParams {
   uint16_t* ccol;           // nnz: the column ids of each row, rows in position order
   int32_t* newidx;          // m: new position of each nonempty row
   int32_t* orig;            // r_max: the row of A at each new position
+  int32_t* cnt2;            // r_max: the entry count at each new position
   int32_t* rowidx2;         // nnz: A' row indices (new positions)
   float* vals2;             // nnz: A' values
 };
@@ -150,13 +151,25 @@ __global__ __launch_bounds__(1024) void k_bal_csr(BalParams B, const int32_t* __
   }
 }
 
+// words of one block's row of the count table: two 16-bit counters a word,
+// an odd number of words so that the 16 candidate blocks of a row, read
+// together, fall in different LDS banks
+__host__ __device__ inline int64_t bal_row_words(int64_t n) { return ((n + 1) >> 1) | 1; }
+
 // min of (cost << 4 | block) over the 16 lanes of a segment (ties: the lower block)
+// (DPP inside the 16-lane rows: lanes swapped in pairs and pairs of pairs,
+// then the row rotated by 4 and by 8; every lane of the row ends with the
+// min; called with all lanes active)
 __device__ __forceinline__ uint32_t seg16_min(uint32_t key) {
-#pragma unroll
-  for (int m = 8; m >= 1; m >>= 1) {
-    const uint32_t o = __shfl_xor(key, m, 16);
-    key = o < key ? o : key;
-  }
+  uint32_t o;
+  o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  key = o < key ? o : key;
+  o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+  key = o < key ? o : key;
+  o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0x124, 0xF, 0xF, false);  // row_ror 4
+  key = o < key ? o : key;
+  o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0x128, 0xF, 0xF, false);  // row_ror 8
+  key = o < key ? o : key;
   return key;
 }
 
@@ -178,7 +191,7 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
   if (s0 >= R) return;
   const int tid = threadIdx.x;
   const int sbm = B.sbm, sb = B.sb, m_b = B.m_b;
-  const int64_t nh = (B.n + 1) >> 1;
+  const int64_t nh = bal_row_words(B.n);
   uint32_t* cntw = bal_lds;                                    // sb * nh
   uint16_t* col_l = reinterpret_cast<uint16_t*>(cntw + sb * nh);  // BAL_CHUNK
   int32_t* off_l = reinterpret_cast<int32_t*>(col_l + BAL_CHUNK);  // BAL_CHUNK_ROWS + 1
@@ -186,6 +199,7 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
   const auto* rowlist = in_global(B.rowlist);
   const auto* rowcnt = in_global(B.rowcnt);
   const auto* rowoff = in_global(B.rowoff);
+  int32_t* cnt2 = B.cnt2;
   const int64_t rows = R - s0 < sbm ? R - s0 : sbm;
 
   if (tid == 0) flag = rows < sbm ? 1 : 0;
@@ -196,8 +210,10 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
   if (flag) {  // in order
     for (int64_t q = tid; q < rows; q += BAL_THREADS) {
       const int32_t r = rowlist[s0 + q];
+      const int32_t c = rowcnt[s0 + q];
       B.newidx[r] = (int32_t)(s0 + q);
       B.orig[s0 + q] = r;
+      cnt2[s0 + q] = c;
     }
     return;
   }
@@ -227,16 +243,12 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
     int64_t q = p;
     while (q < pc) {
       // batch: no larger than the room of any block that has room
-      int nb = BAL_BATCH;
+      // (each lane takes one block's room; the min over the 16 lanes of a
+      // segment, in vector registers: every wave needs it)
+      const int fb = b < sb ? m_b - fill[b] : 0;
+      int nb = (int)seg16_min(fb > 0 ? (uint32_t)fb : 0xFFFFFFFFu);
+      if (nb > BAL_BATCH) nb = BAL_BATCH;
       if (pc - q < nb) nb = (int)(pc - q);
-      int fl[BAL_SB_MAX];
-#pragma unroll
-      for (int bb = 0; bb < BAL_SB_MAX; ++bb) fl[bb] = fill[bb];
-#pragma unroll
-      for (int bb = 0; bb < BAL_SB_MAX; ++bb) {
-        const int fr = m_b - fl[bb];
-        if (bb < sb && fr > 0 && fr < nb) nb = fr;
-      }
       uint32_t key = ~uint32_t(0);
       int32_t o0 = 0, o1 = 0;
       if (i < nb) {
@@ -272,6 +284,24 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
       q += nb;
     }
     p = pc;
+  }
+  // (every block holds exactly m_b rows; should that ever fail, the
+  // super-block keeps its order, so the renumbering stays a permutation)
+  if (tid == 0) {
+    int bad = 0;
+    for (int bb = 0; bb < BAL_SB_MAX; ++bb) bad |= fill[bb] != (bb < sb ? m_b : 0);
+    flag = bad;
+  }
+  __syncthreads();
+  if (flag) {
+    for (int64_t q = tid; q < rows; q += BAL_THREADS) {
+      const int32_t r = rowlist[s0 + q];
+      const int32_t c = rowcnt[s0 + q];
+      B.newidx[r] = (int32_t)(s0 + q);
+      B.orig[s0 + q] = r;
+      cnt2[s0 + q] = c;
+    }
+    return;
   }
   // slots: rank of each position among the super-block's positions of its
   // block, in position order
@@ -310,8 +340,10 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
       if (my < sb && slot < m_b) {  // (always: no block takes more than m_b rows)
         const int64_t np = s0 + (int64_t)my * m_b + slot;
         const int32_t r = rowlist[s0 + q];
+        const int32_t c = rowcnt[s0 + q];
         B.newidx[r] = (int32_t)np;
         B.orig[np] = r;
+        cnt2[np] = c;
       }
     }
 #pragma unroll
@@ -321,7 +353,7 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
 }
 
 __host__ __device__ inline size_t bal_assign_lds(int64_t n, int sb, int sbm) {
-  const size_t words = (size_t)sb * ((n + 1) / 2);
+  const size_t words = (size_t)sb * bal_row_words(n);
   return words * 4 + BAL_CHUNK * 2 + (BAL_CHUNK_ROWS + 1) * 4 + (size_t)sbm;
 }
 
@@ -437,6 +469,25 @@ __global__ __launch_bounds__(256) void k_bal_build(BalParams B) {
       }
     }
     lo = hi;
+  }
+}
+
+// The nonempty-row arrays of A' without counting: its rows 0..R-1 are the
+// new positions, all nonempty (entry counts from the assignment, in cnt2),
+// the rows from R on are empty.  (rowlist is the identity here: the block
+// positions of the inspector compare A' rows; k_bal_remap maps it back.)
+__global__ void k_bal_rows2(BalParams B, int32_t* __restrict__ ridx, int32_t* __restrict__ rcnt,
+                            int32_t* __restrict__ rowlist, int32_t* __restrict__ rowcnt) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > B.m || bal_status(B)) return;
+  const int64_t R = in_global(const_cast<Header*>(B.hdr))->nonempty;
+  ridx[r] = (int32_t)(r < R ? r : R);
+  if (r == B.m) return;
+  const int32_t c = r < R ? B.cnt2[r] : 0;
+  rcnt[r] = c;
+  if (r < R) {
+    rowlist[r] = (int32_t)r;
+    rowcnt[r] = c;
   }
 }
 

@@ -471,7 +471,7 @@ struct Layout {
   int64_t hdr, item, ridx, rcnt, rowlist, rowcnt, bfl, bstart, vbase, pos, seg, ent, bcost, sums,
       rowinfo;
   int64_t dflag, dlist, doff, dhdr, drows, dense, part, total;
-  int64_t bal_rowoff, bal_ccol, bal_newidx, bal_orig, bal_rowidx, bal_vals;
+  int64_t bal_rowoff, bal_ccol, bal_newidx, bal_orig, bal_cnt2, bal_rowidx, bal_vals;
 };
 
 int64_t scan_sums_len(int64_t longest) { return longest / SCAN_CHUNK + 2; }
@@ -509,6 +509,7 @@ Layout layout_for(int64_t m, int64_t n, int64_t nnz, int64_t d, const Plan& P) {
     L.bal_ccol = off;   off = align_up(off + 2 * std::max<int64_t>(nnz, 1));
     L.bal_newidx = off; off = align_up(off + 4 * m);
     L.bal_orig = off;   off = align_up(off + 4 * P.r_max);
+    L.bal_cnt2 = off;   off = align_up(off + 4 * P.r_max);
     L.bal_rowidx = off; off = align_up(off + 4 * std::max<int64_t>(nnz, 1));
     L.bal_vals = off;   off = align_up(off + 4 * std::max<int64_t>(nnz, 1));
   }
@@ -728,15 +729,14 @@ sk_status scan_regions(int32_t* all, int64_t total, Item* it, int count, int32_t
 // a1 + a2 for every item: validation, nonempty rows, entry-balanced row
 // blocks, heavy-column splitting, segments and the entry scatter.  The
 // items' headers must be zero.
-// (a1 and the nonempty rows; `validate` = false: the input was validated
-// before, e.g. A' of the balanced blocks)
+// a1 and the nonempty rows
 sk_status inspect_rows(Item* it, int count, const InspectSizes& Z, const InspectArrays& W,
-                       hipStream_t st, bool validate) {
+                       hipStream_t st) {
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(Z.ridx + 1, 256 * 8)), dim3(256), 0, st,
                      W.ridx, Z.ridx + 1, 0);
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(Z.bfl + 1, 256 * 8)), dim3(256), 0, st,
                      W.bfl, Z.bfl + 1, 0);
-  if (validate) launch_items_cols<&Item::o_valid, OpValidate>(it, count, Z.valid, st);
+  launch_items_cols<&Item::o_valid, OpValidate>(it, count, Z.valid, st);
   if (Z.rt > 0)
     hipLaunchKernelGGL(k_row_counts, dim3((unsigned)Z.rt), dim3(1024), 0, st, it, count, Z.rt);
   if (Z.slabs) launch_items<&Item::o_m, OpRowReduce>(it, count, Z.m, st);
@@ -774,7 +774,7 @@ sk_status inspect_blocks(Item* it, int count, const InspectSizes& Z, const Inspe
 
 sk_status run_inspector(Item* it, int count, const InspectSizes& Z, const InspectArrays& W,
                         hipStream_t st) {
-  sk_status s = inspect_rows(it, count, Z, W, st, true);
+  sk_status s = inspect_rows(it, count, Z, W, st);
   return s != SK_OK ? s : inspect_blocks(it, count, Z, W, st);
 }
 
@@ -1288,13 +1288,14 @@ sk_status colwise_impl(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, u
 // others are the distribution-cost ablation's, on the shapes that have them,
 // without the dense path or the folded virtual columns).
 // a2 with balanced row blocks: the nonempty rows of A, their renumbering
-// (sk_balance.hpp), the full inspector on A' and the row list mapped back to
-// the rows of A (the generator's counters)
+// (sk_balance.hpp), A' with its nonempty rows set directly, the blocked
+// layout of A' and the row list mapped back to the rows of A (the
+// generator's counters)
 sk_status balanced_inspector(const sk_csc* A, const Plan& P, const Item& I, const Layout& L,
                              char* w, Item* d_item, const InspectSizes& Z, const InspectArrays& W,
                              hipStream_t st) {
   sk_status s;
-  if ((s = inspect_rows(d_item, 1, Z, W, st, true)) != SK_OK) return s;
+  if ((s = inspect_rows(d_item, 1, Z, W, st)) != SK_OK) return s;
   BalParams B{};
   B.hdr = I.hdr;
   B.m = A->m; B.n = A->n; B.nnz = A->nnz; B.r_max = P.r_max;
@@ -1305,6 +1306,7 @@ sk_status balanced_inspector(const sk_csc* A, const Plan& P, const Item& I, cons
   B.ccol = (uint16_t*)(w + L.bal_ccol);
   B.newidx = (int32_t*)(w + L.bal_newidx);
   B.orig = (int32_t*)(w + L.bal_orig);
+  B.cnt2 = (int32_t*)(w + L.bal_cnt2);
   B.rowidx2 = (int32_t*)(w + L.bal_rowidx);
   B.vals2 = (float*)(w + L.bal_vals);
   hipLaunchKernelGGL(k_bal_prep, dim3(blocks_for(P.r_max, 256)), dim3(256), 0, st, B);
@@ -1329,7 +1331,10 @@ sk_status balanced_inspector(const sk_csc* A, const Plan& P, const Item& I, cons
   I2.vals = B.vals2;
   I2.vtype = SK_F32;
   hipLaunchKernelGGL(k_put_item, dim3(1), dim3(64), 0, st, I2, d_item);
-  if ((s = inspect_rows(d_item, 1, Z, W, st, false)) != SK_OK) return s;
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(blocks_for(Z.bfl + 1, 256 * 8)), dim3(256), 0, st,
+                     W.bfl, Z.bfl + 1, 0);
+  hipLaunchKernelGGL(k_bal_rows2, dim3(blocks_for(A->m + 1, 256)), dim3(256), 0, st, B, I.ridx,
+                     I.rcnt, I.rowlist, I.rowcnt);
   if ((s = inspect_blocks(d_item, 1, Z, W, st)) != SK_OK) return s;
   hipLaunchKernelGGL(k_bal_remap, dim3(blocks_for(P.r_max, 256)), dim3(256), 0, st, I.hdr,
                      B.orig, P.r_max, I.rowlist);
