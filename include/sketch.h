@@ -110,7 +110,7 @@ typedef struct {
                              A_hat is not S A); 3 = (-1,1) only: S kept as
                              the integers 2^24 s, A_hat scaled by 2^-24 at the
                              end (the integer-scaling trick; same A_hat as 0).
-                             Modes 1 and 3 run on the kernel shapes 3 and 6
+                             Modes 1 and 3 run on the kernel shapes 3, 6 and 9
                              without dense blocks; else SK_EUNSUPPORTED.    */
   int32_t kernel;         /* 0 = auto, 1 = the S-tile kernel (Algorithm 4's
                              reuse of an S tile across a row block; every

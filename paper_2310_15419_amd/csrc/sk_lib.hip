@@ -105,7 +105,8 @@ struct AblationKernels {
         k_sketch<DIST_UNIFORM, DL, Q, CS, WGS, false, false, GEN_SCALED>                     \
   }
 
-const AblationKernels kAblation[] = {SK_ABLATION(2, 8, 4, 8, 1024), SK_ABLATION(5, 4, 4, 2, 1024)};
+const AblationKernels kAblation[] = {SK_ABLATION(2, 8, 4, 8, 1024), SK_ABLATION(5, 4, 4, 2, 1024),
+                                     SK_ABLATION(8, 4, 8, 16, 1024)};
 
 // the ablation kernel of a plan's shape for a generator mode (null: none)
 SketchKernel ablation_kernel(int variant, int gen, int dist) {
@@ -186,10 +187,16 @@ bool plan_for(int64_t m, int64_t n, int64_t nnz, int64_t d, int dist, const sk_t
     // one entry and a lane's per-column setup, not its multiply-adds, is the
     // cost, which shape 4 halves (measured on MI355X: the 4e6 x 1000
     // power-law matrix 4.4 against 5.3 ms, the 2e6 x 2000 one with ten
-    // nonzeros per row 21.6 against 18.1 ms)
+    // nonzeros per row 21.6 against 18.1 ms).  Rows of four or more
+    // nonzeros get balanced row blocks (below) unless the caller keeps the
+    // rows in order; with the lockstep padding then lower, eight lanes per
+    // group and sixteen columns (shape 9) take the lead (the 2e6 x 2000
+    // workload: 16.8 against 17.3 ms)
     const double r_uni = std::max(1.0, (double)m * -std::expm1(-(double)nnz / (double)m));
+    const double per_uni = (double)nnz / r_uni;
     if (n <= 512) v = 5;
-    else if (n <= 2048) v = (double)nnz / r_uni < 2.0 ? 3 : 2;
+    else if (n <= 2048)
+      v = per_uni < 2.0 ? 3 : (per_uni >= 4.0 && !(tune && tune->balance == 1) ? 8 : 2);
     else v = 1;
   }
   const Variant& V = kVariants[v];

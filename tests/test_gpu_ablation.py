@@ -34,7 +34,8 @@ def _run(B, A, d, dist, seed, tune):
 
 
 @pytest.mark.parametrize("variant,shape", [(3, (30_000, 900, 60_000, 300)),
-                                           (6, (20_000, 150, 30_000, 203))])
+                                           (6, (20_000, 150, 30_000, 203)),
+                                           (9, (30_000, 900, 60_000, 300))])
 def test_scaled_and_stored_equal_product(B, oracle_lib, variant, shape):
     import torch
     m, n, nnz, d = shape
