@@ -15,7 +15,7 @@
 // super-block, rows are dealt to its sb blocks greedily in position order,
 // each to the block where the sum over its columns of the squared current
 // counts is least (a block that is full takes no more).  Rows are decided in
-// batches of up to 64 against the counts before the batch; a batch is never
+// batches of up to 128 against the counts before the batch; a batch is never
 // larger than the free room of any block that still has room, so no block
 // overflows.  Inside a block the rows keep their order.  A super-block that
 // is not full, or that holds a row with more than BAL_ROW_MAX entries (dense
@@ -37,7 +37,7 @@ namespace sk {
 
 constexpr int BAL_SB_MAX = 16;        // blocks per super-block
 constexpr int BAL_THREADS = 1024;     // the assignment's workgroup
-constexpr int BAL_BATCH = 64;         // rows decided together
+constexpr int BAL_BATCH = 128;        // rows decided together (eight lanes each)
 constexpr int BAL_CHUNK = 8192;       // column ids staged in LDS at once
 constexpr int BAL_CHUNK_ROWS = 2048;  // rows staged at once
 constexpr int BAL_ROW_MAX = 64;       // longer rows keep their super-block in order
@@ -156,22 +156,20 @@ __global__ __launch_bounds__(1024) void k_bal_csr(BalParams B, const int32_t* __
 // together, fall in different LDS banks
 __host__ __device__ inline int64_t bal_row_words(int64_t n) { return ((n + 1) >> 1) | 1; }
 
-// min of (cost << 4 | block) over the 16 lanes of a segment (ties: the lower block)
-// (DPP inside the 16-lane rows: lanes swapped in pairs and pairs of pairs,
-// then the row rotated by 4 and by 8; every lane of the row ends with the
-// min; called with all lanes active)
-__device__ __forceinline__ uint32_t seg16_min(uint32_t key) {
+// min of (cost << 4 | block) over the 8 lanes of a segment (ties: the lower
+// block); DPP inside the 16-lane rows, called with all lanes active
+__device__ __forceinline__ uint32_t seg8_min(uint32_t key) {
+  // (the 8-lane halves of a row: quad swaps, then the half-row mirrored)
   uint32_t o;
   o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
   key = o < key ? o : key;
   o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
   key = o < key ? o : key;
-  o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0x124, 0xF, 0xF, false);  // row_ror 4
-  key = o < key ? o : key;
-  o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0x128, 0xF, 0xF, false);  // row_ror 8
+  o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0x141, 0xF, 0xF, false);  // row_half_mirror
   key = o < key ? o : key;
   return key;
 }
+
 
 // One workgroup per super-block: the greedy assignment, then the new
 // positions (block b of the super-block takes positions s0 + b m_b + slot,
@@ -221,8 +219,9 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
   if (tid < BAL_SB_MAX) fill[tid] = 0;
   __syncthreads();
 
-  const int i = tid >> 4;  // row of the batch
-  const int b = tid & 15;  // candidate block
+  const int i = tid >> 3;    // row of the batch
+  const int l = tid & 7;     // lane of the row: candidate blocks l and l + 8
+  const int b0 = l, b1 = l + 8;
   int64_t p = s0;
   while (p < s0 + sbm) {
     // stage rows [p, pc): at most BAL_CHUNK_ROWS rows and BAL_CHUNK column ids
@@ -243,10 +242,13 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
     int64_t q = p;
     while (q < pc) {
       // batch: no larger than the room of any block that has room
-      // (each lane takes one block's room; the min over the 16 lanes of a
+      // (each lane takes two blocks' room; the min over the 8 lanes of a
       // segment, in vector registers: every wave needs it)
-      const int fb = b < sb ? m_b - fill[b] : 0;
-      int nb = (int)seg16_min(fb > 0 ? (uint32_t)fb : 0xFFFFFFFFu);
+      const int f0 = b0 < sb ? m_b - fill[b0] : 0;
+      const int f1 = b1 < sb ? m_b - fill[b1] : 0;
+      const uint32_t r0 = f0 > 0 ? (uint32_t)f0 : 0xFFFFFFFFu;
+      const uint32_t r1 = f1 > 0 ? (uint32_t)f1 : 0xFFFFFFFFu;
+      int nb = (int)seg8_min(r0 < r1 ? r0 : r1);
       if (nb > BAL_BATCH) nb = BAL_BATCH;
       if (pc - q < nb) nb = (int)(pc - q);
       uint32_t key = ~uint32_t(0);
@@ -254,28 +256,35 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
       if (i < nb) {
         o0 = off_l[q - p + i];
         o1 = off_l[q - p + i + 1];
-        if (b < sb && fill[b] < m_b) {
-          uint32_t cost = 0;  // (saturating: a tie among huge costs is harmless)
-          const uint32_t* row = cntw + b * nh;
+        const bool ok0 = f0 > 0, ok1 = f1 > 0;
+        uint32_t cost0 = 0, cost1 = 0;  // (saturating: a tie among huge costs is harmless)
+        const uint32_t* row0 = cntw + (ok0 ? b0 : 0) * nh;
+        const uint32_t* row1 = cntw + (ok1 ? b1 : 0) * nh;
 #pragma unroll 4
-          for (int32_t e = o0; e < o1; ++e) {
-            const int c = col_l[e];
-            const uint32_t x = (row[c >> 1] >> ((c & 1) * 16)) & 0xFFFFu;
-            const uint32_t sq = x * x;
-            cost = cost + sq < cost ? 0xFFFFFFFFu : cost + sq;
-          }
-          key = ((cost < 0x07FFFFFFu ? cost : 0x07FFFFFFu) << 4) | (uint32_t)b;
+        for (int32_t e = o0; e < o1; ++e) {
+          const int c = col_l[e];
+          const int sh = (c & 1) * 16;
+          const uint32_t x0 = (row0[c >> 1] >> sh) & 0xFFFFu;
+          const uint32_t x1 = (row1[c >> 1] >> sh) & 0xFFFFu;
+          const uint32_t s0 = x0 * x0, s1 = x1 * x1;
+          cost0 = cost0 + s0 < cost0 ? 0xFFFFFFFFu : cost0 + s0;
+          cost1 = cost1 + s1 < cost1 ? 0xFFFFFFFFu : cost1 + s1;
         }
+        const uint32_t k0 = ok0 ? ((cost0 < 0x07FFFFFFu ? cost0 : 0x07FFFFFFu) << 4) | (uint32_t)b0
+                                : ~uint32_t(0);
+        const uint32_t k1 = ok1 ? ((cost1 < 0x07FFFFFFu ? cost1 : 0x07FFFFFFu) << 4) | (uint32_t)b1
+                                : ~uint32_t(0);
+        key = k0 < k1 ? k0 : k1;
       }
-      key = seg16_min(key);
+      key = seg8_min(key);
       const int pick = (int)(key & 0xF);
       __syncthreads();  // every cost read the counts before this batch
       if (i < nb) {
-        for (int32_t e = o0 + b; e < o1; e += 16) {
+        for (int32_t e = o0 + l; e < o1; e += 8) {
           const int c = col_l[e];
           atomicAdd(&cntw[pick * nh + (c >> 1)], 1u << ((c & 1) * 16));
         }
-        if (b == 0) {
+        if (l == 0) {
           blk_l[q - s0 + i] = (uint8_t)pick;
           atomicAdd(&fill[pick], 1);
         }
