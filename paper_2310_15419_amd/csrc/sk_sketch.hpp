@@ -297,17 +297,21 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
       const int rb = r1_n - r0_n;
       const int32_t blk_beg = beg_n;
       const int32_t blk_end = end_n;
+      // entry positions are kept relative to the first pass's staging start,
+      // in bytes (8 per entry) for the column bounds in LDS
+      const int32_t base0 = blk_beg & ~1;
       __syncthreads();  // the previous block's tile, entries and bounds are consumed
 #pragma unroll
       for (int k = 0; k < KS; ++k) {
         const int i = tid + k * WGS;
-        if (i <= P.col_per_wg) seg_lds[i] = sreg[k];
+        if (i <= P.col_per_wg) seg_lds[i] = (sreg[k] - base0) * (int32_t)sizeof(uint2);
       }
       // pass: entries [sp, s1) are processed; staging starts at the even s0a
-      int32_t sp = blk_beg;
-      int32_t s0a = sp & ~1;
-      int32_t s1 = (blk_end - s0a < P.e_max) ? blk_end : s0a + P.e_max;
-      stage_entries<WGS>(E_lds, P.ent, s0a, s1);
+      // (all relative to base0)
+      int32_t sp = blk_beg - base0;
+      int32_t s0a = 0;
+      int32_t s1 = (blk_end - base0 < P.e_max) ? blk_end - base0 : P.e_max;
+      stage_entries<WGS>(E_lds, P.ent + base0, s0a, s1);
       // fewer generator calls in flight when the accumulators are many
       produce_tile<DIST, WGS, (DL * CS >= 64 ? 2 : 4), COUNT, GEN>(
           S_lds, P, P.rowlist + row_beg, rb, grow0, tid,
@@ -319,14 +323,20 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
         if (first_pass && b + 1 < b_hi) load_bounds(b + 1);
         first_pass = false;
         if (active) {
+          // the column segments clipped to this pass's entries [sp, s1), as
+          // byte offsets; the staged entries start at s0a
+          const int32_t sp_b = sp * (int32_t)sizeof(uint2);
+          const int32_t s1_b = s1 * (int32_t)sizeof(uint2);
+          const unsigned char* const e_base =
+              reinterpret_cast<const unsigned char*>(E_lds) - s0a * (int32_t)sizeof(uint2);
 #pragma unroll
           for (int c = 0; c < CS; ++c) {
             const int32_t pc0 = seg_lds[cl + c], pc1 = seg_lds[cl + c + 1];
-            const int32_t lo = pc0 > sp ? pc0 : sp;
-            const int32_t hi = pc1 < s1 ? pc1 : s1;
+            const int32_t lo = pc0 > sp_b ? pc0 : sp_b;
+            const int32_t hi = pc1 < s1_b ? pc1 : s1_b;
             // walk by LDS pointer: one add and one compare per two entries
-            const uint2* ep = E_lds + (lo - s0a);
-            const uint2* const ep_last = E_lds + (hi - s0a) - 1;
+            const uint2* ep = reinterpret_cast<const uint2*>(e_base + lo);
+            const uint2* const ep_last = reinterpret_cast<const uint2*>(e_base + hi) - 1;
             for (; ep < ep_last; ep += 2) {
               const uint2 e0 = ep[0];
               const uint2 e1 = ep[1];
@@ -350,13 +360,13 @@ __device__ __forceinline__ void sketch_unit(const SketchParams& P, int split, in
             }
           }
         }
-        if (s1 >= blk_end) break;
+        if (s1 >= blk_end - base0) break;
         // more entries than one pass holds: stage the next pass
         sp = s1;
         s0a = sp & ~1;
-        s1 = (blk_end - s0a < P.e_max) ? blk_end : s0a + P.e_max;
+        s1 = (blk_end - base0 - s0a < P.e_max) ? blk_end - base0 : s0a + P.e_max;
         __syncthreads();
-        stage_entries<WGS>(E_lds, P.ent, s0a, s1);
+        stage_entries<WGS>(E_lds, P.ent + base0, s0a, s1);
       }
     }
   }
