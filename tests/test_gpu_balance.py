@@ -159,3 +159,14 @@ def test_balanced_validation_errors(B):
         st = B.sketch_status(ws)
         assert st["status"] == code, (name, st)
         assert torch.isnan(out).all().item()
+
+
+def test_balanced_empty_matrix(B):
+    import torch
+    m, n = 50_000, 600
+    dA = B.DeviceCsc(m, n, torch.zeros(n + 1, dtype=torch.int64, device="cuda"),
+                     torch.zeros(0, dtype=torch.int32, device="cuda"),
+                     torch.zeros(0, dtype=torch.float32, device="cuda"))
+    print("balanced, no nonzeros", flush=True)
+    out = B.sketch(dA, 64, "uniform", 1, tune={"kernel": 1, "balance": 2, "rows_per_block": 64})
+    assert torch.equal(out, torch.zeros_like(out))
