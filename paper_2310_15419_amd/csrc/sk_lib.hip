@@ -656,6 +656,10 @@ sk_status scan_i32(int32_t* a, int64_t count, int32_t* sums, hipStream_t st) {
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, a, int64_t(1), 0);
     return launch_ok();
   }
+  if (nchunks <= 4) {  // short: one workgroup scans it in place (one launch, not three)
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_THREADS), 0, st, a, count, a + count);
+    return launch_ok();
+  }
   hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)nchunks), dim3(SCAN_THREADS), 0, st, a,
                      count, sums);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_THREADS), 0, st, sums, nchunks, a + count);
