@@ -131,9 +131,13 @@ typedef struct {
                              less; A_hat is the same up to rounding, S being
                              a function of the row index).  Needs n <= 2048
                              (else rows in order).  Auto: on for 512 <= n <=
-                             2048 when a block holds about 1 to 16 entries per
-                             column and the matrix has at least four
-                             super-blocks of nonempty rows.                  */
+                             2048 when nonempty rows hold four or more
+                             nonzeros on average, a block about 1 to 16
+                             entries per column, and the matrix at least four
+                             super-blocks of nonempty rows.  It adds to the
+                             inspector's time (on 2e6 rows of ten nonzeros
+                             about 1.1 ms) what it saves in the kernel (2.4
+                             ms there).  Batched calls keep rows in order.   */
 } sk_tuning;
 
 /* Human-readable name of a status code (static storage). */

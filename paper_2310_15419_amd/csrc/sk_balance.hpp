@@ -152,7 +152,7 @@ __global__ __launch_bounds__(1024) void k_bal_csr(BalParams B, const int32_t* __
 }
 
 // words of one block's row of the count table: two 16-bit counters a word,
-// an odd number of words so that the 16 candidate blocks of a row, read
+// an odd number of words so that the candidate blocks of a row, read
 // together, fall in different LDS banks
 __host__ __device__ inline int64_t bal_row_words(int64_t n) { return ((n + 1) >> 1) | 1; }
 
@@ -199,13 +199,8 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
   const auto* rowoff = in_global(B.rowoff);
   int32_t* cnt2 = B.cnt2;
   const int64_t rows = R - s0 < sbm ? R - s0 : sbm;
-
-  if (tid == 0) flag = rows < sbm ? 1 : 0;
-  __syncthreads();
-  for (int64_t q = tid; q < rows && !flag; q += BAL_THREADS)
-    if (rowcnt[s0 + q] > BAL_ROW_MAX) flag = 1;  // (benign race: any writer sets 1)
-  __syncthreads();
-  if (flag) {  // in order
+  // the super-block's rows in order (new position = old position)
+  auto keep_order = [&]() {
     for (int64_t q = tid; q < rows; q += BAL_THREADS) {
       const int32_t r = rowlist[s0 + q];
       const int32_t c = rowcnt[s0 + q];
@@ -213,6 +208,15 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
       B.orig[s0 + q] = r;
       cnt2[s0 + q] = c;
     }
+  };
+
+  if (tid == 0) flag = rows < sbm ? 1 : 0;
+  __syncthreads();
+  for (int64_t q = tid; q < rows && !flag; q += BAL_THREADS)
+    if (rowcnt[s0 + q] > BAL_ROW_MAX) flag = 1;  // (benign race: any writer sets 1)
+  __syncthreads();
+  if (flag) {
+    keep_order();
     return;
   }
   for (int64_t j = tid; j < sb * nh; j += BAL_THREADS) cntw[j] = 0;
@@ -266,9 +270,9 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
           const int sh = (c & 1) * 16;
           const uint32_t x0 = (row0[c >> 1] >> sh) & 0xFFFFu;
           const uint32_t x1 = (row1[c >> 1] >> sh) & 0xFFFFu;
-          const uint32_t s0 = x0 * x0, s1 = x1 * x1;
-          cost0 = cost0 + s0 < cost0 ? 0xFFFFFFFFu : cost0 + s0;
-          cost1 = cost1 + s1 < cost1 ? 0xFFFFFFFFu : cost1 + s1;
+          const uint32_t sq0 = x0 * x0, sq1 = x1 * x1;
+          cost0 = cost0 + sq0 < cost0 ? 0xFFFFFFFFu : cost0 + sq0;
+          cost1 = cost1 + sq1 < cost1 ? 0xFFFFFFFFu : cost1 + sq1;
         }
         const uint32_t k0 = ok0 ? ((cost0 < 0x07FFFFFFu ? cost0 : 0x07FFFFFFu) << 4) | (uint32_t)b0
                                 : ~uint32_t(0);
@@ -303,13 +307,7 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
   }
   __syncthreads();
   if (flag) {
-    for (int64_t q = tid; q < rows; q += BAL_THREADS) {
-      const int32_t r = rowlist[s0 + q];
-      const int32_t c = rowcnt[s0 + q];
-      B.newidx[r] = (int32_t)(s0 + q);
-      B.orig[s0 + q] = r;
-      cnt2[s0 + q] = c;
-    }
+    keep_order();
     return;
   }
   // slots: rank of each position among the super-block's positions of its
