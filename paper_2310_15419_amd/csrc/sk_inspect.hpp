@@ -111,8 +111,8 @@ struct Item {
   int32_t* bfl;       // r_max + 1, region of a concatenated array
   int32_t* bstart;    // nb_max + 1
   int32_t* vbase;     // n + 1, region of a concatenated array; nullptr: no splitting
-  int32_t* pos;       // (nb_max + 1) * nv; after the scan: seg - pos (where a
-                      // (block, column)'s entries go, less its first position)
+  int32_t* pos;       // (nb_max + 1) * nv: first position of each (block,
+                      // column) inside the column's entries
   int32_t* seg;       // nb_max * nv + 1, region of a concatenated array
   uint2* ent;         // nnz + 2
   int2* rowinfo;      // m: {block, row offset in the S tile in bytes} of row r
@@ -864,72 +864,55 @@ struct OpRowInfo {
   }
 };
 
-// pos[t] <- seg[t] - pos[t] (t < nb_max nv): an entry at position q of its
-// (virtual) column in block b goes to pos[b nv + v] + q
-struct OpSegPos {
-  static __device__ void run(const Item& I, int64_t t) {
-    if (I.hdr->status) return;
-    I.pos[t] = I.seg[t] - I.pos[t];
-  }
-};
-
-// ent[pos[b nv + v] + position in v] = {row offset in the S tile, value}
-struct OpScatter {
-  // (v, position in v) of entry p of column k; a position inside one
-  // column fits 32 bits (pos holds int32)
-  static __device__ __forceinline__ void virt(const Item& I, int64_t p, int64_t k, int64_t c0,
-                                              int64_t& v, int64_t& q) {
-    v = k;
-    q = p - c0;
-    if (I.vbase) {
-      const auto* vbase = in_global(I.vbase);
-      const uint32_t s = (uint32_t)(vbase[k + 1] - vbase[k]);
-      const uint32_t q32 = (uint32_t)q;
-      const uint32_t qs = q32 / s;
-      v = vbase[k] + (q32 - qs * s);
-      q = qs;
-    }
-  }
+// ent, one thread per (block b, virtual column v): the segment
+// [seg[b nv + v], seg[b nv + v + 1]) takes the column's entries from its
+// position pos[b nv + v] on (entry t of column k lies in virtual column
+// vbase[k] + t mod s_k at position t / s_k), each as {row offset in the S
+// tile, value}.  The writes of neighbouring threads are neighbouring
+// segments; the reads of one thread are consecutive entries of one column
+// (consecutive blocks read on where the previous one stopped).
+struct OpGather {
+  static constexpr int kPerThread = 1;
   static __device__ __forceinline__ uint32_t tagged(const Item& I, int2 ri, int64_t k) {
     uint32_t x = (uint32_t)ri.y;
     if (I.col_tag) x |= ((uint32_t)k & (uint32_t)(I.col_tag - 1)) << 16;
     return x;
   }
-  static __device__ void run(const Item& I, int64_t p, int64_t k) {
+  static __device__ void run(const Item& I, int64_t t) {
     if (in_global(I.hdr)->status) return;
-    const int2 ri = load_pair(I.rowinfo, in_global(I.rowidx)[p]);
-    int64_t v, q;
-    virt(I, p, k, in_global(I.colptr)[k], v, q);
-    const int64_t dest = (int64_t)in_global(I.pos)[(int64_t)ri.x * I.nv + v] + q;
-    store_pair(I.ent, dest, tagged(I, ri, k), __float_as_uint(load_value(I.vals, I.vtype, p)));
-  }
-  // the same for N entries, stage by stage: rows and values, the rows'
-  // block and offset, the (block, column) positions, then the stores
-  template <int N>
-  static __device__ void run_many(const Item& I, const int64_t (&p)[N], const int64_t (&k)[N],
-                                  const bool (&ok)[N]) {
-    if (in_global(I.hdr)->status) return;
-    const auto* rowidx = in_global(I.rowidx);
-    const auto* colptr = in_global(I.colptr);
-    const auto* pos = in_global(I.pos);
-    int32_t row[N];
-    float a[N];
-    int64_t v[N], q[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      row[j] = rowidx[p[j]];
-      a[j] = load_value(I.vals, I.vtype, p[j]);
-      virt(I, p[j], k[j], colptr[k[j]], v[j], q[j]);
+    const auto* seg = in_global(I.seg);
+    const int32_t s0 = seg[t], s1 = seg[t + 1];
+    if (s1 <= s0) return;
+    const int64_t v = t % I.nv;
+    const int32_t q0 = in_global(I.pos)[t];
+    int64_t k = v, j = 0, sk = 1;
+    if (I.vbase) {
+      const auto* vb = in_global(I.vbase);
+      k = real_column(I.vbase, I.n, v);
+      j = v - vb[k];
+      sk = vb[k + 1] - vb[k];
     }
-    int2 ri[N];
+    const int64_t c0 = in_global(I.colptr)[k];
+    const auto* rowidx = in_global(I.rowidx);
+    const int32_t cnt = s1 - s0;
+    // four entries a round: their loads together, then the row offsets
+    for (int32_t i0 = 0; i0 < cnt; i0 += 4) {
+      int32_t r[4];
+      float a[4];
 #pragma unroll
-    for (int j = 0; j < N; ++j) ri[j] = load_pair(I.rowinfo, row[j]);
-    int32_t base[N];
+      for (int u = 0; u < 4; ++u) {
+        const int32_t i = i0 + u < cnt ? i0 + u : i0;
+        const int64_t p = c0 + (int64_t)(q0 + i) * sk + j;
+        r[u] = rowidx[p];
+        a[u] = load_value(I.vals, I.vtype, p);
+      }
+      int2 ri[4];
 #pragma unroll
-    for (int j = 0; j < N; ++j) base[j] = pos[(int64_t)ri[j].x * I.nv + v[j]];
+      for (int u = 0; u < 4; ++u) ri[u] = load_pair(I.rowinfo, r[u]);
 #pragma unroll
-    for (int j = 0; j < N; ++j)
-      if (ok[j]) store_pair(I.ent, (int64_t)base[j] + q[j], tagged(I, ri[j], k[j]), __float_as_uint(a[j]));
+      for (int u = 0; u < 4; ++u)
+        if (i0 + u < cnt) store_pair(I.ent, (int64_t)s0 + i0 + u, tagged(I, ri[u], k), __float_as_uint(a[u]));
+    }
   }
 };
 

@@ -738,7 +738,7 @@ sk_status scan_regions(int32_t* all, int64_t total, Item* it, int count, int32_t
 }
 
 // a1 + a2 for every item: validation, nonempty rows, entry-balanced row
-// blocks, heavy-column splitting, segments and the entry scatter.  The
+// blocks, heavy-column splitting, segments and the entries' gather.  The
 // items' headers must be zero.
 // a1 and the nonempty rows
 sk_status inspect_rows(Item* it, int count, const InspectSizes& Z, const InspectArrays& W,
@@ -758,7 +758,7 @@ sk_status inspect_rows(Item* it, int count, const InspectSizes& Z, const Inspect
   return launch_ok();
 }
 
-// the row blocks, segments and entry scatter after inspect_rows
+// the row blocks, segments and entries after inspect_rows
 sk_status inspect_blocks(Item* it, int count, const InspectSizes& Z, const InspectArrays& W,
                          hipStream_t st) {
   sk_status s;
@@ -777,9 +777,8 @@ sk_status inspect_blocks(Item* it, int count, const InspectSizes& Z, const Inspe
   launch_items<&Item::o_cnt, OpBlockCnt>(it, count, Z.cnt, st);
   if ((s = scan_regions<SCAN_SEG, &Item::o_seg>(W.seg, Z.seg, it, count, W.sums, st)) != SK_OK)
     return s;
-  launch_items<&Item::o_cnt, OpSegPos>(it, count, Z.cnt, st);
   launch_items<&Item::o_m, OpRowInfo>(it, count, Z.m, st);
-  launch_items_cols<&Item::o_nnz, OpScatter>(it, count, Z.nnz, st);
+  launch_items<&Item::o_cnt, OpGather>(it, count, Z.cnt, st);
   return launch_ok();
 }
 
