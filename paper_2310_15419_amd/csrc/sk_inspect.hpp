@@ -864,6 +864,72 @@ struct OpRowInfo {
   }
 };
 
+// ent[seg[b nv + v] + position in v - pos[b nv + v]] = {row offset in the S
+// tile, value}: one thread per entry (for blocks whose column segments are
+// long, where the per-segment gather below would walk them one by one)
+struct OpScatter {
+  // (v, position in v) of entry p of column k; a position inside one
+  // column fits 32 bits (pos holds int32)
+  static __device__ __forceinline__ void virt(const Item& I, int64_t p, int64_t k, int64_t c0,
+                                              int64_t& v, int64_t& q) {
+    v = k;
+    q = p - c0;
+    if (I.vbase) {
+      const auto* vbase = in_global(I.vbase);
+      const uint32_t s = (uint32_t)(vbase[k + 1] - vbase[k]);
+      const uint32_t q32 = (uint32_t)q;
+      const uint32_t qs = q32 / s;
+      v = vbase[k] + (q32 - qs * s);
+      q = qs;
+    }
+  }
+  static __device__ __forceinline__ uint32_t tagged(const Item& I, int2 ri, int64_t k) {
+    uint32_t x = (uint32_t)ri.y;
+    if (I.col_tag) x |= ((uint32_t)k & (uint32_t)(I.col_tag - 1)) << 16;
+    return x;
+  }
+  static __device__ void run(const Item& I, int64_t p, int64_t k) {
+    if (in_global(I.hdr)->status) return;
+    const int2 ri = load_pair(I.rowinfo, in_global(I.rowidx)[p]);
+    int64_t v, q;
+    virt(I, p, k, in_global(I.colptr)[k], v, q);
+    const int64_t bv = (int64_t)ri.x * I.nv + v;
+    const int64_t dest = (int64_t)in_global(I.seg)[bv] - in_global(I.pos)[bv] + q;
+    store_pair(I.ent, dest, tagged(I, ri, k), __float_as_uint(load_value(I.vals, I.vtype, p)));
+  }
+  // the same for N entries, stage by stage: rows and values, the rows'
+  // block and offset, the (block, column) positions, then the stores
+  template <int N>
+  static __device__ void run_many(const Item& I, const int64_t (&p)[N], const int64_t (&k)[N],
+                                  const bool (&ok)[N]) {
+    if (in_global(I.hdr)->status) return;
+    const auto* rowidx = in_global(I.rowidx);
+    const auto* colptr = in_global(I.colptr);
+    const auto* pos = in_global(I.pos);
+    int32_t row[N];
+    float a[N];
+    int64_t v[N], q[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      row[j] = rowidx[p[j]];
+      a[j] = load_value(I.vals, I.vtype, p[j]);
+      virt(I, p[j], k[j], colptr[k[j]], v[j], q[j]);
+    }
+    int2 ri[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) ri[j] = load_pair(I.rowinfo, row[j]);
+    int32_t base[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int64_t bv = (int64_t)ri[j].x * I.nv + v[j];
+      base[j] = in_global(I.seg)[bv] - pos[bv];
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (ok[j]) store_pair(I.ent, (int64_t)base[j] + q[j], tagged(I, ri[j], k[j]), __float_as_uint(a[j]));
+  }
+};
+
 // ent, one thread per (block b, virtual column v): the segment
 // [seg[b nv + v], seg[b nv + v + 1]) takes the column's entries from its
 // position pos[b nv + v] on (entry t of column k lies in virtual column

@@ -758,9 +758,10 @@ sk_status inspect_rows(Item* it, int count, const InspectSizes& Z, const Inspect
   return launch_ok();
 }
 
-// the row blocks, segments and entries after inspect_rows
+// the row blocks, segments and entries after inspect_rows; `gather`: the
+// entries by (block, column) segment (short segments), else by entry
 sk_status inspect_blocks(Item* it, int count, const InspectSizes& Z, const InspectArrays& W,
-                         hipStream_t st) {
+                         hipStream_t st, bool gather) {
   sk_status s;
   hipLaunchKernelGGL(k_partition, dim3(blocks_for(Z.grp * 64, 256)), dim3(256), 0, st, it, count,
                      Z.grp);
@@ -778,14 +779,24 @@ sk_status inspect_blocks(Item* it, int count, const InspectSizes& Z, const Inspe
   if ((s = scan_regions<SCAN_SEG, &Item::o_seg>(W.seg, Z.seg, it, count, W.sums, st)) != SK_OK)
     return s;
   launch_items<&Item::o_m, OpRowInfo>(it, count, Z.m, st);
-  launch_items<&Item::o_cnt, OpGather>(it, count, Z.cnt, st);
+  if (gather) launch_items<&Item::o_cnt, OpGather>(it, count, Z.cnt, st);
+  else launch_items_cols<&Item::o_nnz, OpScatter>(it, count, Z.nnz, st);
   return launch_ok();
 }
 
 sk_status run_inspector(Item* it, int count, const InspectSizes& Z, const InspectArrays& W,
-                        hipStream_t st) {
+                        hipStream_t st, bool gather = false) {
   sk_status s = inspect_rows(it, count, Z, W, st);
-  return s != SK_OK ? s : inspect_blocks(it, count, Z, W, st);
+  return s != SK_OK ? s : inspect_blocks(it, count, Z, W, st, gather);
+}
+
+// The entries' gather walks a (block, column) segment in one thread: it pays
+// where segments are short (the plain-scale workload: 3.7 entries, 0.46 ->
+// 0.31 ms), not where few blocks hold long ones (small items: one thread
+// per entry is faster).  Estimated from the plan: entries per (row group,
+// column).
+bool gather_pays(const Plan& P, int64_t nnz) {
+  return (double)nnz <= 8.0 * (double)std::max<int64_t>(P.ngroups, 1) * (double)P.nv;
 }
 
 // block costs and their prefix (after the dense selection, if any)
@@ -1345,7 +1356,7 @@ sk_status balanced_inspector(const sk_csc* A, const Plan& P, const Item& I, cons
                      W.bfl, Z.bfl + 1, 0);
   hipLaunchKernelGGL(k_bal_rows2, dim3(blocks_for(A->m + 1, 256)), dim3(256), 0, st, B, I.ridx,
                      I.rcnt, I.rowlist, I.rowcnt);
-  if ((s = inspect_blocks(d_item, 1, Z, W, st)) != SK_OK) return s;
+  if ((s = inspect_blocks(d_item, 1, Z, W, st, gather_pays(P, A->nnz))) != SK_OK) return s;
   hipLaunchKernelGGL(k_bal_remap, dim3(blocks_for(P.r_max, 256)), dim3(256), 0, st, I.hdr,
                      B.orig, P.r_max, I.rowlist);
   return launch_ok();
@@ -1427,7 +1438,7 @@ sk_status sketch_impl(const sk_csc* A, int64_t row0, int64_t d, int32_t dist, ui
     const InspectArrays W{I.ridx, I.rcnt, I.bfl, I.vbase, I.seg, I.bcost, (int32_t*)(w + L.sums)};
     if (P.bal_sb) {
       if ((s = balanced_inspector(A, P, I, L, w, d_item, Z, W, st)) != SK_OK) return s;
-    } else if ((s = run_inspector(d_item, 1, Z, W, st)) != SK_OK) {
+    } else if ((s = run_inspector(d_item, 1, Z, W, st, gather_pays(P, A->nnz))) != SK_OK) {
       return s;
     }
     // a5 (selection): dense row blocks, their rows concatenated and densified
