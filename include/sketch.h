@@ -136,7 +136,7 @@ typedef struct {
                              entries per column, and the matrix at least four
                              super-blocks of nonempty rows.  It adds to the
                              inspector's time (on 2e6 rows of ten nonzeros
-                             about 1.1 ms) what it saves in the kernel (2.4
+                             about 1 ms) and saves more in the kernel (2.4
                              ms there).  Batched calls keep rows in order.   */
 } sk_tuning;
 
