@@ -15,9 +15,10 @@
 // super-block, rows are dealt to its sb blocks greedily in position order,
 // each to the block where the sum over its columns of the squared current
 // counts is least (a block that is full takes no more).  Rows are decided in
-// batches of up to 128 against the counts before the batch; a batch is never
-// larger than the free room of any block that still has room, so no block
-// overflows.  Inside a block the rows keep their order.  A super-block that
+// batches of up to 128 against the counts before the batch; a batch keeps its
+// rows up to the first one whose block would overflow, and the next batch
+// starts there, so no block overflows.  Inside a block the rows keep their
+// order.  A super-block that
 // is not full, or that holds a row with more than BAL_ROW_MAX entries (dense
 // rows belong together, for the dense path), keeps its order.
 //
@@ -179,6 +180,7 @@ __device__ __forceinline__ uint32_t seg8_min(uint32_t key) {
 __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
   extern __shared__ __align__(16) uint32_t bal_lds[];
   __shared__ int32_t fill[BAL_SB_MAX];
+  __shared__ uint8_t pick_l[BAL_BATCH];
   __shared__ int32_t wtot[BAL_THREADS / 64][BAL_SB_MAX];
   __shared__ int32_t wsum[BAL_SB_MAX];
   __shared__ int32_t flag;
@@ -226,6 +228,8 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
   const int i = tid >> 3;    // row of the batch
   const int l = tid & 7;     // lane of the row: candidate blocks l and l + 8
   const int b0 = l, b1 = l + 8;
+  const int lane = tid & 63;
+  const uint64_t le = ~uint64_t(0) >> (63 - lane);  // lanes 0..lane
   int64_t p = s0;
   while (p < s0 + sbm) {
     // stage rows [p, pc): at most BAL_CHUNK_ROWS rows and BAL_CHUNK column ids
@@ -245,16 +249,20 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
     __syncthreads();
     int64_t q = p;
     while (q < pc) {
-      // batch: no larger than the room of any block that has room
-      // (each lane takes two blocks' room; the min over the 8 lanes of a
-      // segment, in vector registers: every wave needs it)
+      // every row of the batch picks, against the counts before the batch,
+      // its cheapest block among those with room; the batch keeps its rows
+      // up to the first one whose block would take more rows than its room
+      // (that row and the later ones start the next batch; the first row
+      // always fits, so every batch decides at least one row)
+      const int nb = pc - q < BAL_BATCH ? (int)(pc - q) : BAL_BATCH;
+      // room of blocks b0 and b1 (every segment of 8 lanes holds the same),
+      // and the least room of a block that has room (in vector registers:
+      // every wave needs it)
       const int f0 = b0 < sb ? m_b - fill[b0] : 0;
       const int f1 = b1 < sb ? m_b - fill[b1] : 0;
       const uint32_t r0 = f0 > 0 ? (uint32_t)f0 : 0xFFFFFFFFu;
       const uint32_t r1 = f1 > 0 ? (uint32_t)f1 : 0xFFFFFFFFu;
-      int nb = (int)seg8_min(r0 < r1 ? r0 : r1);
-      if (nb > BAL_BATCH) nb = BAL_BATCH;
-      if (pc - q < nb) nb = (int)(pc - q);
+      const uint32_t least = (uint32_t)__builtin_amdgcn_readfirstlane((int)seg8_min(r0 < r1 ? r0 : r1));
       uint32_t key = ~uint32_t(0);
       int32_t o0 = 0, o1 = 0;
       if (i < nb) {
@@ -282,8 +290,29 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
       }
       key = seg8_min(key);
       const int pick = (int)(key & 0xF);
-      __syncthreads();  // every cost read the counts before this batch
-      if (i < nb) {
+      if (i < nb && l == 0) pick_l[i] = (uint8_t)pick;
+      __syncthreads();  // every cost read the counts and rooms before this batch; the picks are in
+      int acc = nb;
+      if ((uint32_t)nb > least) {
+        // the accepted prefix: lane L looks at batch rows L and 64 + L
+        const int p_lo = lane < nb ? pick_l[lane] : 0xFF;
+        const int p_hi = 64 + lane < nb ? pick_l[64 + lane] : 0xFF;
+        bool bad_lo = false, bad_hi = false;
+#pragma unroll
+        for (int bb = 0; bb < BAL_SB_MAX; ++bb) {
+          const int rb = __builtin_amdgcn_readlane(bb < 8 ? f0 : f1, bb & 7);  // room of block bb
+          const uint64_t m_lo = __ballot(p_lo == bb), m_hi = __ballot(p_hi == bb);
+          bad_lo |= p_lo == bb && __popcll(m_lo & le) > rb;
+          bad_hi |= p_hi == bb && __popcll(m_lo) + __popcll(m_hi & le) > rb;
+        }
+        const uint64_t x_lo = __ballot(bad_lo), x_hi = __ballot(bad_hi);
+        // (at least one row, so that the loop ends whatever the rooms: a row
+        // that found no room overfills a block, and the check after the
+        // loop then keeps the super-block in order)
+        acc = x_lo ? __builtin_ctzll(x_lo) : (x_hi ? 64 + __builtin_ctzll(x_hi) : nb);
+        acc = acc > 0 ? acc : 1;
+      }
+      if (i < acc && pick < sb) {
         for (int32_t e = o0 + l; e < o1; e += 8) {
           const int c = col_l[e];
           atomicAdd(&cntw[pick * nh + (c >> 1)], 1u << ((c & 1) * 16));
@@ -294,7 +323,7 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
         }
       }
       __syncthreads();
-      q += nb;
+      q += acc;
     }
     p = pc;
   }
@@ -312,7 +341,7 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
   }
   // slots: rank of each position among the super-block's positions of its
   // block, in position order
-  const int wave = tid >> 6, lane = tid & 63;
+  const int wave = tid >> 6;
   int32_t base[BAL_SB_MAX];
 #pragma unroll
   for (int bb = 0; bb < BAL_SB_MAX; ++bb) base[bb] = 0;
