@@ -634,7 +634,8 @@ def bench_spmm_shapes(B, which: str, steps: int) -> dict:
 
 def bench_tuner(B, names, steps: int) -> dict:
     """The measured tuner against an exhaustive sweep of the same space
-    (Algorithm 3 kernel; every S-tile kernel shape x splits 1..64) timed
+    (Algorithm 3 kernel; every S-tile kernel shape x splits 1..64 x rows in
+    order or balanced row blocks) timed
     the bench's way (event-timed average of `steps` calls), per workload."""
     import torch
     stream = torch.cuda.current_stream()
@@ -660,13 +661,16 @@ def bench_tuner(B, names, steps: int) -> dict:
         sweep = [{"kernel": 2, "ms": run({"kernel": 2})}]
         for v in range(1, B.variant_count() + 1):
             for sp in (1, 2, 4, 6, 8, 12, 16, 20, 24, 32, 48, 64):
-                t = {"kernel": 1, "variant": v, "splits": sp}
-                try:
-                    ms = run(t)
-                except (B.SketchError, RuntimeError) as e:  # too many partial slices, ...
-                    log(f"{name}: sweep point {t} skipped: {e}")
-                    continue
-                sweep.append(dict(t, ms=ms))
+                for bal in (1, 2):  # rows in order, balanced row blocks
+                    t = {"kernel": 1, "variant": v, "splits": sp, "balance": bal}
+                    if bal == 2 and B.plan_info(dA, d, dist, tune=t)["balance_sb"] == 0:
+                        continue  # (the plan has no balanced form)
+                    try:
+                        ms = run(t)
+                    except (B.SketchError, RuntimeError) as e:  # too many partial slices, ...
+                        log(f"{name}: sweep point {t} skipped: {e}")
+                        continue
+                    sweep.append(dict(t, ms=ms))
             log(f"{name}: swept variant {v}")
         best = min(sweep, key=lambda r: r["ms"])
         row = {"workload": name, "d": d, "dist": dist, "model_tuning": model,

@@ -269,10 +269,14 @@ sk_status sk_plan_info(const sk_csc* A, int64_t d, int32_t dist, int32_t prec,
 /* Autotuner, measured form: runs the candidates on the device and keeps the
  * fastest.  Stage one times the Algorithm 3 kernel (FP32 only) and every
  * S-tile kernel shape at the model's splits (the matrix-core path: its one
- * shape); stage two times splits 1..64 for the three fastest S-tile shapes.
+ * shape); stage two times splits 1..64 for the three fastest S-tile shapes
+ * (balanced row blocks as the model's rule decides); stage three times the
+ * winner with the balanced row blocks switched the other way (balance 1 or
+ * 2), where the S-tile kernel runs it and the plan allows the switch.
  * Each candidate: one untimed call, then the best of up to three calls timed
  * with events on hip_stream (one when already 1.5x slower than the best).
- * The winner (fields kernel, variant, splits; the rest 0) is written to *out,
+ * The winner (fields kernel, variant, splits, balance; the rest 0) is
+ * written to *out,
  * its time in ms to *best_ms (may be NULL), and stored in the process-wide
  * plan cache under the request's shape class: distribution, precision and
  * the sizes m, n, nnz, d each rounded to half an octave.  From then on

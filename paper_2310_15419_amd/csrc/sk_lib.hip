@@ -1571,13 +1571,39 @@ std::vector<sk_tuning> tune_stage_two(const sk_csc* A, int64_t d, int dist, int 
   return c;
 }
 
-// every candidate either stage may run (for the workspace bound)
+// stage three: the winner with the balanced row blocks switched the other
+// way (on where its plan has them off, off where on), when that plan exists
+bool tune_stage_three(const sk_csc* A, int64_t d, int dist, int prec, const sk_tuning& win,
+                      sk_tuning* flip) {
+  if (win.kernel != KERNEL_TILE || win.variant == 0) return false;
+  Plan P;
+  if (!plan_any(A->m, A->n, A->nnz, d, dist, prec, &win, P) || P.mfma) return false;
+  sk_tuning t = win;
+  t.balance = P.bal_sb ? 1 : 2;
+  Plan P2;
+  if (!plan_any(A->m, A->n, A->nnz, d, dist, prec, &t, P2)) return false;
+  if ((P2.bal_sb != 0) == (P.bal_sb != 0)) return false;  // (the rule refuses the switch)
+  *flip = t;
+  return true;
+}
+
+// every candidate the stages may run (for the workspace bound): the S-tile
+// candidates also with the balanced row blocks on and off
 std::vector<sk_tuning> tune_candidates_all(const sk_csc* A, int64_t d, int dist, int prec) {
   std::vector<sk_tuning> c = tune_stage_one(A, dist, prec);
   const size_t first = c.size();
   for (size_t i = 0; i < first; ++i)
     if (c[i].kernel == KERNEL_TILE)
       for (const sk_tuning& t : tune_stage_two(A, d, dist, prec, c[i].variant)) c.push_back(t);
+  const size_t all = c.size();
+  for (size_t i = 0; i < all; ++i) {
+    if (c[i].kernel != KERNEL_TILE || c[i].variant == 0) continue;
+    for (int b = 1; b <= 2; ++b) {
+      sk_tuning t = c[i];
+      t.balance = b;
+      c.push_back(t);
+    }
+  }
   return c;
 }
 
@@ -2080,9 +2106,18 @@ sk_status sk_autotune_measure(const sk_csc* A, int64_t d, int32_t dist, uint64_t
       best = std::min(best, ms);
     }
   }
-  const auto win = std::min_element(timed.begin(), timed.end(), [](const auto& a, const auto& b) {
-    return a.first < b.first;
-  });
+  auto faster = [](const auto& a, const auto& b) { return a.first < b.first; };
+  // stage three: the winner with the balanced row blocks switched
+  sk_tuning flip;
+  if (tune_stage_three(A, d, dist, prec, std::min_element(timed.begin(), timed.end(), faster)->second,
+                       &flip)) {
+    double ms = 0.0;
+    s = time_call(A, d, dist, seed, prec, flip, Ahat, ld, ws, ws_bytes, st, 1.5 * best, &ms);
+    if (s == SK_OK) s = sk_sketch_status(ws, st, nullptr, nullptr);
+    if (s == SK_OK) timed.emplace_back(ms, flip);
+    else if (s != SK_EUNSUPPORTED && s != SK_EINVAL) return s;
+  }
+  const auto win = std::min_element(timed.begin(), timed.end(), faster);
   *out = win->second;
   if (best_ms) *best_ms = win->first;
   {

@@ -93,6 +93,31 @@ def test_measured_tuner_caches_its_winner(B, oracle_lib):
     assert B.plan_cache_lookup(dA, d, "gaussian") is None
 
 
+def test_measured_tuner_balance_stage(B, oracle_lib):
+    # ten nonzeros per row over 1000 columns: the S-tile kernel wins, so the
+    # third stage times the winner with the balanced row blocks switched;
+    # the tuner's own workspace bound must hold both forms of every shape
+    import torch
+    B.plan_cache_clear()
+    m, n, d = 300_000, 1000, 2000
+    A = inputs.per_row_columns(m, n, 10, seed=31)
+    dA = B.DeviceCsc.from_host(A)
+    out = torch.full((n, d), float("nan"), dtype=torch.float32, device="cuda")
+    print("measured tuner, balance stage", flush=True)
+    tune, ms = B.autotune_measure(dA, d, "uniform", 17, out)
+    torch.cuda.synchronize()
+    print(f"winner {tune} {ms:.3f} ms", flush=True)
+    assert tune["kernel"] == B.KERNEL_TILE and tune["balance"] in (0, 1, 2), tune
+    explicit = _sketch(B, dA, d, "uniform", 17, tune=tune)
+    assert torch.equal(out, explicit)
+    sub = np.arange(0, n, 9)  # every ninth column against the oracle
+    As = inputs.Csc(m, sub.size, np.concatenate([[0], np.cumsum(np.diff(A.colptr)[sub])]),
+                    np.concatenate([A.rowidx[A.colptr[k]:A.colptr[k + 1]] for k in sub]),
+                    np.concatenate([A.vals[A.colptr[k]:A.colptr[k + 1]] for k in sub]))
+    _oracle_check(oracle_lib, out[sub], As, d, "uniform", 17, "tuned, column sample")
+    B.plan_cache_clear()
+
+
 def test_measured_tuner_precision_path(B, oracle_lib):
     import torch
     B.plan_cache_clear()
