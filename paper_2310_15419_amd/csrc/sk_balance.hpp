@@ -39,10 +39,11 @@ namespace sk {
 constexpr int BAL_SB_MAX = 16;        // blocks per super-block
 constexpr int BAL_THREADS = 1024;     // the assignment's workgroup
 constexpr int BAL_BATCH = 128;        // rows decided together (eight lanes each)
-constexpr int BAL_CHUNK = 8192;       // column ids staged in LDS at once
+constexpr int BAL_CHUNK = 8192;       // column ids staged in LDS at once (a multiple of BAL_THREADS)
 constexpr int BAL_CHUNK_ROWS = 2048;  // rows staged at once
 constexpr int BAL_ROW_MAX = 64;       // longer rows keep their super-block in order
 constexpr int BAL_SBM_MAX = 16384;    // positions per super-block
+static_assert(BAL_CHUNK % BAL_THREADS == 0, "column-id staging: whole rounds of the workgroup");
 constexpr int BAL_N_MAX = 2048;       // columns (the count table: sb x n 16-bit counters)
 
 struct BalParams {
@@ -236,16 +237,43 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
     // (the offsets first, then the last row end within BAL_CHUNK; a row has
     // at most BAL_ROW_MAX entries, so one row always fits)
     const int64_t pmax = p + BAL_CHUNK_ROWS < s0 + sbm ? p + BAL_CHUNK_ROWS : s0 + sbm;
+    // (each thread's loads issued together, then stored)
     const int32_t o_p = rowoff[p];
     if (tid == 0) chunk_end = 1;
-    for (int64_t j = tid; j <= pmax - p; j += BAL_THREADS) off_l[j] = rowoff[p + j] - o_p;
+    {
+      constexpr int K = (BAL_CHUNK_ROWS + BAL_THREADS) / BAL_THREADS;  // covers BAL_CHUNK_ROWS + 1
+      int32_t x[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int64_t j = tid + k * BAL_THREADS;
+        x[k] = j <= pmax - p ? rowoff[p + j] : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int64_t j = tid + k * BAL_THREADS;
+        if (j <= pmax - p) off_l[j] = x[k] - o_p;
+      }
+    }
     __syncthreads();
     for (int64_t j = tid + 1; j <= pmax - p; j += BAL_THREADS)
       if (off_l[j] <= BAL_CHUNK) atomicMax(&chunk_end, (int)j);
     __syncthreads();
     const int64_t pc = p + chunk_end;
     const int32_t ncol = off_l[chunk_end];
-    for (int j = tid; j < ncol; j += BAL_THREADS) col_l[j] = B.ccol[o_p + j];
+    {
+      constexpr int K = BAL_CHUNK / BAL_THREADS;
+      uint16_t x[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int j = tid + k * BAL_THREADS;
+        x[k] = j < ncol ? B.ccol[o_p + j] : (uint16_t)0;
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int j = tid + k * BAL_THREADS;
+        if (j < ncol) col_l[j] = x[k];
+      }
+    }
     __syncthreads();
     int64_t q = p;
     while (q < pc) {
