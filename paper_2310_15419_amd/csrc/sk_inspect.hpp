@@ -156,58 +156,110 @@ __device__ __forceinline__ float load_value(const void* vals, int vtype, int64_t
 
 // ------------------------------------------------------------- scan (int32)
 // In-place exclusive scan of a[0..count) in chunks of SCAN_CHUNK; the grand
-// total goes to a[count].  Three passes: chunk-local scans (+ chunk sums),
-// scan of the chunk sums (one workgroup), add the chunk offsets.
+// total goes to a[count].  Three passes: the chunk sums (a read), their scan
+// (one workgroup), and the chunk-local scans from those offsets (a read and a
+// write).  Block scans are wave scans by lane shuffles plus one exchange of
+// the wave totals through LDS.
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_CHUNK = SCAN_THREADS * SCAN_ITEMS;
 
-__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t* sh, int32_t& total) {
-  // sh: SCAN_THREADS ints
-  const int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int off = 1; off < SCAN_THREADS; off <<= 1) {
-    const int32_t add = tid >= off ? sh[tid - off] : 0;
-    __syncthreads();
-    sh[tid] += add;
-    __syncthreads();
+__device__ __forceinline__ int32_t wave_inclusive_scan(int32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
   }
-  total = sh[SCAN_THREADS - 1];
-  const int32_t excl = sh[tid] - v;
-  __syncthreads();
-  return excl;
+  return x;
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_chunks(int32_t* __restrict__ a,
+// exclusive scan of one value per thread over the workgroup; the total to
+// every thread.  sh: SCAN_THREADS / 64 ints, free again on return.
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t* sh, int32_t& total) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int32_t inc = wave_inclusive_scan(v);
+  if (lane == 63) sh[w] = inc;
+  __syncthreads();
+  int32_t before = 0;
+  total = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_THREADS / 64; ++i) {
+    const int32_t t = sh[i];
+    before += i < w ? t : 0;
+    total += t;
+  }
+  __syncthreads();
+  return before + inc - v;
+}
+
+// a thread's SCAN_ITEMS consecutive values (zero past count); VEC: a is
+// 16-byte aligned, so a whole run is two 16-byte loads
+template <bool VEC>
+__device__ __forceinline__ void scan_load(const int32_t* __restrict__ a, int64_t base,
+                                          int64_t count, int32_t (&v)[SCAN_ITEMS]) {
+  if (VEC && base + SCAN_ITEMS <= count) {
+    const int4 x = *reinterpret_cast<const int4*>(a + base);
+    const int4 y = *reinterpret_cast<const int4*>(a + base + 4);
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) v[i] = base + i < count ? a[base + i] : 0;
+  }
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const int32_t* __restrict__ a,
                                                               int64_t count,
                                                               int32_t* __restrict__ sums) {
-  __shared__ int32_t sh[SCAN_THREADS];
+  __shared__ int32_t sh[SCAN_THREADS / 64];
   const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
   int32_t v[SCAN_ITEMS];
+  scan_load<VEC>(a, base, count, v);
   int32_t run = 0;
 #pragma unroll
-  for (int i = 0; i < SCAN_ITEMS; ++i) {
-    const int64_t idx = base + i;
-    v[i] = idx < count ? a[idx] : 0;
-    run += v[i];
-  }
+  for (int i = 0; i < SCAN_ITEMS; ++i) run += v[i];
   int32_t total;
-  int32_t off = block_exclusive_scan(run, sh, total);
+  block_exclusive_scan(run, sh, total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// chunk-local exclusive scans, offset by the scanned chunk sums
+template <bool VEC>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(int32_t* __restrict__ a,
+                                                             int64_t count,
+                                                             const int32_t* __restrict__ sums) {
+  __shared__ int32_t sh[SCAN_THREADS / 64];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int32_t v[SCAN_ITEMS];
+  scan_load<VEC>(a, base, count, v);
+  int32_t run = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) run += v[i];
+  int32_t total;
+  int32_t off = block_exclusive_scan(run, sh, total) + sums[blockIdx.x];
+  int32_t o[SCAN_ITEMS];
 #pragma unroll
   for (int i = 0; i < SCAN_ITEMS; ++i) {
-    const int64_t idx = base + i;
-    if (idx < count) a[idx] = off;
+    o[i] = off;
     off += v[i];
   }
-  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+  if (VEC && base + SCAN_ITEMS <= count) {
+    *reinterpret_cast<int4*>(a + base) = make_int4(o[0], o[1], o[2], o[3]);
+    *reinterpret_cast<int4*>(a + base + 4) = make_int4(o[4], o[5], o[6], o[7]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i)
+      if (base + i < count) a[base + i] = o[i];
+  }
 }
 
 // one workgroup: exclusive scan of sums[0..nchunks), total -> *grand
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(int32_t* __restrict__ sums,
                                                             int64_t nchunks,
                                                             int32_t* __restrict__ grand) {
-  __shared__ int32_t sh[SCAN_THREADS];
+  __shared__ int32_t sh[SCAN_THREADS / 64];
   int32_t carry = 0;
   for (int64_t base = 0; base < nchunks; base += SCAN_CHUNK) {
     const int64_t b0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
@@ -230,11 +282,6 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(int32_t* __restrict_
   if (threadIdx.x == 0) *grand = carry;
 }
 
-__global__ void k_scan_add(int32_t* __restrict__ a, int64_t count,
-                           const int32_t* __restrict__ sums) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) a[i] += sums[i / SCAN_CHUNK];
-}
 
 
 // item owning flattened index t of the space whose offsets are field F

@@ -660,10 +660,20 @@ sk_status scan_i32(int32_t* a, int64_t count, int32_t* sums, hipStream_t st) {
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_THREADS), 0, st, a, count, a + count);
     return launch_ok();
   }
-  hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)nchunks), dim3(SCAN_THREADS), 0, st, a,
-                     count, sums);
+  const bool vec = ((uintptr_t)a & 15) == 0;
+  if (vec)
+    hipLaunchKernelGGL(k_scan_reduce<true>, dim3((unsigned)nchunks), dim3(SCAN_THREADS), 0, st, a,
+                       count, sums);
+  else
+    hipLaunchKernelGGL(k_scan_reduce<false>, dim3((unsigned)nchunks), dim3(SCAN_THREADS), 0, st,
+                       a, count, sums);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_THREADS), 0, st, sums, nchunks, a + count);
-  hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(count, 256)), dim3(256), 0, st, a, count, sums);
+  if (vec)
+    hipLaunchKernelGGL(k_scan_apply<true>, dim3((unsigned)nchunks), dim3(SCAN_THREADS), 0, st, a,
+                       count, sums);
+  else
+    hipLaunchKernelGGL(k_scan_apply<false>, dim3((unsigned)nchunks), dim3(SCAN_THREADS), 0, st, a,
+                       count, sums);
   return launch_ok();
 }
 
