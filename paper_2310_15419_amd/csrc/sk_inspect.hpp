@@ -981,9 +981,12 @@ struct OpScatter {
 // [seg[b nv + v], seg[b nv + v + 1]) takes the column's entries from its
 // position pos[b nv + v] on (entry t of column k lies in virtual column
 // vbase[k] + t mod s_k at position t / s_k), each as {row offset in the S
-// tile, value}.  The writes of neighbouring threads are neighbouring
-// segments; the reads of one thread are consecutive entries of one column
-// (consecutive blocks read on where the previous one stopped).
+// tile, value}.  Thread index -> (b, v) in bands of GA_TB blocks, the block
+// fastest: the eight lanes of a column read its consecutive segments, which
+// lie one after another in the column (a segment is a few entries, far
+// shorter than a cache line), and a workgroup writes 32 columns' segments of
+// each of its blocks, which lie one after another in ent.
+constexpr int GA_TB = 8;
 struct OpGather {
   static constexpr int kPerThread = 1;
   static __device__ __forceinline__ uint32_t tagged(const Item& I, int2 ri, int64_t k) {
@@ -991,12 +994,19 @@ struct OpGather {
     if (I.col_tag) x |= ((uint32_t)k & (uint32_t)(I.col_tag - 1)) << 16;
     return x;
   }
-  static __device__ void run(const Item& I, int64_t t) {
+  static __device__ void run(const Item& I, int64_t x) {
     if (in_global(I.hdr)->status) return;
+    // (b, v) of thread index x in [0, nb_max nv): band of GA_TB blocks (the
+    // last one possibly shorter), then column, then block
+    const int64_t band = x / ((int64_t)GA_TB * I.nv);
+    const int64_t rem = x - band * GA_TB * I.nv;
+    const int64_t b_lo = band * GA_TB;
+    const int64_t rows = I.nb_max - b_lo < GA_TB ? I.nb_max - b_lo : GA_TB;
+    const int64_t v = rows == GA_TB ? rem / GA_TB : rem / rows;
+    const int64_t t = (b_lo + (rem - v * rows)) * I.nv + v;
     const auto* seg = in_global(I.seg);
     const int32_t s0 = seg[t], s1 = seg[t + 1];
     if (s1 <= s0) return;
-    const int64_t v = t % I.nv;
     const int32_t q0 = in_global(I.pos)[t];
     int64_t k = v, j = 0, sk = 1;
     if (I.vbase) {
