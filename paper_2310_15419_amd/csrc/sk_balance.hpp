@@ -101,14 +101,23 @@ __global__ void k_bal_slab_prefix(BalParams B, int32_t* __restrict__ rpart) {
 // the value an LDS counter had before the entry's increment, added to the
 // row's base (its list's start plus the slab's offset in it), staged in LDS
 // for the tile.  The order inside a row does not matter (only sums over it
-// are taken).
+// are taken).  A row's list is written by every slab's workgroup, two bytes
+// at a time; the workgroups are dealt to the chip's eight L2 slices (XCDs)
+// round-robin by their index, so the slabs of a tile get indices equal
+// modulo 8 (runs of 8 tiles, the tile fastest): a list's cache lines are
+// then completed in one L2 rather than written in pieces from eight.
 __global__ __launch_bounds__(1024) void k_bal_csr(BalParams B, const int32_t* __restrict__ rpart) {
   __shared__ int32_t cnt[RT_ROWS];
   __shared__ int32_t base_l[RT_ROWS];
   if (bal_status(B)) return;
   const int64_t slabs = rt_slabs(B.n);
-  const int64_t w = blockIdx.x;
-  const int64_t tile = w / slabs, slab = w - tile * slabs;
+  const int64_t tiles = (B.m + RT_ROWS - 1) / RT_ROWS;
+  const int64_t x = blockIdx.x;
+  const int64_t run = x / (8 * slabs), within = x - run * 8 * slabs;
+  const int64_t nt = tiles - run * 8 < 8 ? tiles - run * 8 : 8;  // tiles of this run
+  if (within >= nt * slabs) return;  // (no such pair: x is past the last one)
+  const int64_t tile = run * 8 + within % nt, slab = within / nt;
+  const int64_t w = tile * slabs + slab;  // the pair's index in the row-count pass
   const int64_t r0 = tile * RT_ROWS;
   if (r0 >= B.m) return;
   const int64_t r1 = r0 + RT_ROWS < B.m ? r0 + RT_ROWS : B.m;
