@@ -459,15 +459,15 @@ __global__ __launch_bounds__(256) void k_bal_build(BalParams B) {
     if (B.vtype == 1) return in_global(static_cast<const float*>(B.vals))[e];
     return __uint_as_float((uint32_t)in_global(static_cast<const uint16_t*>(B.vals))[e] << 16);
   };
-  // first entry of the column with row >= r: a 64-way search (each step
-  // probes 64 evenly spaced entries, one per lane; the answer stays in
-  // [lo, hi])
+  // first entry of the column with row >= r: an 8-way search (each step
+  // probes 8 evenly spaced entries, lanes 0..7: few cache lines per step;
+  // the answer stays in [lo, hi]), then one window of 64
   auto first_at = [&](int64_t r) {
     int64_t lo = c0, hi = c1;
     while (hi - lo > 64) {
-      const int64_t step = (hi - lo + 63) >> 6;
+      const int64_t step = (hi - lo + 7) >> 3;
       const int64_t q = lo + (int64_t)(lane + 1) * step - 1;
-      const int below = __popcll(__ballot(q < hi && rowidx[q < hi ? q : lo] < r));
+      const int below = __popcll(__ballot(lane < 8 && q < hi && rowidx[q < hi ? q : lo] < r));
       const int64_t nhi = lo + (int64_t)(below + 1) * step - 1;
       lo += (int64_t)below * step;
       if (nhi < hi) hi = nhi;
@@ -475,10 +475,22 @@ __global__ __launch_bounds__(256) void k_bal_build(BalParams B) {
     const int64_t q = lo + lane;
     return lo + __popcll(__ballot(q < hi && rowidx[q < hi ? q : lo] < r));
   };
+  // new block of new position np inside the super-block at base: (np - base)
+  // / m_b from a float reciprocal, corrected by one step (the quotient's
+  // operands are below 2^14 = BAL_SBM_MAX, exact in FP32)
+  const float inv_mb = 1.0f / (float)B.m_b;
+  int64_t base = 0;
+  auto blk_of = [&](int32_t np) {
+    const int x = (int)(np - base);
+    int q = (int)((float)x * inv_mb);
+    if (q * B.m_b > x) --q;
+    else if ((q + 1) * B.m_b <= x) ++q;
+    return q;
+  };
   const int64_t s_end = (sg + 1) * BAL_BUILD_G < nsb ? (sg + 1) * BAL_BUILD_G : nsb;
   int64_t lo = first_at(rowlist[sg * BAL_BUILD_G * B.sbm]);
   for (int64_t s = sg * BAL_BUILD_G; s < s_end; ++s) {
-    const int64_t base = s * B.sbm;
+    base = s * B.sbm;
     const int64_t rhi = base + B.sbm < R ? (int64_t)rowlist[base + B.sbm] : B.m;
     // walk: entries per new block, and the run's end
     int32_t off[BAL_SB_MAX];
@@ -494,7 +506,7 @@ __global__ __launch_bounds__(256) void k_bal_build(BalParams B) {
       const bool in = r < rhi;  // (rows are sorted: a prefix of the lanes)
       const int cnt = __popcll(__ballot(in));
       const int32_t np = in ? newidx[r] : 0;
-      const int my = in ? (int)((np - base) / B.m_b) : -1;
+      const int my = in ? blk_of(np) : -1;
 #pragma unroll
       for (int bb = 0; bb < BAL_SB_MAX; ++bb) off[bb] += __popcll(__ballot(my == bb));
       if (e0 == lo) {
@@ -526,7 +538,7 @@ __global__ __launch_bounds__(256) void k_bal_build(BalParams B) {
         const bool in = e < hi;
         const int32_t r = in ? rowidx[e] : 0;
         np = in ? newidx[r] : 0;
-        my = in ? (int)((np - base) / B.m_b) : -1;
+        my = in ? blk_of(np) : -1;
         v = in ? value(e) : 0.0f;
       }
       int64_t dst = 0;
