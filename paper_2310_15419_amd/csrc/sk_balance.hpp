@@ -162,10 +162,12 @@ __global__ __launch_bounds__(1024) void k_bal_csr(BalParams B, const int32_t* __
   }
 }
 
-// words of one block's row of the count table: two 16-bit counters a word,
-// an odd number of words so that the candidate blocks of a row, read
-// together, fall in different LDS banks
-__host__ __device__ inline int64_t bal_row_words(int64_t n) { return ((n + 1) >> 1) | 1; }
+// The count table: row j (j = 0..7) holds, for every column c, the counters
+// of blocks j and j + 8 in the low and high halves of word c, so a lane's two
+// candidate blocks are one read; rows of an odd number of words, so that the
+// eight lanes of a row (rows 0..7), reading one column together, fall in
+// different LDS banks.  (A counter stays below 2^14 = BAL_SBM_MAX.)
+__host__ __device__ inline int64_t bal_pair_words(int64_t n) { return n | 1; }
 
 // min of (cost << 4 | block) over the 8 lanes of a segment (ties: the lower
 // block); DPP inside the 16-lane rows, called with all lanes active
@@ -184,9 +186,9 @@ __device__ __forceinline__ uint32_t seg8_min(uint32_t key) {
 
 // One workgroup per super-block: the greedy assignment, then the new
 // positions (block b of the super-block takes positions s0 + b m_b + slot,
-// slots in position order).  LDS: the count table (sb x n 16-bit counters,
-// two to a word), the staged column ids and row offsets, the block of each
-// position.
+// slots in position order).  LDS: the count table (16-bit counters, blocks j
+// and j + 8 in one word), the staged column ids and row offsets, the block
+// of each position.
 __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
   extern __shared__ __align__(16) uint32_t bal_lds[];
   __shared__ int32_t fill[BAL_SB_MAX];
@@ -201,9 +203,9 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
   if (s0 >= R) return;
   const int tid = threadIdx.x;
   const int sbm = B.sbm, sb = B.sb, m_b = B.m_b;
-  const int64_t nh = bal_row_words(B.n);
-  uint32_t* cntw = bal_lds;                                    // sb * nh
-  uint16_t* col_l = reinterpret_cast<uint16_t*>(cntw + sb * nh);  // BAL_CHUNK
+  const int64_t nh = bal_pair_words(B.n);
+  uint32_t* cntw = bal_lds;                                    // 8 * nh
+  uint16_t* col_l = reinterpret_cast<uint16_t*>(cntw + 8 * nh);  // BAL_CHUNK
   int32_t* off_l = reinterpret_cast<int32_t*>(col_l + BAL_CHUNK);  // BAL_CHUNK_ROWS + 1
   uint8_t* blk_l = reinterpret_cast<uint8_t*>(off_l + BAL_CHUNK_ROWS + 1);  // sbm
   const auto* rowlist = in_global(B.rowlist);
@@ -231,7 +233,7 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
     keep_order();
     return;
   }
-  for (int64_t j = tid; j < sb * nh; j += BAL_THREADS) cntw[j] = 0;
+  for (int64_t j = tid; j < 8 * nh; j += BAL_THREADS) cntw[j] = 0;
   if (tid < BAL_SB_MAX) fill[tid] = 0;
   __syncthreads();
 
@@ -306,18 +308,15 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
         o0 = off_l[q - p + i];
         o1 = off_l[q - p + i + 1];
         const bool ok0 = f0 > 0, ok1 = f1 > 0;
-        uint32_t cost0 = 0, cost1 = 0;  // (saturating: a tie among huge costs is harmless)
-        const uint32_t* row0 = cntw + (ok0 ? b0 : 0) * nh;
-        const uint32_t* row1 = cntw + (ok1 ? b1 : 0) * nh;
+        // (saturating sums: a tie among huge costs is harmless)
+        uint32_t cost0 = 0, cost1 = 0;
+        const uint32_t* row = cntw + b0 * nh;  // blocks b0 (low half) and b1 (high)
 #pragma unroll 4
         for (int32_t e = o0; e < o1; ++e) {
-          const int c = col_l[e];
-          const int sh = (c & 1) * 16;
-          const uint32_t x0 = (row0[c >> 1] >> sh) & 0xFFFFu;
-          const uint32_t x1 = (row1[c >> 1] >> sh) & 0xFFFFu;
-          const uint32_t sq0 = x0 * x0, sq1 = x1 * x1;
-          cost0 = cost0 + sq0 < cost0 ? 0xFFFFFFFFu : cost0 + sq0;
-          cost1 = cost1 + sq1 < cost1 ? 0xFFFFFFFFu : cost1 + sq1;
+          const uint32_t w = row[col_l[e]];
+          const uint32_t x0 = w & 0xFFFFu, x1 = w >> 16;
+          cost0 = __builtin_elementwise_add_sat(cost0, x0 * x0);
+          cost1 = __builtin_elementwise_add_sat(cost1, x1 * x1);
         }
         const uint32_t k0 = ok0 ? ((cost0 < 0x07FFFFFFu ? cost0 : 0x07FFFFFFu) << 4) | (uint32_t)b0
                                 : ~uint32_t(0);
@@ -352,7 +351,7 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
       if (i < acc && pick < sb) {
         for (int32_t e = o0 + l; e < o1; e += 8) {
           const int c = col_l[e];
-          atomicAdd(&cntw[pick * nh + (c >> 1)], 1u << ((c & 1) * 16));
+          atomicAdd(&cntw[(pick & 7) * nh + c], pick >= 8 ? 0x10000u : 1u);
         }
         if (l == 0) {
           blk_l[q - s0 + i] = (uint8_t)pick;
@@ -426,7 +425,7 @@ __global__ __launch_bounds__(BAL_THREADS) void k_bal_assign(BalParams B) {
 }
 
 __host__ __device__ inline size_t bal_assign_lds(int64_t n, int sb, int sbm) {
-  const size_t words = (size_t)sb * bal_row_words(n);
+  const size_t words = (size_t)8 * bal_pair_words(n);
   return words * 4 + BAL_CHUNK * 2 + (BAL_CHUNK_ROWS + 1) * 4 + (size_t)sbm;
 }
 
