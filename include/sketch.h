@@ -88,8 +88,12 @@ typedef struct {
                              2 = S tiles + sparse accumulation, 4 = split
                              reduction, 8 = dense blocks on the matrix cores.
                              Running a subset reuses the workspace contents of
-                             an earlier full call with the same A, d and tuning
-                             (used to time one phase in isolation).           */
+                             an earlier full call with the same A (unchanged),
+                             d, distribution, precision and tuning: phases
+                             2|4|8 sketch another seed or row0 from that call's
+                             layout without validating and inspecting A again
+                             (repeated sketches of one A; also used to time
+                             one phase in isolation).                         */
   int32_t tile_rows;      /* S rows per workgroup tile (0 = autotuner's choice;
                              else a power-of-two multiple of the kernel shape's
                              rows per column group)                           */

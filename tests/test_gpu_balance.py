@@ -8,7 +8,8 @@ applies unchanged: normwise <= 1e-5, columns <= 1e-4, every element within
 super-blocks and a partial last one (kept in order), super-blocks holding
 dense rows (kept in order), the value types of the renumbered copy, columns
 with no entries in a super-block, bitwise reproducibility, the model's choice
-on the plain-scale class, and malformed input refused on the balanced path.
+on the plain-scale class, malformed input refused on the balanced path, and a
+workspace's layout reused (phases 2|4|8) for other seeds and S rows.
 """
 import numpy as np
 import pytest
@@ -170,3 +171,39 @@ def test_balanced_empty_matrix(B):
     print("balanced, no nonzeros", flush=True)
     out = B.sketch(dA, 64, "uniform", 1, tune={"kernel": 1, "balance": 2, "rows_per_block": 64})
     assert torch.equal(out, torch.zeros_like(out))
+
+
+@pytest.mark.parametrize("balance", [1, 2])
+def test_layout_reused_across_seeds_and_row_offsets(B, oracle_lib, balance):
+    # a full call lays A out in the workspace; calls with phases 2|4|8 (S
+    # tiles and accumulation, reduction, dense blocks) then sketch other
+    # seeds and S-row offsets from that layout: bitwise equal to full calls,
+    # and within the oracle's bar
+    import torch
+    m, n, d = 200_000, 1000, 512
+    A = inputs.per_row_columns(m, n, 8, seed=41)
+    dA = B.DeviceCsc.from_host(A)
+    t = dict(B.autotune(dA, d, "uniform"), kernel=B.KERNEL_TILE, balance=balance)
+    assert (B.plan_info(dA, d, "uniform", tune=t)["balance_sb"] > 0) == (balance == 2)
+    ws = B.alloc_workspace(B.workspace_bytes(dA, d, "uniform", tune=t))
+    out = torch.full((n, d), float("nan"), dtype=torch.float32, device="cuda")
+    print(f"layout reuse, balance {balance}: full call", flush=True)
+    B.sketch_into(dA, d, "uniform", 1, out, ws, tune=t)
+    reuse = dict(t, phases=2 | 4 | 8)
+    for seed, row0 in ((2, 0), (3, 777), (1, 5000)):
+        print(f"layout reuse: seed {seed}, row0 {row0}", flush=True)
+        got = torch.full((n, d), float("nan"), dtype=torch.float32, device="cuda")
+        B.sketch_into(dA, d, "uniform", seed, got, ws, row0=row0, tune=reuse)
+        full = torch.full((n, d), float("nan"), dtype=torch.float32, device="cuda")
+        ws2 = B.alloc_workspace(B.workspace_bytes(dA, d, "uniform", tune=t))
+        B.sketch_into(dA, d, "uniform", seed, full, ws2, row0=row0, tune=t)
+        torch.cuda.synchronize()
+        assert torch.equal(got, full), (seed, row0)
+        del ws2
+    sub = np.arange(0, n, 13)  # the last one against the oracle, a column sample
+    As = inputs.Csc(m, sub.size, np.concatenate([[0], np.cumsum(np.diff(A.colptr)[sub])]),
+                    np.concatenate([A.rowidx[A.colptr[k]:A.colptr[k + 1]] for k in sub]),
+                    np.concatenate([A.vals[A.colptr[k]:A.colptr[k + 1]] for k in sub]))
+    ref = oracle_lib.sketch(As.m, As.n, As.colptr, As.rowidx, As.vals.astype(np.float64), d,
+                            "uniform", 1, row0=5000)
+    assert_parity(got.cpu().numpy().astype(np.float64)[sub].T, ref, As, "uniform", "reused layout")
