@@ -59,6 +59,10 @@ __global__ __launch_bounds__(256) void k_dense_select(const int32_t* __restrict_
       // density >= min_pct %  <=>  100 cnt >= min_pct rb n
       flag = (!full && 100 * cnt >= (int64_t)min_pct * rb * n) ? 1 : 0;
     }
+    if (!__syncthreads_or(flag)) {  // (usual: no dense block here, nothing taken)
+      if (b < nb) dflag[b] = 0;
+      continue;
+    }
     sh_f[tid] = flag;
     sh_r[tid] = flag ? rb : 0;
     __syncthreads();
