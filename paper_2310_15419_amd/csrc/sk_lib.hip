@@ -890,6 +890,7 @@ SketchParams make_params(const Plan& P, const Item& I, int64_t d, int64_t row0, 
   K.m_b = P.m_b; K.e_max = P.e_max; K.d_b = P.d_b; K.ldS = P.ldS; K.log2_cpr = P.log2_cpr;
   K.dt = P.dt; K.cg = P.cg; K.tiles = P.tiles; K.splits = P.splits;
   K.col_per_wg = P.col_per_wg;
+  K.split_slow = P.bal_sb ? 0 : 1;
   K.vbase = nullptr;
   K.nreal = P.nv;
   return K;

@@ -48,6 +48,8 @@ struct SketchParams {
   int32_t tiles;    // ceil(d / d_b)
   int32_t splits;   // row-range splits
   int32_t col_per_wg; // columns one workgroup covers (cg * CS)
+  int32_t split_slow; // workgroup index -> unit: 0 the split fastest, then
+                      // the tile, then the column range; 1 the split slowest
   float* out;       // A_hat (splits == 1) or the split partials
   int64_t ld;       // leading dimension of out
   int64_t split_stride;
@@ -427,11 +429,26 @@ template <int DIST, int DL, int Q, int CS, int WGS, bool FOLD = false, bool COUN
 __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(4))) void k_sketch(
     SketchParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int bid = blockIdx.x;
-  const int split = bid % P.splits;
-  const int rest = bid / P.splits;
-  sketch_unit<DIST, DL, Q, CS, WGS, FOLD, COUNT, GEN>(P, split, rest % P.tiles, rest / P.tiles,
-                                                      smem);
+  // Units in one of two orders.  With the split slowest, each split's units
+  // run together, spread over the whole chip, so a split whose blocks cost
+  // more than their estimate (uneven blocks) slows one stretch of the launch
+  // on every CU instead of a few CUs at its end (skewed workload, 4 splits:
+  // 3.45 ms per step against 4.34 with the split fastest).  With balanced
+  // row blocks the estimates hold, and the split fastest is faster (plain
+  // workload, 6 splits: kernel 14.38 ms against 14.80: with the split
+  // slowest every CU reads the same split's blocks at once).
+  int split;
+  int64_t rest;
+  if (P.split_slow) {
+    const int64_t units = (int64_t)P.tiles * ((P.n + P.col_per_wg - 1) / P.col_per_wg);
+    split = (int)(blockIdx.x / units);
+    rest = blockIdx.x - (int64_t)split * units;
+  } else {
+    split = (int)(blockIdx.x % P.splits);
+    rest = blockIdx.x / P.splits;
+  }
+  sketch_unit<DIST, DL, Q, CS, WGS, FOLD, COUNT, GEN>(P, split, (int)(rest % P.tiles),
+                                                      (int)(rest / P.tiles), smem);
 }
 
 // Generator throughput (the measured cost h of the ablation): each thread
